@@ -1,0 +1,187 @@
+/*
+ * grpic.h -- C ABI of the MI355X GRPIC hot path.
+ *
+ * One handle holds one general-relativistic electromagnetic particle-in-cell
+ * run in Kerr space-time, Cartesian Kerr-Schild coordinates (Watson &
+ * Nishikawa, arXiv:0904.0232).  The problem statement follows Sec. 2.2 of the
+ * paper: particles carry (q, m, x, u) with u the four-velocity, and the
+ * Maxwell field tensor lives on a Yee-staggered grid (Sec. 3).  Units: the
+ * cell edge is 1 and x^4 = c t; m (hole mass) and a (spin parameter, the
+ * hole carries angular momentum m a) are lengths in cells.
+ *
+ * All device memory belongs to the handle (allocated through the optional
+ * allocator callbacks, else hipMalloc).  Host pointers passed in are only
+ * read during the call; the caller keeps ownership.  Every call returns 0 or
+ * a negative GRPIC_E* code and never throws.  A handle is not thread-safe.
+ * Work is enqueued on the HIP stream given at creation; grpic_step is
+ * asynchronous, the dump and diagnostics calls synchronise that stream.
+ */
+#ifndef GRPIC_H
+#define GRPIC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define GRPIC_MAX_SPECIES 8
+#define GRPIC_DEAD 0xFF
+
+enum {
+    GRPIC_OK = 0,
+    GRPIC_EINVAL = -1,    /* invalid argument or configuration              */
+    GRPIC_ENOMEM = -2,    /* allocation failed or capacity exceeded         */
+    GRPIC_EDEVICE = -3,   /* a HIP call failed                              */
+    GRPIC_EOVERFLOW = -4, /* fixed-point current accumulator out of range   */
+    GRPIC_ESTATE = -5,    /* call not valid in the handle's current state   */
+    GRPIC_EAGAIN = -6     /* batch: no slot or memory free right now         */
+};
+
+enum { GRPIC_FP64 = 0, GRPIC_FP32_MIXED = 1 };
+/* Stage time-dilation factor of the RK4 pusher (Sec. 3.3, the gamma_i
+ * estimate): PAPER = the printed estimate from u^4 and a^4; U4 = u^4/c. */
+enum { GRPIC_GAMMA_PAPER = 0, GRPIC_GAMMA_U4 = 1 };
+/* Transverse current weights (Sec. 4): CURVED = face-area fractions with the
+ * metric area density; FLAT = bilinear (exactly charge conserving). */
+enum { GRPIC_DEPOSIT_CURVED = 0, GRPIC_DEPOSIT_FLAT = 1 };
+
+typedef void *(*grpic_alloc_fn)(size_t bytes, void *ctx);
+typedef void (*grpic_free_fn)(void *ptr, void *ctx);
+
+typedef struct {
+    int32_t nx, ny, nz;     /* cells per axis, each >= 4                          */
+    int32_t precision;      /* GRPIC_FP64 or GRPIC_FP32_MIXED                      */
+    int32_t gamma_mode;     /* GRPIC_GAMMA_*                                        */
+    int32_t deposit_mode;   /* GRPIC_DEPOSIT_*                                      */
+    int32_t field_iters;    /* constitutive passes per half-cycle, >= 1 (3)         */
+    int32_t sort_every;     /* steps between cell sorts; 0 = never                 */
+    int32_t tile;           /* sort tile edge in cells (8)                         */
+    int32_t fp_bits;        /* fraction bits of the int64 current accumulator (44) */
+    int32_t nspecies;       /* 1..GRPIC_MAX_SPECIES                                 */
+    int32_t init_covariant; /* 0: uniform contravariant B0 (paper); 1: covariant    */
+    double c, dt;           /* speed of light and time step                        */
+    double m, a;            /* hole mass and spin parameter, |a| <= m               */
+    double center[3];       /* hole position in node coordinates                   */
+    double r_rm;            /* particles with r < r_rm are removed                 */
+    double r_exc;           /* field points with r < r_exc are frozen (flat)        */
+    double r_damp;          /* fields relax to their initial values below r_damp   */
+    double damp_max;        /* relaxation fraction per step at r = r_exc            */
+    double B0[3];           /* initial (F^23, F^31, F^12), or covariant if flagged  */
+    double charge[GRPIC_MAX_SPECIES]; /* macro-particle charge per species          */
+    double mass[GRPIC_MAX_SPECIES];   /* macro-particle mass per species (> 0)      */
+    int64_t capacity;       /* particle slots to allocate                          */
+    grpic_alloc_fn alloc;   /* optional device allocator (NULL: hipMalloc)          */
+    grpic_free_fn free;
+    void *alloc_ctx;
+} grpic_config;
+
+typedef struct {
+    int64_t n_alive[GRPIC_MAX_SPECIES];
+    int64_t n_removed_horizon; /* cumulative removals inside r_rm          */
+    int64_t n_removed_outer;   /* cumulative removals at the outer boundary */
+    int64_t gamma_clamps;      /* negative gamma discriminants clamped       */
+    int64_t flags;             /* bit 0: move > 1 cell; bit 1: fixed-point range */
+    double charge_total;
+    double energy_particles;   /* sum M c (-u_4)                              */
+    double lz_particles;       /* sum M (x u_y - y u_x), covariant u          */
+    double energy_field;       /* (1/8pi)[sum -E_cov D + sum B_cov H]         */
+    double gauss_residual_max; /* max |-div D - 4 pi rho| at checked nodes    */
+    double mass_shell_residual_max; /* max |g(u,u) + c^2|                    */
+} grpic_diag;
+
+typedef struct grpic_s grpic_t;
+
+/* Fill *cfg with the defaults for an nx x ny x nz grid: c = 1, dt = 0.5,
+ * m = a = 0, centre at the grid centre, r_rm = 1.1 r_+, r_exc = 0.5 r_+,
+ * r_damp = r_+, damp_max = 0.1, field_iters = 3, sort_every = 10, tile = 8,
+ * fp_bits = 44, FP64, PAPER gamma, CURVED deposit, one species (-1, 1). */
+void grpic_config_default(grpic_config *cfg, int32_t nx, int32_t ny, int32_t nz);
+
+/* Create a run.  Validates the configuration (grid >= 4 cells per axis,
+ * 0 <= |a| <= m, c > 0, dt > 0, Courant c dt < 1/sqrt(3), r_exc < r_rm,
+ * masses > 0) and initialises the fields (Sec. 6: uniform contravariant
+ * field).  stream is a hipStream_t (NULL: the null stream).
+ * Returns GRPIC_EINVAL, GRPIC_ENOMEM or GRPIC_EDEVICE on failure. */
+int grpic_create(const grpic_config *cfg, void *stream, grpic_t **out);
+
+/* Load n particles of one species.  x: host SoA [3][n] node coordinates;
+ * ucov: host SoA [3][n] covariant spatial four-velocity u_1..u_3.  u_4 is
+ * the future root of the mass shell g(u,u) = -c^2 (Sec. 2.1) and the stored
+ * state is the contravariant u^a.  Particles with non-finite input, outside
+ * [0, n)^3 or inside r_rm are dropped; *kept (may be NULL) receives the
+ * number kept.  Synchronous.  GRPIC_ENOMEM if the capacity is exceeded. */
+int grpic_load_particles(grpic_t *h, int32_t species, int64_t n, const double *x,
+                         const double *ucov, int64_t *kept);
+
+/* Enqueue nsteps full cycles (Sec. 2.2 and Sec. 3): magnetic half-step,
+ * RK4 push, magnetic half-step, current deposition, electric step, removal,
+ * and a cell sort every sort_every steps.  Asynchronous. */
+int grpic_step(grpic_t *h, int32_t nsteps);
+
+/* Synchronise and compute the diagnostics (FP64, deterministic order). */
+int grpic_diagnostics(grpic_t *h, grpic_diag *out);
+
+/* Number of particle slots in use (alive or dead) and capacity. */
+int grpic_particle_count(grpic_t *h, int64_t *n_slots, int64_t *capacity);
+
+/* Copy the particle state to host: x [3][n] node coordinates, u [4][n]
+ * contravariant four-velocity, sp [n] species (GRPIC_DEAD when removed);
+ * n = the slot count of grpic_particle_count.  Synchronous. */
+int grpic_dump_particles(grpic_t *h, double *x, double *u, uint8_t *sp);
+
+/* Replace the particle state verbatim (the inverse of the dump).  n <= capacity. */
+int grpic_restore_particles(grpic_t *h, int64_t n, const double *x, const double *u,
+                            const uint8_t *sp);
+
+/* Number of entries of one ghosted field component: (nx+3)(ny+3)(nz+3);
+ * entry (i,j,k), i in [-1, nx+1], is at ((k+1)(ny+3) + j+1)(nx+3) + i+1, and a
+ * component staggered by +1/2 along an axis stores i+1/2 at index i. */
+int64_t grpic_field_size(const grpic_t *h);
+
+/* Copy fields to host, each [3][field_size] doubles.  which: 0 D = F^{j4},
+ * 1 B_cov = (F_23, F_31, F_12), 2 E_cov = F_{j4}, 3 H = (F^23, F^31, F^12),
+ * 4 J (current of the last step).  Synchronous. */
+int grpic_dump_fields(grpic_t *h, int32_t which, double *out);
+
+/* Replace the evolved fields D and B_cov (each [3][field_size]). */
+int grpic_restore_fields(grpic_t *h, const double *D, const double *B);
+
+/* Copy the node tensor F^a_b of the last step, [(nx+1)(ny+1)(nz+1)][4][4]. */
+int grpic_dump_nodes(grpic_t *h, double *out);
+
+/* Push the particles nsteps times with the node tensor frozen and without
+ * deposition, removal or field update (test-particle mode).  Recomputes the
+ * node tensor from the current fields first. */
+int grpic_push_only(grpic_t *h, int32_t nsteps);
+
+/* Stable tile-major cell sort now: keys (tile T) then particle order.
+ * If keys_out is not NULL it receives the sorted keys of all slots
+ * (dead particles: 0xFFFFFFFF), and perm_out the original slot index of each
+ * sorted position.  Dead particles are compacted away afterwards. */
+int grpic_sort(grpic_t *h, uint32_t *keys_out, int64_t *perm_out);
+
+/* Kernel timing with HIP events recorded on the run's stream around each
+ * kernel group: PUSH (gather + RK4 pusher), DEPOSIT (current + removal),
+ * FIELDS (every field kernel of a step), SORT.  Off by default. */
+enum { GRPIC_TIMER_PUSH = 0, GRPIC_TIMER_DEPOSIT = 1, GRPIC_TIMER_FIELDS = 2, GRPIC_TIMER_SORT = 3,
+       GRPIC_NTIMERS = 4 };
+int grpic_set_timing(grpic_t *h, int32_t enable);
+
+/* Synchronise; ms[t] receives the summed event time of timer t and
+ * launches[t] the number of timed groups since the previous read (both
+ * arrays of GRPIC_NTIMERS entries, either may be NULL).  Resets the sums. */
+int grpic_read_timing(grpic_t *h, double *ms, int64_t *launches);
+
+/* Synchronise; *out = particle pushes performed since creation (the sum
+ * over steps of the live particles pushed). */
+int grpic_particle_steps(grpic_t *h, int64_t *out);
+
+void grpic_destroy(grpic_t *h);
+const char *grpic_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GRPIC_H */

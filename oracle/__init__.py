@@ -94,6 +94,7 @@ def lib():
         L.or_sim_node_count.restype = ctypes.c_size_t
         L.or_sim_node_count.argtypes = [ctypes.c_void_p]
         L.or_sim_compute_nodes.argtypes = [ctypes.c_void_p]
+        L.or_sim_prepare_push.argtypes = [ctypes.c_void_p]
         L.or_sim_compute_derived.argtypes = [ctypes.c_void_p]
         L.or_sim_get_nodes.argtypes = [ctypes.c_void_p, _D]
         L.or_sim_set_nodes.argtypes = [ctypes.c_void_p, _D]
@@ -246,6 +247,9 @@ class Sim:
 
     def compute_nodes(self):
         self.L.or_sim_compute_nodes(self.h)
+
+    def prepare_push(self):
+        self.L.or_sim_prepare_push(self.h)
 
     def compute_derived(self):
         self.L.or_sim_compute_derived(self.h)

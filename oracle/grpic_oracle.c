@@ -1275,6 +1275,15 @@ void or_sim_push_only(or_sim *s, int nsteps, int use_nodes)
         }
 }
 
+/* The first half of a cycle: magnetic half-step to B^n with the
+ * self-consistent E_cov^n, then the node tensor from (D^n, B^n); the state
+ * is left exactly as the push of or_sim_step sees it. */
+void or_sim_prepare_push(or_sim *s)
+{
+    field_b_to_n(s);
+    compute_nodes(s);
+}
+
 /* Deposit the current of moves x1 -> x2 for n test particles (zeroes J). */
 void or_sim_deposit_moves(or_sim *s, int64_t n, const double *x1, const double *x2, const double *Q)
 {

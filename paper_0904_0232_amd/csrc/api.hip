@@ -1,0 +1,657 @@
+// C ABI of the GRPIC hot path (declared in include/grpic.h): handle state,
+// allocation, the per-step driver and the host<->device copies.
+#include <math.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <new>
+#include <vector>
+
+#include "../../include/grpic.h"
+#include "grpic_dev.h"
+#include "grpic_impl.h"
+
+using namespace grpic;
+
+struct grpic_s {
+    grpic_config cfg;
+    hipStream_t stream;
+    Grid G;
+    Hole h;
+    Species S;
+    FieldPtrs F;
+    double *px[2][3];
+    double *pu[2][4];
+    uint8_t *psp[2];
+    int xc, uc;
+    int64_t n_slots, cap;
+    unsigned long long *counters;
+    double jscale, rscale;
+    uint32_t *keys, *keys_alt, *idx, *idx_alt;
+    void *sort_temp;
+    size_t sort_temp_bytes;
+    int key_bits;
+    unsigned long long *rho_scratch;
+    double *red;
+    int64_t red_cap;
+    std::vector<void *> allocs;
+    int64_t step_count;
+    int sticky;
+    // event timing
+    int timing;
+    std::vector<hipEvent_t> ev_pool;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_used[GRPIC_NTIMERS];
+};
+
+namespace {
+
+int check_at(hipError_t e, const char *what, int line) {
+    if (e == hipSuccess) return GRPIC_OK;
+    fprintf(stderr, "grpic: %s failed at api.hip:%d: HIP error %d (%s)\n", what, line, (int)e, hipGetErrorString(e));
+    return GRPIC_EDEVICE;
+}
+#define check(e) check_at((e), #e, __LINE__)
+#define FAILS(e) (check_at((e), #e, __LINE__) != GRPIC_OK)
+
+void *dev_alloc(grpic_t *h, size_t bytes) {
+    if (bytes == 0) bytes = 256;
+    bytes = (bytes + 255) & ~(size_t)255;
+    void *p = nullptr;
+    if (h->cfg.alloc) {
+        p = h->cfg.alloc(bytes, h->cfg.alloc_ctx);
+    } else {
+        if (FAILS(hipMalloc(&p, bytes))) p = nullptr;
+    }
+    if (p)
+        h->allocs.push_back(p);
+    else
+        fprintf(stderr, "grpic: device allocation of %zu bytes failed\n", bytes);
+    return p;
+}
+
+void dev_free(grpic_t *h, void *p) {
+    if (!p) return;
+    if (h->cfg.alloc) {
+        if (h->cfg.free) h->cfg.free(p, h->cfg.alloc_ctx);
+    } else {
+        (void)hipFree(p);
+    }
+}
+
+ParticlePtrs pp(grpic_t *h, int xb, int ub) {
+    ParticlePtrs P;
+    for (int q = 0; q < 3; q++) P.x[q] = h->px[xb][q];
+    for (int q = 0; q < 4; q++) P.u[q] = h->pu[ub][q];
+    P.sp = h->psp[ub];
+    return P;
+}
+
+hipEvent_t take_event(grpic_t *h) {
+    if (!h->ev_pool.empty()) {
+        hipEvent_t e = h->ev_pool.back();
+        h->ev_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (FAILS(hipEventCreate(&e))) return nullptr;
+    return e;
+}
+
+// Bracket a kernel group with events when timing is on.
+struct TimedGroup {
+    grpic_t *h;
+    int t;
+    hipEvent_t a, b;
+    TimedGroup(grpic_t *hh, int tt) : h(hh), t(tt), a(nullptr), b(nullptr) {
+        if (!h->timing) return;
+        a = take_event(h);
+        b = take_event(h);
+        if (a) (void)hipEventRecord(a, h->stream);
+    }
+    ~TimedGroup() {
+        if (!h->timing || !a || !b) return;
+        (void)hipEventRecord(b, h->stream);
+        h->ev_used[t].push_back({a, b});
+    }
+};
+
+
+// Errors left by earlier HIP calls of the host program (not this library)
+// must not be reported as ours: clear them on entry.
+void clear_foreign_error() { (void)hipGetLastError(); }
+
+int validate(const grpic_config *c) {
+    if (!c) return GRPIC_EINVAL;
+    if (c->nx < 4 || c->ny < 4 || c->nz < 4) return GRPIC_EINVAL;
+    if ((int64_t)c->nx * c->ny * c->nz > (int64_t)1 << 30) return GRPIC_EINVAL;
+    if (c->precision != GRPIC_FP64 && c->precision != GRPIC_FP32_MIXED) return GRPIC_EINVAL;
+    if (c->gamma_mode != GRPIC_GAMMA_PAPER && c->gamma_mode != GRPIC_GAMMA_U4) return GRPIC_EINVAL;
+    if (c->deposit_mode != GRPIC_DEPOSIT_CURVED && c->deposit_mode != GRPIC_DEPOSIT_FLAT) return GRPIC_EINVAL;
+    if (c->field_iters < 1 || c->field_iters > 16) return GRPIC_EINVAL;
+    if (c->sort_every < 0 || c->tile < 1 || c->tile > 64) return GRPIC_EINVAL;
+    if (c->fp_bits < 16 || c->fp_bits > 56) return GRPIC_EINVAL;
+    if (c->nspecies < 1 || c->nspecies > GRPIC_MAX_SPECIES) return GRPIC_EINVAL;
+    if (!(c->c > 0.0) || !(c->dt > 0.0) || !isfinite(c->c) || !isfinite(c->dt)) return GRPIC_EINVAL;
+    // Courant condition of the 3D Yee scheme with unit cells
+    if (!(c->c * c->dt < 1.0 / sqrt(3.0))) return GRPIC_EINVAL;
+    if (!(c->m >= 0.0) || !(fabs(c->a) <= c->m) || !isfinite(c->m)) return GRPIC_EINVAL;
+    if (c->m > 0.0 && !(c->r_exc >= 0.0 && c->r_exc < c->r_rm)) return GRPIC_EINVAL;
+    if (c->damp_max < 0.0 || c->damp_max > 1.0) return GRPIC_EINVAL;
+    for (int s = 0; s < c->nspecies; s++) {
+        if (!(c->mass[s] > 0.0) || !isfinite(c->charge[s])) return GRPIC_EINVAL;
+    }
+    if (c->capacity < 0 || c->capacity > ((int64_t)1 << 31) - 1) return GRPIC_EINVAL;
+    return GRPIC_OK;
+}
+
+int enqueue_field_derivation_reference(grpic_t *h) {
+    FieldPtrs &F = h->F;
+    hipStream_t s = h->stream;
+    int64_t gs = h->G.gsize();
+    for (int c = 0; c < 3; c++) {
+        if (FAILS(hipMemcpyAsync(F.D0[c], F.D[c], gs * 8, hipMemcpyDeviceToDevice, s))) return GRPIC_EDEVICE;
+        if (FAILS(hipMemcpyAsync(F.B0[c], F.B[c], gs * 8, hipMemcpyDeviceToDevice, s))) return GRPIC_EDEVICE;
+    }
+    launch_derived(h->G, F, false, true, true, s);
+    for (int c = 0; c < 3; c++) {
+        if (FAILS(hipMemcpyAsync(F.E0[c], F.E[c], gs * 8, hipMemcpyDeviceToDevice, s))) return GRPIC_EDEVICE;
+        if (FAILS(hipMemcpyAsync(F.H0[c], F.H[c], gs * 8, hipMemcpyDeviceToDevice, s))) return GRPIC_EDEVICE;
+    }
+    return GRPIC_OK;
+}
+
+int do_sort(grpic_t *h) {
+    TimedGroup tg(h, GRPIC_TIMER_SORT);
+    ParticlePtrs in = pp(h, h->xc, h->uc);
+    ParticlePtrs out = pp(h, 1 - h->xc, 1 - h->uc);
+    launch_sort(h->G, h->cfg.tile, h->n_slots, in, out, h->keys, h->keys_alt, h->idx, h->idx_alt, h->sort_temp,
+                h->sort_temp_bytes, h->key_bits, h->counters, h->stream);
+    h->xc = 1 - h->xc;
+    h->uc = 1 - h->uc;
+    return check(hipGetLastError());
+}
+
+int one_step(grpic_t *h) {
+    const grpic_config &c = h->cfg;
+    FieldPtrs &F = h->F;
+    hipStream_t s = h->stream;
+    const Grid &G = h->G;
+    int64_t gs = G.gsize();
+    double hstep = 0.5 * c.c * c.dt;
+    // magnetic half-step to time n with E_cov^n made consistent with B^n
+    for (int q = 0; q < 3; q++)
+        if (FAILS(hipMemcpyAsync(F.Bsave[q], F.B[q], gs * 8, hipMemcpyDeviceToDevice, s)))
+            return GRPIC_EDEVICE;
+    const double *Bsave[3] = {F.Bsave[0], F.Bsave[1], F.Bsave[2]};
+    {
+        TimedGroup tg(h, GRPIC_TIMER_FIELDS);
+        for (int it = 0; it < c.field_iters; it++) {
+            launch_derived(G, F, true, true, false, s);
+            launch_bhalf(G, F, Bsave, hstep, s);
+        }
+        launch_node_tensor(G, F, s);
+    }
+    // particle push x_n -> x_{n+1}
+    PushParams P;
+    P.G = G;
+    P.h = h->h;
+    P.c = c.c;
+    P.dt = c.dt;
+    P.gamma_mode = c.gamma_mode;
+    P.n = h->n_slots;
+    ParticlePtrs cur = pp(h, h->xc, h->uc);
+    ParticlePtrs nxt = pp(h, 1 - h->xc, h->uc);
+    {
+        TimedGroup tg(h, GRPIC_TIMER_PUSH);
+        launch_push(P, h->S, F.node, cur, nxt, h->counters, s);
+    }
+    // second magnetic half-step with the same E_cov^n
+    const double *Bcur[3] = {F.B[0], F.B[1], F.B[2]};
+    {
+        TimedGroup tg(h, GRPIC_TIMER_FIELDS);
+        launch_bhalf(G, F, Bcur, hstep, s);
+        for (int q = 0; q < 3; q++) launch_zero_u64(F.Jint[q], gs, s);
+    }
+    // current of the chords
+    {
+        TimedGroup tg(h, GRPIC_TIMER_DEPOSIT);
+        launch_deposit(G, h->h, c.dt, c.deposit_mode, c.r_rm, h->jscale, h->rscale, h->S, cur, nxt, h->n_slots, F,
+                       h->counters, s);
+    }
+    // electric step around D^{n+1/2}
+    for (int q = 0; q < 3; q++)
+        if (FAILS(hipMemcpyAsync(F.Dsave[q], F.D[q], gs * 8, hipMemcpyDeviceToDevice, s)))
+            return GRPIC_EDEVICE;
+    const double *Dsave[3] = {F.Dsave[0], F.Dsave[1], F.Dsave[2]};
+    double inv_js = 1.0 / h->jscale;
+    double fpc = 4.0 * M_PI / c.c;
+    {
+        TimedGroup tg(h, GRPIC_TIMER_FIELDS);
+        for (int it = 0; it < c.field_iters; it++) {
+            launch_derived(G, F, true, false, true, s);
+            double dtp = (it < c.field_iters - 1) ? 0.5 * c.dt : c.dt;
+            launch_dstep(G, F, Dsave, c.c * dtp, fpc, inv_js, s);
+        }
+        launch_relax(G, h->h, F, c.r_damp, c.damp_max, s);
+    }
+    h->xc = 1 - h->xc;
+    h->step_count++;
+    if (c.sort_every > 0 && h->step_count % c.sort_every == 0) return do_sort(h);
+    return check(hipGetLastError());
+}
+
+}  // namespace
+
+extern "C" {
+
+void grpic_config_default(grpic_config *cfg, int32_t nx, int32_t ny, int32_t nz) {
+    memset(cfg, 0, sizeof(*cfg));
+    cfg->nx = nx;
+    cfg->ny = ny;
+    cfg->nz = nz;
+    cfg->precision = GRPIC_FP64;
+    cfg->gamma_mode = GRPIC_GAMMA_PAPER;
+    cfg->deposit_mode = GRPIC_DEPOSIT_CURVED;
+    cfg->field_iters = 3;
+    cfg->sort_every = 10;
+    cfg->tile = 8;
+    cfg->fp_bits = 44;
+    cfg->nspecies = 1;
+    cfg->c = 1.0;
+    cfg->dt = 0.5;
+    cfg->center[0] = nx / 2.0;
+    cfg->center[1] = ny / 2.0;
+    cfg->center[2] = nz / 2.0;
+    cfg->r_rm = 0.0;
+    cfg->r_exc = 0.0;
+    cfg->r_damp = 0.0;
+    cfg->damp_max = 0.1;
+    cfg->charge[0] = -1.0;
+    cfg->mass[0] = 1.0;
+}
+
+const char *grpic_strerror(int code) {
+    switch (code) {
+    case GRPIC_OK: return "ok";
+    case GRPIC_EINVAL: return "invalid argument";
+    case GRPIC_ENOMEM: return "out of memory or capacity";
+    case GRPIC_EDEVICE: return "HIP error";
+    case GRPIC_EOVERFLOW: return "fixed-point overflow";
+    case GRPIC_ESTATE: return "invalid state";
+    case GRPIC_EAGAIN: return "no free slot or memory";
+    default: return "unknown error";
+    }
+}
+
+void grpic_destroy(grpic_t *h) {
+    if (!h) return;
+    (void)hipStreamSynchronize(h->stream);
+    for (auto e : h->ev_pool) (void)hipEventDestroy(e);
+    for (int t = 0; t < GRPIC_NTIMERS; t++)
+        for (auto &pr : h->ev_used[t]) {
+            (void)hipEventDestroy(pr.first);
+            (void)hipEventDestroy(pr.second);
+        }
+    for (void *p : h->allocs) dev_free(h, p);
+    delete h;
+}
+
+int grpic_create(const grpic_config *cfg, void *stream, grpic_t **out) {
+    clear_foreign_error();
+    if (!out) return GRPIC_EINVAL;
+    *out = nullptr;
+    int rc = validate(cfg);
+    if (rc) return rc;
+    if (cfg->precision != GRPIC_FP64) return GRPIC_EINVAL;  // FP32-mixed lives in its own entry
+    grpic_t *h = new (std::nothrow) grpic_s();
+    if (!h) return GRPIC_ENOMEM;
+    h->cfg = *cfg;
+    h->stream = (hipStream_t)stream;
+    h->G.nx = cfg->nx;
+    h->G.ny = cfg->ny;
+    h->G.nz = cfg->nz;
+    h->G.sx = cfg->nx + 3;
+    h->G.sy = (int64_t)(cfg->ny + 3) * (cfg->nx + 3);
+    h->h.m = cfg->m;
+    h->h.a = cfg->a;
+    h->h.cx = cfg->center[0];
+    h->h.cy = cfg->center[1];
+    h->h.cz = cfg->center[2];
+    h->h.r_exc = cfg->r_exc;
+    double qmax = 0.0;
+    for (int s = 0; s < kMaxSpecies; s++) {
+        bool on = s < cfg->nspecies;
+        h->S.charge[s] = on ? cfg->charge[s] : 0.0;
+        h->S.mass[s] = on ? cfg->mass[s] : 1.0;
+        h->S.qm[s] = on ? cfg->charge[s] / cfg->mass[s] : 0.0;
+        if (on && fabs(cfg->charge[s]) > qmax) qmax = fabs(cfg->charge[s]);
+    }
+    if (qmax == 0.0) qmax = 1.0;
+    h->rscale = ldexp(1.0, cfg->fp_bits) / qmax;
+    h->jscale = ldexp(1.0, cfg->fp_bits) * cfg->dt / qmax;
+    h->cap = cfg->capacity;
+    h->n_slots = 0;
+    h->xc = h->uc = 0;
+
+    const Grid &G = h->G;
+    int64_t gs = G.gsize(), nn = G.nnodes();
+    FieldPtrs &F = h->F;
+    bool ok = true;
+    auto A = [&](size_t bytes) -> void * {
+        void *p = dev_alloc(h, bytes);
+        if (!p) ok = false;
+        return p;
+    };
+    for (int c = 0; c < 3; c++) {
+        F.D[c] = (double *)A(gs * 8);
+        F.B[c] = (double *)A(gs * 8);
+        F.E[c] = (double *)A(gs * 8);
+        F.H[c] = (double *)A(gs * 8);
+        F.D0[c] = (double *)A(gs * 8);
+        F.B0[c] = (double *)A(gs * 8);
+        F.E0[c] = (double *)A(gs * 8);
+        F.H0[c] = (double *)A(gs * 8);
+        F.Dsave[c] = (double *)A(gs * 8);
+        F.Bsave[c] = (double *)A(gs * 8);
+        F.Jint[c] = (unsigned long long *)A(gs * 8);
+    }
+    F.rho_abs = (unsigned long long *)A(gs * 8);
+    F.mask = (uint8_t *)A(gs);
+    F.dS = (double *)A(21 * nn * 8);
+    F.gn = (double *)A(10 * nn * 8);
+    F.w = (double *)A(6 * nn * 8);
+    F.node = (double *)A(16 * nn * 8);
+    int64_t cap = h->cap > 0 ? h->cap : 1;
+    for (int b = 0; b < 2; b++) {
+        for (int q = 0; q < 3; q++) h->px[b][q] = (double *)A(cap * 8);
+        for (int q = 0; q < 4; q++) h->pu[b][q] = (double *)A(cap * 8);
+        h->psp[b] = (uint8_t *)A(cap);
+    }
+    h->counters = (unsigned long long *)A(C_NCOUNTERS * 8);
+    h->keys = (uint32_t *)A(cap * 4);
+    h->keys_alt = (uint32_t *)A(cap * 4);
+    h->idx = (uint32_t *)A(cap * 4);
+    h->idx_alt = (uint32_t *)A(cap * 4);
+    h->sort_temp_bytes = sort_temp_bytes(cap);
+    h->sort_temp = A(h->sort_temp_bytes);
+    h->rho_scratch = (unsigned long long *)A(gs * 8);
+    h->red_cap = ((cap + 255) / 256) * 12 + ((nn + 255) / 256) * 3 + 64;
+    h->red = (double *)A(h->red_cap * 8);
+    if (!ok) {
+        grpic_destroy(h);
+        return GRPIC_ENOMEM;
+    }
+    int nTx = (cfg->nx + cfg->tile - 1) / cfg->tile, nTy = (cfg->ny + cfg->tile - 1) / cfg->tile,
+        nTz = (cfg->nz + cfg->tile - 1) / cfg->tile;
+    uint64_t maxkey = (uint64_t)nTx * nTy * nTz * cfg->tile * cfg->tile * cfg->tile;  // sentinel must exceed it
+    int kb = 1;
+    while (kb < 32 && (((uint64_t)1 << kb) - 1) <= maxkey) kb++;
+    h->key_bits = kb;
+
+    hipStream_t s = h->stream;
+    rc = GRPIC_OK;
+    if (FAILS(hipMemsetAsync(h->counters, 0, C_NCOUNTERS * 8, s))) rc = GRPIC_EDEVICE;
+    for (int c = 0; c < 3 && !rc; c++) {
+        if (FAILS(hipMemsetAsync(F.E[c], 0, gs * 8, s))) rc = GRPIC_EDEVICE;
+        if (FAILS(hipMemsetAsync(F.H[c], 0, gs * 8, s))) rc = GRPIC_EDEVICE;
+        if (FAILS(hipMemsetAsync(F.Jint[c], 0, gs * 8, s))) rc = GRPIC_EDEVICE;
+    }
+    if (!rc && FAILS(hipMemsetAsync(F.rho_abs, 0, gs * 8, s))) rc = GRPIC_EDEVICE;
+    for (int b = 0; b < 2 && !rc; b++)
+        if (FAILS(hipMemsetAsync(h->psp[b], GRPIC_DEAD, cap, s))) rc = GRPIC_EDEVICE;
+    if (!rc) {
+        launch_bake(G, h->h, F, s);
+        launch_init_fields(G, h->h, F, cfg->B0, cfg->init_covariant, s);
+        rc = enqueue_field_derivation_reference(h);
+    }
+    if (!rc) rc = check(hipGetLastError());
+    if (!rc) rc = check(hipStreamSynchronize(s));
+    if (rc) {
+        grpic_destroy(h);
+        return rc;
+    }
+    *out = h;
+    return GRPIC_OK;
+}
+
+int grpic_load_particles(grpic_t *h, int32_t species, int64_t n, const double *x, const double *ucov,
+                         int64_t *kept) {
+    if (!h || n < 0 || (n > 0 && (!x || !ucov))) return GRPIC_EINVAL;
+    if (species < 0 || species >= h->cfg.nspecies) return GRPIC_EINVAL;
+    if (h->n_slots + n > h->cap) return GRPIC_ENOMEM;
+    clear_foreign_error();
+    if (kept) *kept = 0;
+    if (n == 0) return GRPIC_OK;
+    hipStream_t s = h->stream;
+    double *stage = nullptr;
+    size_t bytes = (size_t)6 * n * 8;
+    if (h->cfg.alloc)
+        stage = (double *)h->cfg.alloc(bytes, h->cfg.alloc_ctx);
+    else if (FAILS(hipMalloc((void **)&stage, bytes)))
+        stage = nullptr;
+    if (!stage) return GRPIC_ENOMEM;
+    int rc = GRPIC_OK;
+    unsigned long long before = 0, after = 0;
+    if (FAILS(hipMemcpyAsync(stage, x, 3 * n * 8, hipMemcpyHostToDevice, s))) rc = GRPIC_EDEVICE;
+    if (!rc && FAILS(hipMemcpyAsync(stage + 3 * n, ucov, 3 * n * 8, hipMemcpyHostToDevice, s)))
+        rc = GRPIC_EDEVICE;
+    if (!rc && FAILS(hipMemcpyAsync(&before, h->counters + C_LOAD_KEPT, 8, hipMemcpyDeviceToHost, s)))
+        rc = GRPIC_EDEVICE;
+    if (!rc) {
+        launch_load(h->G, h->h, h->cfg.c, h->cfg.r_rm, stage, stage + 3 * n, n, species, pp(h, h->xc, h->uc),
+                    h->n_slots, h->counters, s);
+        rc = check(hipGetLastError());
+    }
+    if (!rc && FAILS(hipMemcpyAsync(&after, h->counters + C_LOAD_KEPT, 8, hipMemcpyDeviceToHost, s)))
+        rc = GRPIC_EDEVICE;
+    if (!rc) rc = check(hipStreamSynchronize(s));
+    if (h->cfg.alloc) {
+        if (h->cfg.free) h->cfg.free(stage, h->cfg.alloc_ctx);
+    } else {
+        (void)hipFree(stage);
+    }
+    if (rc) return rc;
+    h->n_slots += n;
+    if (kept) *kept = (int64_t)(after - before);
+    return GRPIC_OK;
+}
+
+int grpic_step(grpic_t *h, int32_t nsteps) {
+    clear_foreign_error();
+    if (!h || nsteps < 0) return GRPIC_EINVAL;
+    if (h->sticky) return h->sticky;
+    for (int i = 0; i < nsteps; i++) {
+        int rc = one_step(h);
+        if (rc) {
+            h->sticky = rc;
+            return rc;
+        }
+    }
+    return GRPIC_OK;
+}
+
+int grpic_push_only(grpic_t *h, int32_t nsteps) {
+    clear_foreign_error();
+    if (!h || nsteps < 0) return GRPIC_EINVAL;
+    launch_node_tensor(h->G, h->F, h->stream);
+    for (int i = 0; i < nsteps; i++) {
+        PushParams P;
+        P.G = h->G;
+        P.h = h->h;
+        P.c = h->cfg.c;
+        P.dt = h->cfg.dt;
+        P.gamma_mode = h->cfg.gamma_mode;
+        P.n = h->n_slots;
+        launch_push(P, h->S, h->F.node, pp(h, h->xc, h->uc), pp(h, 1 - h->xc, h->uc), h->counters, h->stream);
+        h->xc = 1 - h->xc;
+    }
+    return check(hipGetLastError());
+}
+
+int grpic_particle_count(grpic_t *h, int64_t *n_slots, int64_t *capacity) {
+    if (!h) return GRPIC_EINVAL;
+    if (n_slots) *n_slots = h->n_slots;
+    if (capacity) *capacity = h->cap;
+    return GRPIC_OK;
+}
+
+int grpic_dump_particles(grpic_t *h, double *x, double *u, uint8_t *sp) {
+    if (!h) return GRPIC_EINVAL;
+    int64_t n = h->n_slots;
+    hipStream_t s = h->stream;
+    int rc = GRPIC_OK;
+    for (int q = 0; q < 3 && x && !rc; q++)
+        rc = check(hipMemcpyAsync(x + q * n, h->px[h->xc][q], n * 8, hipMemcpyDeviceToHost, s));
+    for (int q = 0; q < 4 && u && !rc; q++)
+        rc = check(hipMemcpyAsync(u + q * n, h->pu[h->uc][q], n * 8, hipMemcpyDeviceToHost, s));
+    if (sp && !rc) rc = check(hipMemcpyAsync(sp, h->psp[h->uc], n, hipMemcpyDeviceToHost, s));
+    if (!rc) rc = check(hipStreamSynchronize(s));
+    return rc;
+}
+
+int grpic_restore_particles(grpic_t *h, int64_t n, const double *x, const double *u, const uint8_t *sp) {
+    if (!h || n < 0 || n > h->cap || (n > 0 && (!x || !u || !sp))) return GRPIC_EINVAL;
+    hipStream_t s = h->stream;
+    int rc = GRPIC_OK;
+    for (int q = 0; q < 3 && !rc; q++)
+        rc = check(hipMemcpyAsync(h->px[h->xc][q], x + q * n, n * 8, hipMemcpyHostToDevice, s));
+    for (int q = 0; q < 4 && !rc; q++)
+        rc = check(hipMemcpyAsync(h->pu[h->uc][q], u + q * n, n * 8, hipMemcpyHostToDevice, s));
+    if (!rc) rc = check(hipMemcpyAsync(h->psp[h->uc], sp, n, hipMemcpyHostToDevice, s));
+    if (!rc) rc = check(hipStreamSynchronize(s));
+    if (!rc) h->n_slots = n;
+    return rc;
+}
+
+int64_t grpic_field_size(const grpic_t *h) { return h ? h->G.gsize() : 0; }
+
+int grpic_dump_fields(grpic_t *h, int32_t which, double *out) {
+    if (!h || !out || which < 0 || which > 4) return GRPIC_EINVAL;
+    int64_t gs = h->G.gsize();
+    hipStream_t s = h->stream;
+    int rc = GRPIC_OK;
+    if (which == 4) {
+        std::vector<long long> tmp(gs);
+        for (int q = 0; q < 3 && !rc; q++) {
+            rc = check(hipMemcpyAsync(tmp.data(), h->F.Jint[q], gs * 8, hipMemcpyDeviceToHost, s));
+            if (!rc) rc = check(hipStreamSynchronize(s));
+            for (int64_t i = 0; i < gs && !rc; i++) out[q * gs + i] = (double)tmp[i] / h->jscale;
+        }
+        return rc;
+    }
+    for (int q = 0; q < 3 && !rc; q++) {
+        double *src = which == 0 ? h->F.D[q] : which == 1 ? h->F.B[q] : which == 2 ? h->F.E[q] : h->F.H[q];
+        rc = check(hipMemcpyAsync(out + q * gs, src, gs * 8, hipMemcpyDeviceToHost, s));
+    }
+    if (!rc) rc = check(hipStreamSynchronize(s));
+    return rc;
+}
+
+int grpic_restore_fields(grpic_t *h, const double *D, const double *B) {
+    if (!h || !D || !B) return GRPIC_EINVAL;
+    int64_t gs = h->G.gsize();
+    hipStream_t s = h->stream;
+    int rc = GRPIC_OK;
+    for (int q = 0; q < 3 && !rc; q++) {
+        rc = check(hipMemcpyAsync(h->F.D[q], D + q * gs, gs * 8, hipMemcpyHostToDevice, s));
+        if (!rc) rc = check(hipMemcpyAsync(h->F.B[q], B + q * gs, gs * 8, hipMemcpyHostToDevice, s));
+    }
+    if (!rc) rc = check(hipStreamSynchronize(s));
+    return rc;
+}
+
+int grpic_dump_nodes(grpic_t *h, double *out) {
+    if (!h || !out) return GRPIC_EINVAL;
+    int rc = check(hipMemcpyAsync(out, h->F.node, h->G.nnodes() * 16 * 8, hipMemcpyDeviceToHost, h->stream));
+    if (!rc) rc = check(hipStreamSynchronize(h->stream));
+    return rc;
+}
+
+int grpic_sort(grpic_t *h, uint32_t *keys_out, int64_t *perm_out) {
+    clear_foreign_error();
+    if (!h) return GRPIC_EINVAL;
+    int64_t n = h->n_slots;
+    int rc = do_sort(h);
+    if (rc) return rc;
+    hipStream_t s = h->stream;
+    std::vector<uint32_t> k(n), p(n);
+    unsigned long long cnt[C_NCOUNTERS];
+    rc = check(hipMemcpyAsync(k.data(), h->keys_alt, n * 4, hipMemcpyDeviceToHost, s));
+    if (!rc) rc = check(hipMemcpyAsync(p.data(), h->idx_alt, n * 4, hipMemcpyDeviceToHost, s));
+    if (!rc) rc = check(hipMemcpyAsync(cnt, h->counters, sizeof(cnt), hipMemcpyDeviceToHost, s));
+    if (!rc) rc = check(hipStreamSynchronize(s));
+    if (rc) return rc;
+    uint32_t sentinel = h->key_bits >= 32 ? 0xFFFFFFFFu : ((1u << h->key_bits) - 1u);
+    for (int64_t i = 0; i < n; i++) {
+        if (keys_out) keys_out[i] = k[i] == sentinel ? 0xFFFFFFFFu : k[i];
+        if (perm_out) perm_out[i] = (int64_t)p[i];
+    }
+    if (n > 0) h->n_slots = (int64_t)cnt[C_NALIVE];
+    return GRPIC_OK;
+}
+
+int grpic_diagnostics(grpic_t *h, grpic_diag *out) {
+    clear_foreign_error();
+    if (!h || !out) return GRPIC_EINVAL;
+    memset(out, 0, sizeof(*out));
+    hipStream_t s = h->stream;
+    // derived fields of the current state (frozen points keep their initial values)
+    launch_derived(h->G, h->F, true, true, true, s);
+    DiagOut d;
+    int rc = run_diag(h->G, h->h, h->cfg.c, h->rscale, h->S, pp(h, h->xc, h->uc), h->n_slots, h->F,
+                      h->cfg.r_damp, h->cfg.damp_max, h->rho_scratch, h->red, h->red_cap, d, s);
+    if (rc) return GRPIC_EDEVICE;
+    unsigned long long cnt[C_NCOUNTERS];
+    rc = check(hipMemcpyAsync(cnt, h->counters, sizeof(cnt), hipMemcpyDeviceToHost, s));
+    if (!rc) rc = check(hipStreamSynchronize(s));
+    if (rc) return rc;
+    for (int q = 0; q < GRPIC_MAX_SPECIES; q++) out->n_alive[q] = d.n_alive[q];
+    out->n_removed_horizon = (int64_t)cnt[C_REMOVED_HORIZON];
+    out->n_removed_outer = (int64_t)cnt[C_REMOVED_OUTER];
+    out->gamma_clamps = (int64_t)cnt[C_GAMMA_CLAMPS];
+    out->flags = (int64_t)cnt[C_FLAGS];
+    out->charge_total = d.charge_total;
+    out->energy_particles = d.energy_particles;
+    out->lz_particles = d.lz_particles;
+    out->energy_field = d.energy_field;
+    out->gauss_residual_max = d.gauss_max;
+    out->mass_shell_residual_max = d.shell_max;
+    return h->sticky ? h->sticky : GRPIC_OK;
+}
+
+int grpic_set_timing(grpic_t *h, int32_t enable) {
+    if (!h) return GRPIC_EINVAL;
+    h->timing = enable ? 1 : 0;
+    return GRPIC_OK;
+}
+
+int grpic_read_timing(grpic_t *h, double *ms, int64_t *launches) {
+    if (!h) return GRPIC_EINVAL;
+    int rc = check(hipStreamSynchronize(h->stream));
+    for (int t = 0; t < GRPIC_NTIMERS; t++) {
+        double tot = 0.0;
+        for (auto &pr : h->ev_used[t]) {
+            float e = 0.0f;
+            if (!rc) rc = check(hipEventElapsedTime(&e, pr.first, pr.second));
+            tot += e;
+            h->ev_pool.push_back(pr.first);
+            h->ev_pool.push_back(pr.second);
+        }
+        if (ms) ms[t] = tot;
+        if (launches) launches[t] = (int64_t)h->ev_used[t].size();
+        h->ev_used[t].clear();
+    }
+    return rc;
+}
+
+int grpic_particle_steps(grpic_t *h, int64_t *out) {
+    if (!h || !out) return GRPIC_EINVAL;
+    unsigned long long v = 0;
+    int rc = check(hipMemcpyAsync(&v, h->counters + C_PUSHED, 8, hipMemcpyDeviceToHost, h->stream));
+    if (!rc) rc = check(hipStreamSynchronize(h->stream));
+    *out = (int64_t)v;
+    return rc;
+}
+
+}  // extern "C"

@@ -1,0 +1,437 @@
+// Yee-staggered F-tensor field kernels (FP64) for the GRPIC cycle (Sec. 3).
+//
+// Evolved pair: B_c = (F_23, F_31, F_12)[c] at face centres (offset 1/2 in the
+// two axes other than c, the magnetic shift of Sec. 3.1) and D^c = F^{c4} at
+// edge centres (offset 1/2 along c, the electric shift of Sec. 3.2).  The
+// magnetic half-step is the forward-difference Faraday update of Sec. 3.1;
+// the electric step is the backward-difference divergence update of
+// Sec. 3.2 in its continuous form, whose Christoffel terms vanish because
+// det g = -1.
+//
+// Constitutive step (index raising/lowering): pointwise the map
+// (D, B_cov) -> (-E_cov, H) is a symmetric 6x6 matrix S built from g^{-1}
+// (S = I in flat space).  On the grid it is applied as
+//   (-E_cov, H) = (D, B_cov) + P^T (S - I) P (D, B_cov)
+// with P the average of the six components onto the nodes (1/2 of the two
+// E points along c, 1/4 of the four B points) and P^T its transpose, so the
+// discrete map is symmetric and reduces to Yee's identity at m = 0.
+// (S - I) and g are baked per node once (the metric is stationary).
+#include "grpic_dev.h"
+#include "grpic_impl.h"
+
+namespace grpic {
+
+// Pairs: s = {23, 31, 12}, t = {14, 24, 34} (0-based: (1,2),(2,0),(0,1),(0,3),(1,3),(2,3)).
+__constant__ int kPair[6][2] = {{1, 2}, {2, 0}, {0, 1}, {0, 3}, {1, 3}, {2, 3}};
+
+// packed symmetric 6x6: index of (i,j)
+__device__ __forceinline__ int sym6(int i, int j) {
+    int lo = i < j ? i : j, hi = i < j ? j : i;
+    return lo * 6 - (lo * (lo - 1)) / 2 + (hi - lo);
+}
+
+// ---------------------------------------------------------------------------
+// Bake: per node the curvature part dS = S - I of the constitutive map and
+// the covariant metric g (for lowering the node tensor).
+// Variable order v = (D^0, D^1, D^2, B_0, B_1, B_2).
+__global__ void k_bake_nodes(Grid G, Hole h, double *__restrict__ dS, double *__restrict__ gn) {
+    int64_t nn = G.nnodes();
+    int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (id >= nn) return;
+    int i = (int)(id % (G.nx + 1));
+    int64_t t = id / (G.nx + 1);
+    int j = (int)(t % (G.ny + 1));
+    int k = (int)(t / (G.ny + 1));
+    Sym4 g, gi;
+    grid_metric(h, (double)i, (double)j, (double)k, g, gi);
+    for (int q = 0; q < 10; q++) gn[q * nn + id] = g.v[q];
+    // M over the pairs: M[A][B] = gi^{mu al} gi^{nu be} - gi^{mu be} gi^{nu al}
+    double M[6][6];
+    for (int A = 0; A < 6; A++)
+        for (int B = 0; B < 6; B++) {
+            int mu = kPair[A][0], nu = kPair[A][1], al = kPair[B][0], be = kPair[B][1];
+            M[A][B] = gi.v[sym4(mu, al)] * gi.v[sym4(nu, be)] - gi.v[sym4(mu, be)] * gi.v[sym4(nu, al)];
+        }
+    // Minv = M_tt^{-1} by the adjugate
+    double a00 = M[3][3], a01 = M[3][4], a02 = M[3][5];
+    double a10 = M[4][3], a11 = M[4][4], a12 = M[4][5];
+    double a20 = M[5][3], a21 = M[5][4], a22 = M[5][5];
+    double c00 = a11 * a22 - a12 * a21, c01 = a02 * a21 - a01 * a22, c02 = a01 * a12 - a02 * a11;
+    double c10 = a12 * a20 - a10 * a22, c11 = a00 * a22 - a02 * a20, c12 = a02 * a10 - a00 * a12;
+    double c20 = a10 * a21 - a11 * a20, c21 = a01 * a20 - a00 * a21, c22 = a00 * a11 - a01 * a10;
+    double idet = 1.0 / (a00 * c00 + a01 * c10 + a02 * c20);
+    double Mi[3][3] = {{c00 * idet, c01 * idet, c02 * idet},
+                       {c10 * idet, c11 * idet, c12 * idet},
+                       {c20 * idet, c21 * idet, c22 * idet}};
+    // S_DD = -Mi ; S_DB = Mi M_ts ; S_BB = M_ss - M_st Mi M_ts
+    double SDB[3][3];
+    for (int r = 0; r < 3; r++)
+        for (int c = 0; c < 3; c++) {
+            double s = 0.0;
+            for (int q = 0; q < 3; q++) s += Mi[r][q] * M[3 + q][c];
+            SDB[r][c] = s;
+        }
+    double S[6][6];
+    for (int r = 0; r < 3; r++)
+        for (int c = 0; c < 3; c++) {
+            S[r][c] = -Mi[r][c];
+            S[r][3 + c] = SDB[r][c];
+            S[3 + c][r] = SDB[r][c];
+            double s = M[r][c];
+            for (int q = 0; q < 3; q++) s -= M[r][3 + q] * SDB[q][c];
+            S[3 + r][3 + c] = s;
+        }
+    for (int r = 0; r < 6; r++)
+        for (int c = r; c < 6; c++) dS[sym6(r, c) * nn + id] = S[r][c] - (r == c ? 1.0 : 0.0);
+}
+
+// Update masks: bit c set if E_c at this index is updated, bit 3+c for B_c.
+// Updated = integer axes in [1, n-1], half axes in [0, n-1], not excised.
+__global__ void k_masks(Grid G, Hole h, uint8_t *__restrict__ mask) {
+    int64_t gs = G.gsize();
+    int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (id >= gs) return;
+    int i = (int)(id % G.sx) - 1;
+    int64_t t = id / G.sx;
+    int j = (int)(t % (G.ny + 3)) - 1;
+    int k = (int)(t / (G.ny + 3)) - 1;
+    int idx[3] = {i, j, k};
+    uint8_t mk = 0;
+    for (int kind = 0; kind < 2; kind++)
+        for (int c = 0; c < 3; c++) {
+            bool ok = true;
+            double X[3];
+            for (int ax = 0; ax < 3; ax++) {
+                bool half = kind == 0 ? (ax == c) : (ax != c);
+                int n = G.dim(ax);
+                if (half) {
+                    ok = ok && idx[ax] >= 0 && idx[ax] <= n - 1;
+                    X[ax] = idx[ax] + 0.5;
+                } else {
+                    ok = ok && idx[ax] >= 1 && idx[ax] <= n - 1;
+                    X[ax] = (double)idx[ax];
+                }
+            }
+            if (ok && grid_excised(h, X[0], X[1], X[2])) ok = false;
+            if (ok) mk |= (uint8_t)(1u << (kind * 3 + c));
+        }
+    mask[id] = mk;
+}
+
+// Node averages of the evolved pair.
+__device__ __forceinline__ void node_pair(const Grid &G, const FieldPtrs &F, const double *const D[3],
+                                          const double *const B[3], int i, int j, int k, double v[6]) {
+    v[0] = 0.5 * (D[0][G.g(i - 1, j, k)] + D[0][G.g(i, j, k)]);
+    v[1] = 0.5 * (D[1][G.g(i, j - 1, k)] + D[1][G.g(i, j, k)]);
+    v[2] = 0.5 * (D[2][G.g(i, j, k - 1)] + D[2][G.g(i, j, k)]);
+    v[3] = 0.25 * (B[0][G.g(i, j - 1, k - 1)] + B[0][G.g(i, j, k - 1)] + B[0][G.g(i, j - 1, k)] +
+                   B[0][G.g(i, j, k)]);
+    v[4] = 0.25 * (B[1][G.g(i - 1, j, k - 1)] + B[1][G.g(i, j, k - 1)] + B[1][G.g(i - 1, j, k)] +
+                   B[1][G.g(i, j, k)]);
+    v[5] = 0.25 * (B[2][G.g(i - 1, j - 1, k)] + B[2][G.g(i, j - 1, k)] + B[2][G.g(i - 1, j, k)] +
+                   B[2][G.g(i, j, k)]);
+}
+
+__device__ __forceinline__ void apply_dS(const double *__restrict__ dS, int64_t nn, int64_t id,
+                                         const double v[6], double w[6]) {
+    for (int r = 0; r < 6; r++) w[r] = 0.0;
+    for (int r = 0; r < 6; r++)
+        for (int c = r; c < 6; c++) {
+            double s = dS[sym6(r, c) * nn + id];
+            w[r] += s * v[c];
+            if (c != r) w[c] += s * v[r];
+        }
+}
+
+// w = (S - I) P (D, B) at every node.
+__global__ void k_node_w(Grid G, FieldPtrs F, const double *__restrict__ B0p, const double *__restrict__ B1p,
+                         const double *__restrict__ B2p, double *__restrict__ w) {
+    int64_t nn = G.nnodes();
+    int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (id >= nn) return;
+    int i = (int)(id % (G.nx + 1));
+    int64_t t = id / (G.nx + 1);
+    int j = (int)(t % (G.ny + 1));
+    int k = (int)(t / (G.ny + 1));
+    const double *D[3] = {F.D[0], F.D[1], F.D[2]};
+    const double *B[3] = {B0p, B1p, B2p};
+    double v[6], o[6];
+    node_pair(G, F, D, B, i, j, k, v);
+    apply_dS(F.dS, nn, id, v, o);
+    for (int q = 0; q < 6; q++) w[q * nn + id] = o[q];
+}
+
+__device__ __forceinline__ bool in_domain(const Grid &G, int kind, int c, int i, int j, int k) {
+    int idx[3] = {i, j, k};
+    for (int ax = 0; ax < 3; ax++) {
+        bool half = kind == 0 ? (ax == c) : (ax != c);
+        int n = G.dim(ax);
+        if (idx[ax] < 0 || idx[ax] > (half ? n - 1 : n)) return false;
+    }
+    return true;
+}
+
+// E_cov at every in-domain E point: -(D + P^T w) where updated, else the
+// initial value.  Thread per index (i,j,k) in [0,n]^3, all three components.
+__global__ void k_ecov(Grid G, FieldPtrs F, const double *__restrict__ w, bool use_ref) {
+    int64_t nn = G.nnodes();
+    int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (id >= nn) return;
+    int i = (int)(id % (G.nx + 1));
+    int64_t t = id / (G.nx + 1);
+    int j = (int)(t % (G.ny + 1));
+    int k = (int)(t / (G.ny + 1));
+    int64_t gi = G.g(i, j, k);
+    uint8_t mk = F.mask[gi];
+    int64_t n0 = G.node(i, j, k);
+    int64_t step[3] = {1, (int64_t)(G.nx + 1), (int64_t)(G.nx + 1) * (G.ny + 1)};
+    for (int c = 0; c < 3; c++) {
+        if (!in_domain(G, 0, c, i, j, k)) continue;
+        double val;
+        if (use_ref && !(mk & (1u << c))) {
+            val = F.E0[c][gi];
+        } else {
+            double corr = 0.5 * (w[c * nn + n0] + w[c * nn + n0 + step[c]]);
+            val = -(F.D[c][gi] + corr);
+        }
+        F.E[c][gi] = val;
+    }
+}
+
+// H at every in-domain B point: B + P^T w where updated, else the initial value.
+__global__ void k_hfield(Grid G, FieldPtrs F, const double *__restrict__ w, bool use_ref) {
+    int64_t nn = G.nnodes();
+    int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (id >= nn) return;
+    int i = (int)(id % (G.nx + 1));
+    int64_t t = id / (G.nx + 1);
+    int j = (int)(t % (G.ny + 1));
+    int k = (int)(t / (G.ny + 1));
+    int64_t gi = G.g(i, j, k);
+    uint8_t mk = F.mask[gi];
+    int64_t n0 = G.node(i, j, k);
+    int64_t step[3] = {1, (int64_t)(G.nx + 1), (int64_t)(G.nx + 1) * (G.ny + 1)};
+    for (int c = 0; c < 3; c++) {
+        if (!in_domain(G, 1, c, i, j, k)) continue;
+        double val;
+        if (use_ref && !(mk & (1u << (3 + c)))) {
+            val = F.H0[c][gi];
+        } else {
+            int a1 = (c + 1) % 3, a2 = (c + 2) % 3;
+            const double *wc = w + (3 + c) * nn;
+            double corr = 0.25 * (wc[n0] + wc[n0 + step[a1]] + wc[n0 + step[a2]] + wc[n0 + step[a1] + step[a2]]);
+            val = F.B[c][gi] + corr;
+        }
+        F.H[c][gi] = val;
+    }
+}
+
+// Magnetic half-step (Sec. 3.1) for the pair (al, be) of component c:
+//   Bout_c = Bin_c - h [ (E_be(x + e_al) - E_be(x)) - (E_al(x + e_be) - E_al(x)) ],  h = c dt / 2.
+// Points that are not updated copy Bin (when Bin and Bout differ).
+__global__ void k_bhalf(Grid G, FieldPtrs F, const double *__restrict__ Bin0, const double *__restrict__ Bin1,
+                        const double *__restrict__ Bin2, double hstep) {
+    int64_t nn = G.nnodes();
+    int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (id >= nn) return;
+    int i = (int)(id % (G.nx + 1));
+    int64_t t = id / (G.nx + 1);
+    int j = (int)(t % (G.ny + 1));
+    int k = (int)(t / (G.ny + 1));
+    int64_t gi = G.g(i, j, k);
+    uint8_t mk = F.mask[gi];
+    const double *Bin[3] = {Bin0, Bin1, Bin2};
+    int64_t st[3] = {1, G.sx, G.sy};
+    for (int c = 0; c < 3; c++) {
+        if (!in_domain(G, 1, c, i, j, k)) continue;
+        double b = Bin[c][gi];
+        if (mk & (1u << (3 + c))) {
+            int al = (c + 1) % 3, be = (c + 2) % 3;
+            double d1 = F.E[be][gi + st[al]] - F.E[be][gi];
+            double d2 = F.E[al][gi + st[be]] - F.E[al][gi];
+            b -= (d1 - d2) * hstep;
+        }
+        F.B[c][gi] = b;
+    }
+}
+
+// Electric step (Sec. 3.2):
+//   Dout_c = Din_c + dx4 [ (4 pi / c) J_c - sum_k d_k F^{c k} ],
+// F^{c,c+1} = H[c+2], F^{c,c+2} = -H[c+1], backward differences; J from the
+// int64 accumulator.
+__global__ void k_dstep(Grid G, FieldPtrs F, const double *__restrict__ Din0, const double *__restrict__ Din1,
+                        const double *__restrict__ Din2, double dx4, double four_pi_over_c, double inv_jscale) {
+    int64_t nn = G.nnodes();
+    int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (id >= nn) return;
+    int i = (int)(id % (G.nx + 1));
+    int64_t t = id / (G.nx + 1);
+    int j = (int)(t % (G.ny + 1));
+    int k = (int)(t / (G.ny + 1));
+    int64_t gi = G.g(i, j, k);
+    uint8_t mk = F.mask[gi];
+    const double *Din[3] = {Din0, Din1, Din2};
+    int64_t st[3] = {1, G.sx, G.sy};
+    for (int c = 0; c < 3; c++) {
+        if (!in_domain(G, 0, c, i, j, k)) continue;
+        double d = Din[c][gi];
+        if (mk & (1u << c)) {
+            int c1 = (c + 1) % 3, c2 = (c + 2) % 3;
+            // + d_{c1} H[c2] - d_{c2} H[c1]
+            double div = (F.H[c2][gi] - F.H[c2][gi - st[c1]]) - (F.H[c1][gi] - F.H[c1][gi - st[c2]]);
+            double Jc = (double)(long long)F.Jint[c][gi] * inv_jscale;
+            d += dx4 * (four_pi_over_c * Jc - div);
+        }
+        F.D[c][gi] = d;
+    }
+}
+
+// Relaxation layer inside the horizon: updated points with r_exc <= r < r_damp
+// move toward their initial values by damp_max ((r_damp - r)/(r_damp - r_exc))^2.
+__global__ void k_relax(Grid G, Hole h, FieldPtrs F, double r_damp, double damp_max, int i0, int j0, int k0,
+                        int bx, int by, int bz) {
+    int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t tot = (int64_t)bx * by * bz;
+    if (id >= tot) return;
+    int i = i0 + (int)(id % bx);
+    int64_t t = id / bx;
+    int j = j0 + (int)(t % by);
+    int k = k0 + (int)(t / by);
+    int64_t gi = G.g(i, j, k);
+    uint8_t mk = F.mask[gi];
+    for (int kind = 0; kind < 2; kind++)
+        for (int c = 0; c < 3; c++) {
+            if (!(mk & (1u << (kind * 3 + c)))) continue;
+            double X = i + ((kind == 0 ? c == 0 : c != 0) ? 0.5 : 0.0);
+            double Y = j + ((kind == 0 ? c == 1 : c != 1) ? 0.5 : 0.0);
+            double Z = k + ((kind == 0 ? c == 2 : c != 2) ? 0.5 : 0.0);
+            double r = ks_radius(h.a, X - h.cx, Y - h.cy, Z - h.cz);
+            if (!(r < r_damp)) continue;
+            double tt = (r_damp - r) / (r_damp - h.r_exc);
+            double sg = damp_max * tt * tt;
+            double *Fp = kind == 0 ? F.D[c] : F.B[c];
+            const double *F0 = kind == 0 ? F.D0[c] : F.B0[c];
+            Fp[gi] -= sg * (Fp[gi] - F0[gi]);
+        }
+}
+
+// Node tensor F^a_b = F^{ag} g_{gb} from the node pair completed by S.
+__global__ void k_node_tensor(Grid G, FieldPtrs F, double *__restrict__ out) {
+    int64_t nn = G.nnodes();
+    int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (id >= nn) return;
+    int i = (int)(id % (G.nx + 1));
+    int64_t t = id / (G.nx + 1);
+    int j = (int)(t % (G.ny + 1));
+    int k = (int)(t / (G.ny + 1));
+    const double *D[3] = {F.D[0], F.D[1], F.D[2]};
+    const double *B[3] = {F.B[0], F.B[1], F.B[2]};
+    double v[6], w[6];
+    node_pair(G, F, D, B, i, j, k, v);
+    apply_dS(F.dS, nn, id, v, w);
+    // contravariant components: F^{c4} = v_D, F^{s} = v_B + w_B
+    double Fu[4][4];
+    for (int a = 0; a < 4; a++) Fu[a][a] = 0.0;
+    double Hs[3] = {v[3] + w[3], v[4] + w[4], v[5] + w[5]};
+    Fu[1][2] = Hs[0]; Fu[2][1] = -Hs[0];
+    Fu[2][0] = Hs[1]; Fu[0][2] = -Hs[1];
+    Fu[0][1] = Hs[2]; Fu[1][0] = -Hs[2];
+    for (int c = 0; c < 3; c++) {
+        Fu[c][3] = v[c];
+        Fu[3][c] = -v[c];
+    }
+    double g[10];
+    for (int q = 0; q < 10; q++) g[q] = F.gn[q * nn + id];
+    double *o = out + 16 * id;
+    for (int a = 0; a < 4; a++)
+        for (int b = 0; b < 4; b++) {
+            double s = 0.0;
+            for (int c = 0; c < 4; c++) s += Fu[a][c] * g[sym4(c, b)];
+            o[a * 4 + b] = s;
+        }
+}
+
+// Initial fields: uniform F (contravariant or covariant B0) lowered/raised
+// with the point metric at every ghosted point.
+__global__ void k_init_fields(Grid G, Hole h, FieldPtrs F, double b0, double b1, double b2, int covariant) {
+    int64_t gs = G.gsize();
+    int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (id >= gs) return;
+    int i = (int)(id % G.sx) - 1;
+    int64_t t = id / G.sx;
+    int j = (int)(t % (G.ny + 3)) - 1;
+    int k = (int)(t / (G.ny + 3)) - 1;
+    double Fm[4][4] = {{0, b2, -b1, 0}, {-b2, 0, b0, 0}, {b1, -b0, 0, 0}, {0, 0, 0, 0}};
+    const double Bc[3] = {b0, b1, b2};
+    for (int kind = 0; kind < 2; kind++)
+        for (int c = 0; c < 3; c++) {
+            double X = i + ((kind == 0 ? c == 0 : c != 0) ? 0.5 : 0.0);
+            double Y = j + ((kind == 0 ? c == 1 : c != 1) ? 0.5 : 0.0);
+            double Z = k + ((kind == 0 ? c == 2 : c != 2) ? 0.5 : 0.0);
+            Sym4 g, gi;
+            grid_metric(h, X, Y, Z, g, gi);
+            const Sym4 &T = covariant ? gi : g;
+            int al = kind == 1 ? kPair[c][0] : kPair[3 + c][0];
+            int be = kind == 1 ? kPair[c][1] : kPair[3 + c][1];
+            double v = 0.0;
+            for (int mu = 0; mu < 4; mu++)
+                for (int nu = 0; nu < 4; nu++) v += T.v[sym4(al, mu)] * T.v[sym4(be, nu)] * Fm[mu][nu];
+            if (kind == 1)
+                F.B[c][id] = covariant ? Bc[c] : v;
+            else
+                F.D[c][id] = covariant ? v : 0.0;
+        }
+}
+
+// ---------------------------------------------------------------------------
+static inline unsigned nblk(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
+
+void launch_bake(const Grid &G, const Hole &h, FieldPtrs &F, hipStream_t s) {
+    hipLaunchKernelGGL(k_bake_nodes, dim3(nblk(G.nnodes(), 128)), dim3(128), 0, s, G, h, F.dS, F.gn);
+    hipLaunchKernelGGL(k_masks, dim3(nblk(G.gsize(), 256)), dim3(256), 0, s, G, h, F.mask);
+}
+
+void launch_init_fields(const Grid &G, const Hole &h, FieldPtrs &F, const double B0[3], int covariant,
+                        hipStream_t s) {
+    hipLaunchKernelGGL(k_init_fields, dim3(nblk(G.gsize(), 128)), dim3(128), 0, s, G, h, F, B0[0], B0[1],
+                       B0[2], covariant);
+}
+
+void launch_derived(const Grid &G, FieldPtrs &F, bool use_ref, bool do_e, bool do_h, hipStream_t s) {
+    unsigned nb = nblk(G.nnodes(), 256);
+    hipLaunchKernelGGL(k_node_w, dim3(nb), dim3(256), 0, s, G, F, F.B[0], F.B[1], F.B[2], F.w);
+    if (do_e) hipLaunchKernelGGL(k_ecov, dim3(nb), dim3(256), 0, s, G, F, F.w, use_ref);
+    if (do_h) hipLaunchKernelGGL(k_hfield, dim3(nb), dim3(256), 0, s, G, F, F.w, use_ref);
+}
+
+void launch_bhalf(const Grid &G, FieldPtrs &F, const double *const Bin[3], double hstep, hipStream_t s) {
+    hipLaunchKernelGGL(k_bhalf, dim3(nblk(G.nnodes(), 256)), dim3(256), 0, s, G, F, Bin[0], Bin[1], Bin[2],
+                       hstep);
+}
+
+void launch_dstep(const Grid &G, FieldPtrs &F, const double *const Din[3], double dx4, double fpc,
+                  double inv_jscale, hipStream_t s) {
+    hipLaunchKernelGGL(k_dstep, dim3(nblk(G.nnodes(), 256)), dim3(256), 0, s, G, F, Din[0], Din[1], Din[2],
+                       dx4, fpc, inv_jscale);
+}
+
+void launch_relax(const Grid &G, const Hole &h, FieldPtrs &F, double r_damp, double damp_max, hipStream_t s) {
+    if (!(r_damp > h.r_exc) || !(damp_max > 0.0) || h.m == 0.0) return;
+    // bounding box of the oblate region r < r_damp: |x|,|y| <= sqrt(r^2+a^2), |z| <= r
+    double ext_xy = sqrt(r_damp * r_damp + h.a * h.a) + 1.0, ext_z = r_damp + 1.0;
+    int i0 = (int)floor(h.cx - ext_xy), i1 = (int)ceil(h.cx + ext_xy);
+    int j0 = (int)floor(h.cy - ext_xy), j1 = (int)ceil(h.cy + ext_xy);
+    int k0 = (int)floor(h.cz - ext_z), k1 = (int)ceil(h.cz + ext_z);
+    i0 = i0 < 0 ? 0 : i0; j0 = j0 < 0 ? 0 : j0; k0 = k0 < 0 ? 0 : k0;
+    i1 = i1 > G.nx ? G.nx : i1; j1 = j1 > G.ny ? G.ny : j1; k1 = k1 > G.nz ? G.nz : k1;
+    if (i1 < i0 || j1 < j0 || k1 < k0) return;
+    int bx = i1 - i0 + 1, by = j1 - j0 + 1, bz = k1 - k0 + 1;
+    hipLaunchKernelGGL(k_relax, dim3(nblk((int64_t)bx * by * bz, 128)), dim3(128), 0, s, G, h, F, r_damp,
+                       damp_max, i0, j0, k0, bx, by, bz);
+}
+
+void launch_node_tensor(const Grid &G, FieldPtrs &F, hipStream_t s) {
+    hipLaunchKernelGGL(k_node_tensor, dim3(nblk(G.nnodes(), 128)), dim3(128), 0, s, G, F, F.node);
+}
+
+}  // namespace grpic

@@ -1,0 +1,198 @@
+// Device-side building blocks of the GRPIC hot path for gfx950 (CDNA4).
+//
+// Metric: Kerr in Cartesian Kerr-Schild form, g = eta + f k k with
+// eta = diag(1,1,1,-1), f = 2 m r^3 / (r^4 + a^2 z^2) and the null one-form
+// k = ((r x - a y)/(r^2+a^2), (r y + a x)/(r^2+a^2), z/r, 1) (Sec. 2.1, eq.
+// kerr_metric and the expression for k), r the root of
+// r^4 - (R^2 - a^2) r^2 - a^2 z^2 = 0 (eq. radius_eqn).  Because k is null,
+// g^{-1} = eta - f k^a k^b with k^a = (k_1, k_2, k_3, -1), and det g = -1.
+// The Christoffel contraction Gamma^a_{mn} u^m u^n is formed directly from
+// f, k and their gradients (rank-one structure), never as a 4x4x4 array.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace grpic {
+
+constexpr int kMaxSpecies = 8;
+constexpr uint8_t kDead = 0xFF;
+
+// Ghosted field layout shared by every staggered component: index
+// (i,j,k) with i in [-1, nx+1] at ((k+1)*sy + (j+1))*sx + (i+1).
+struct Grid {
+    int nx, ny, nz;
+    int64_t sx, sy;  // strides: sx = nx+3, sy = (ny+3)*(nx+3)
+    __host__ __device__ inline int64_t g(int i, int j, int k) const {
+        return (int64_t)(k + 1) * sy + (int64_t)(j + 1) * sx + (i + 1);
+    }
+    __host__ __device__ inline int64_t node(int i, int j, int k) const {
+        return ((int64_t)k * (ny + 1) + j) * (nx + 1) + i;
+    }
+    __host__ __device__ inline int64_t gsize() const { return sy * (nz + 3); }
+    __host__ __device__ inline int64_t nnodes() const {
+        return (int64_t)(nx + 1) * (ny + 1) * (nz + 1);
+    }
+    __host__ __device__ inline int dim(int ax) const { return ax == 0 ? nx : (ax == 1 ? ny : nz); }
+};
+
+// Hole parameters every kernel needs.
+struct Hole {
+    double m, a;
+    double cx, cy, cz;
+    double r_exc;
+};
+
+// Radius from the quartic, always in FP64: the cancellation-free root for
+// r^2 on each side of R^2 = a^2.
+__device__ __forceinline__ double ks_radius(double a, double x, double y, double z) {
+    double R2 = x * x + y * y + z * z;
+    double b = R2 - a * a;
+    double a2z2 = a * a * z * z;
+    double s = sqrt(b * b + 4.0 * a2z2);
+    double r2 = (b >= 0.0) ? 0.5 * (b + s) : (2.0 * a2z2) / (s - b);
+    return sqrt(r2);
+}
+
+// f and the spatial part of k at a hole-relative point (m > 0, r > 0).
+template <typename T>
+struct KSPoint {
+    T r, f, k0, k1, k2;
+};
+
+__device__ __forceinline__ void ks_point(double m, double a, double x, double y, double z,
+                                         KSPoint<double> &o) {
+    double r = ks_radius(a, x, y, z);
+    double rr = r * r;
+    double iden = 1.0 / (rr + a * a);
+    double S4 = rr * rr + a * a * z * z;
+    o.r = r;
+    o.f = 2.0 * m * r * rr / S4;
+    o.k0 = (r * x - a * y) * iden;
+    o.k1 = (r * y + a * x) * iden;
+    o.k2 = z / r;
+}
+
+// Inverse metric components g^{ab} = eta^{ab} - f k^a k^b (packed symmetric
+// 4x4, order 00 01 02 03 11 12 13 22 23 33) at a grid point; flat inside
+// r_exc or when m = 0.
+struct Sym4 {
+    double v[10];
+};
+
+__device__ __forceinline__ int sym4(int a, int b) {
+    // index of (a,b) in the packed upper triangle
+    int lo = a < b ? a : b, hi = a < b ? b : a;
+    return lo * 4 - (lo * (lo - 1)) / 2 + (hi - lo);
+}
+
+// g_{ab} and g^{ab} at a grid point (node coordinates X, Y, Z).
+__device__ inline void grid_metric(const Hole &h, double X, double Y, double Z, Sym4 &g, Sym4 &gi) {
+    double x = X - h.cx, y = Y - h.cy, z = Z - h.cz;
+    double k[4] = {0.0, 0.0, 0.0, 1.0};
+    double f = 0.0;
+    if (h.m != 0.0) {
+        double r = ks_radius(h.a, x, y, z);
+        if (!(r < h.r_exc)) {
+            KSPoint<double> p;
+            ks_point(h.m, h.a, x, y, z, p);
+            f = p.f;
+            k[0] = p.k0;
+            k[1] = p.k1;
+            k[2] = p.k2;
+        }
+    }
+    const double eta[4] = {1.0, 1.0, 1.0, -1.0};
+    const double ku[4] = {k[0], k[1], k[2], -1.0};
+    for (int a = 0; a < 4; a++)
+        for (int b = a; b < 4; b++) {
+            int s = sym4(a, b);
+            g.v[s] = (a == b ? eta[a] : 0.0) + f * k[a] * k[b];
+            gi.v[s] = (a == b ? eta[a] : 0.0) - f * ku[a] * ku[b];
+        }
+}
+
+__device__ __forceinline__ bool grid_excised(const Hole &h, double X, double Y, double Z) {
+    if (h.m == 0.0) return false;
+    return ks_radius(h.a, X - h.cx, Y - h.cy, Z - h.cz) < h.r_exc;
+}
+
+// Kerr-Schild point with the gradients the pusher needs:
+//   d_i r = x_i r^3/(r^4+a^2 z^2) (x, y),  z r (r^2+a^2)/(r^4+a^2 z^2) (z);
+//   d_i f = f (3 d_i r / r - d_i S4 / S4),  S4 = r^4 + a^2 z^2;
+//   dk[j][i] = d_i k_j.
+struct KSGrad {
+    double r, f, k[3];
+    double df[3];
+    double dk[3][3];
+};
+
+__device__ __forceinline__ void ks_grad(double m, double a, double x, double y, double z, KSGrad &o) {
+    double r = ks_radius(a, x, y, z);
+    double rr = r * r;
+    double a2 = a * a;
+    double S4 = rr * rr + a2 * z * z;
+    double iS4 = 1.0 / S4;
+    double iden = 1.0 / (rr + a2);
+    double ir = 1.0 / r;
+    double f = 2.0 * m * r * rr * iS4;
+    double k0 = (r * x - a * y) * iden;
+    double k1 = (r * y + a * x) * iden;
+    double k2 = z * ir;
+    double c = r * rr * iS4;
+    double dr[3] = {x * c, y * c, z * r * (rr + a2) * iS4};
+    double f3r = 3.0 * f * ir;
+    double f4 = 4.0 * f * rr * r * iS4;
+    for (int i = 0; i < 3; i++) o.df[i] = (f3r - f4) * dr[i];
+    o.df[2] -= f * 2.0 * a2 * z * iS4;
+    double two_r = 2.0 * r;
+    for (int i = 0; i < 3; i++) {
+        double dd = two_r * dr[i];
+        o.dk[0][i] = (dr[i] * x - k0 * dd) * iden;
+        o.dk[1][i] = (dr[i] * y - k1 * dd) * iden;
+        o.dk[2][i] = -k2 * dr[i] * ir;
+    }
+    o.dk[0][0] += r * iden;
+    o.dk[0][1] -= a * iden;
+    o.dk[1][1] += r * iden;
+    o.dk[1][0] += a * iden;
+    o.dk[2][2] += ir;
+    o.r = r;
+    o.f = f;
+    o.k[0] = k0;
+    o.k[1] = k1;
+    o.k[2] = k2;
+}
+
+// G^a = Gamma^a_{mn} u^m u^n for g = eta + f k k (stationary, k_4 = 1):
+//   G_b = s (Df k_b + f Dk_b) + f q k_b - s^2/2 d_b f - f s w_b   (b spatial)
+//   G_4 = s Df + f q
+// with s = k.u, D = u^i d_i, Dk_j = u^i d_i k_j, q = u^j Dk_j,
+// w_b = u^j d_b k_j, then G^a = g^{ab} G_b = eta^{ab} G_b - f k^a (k^b G_b).
+__device__ __forceinline__ void gamma_uu(const KSGrad &p, const double u[4], double G[4]) {
+    const double f = p.f;
+    double s = p.k[0] * u[0] + p.k[1] * u[1] + p.k[2] * u[2] + u[3];
+    double Df = p.df[0] * u[0] + p.df[1] * u[1] + p.df[2] * u[2];
+    double Dk[3], w[3];
+    for (int j = 0; j < 3; j++) Dk[j] = p.dk[j][0] * u[0] + p.dk[j][1] * u[1] + p.dk[j][2] * u[2];
+    for (int b = 0; b < 3; b++) w[b] = p.dk[0][b] * u[0] + p.dk[1][b] * u[1] + p.dk[2][b] * u[2];
+    double q = Dk[0] * u[0] + Dk[1] * u[1] + Dk[2] * u[2];
+    double Gl[4];
+    double hs2 = 0.5 * s * s;
+    double fs = f * s;
+    double sDf_fq = s * Df + f * q;
+    for (int b = 0; b < 3; b++) Gl[b] = sDf_fq * p.k[b] + fs * Dk[b] - hs2 * p.df[b] - fs * w[b];
+    Gl[3] = sDf_fq;
+    double kG = p.k[0] * Gl[0] + p.k[1] * Gl[1] + p.k[2] * Gl[2] - Gl[3];
+    double fkG = f * kG;
+    G[0] = Gl[0] - fkG * p.k[0];
+    G[1] = Gl[1] - fkG * p.k[1];
+    G[2] = Gl[2] - fkG * p.k[2];
+    G[3] = -Gl[3] + fkG;
+}
+
+// Fixed-point conversion of one current or charge contribution.
+__device__ __forceinline__ unsigned long long to_fixed(double v, double scale) {
+    return (unsigned long long)(long long)__double2ll_rn(v * scale);
+}
+
+}  // namespace grpic

@@ -1,0 +1,385 @@
+// Particle kernels (FP64): gather + RK4 push (Sec. 3.3), zigzag current
+// deposition with curved face weights (Sec. 4), removal, and loading with the
+// mass-shell solve (Sec. 2.1).  One thread per particle slot, SoA storage, so
+// a wavefront of 64 lanes reads 64 consecutive doubles per component.
+#include "grpic_dev.h"
+#include "grpic_impl.h"
+
+namespace grpic {
+
+
+// Trilinear gather of the 16 mixed components at X (cloud-in-cell with
+// sqrt(-det g) = 1, Sec. 3.3).  The cell is floor(X) clamped to the grid; the
+// offset is not clamped.
+__device__ __forceinline__ void gather16(const Grid &G, const double *__restrict__ node, const double X[3],
+                                         double F[16]) {
+    int c[3];
+    double w[3];
+    for (int ax = 0; ax < 3; ax++) {
+        int n = G.dim(ax);
+        int ci = (int)floor(X[ax]);
+        ci = ci < 0 ? 0 : (ci > n - 1 ? n - 1 : ci);
+        c[ax] = ci;
+        w[ax] = X[ax] - (double)ci;
+    }
+    for (int q = 0; q < 16; q++) F[q] = 0.0;
+    const int64_t sj = G.nx + 1, sk = (int64_t)(G.nx + 1) * (G.ny + 1);
+    const double *base = node + 16 * G.node(c[0], c[1], c[2]);
+#pragma unroll
+    for (int dk = 0; dk < 2; dk++) {
+        double wz = dk ? w[2] : 1.0 - w[2];
+#pragma unroll
+        for (int dj = 0; dj < 2; dj++) {
+            double wyz = (dj ? w[1] : 1.0 - w[1]) * wz;
+#pragma unroll
+            for (int di = 0; di < 2; di++) {
+                double W = (di ? w[0] : 1.0 - w[0]) * wyz;
+                const double2 *p = reinterpret_cast<const double2 *>(base + 16 * (di + dj * sj + dk * sk));
+#pragma unroll
+                for (int q = 0; q < 8; q++) {
+                    double2 v = p[q];
+                    F[2 * q] += W * v.x;
+                    F[2 * q + 1] += W * v.y;
+                }
+            }
+        }
+    }
+}
+
+// du^a/dtau = (q/m) F^a_b u^b - Gamma^a_{mn} u^m u^n  (Sec. 3.3)
+__device__ __forceinline__ void accel(const PushParams &P, const double *__restrict__ node, double qm,
+                                      const double X[3], const double U[4], double A[4]) {
+    double Gm[4] = {0.0, 0.0, 0.0, 0.0};
+    if (P.h.m != 0.0) {
+        KSGrad kp;
+        ks_grad(P.h.m, P.h.a, X[0] - P.h.cx, X[1] - P.h.cy, X[2] - P.h.cz, kp);
+        gamma_uu(kp, U, Gm);
+    }
+    double F[16];
+    gather16(P.G, node, X, F);
+#pragma unroll
+    for (int a = 0; a < 4; a++) {
+        double l = F[4 * a] * U[0] + F[4 * a + 1] * U[1] + F[4 * a + 2] * U[2] + F[4 * a + 3] * U[3];
+        A[a] = qm * l - Gm[a];
+    }
+}
+
+// Stage time-dilation factor: PAPER = 1/2 [u4/c + sqrt((u4/c)^2 + 2 a4 dt / c)]
+// (negative discriminant clamped to 0 and counted), U4 = u4/c.
+__device__ __forceinline__ double stage_gamma(const PushParams &P, double u4, double a4, int &clamps) {
+    double uc = u4 / P.c;
+    if (P.gamma_mode == 1) return uc;
+    double disc = uc * uc + 4.0 * a4 * (P.dt / (2.0 * P.c));
+    if (disc < 0.0) {
+        disc = 0.0;
+        clamps++;
+    }
+    return 0.5 * (uc + sqrt(disc));
+}
+
+// Classic RK4 in coordinate time on Y = (x, u): K_k = (u_k, A_k)/gamma_k,
+// stages at dt/2, dt/2, dt, combination 1:2:2:1 over 6.
+__global__ __launch_bounds__(256) void k_push(PushParams P, Species cS, const double *__restrict__ node,
+                                              ParticlePtrs in, ParticlePtrs out, unsigned long long *counters) {
+    int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int clamps = 0;
+    uint8_t sp = id < P.n ? in.sp[id] : kDead;
+    unsigned long long live = __ballot(sp != kDead);
+    if ((threadIdx.x & 63) == 0 && live) atomicAdd(&counters[C_PUSHED], (unsigned long long)__popcll(live));
+    {
+        if (sp != kDead) {
+            double qm = cS.qm[sp];
+            double X0[3] = {in.x[0][id], in.x[1][id], in.x[2][id]};
+            double U0[4] = {in.u[0][id], in.u[1][id], in.u[2][id], in.u[3][id]};
+            double Xs[3] = {X0[0], X0[1], X0[2]};
+            double Us[4] = {U0[0], U0[1], U0[2], U0[3]};
+            double Sx[3] = {0.0, 0.0, 0.0}, Su[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll 1
+            for (int st = 0; st < 4; st++) {
+                double A[4];
+                accel(P, node, qm, Xs, Us, A);
+                double gam = stage_gamma(P, Us[3], A[3], clamps);
+                double ig = 1.0 / gam;
+                double Kx[3] = {Us[0] * ig, Us[1] * ig, Us[2] * ig};
+                double Ku[4] = {A[0] * ig, A[1] * ig, A[2] * ig, A[3] * ig};
+                double wgt = (st == 0 || st == 3) ? 1.0 : 2.0;
+                for (int q = 0; q < 3; q++) Sx[q] += wgt * Kx[q];
+                for (int q = 0; q < 4; q++) Su[q] += wgt * Ku[q];
+                if (st < 3) {
+                    double fac = (st < 2 ? 0.5 : 1.0) * P.dt;
+                    for (int q = 0; q < 3; q++) Xs[q] = X0[q] + fac * Kx[q];
+                    for (int q = 0; q < 4; q++) Us[q] = U0[q] + fac * Ku[q];
+                }
+            }
+            double h6 = P.dt / 6.0;
+            for (int q = 0; q < 3; q++) out.x[q][id] = X0[q] + h6 * Sx[q];
+            for (int q = 0; q < 4; q++) out.u[q][id] = U0[q] + h6 * Su[q];
+        }
+    }
+    if (clamps) atomicAdd(&counters[C_GAMMA_CLAMPS], (unsigned long long)clamps);
+}
+
+void launch_push(const PushParams &P, const Species &S, const double *node, ParticlePtrs in, ParticlePtrs out,
+                 unsigned long long *counters, hipStream_t s) {
+    if (P.n <= 0) return;
+    unsigned nb = (unsigned)((P.n + 255) / 256);
+    hipLaunchKernelGGL(k_push, dim3(nb), dim3(256), 0, s, P, S, node, in, out, counters);
+}
+
+// ---------------------------------------------------------------------------
+// Deposition (Sec. 4).  The chord x_n -> x_{n+1} is split per axis at
+//   x_r = min(min(i1,i2)+1, max(max(i1,i2), (x1+x2)/2))
+// into two segments inside one cell each; a segment of displacement d adds
+// FLUX^K = q d^K / dt to the four K-edges of its cell with transverse weights
+// over the (I,J) face.  CURVED: area of the sub-rectangle opposite each node
+// by the midpoint rule with density sqrt(g_II g_JJ - g_IJ^2) =
+// sqrt(1 + f (1 - k_K^2)) (k null: k_1^2 + k_2^2 + k_3^2 = 1), normalised by
+// their sum; FLAT: bilinear at the segment midpoint; both plus the exact
+// segment-average term +-dI dJ / 12.  Current goes into int64 fixed point,
+// so the sums do not depend on the order of the atomics.
+
+struct DepCtx {
+    Grid G;
+    Hole h;
+    double inv_dt;
+    double jscale;
+    int curved;
+};
+
+__device__ __forceinline__ double area_density(const DepCtx &D, int K, double X, double Y, double Z) {
+    if (D.h.m == 0.0) return 1.0;
+    double x = X - D.h.cx, y = Y - D.h.cy, z = Z - D.h.cz;
+    double a = D.h.a;
+    double r = ks_radius(a, x, y, z);
+    if (r < D.h.r_exc) return 1.0;
+    double rr = r * r;
+    double f = 2.0 * D.h.m * r * rr / (rr * rr + a * a * z * z);
+    double kK;
+    if (K == 0)
+        kK = (r * x - a * y) / (rr + a * a);
+    else if (K == 1)
+        kK = (r * y + a * x) / (rr + a * a);
+    else
+        kK = z / r;
+    return sqrt(1.0 + f * (1.0 - kK * kK));
+}
+
+__device__ __forceinline__ void dep_segment(const DepCtx &D, FieldPtrs &F, const double A[3], const double B[3],
+                                            const int cell[3], double Q) {
+    double d[3], mid[3];
+    for (int ax = 0; ax < 3; ax++) {
+        d[ax] = B[ax] - A[ax];
+        mid[ax] = 0.5 * (A[ax] + B[ax]);
+    }
+#pragma unroll
+    for (int K = 0; K < 3; K++) {
+        const int I = (K + 1) % 3, J = (K + 2) % 3;
+        double flux = Q * d[K] * D.inv_dt;
+        if (flux == 0.0) continue;
+        double t = d[I] * d[J] * (1.0 / 12.0);
+        double loI = (double)cell[I], loJ = (double)cell[J];
+        double w00, w10, w01, w11;
+        double xi = mid[I] - loI, eta = mid[J] - loJ;
+        if (!D.curved) {
+            w00 = (1.0 - xi) * (1.0 - eta);
+            w10 = xi * (1.0 - eta);
+            w01 = (1.0 - xi) * eta;
+            w11 = xi * eta;
+        } else {
+            double area[2][2];
+            for (int bj = 0; bj < 2; bj++)
+                for (int bi = 0; bi < 2; bi++) {
+                    double i0 = bi ? loI : mid[I], i1 = bi ? mid[I] : loI + 1.0;
+                    double j0 = bj ? loJ : mid[J], j1 = bj ? mid[J] : loJ + 1.0;
+                    double P3[3];
+                    P3[K] = mid[K];
+                    P3[I] = 0.5 * (i0 + i1);
+                    P3[J] = 0.5 * (j0 + j1);
+                    area[bi][bj] = area_density(D, K, P3[0], P3[1], P3[2]) * ((i1 - i0) * (j1 - j0));
+                }
+            double inv = 1.0 / (area[0][0] + area[1][0] + area[0][1] + area[1][1]);
+            w00 = area[0][0] * inv;
+            w10 = area[1][0] * inv;
+            w01 = area[0][1] * inv;
+            w11 = area[1][1] * inv;
+        }
+        w00 += t;
+        w11 += t;
+        w10 -= t;
+        w01 -= t;
+        int id[3];
+        id[K] = cell[K];
+        id[I] = cell[I];
+        id[J] = cell[J];
+        const int64_t sI = I == 0 ? 1 : (I == 1 ? D.G.sx : D.G.sy);
+        const int64_t sJ = J == 0 ? 1 : (J == 1 ? D.G.sx : D.G.sy);
+        int64_t g0 = D.G.g(id[0], id[1], id[2]);
+        unsigned long long *Jk = F.Jint[K];
+        double sc = flux * D.jscale;
+        atomicAdd(&Jk[g0], (unsigned long long)__double2ll_rn(sc * w00));
+        atomicAdd(&Jk[g0 + sI], (unsigned long long)__double2ll_rn(sc * w10));
+        atomicAdd(&Jk[g0 + sJ], (unsigned long long)__double2ll_rn(sc * w01));
+        atomicAdd(&Jk[g0 + sI + sJ], (unsigned long long)__double2ll_rn(sc * w11));
+    }
+}
+
+__global__ __launch_bounds__(256) void k_deposit(DepCtx D, Species cS, double r_rm, double rscale, ParticlePtrs xo,
+                                                 ParticlePtrs xn, int64_t n, FieldPtrs F,
+                                                 unsigned long long *counters) {
+    int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (id >= n) return;
+    uint8_t sp = xo.sp[id];
+    if (sp == kDead) return;
+    double Q = cS.charge[sp];
+    double x1[3] = {xo.x[0][id], xo.x[1][id], xo.x[2][id]};
+    double x2[3] = {xn.x[0][id], xn.x[1][id], xn.x[2][id]};
+    double xr[3];
+    int c1[3], c2[3];
+    bool ok = true;
+    for (int ax = 0; ax < 3; ax++) {
+        int i1 = (int)floor(x1[ax]), i2 = (int)floor(x2[ax]);
+        double lo = (double)((i1 < i2 ? i1 : i2) + 1);
+        double hi = (double)(i1 > i2 ? i1 : i2);
+        double mid = 0.5 * (x1[ax] + x2[ax]);
+        double v = mid > hi ? mid : hi;
+        xr[ax] = v < lo ? v : lo;
+        c1[ax] = i1;
+        c2[ax] = i2;
+        int nn = D.G.dim(ax);
+        if (c1[ax] < -1 || c1[ax] > nn || c2[ax] < -1 || c2[ax] > nn || !(fabs(x2[ax] - x1[ax]) < 1.0))
+            ok = false;
+    }
+    if (ok && Q != 0.0) {
+        dep_segment(D, F, x1, xr, c1, Q);
+        dep_segment(D, F, xr, x2, c2, Q);
+    } else if (!ok) {
+        atomicOr(&counters[C_FLAGS], 1ull);
+    }
+    // removal after the final move is deposited (paper silent; inside r_rm or outside the grid)
+    double r = ks_radius(D.h.a, x2[0] - D.h.cx, x2[1] - D.h.cy, x2[2] - D.h.cz);
+    bool outside = false;
+    for (int ax = 0; ax < 3; ax++) {
+        double nn = (double)D.G.dim(ax);
+        if (!(x2[ax] >= 0.0 && x2[ax] < nn)) outside = true;
+    }
+    if (r < r_rm) {
+        // keep the removed charge on the nodes for the Gauss diagnostic
+        int c[3];
+        double w[3];
+        bool inb = true;
+        for (int ax = 0; ax < 3; ax++) {
+            c[ax] = (int)floor(x2[ax]);
+            w[ax] = x2[ax] - (double)c[ax];
+            if (c[ax] < -1 || c[ax] > D.G.dim(ax)) inb = false;
+        }
+        if (inb && Q != 0.0) {
+            double sc = Q * rscale;
+            for (int dk = 0; dk < 2; dk++)
+                for (int dj = 0; dj < 2; dj++)
+                    for (int di = 0; di < 2; di++) {
+                        double W = (di ? w[0] : 1.0 - w[0]) * (dj ? w[1] : 1.0 - w[1]) * (dk ? w[2] : 1.0 - w[2]);
+                        atomicAdd(&F.rho_abs[D.G.g(c[0] + di, c[1] + dj, c[2] + dk)],
+                                  (unsigned long long)__double2ll_rn(sc * W));
+                    }
+        }
+        xo.sp[id] = kDead;
+        atomicAdd(&counters[C_REMOVED_HORIZON], 1ull);
+    } else if (outside) {
+        xo.sp[id] = kDead;
+        atomicAdd(&counters[C_REMOVED_OUTER], 1ull);
+    }
+}
+
+void launch_deposit(const Grid &G, const Hole &h, double dt, int deposit_mode, double r_rm, double jscale,
+                    double rscale, const Species &S, ParticlePtrs xold, ParticlePtrs xnew, int64_t n,
+                    FieldPtrs &F, unsigned long long *counters, hipStream_t s) {
+    if (n <= 0) return;
+    DepCtx D;
+    D.G = G;
+    D.h = h;
+    D.inv_dt = 1.0 / dt;
+    D.jscale = jscale;
+    D.curved = deposit_mode == 0;
+    unsigned nb = (unsigned)((n + 255) / 256);
+    hipLaunchKernelGGL(k_deposit, dim3(nb), dim3(256), 0, s, D, S, r_rm, rscale, xold, xnew, n, F, counters);
+}
+
+// ---------------------------------------------------------------------------
+// Load: future root of the mass shell from the covariant spatial components,
+//   g^{44} u_4^2 + 2 (g^{4i} u_i) u_4 + g^{ij} u_i u_j + c^2 = 0,  u^4 = g^{4b} u_b > 0,
+// then u^a = g^{ab} u_b.  Dropped particles (non-finite, outside the grid,
+// inside r_rm) are stored as dead slots.
+__global__ void k_load(Grid G, Hole h, double c, double r_rm, const double *__restrict__ xin,
+                       const double *__restrict__ ucin, int64_t n, int species, ParticlePtrs out, int64_t off,
+                       unsigned long long *counters) {
+    int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (id >= n) return;
+    double X[3] = {xin[id], xin[n + id], xin[2 * n + id]};
+    double uc[3] = {ucin[id], ucin[n + id], ucin[2 * n + id]};
+    bool ok = true;
+    for (int ax = 0; ax < 3; ax++) {
+        if (!isfinite(X[ax]) || !isfinite(uc[ax])) ok = false;
+        if (!(X[ax] >= 0.0 && X[ax] < (double)G.dim(ax))) ok = false;
+    }
+    double U[4] = {0.0, 0.0, 0.0, c};
+    if (ok) {
+        double x = X[0] - h.cx, y = X[1] - h.cy, z = X[2] - h.cz;
+        double f = 0.0, k[3] = {0.0, 0.0, 0.0};
+        if (h.m != 0.0) {
+            double r = ks_radius(h.a, x, y, z);
+            if (r < r_rm) ok = false;
+            if (ok) {
+                KSPoint<double> p;
+                ks_point(h.m, h.a, x, y, z, p);
+                f = p.f;
+                k[0] = p.k0;
+                k[1] = p.k1;
+                k[2] = p.k2;
+            }
+        }
+        if (ok) {
+            // g^{ab} = eta^{ab} - f k^a k^b, k^a = (k_1, k_2, k_3, -1)
+            double ku[4] = {k[0], k[1], k[2], -1.0};
+            const double eta[4] = {1.0, 1.0, 1.0, -1.0};
+            double gi[4][4];
+            for (int a = 0; a < 4; a++)
+                for (int b = 0; b < 4; b++) gi[a][b] = (a == b ? eta[a] : 0.0) - f * ku[a] * ku[b];
+            double A = gi[3][3];
+            double B = gi[3][0] * uc[0] + gi[3][1] * uc[1] + gi[3][2] * uc[2];
+            double C = c * c;
+            for (int i = 0; i < 3; i++)
+                for (int j = 0; j < 3; j++) C += gi[i][j] * uc[i] * uc[j];
+            double disc = B * B - A * C;
+            disc = disc < 0.0 ? 0.0 : disc;
+            double sq = sqrt(disc);
+            double u4l = (B <= 0.0) ? (sq - B) / A : -C / (sq + B);
+            double ul[4] = {uc[0], uc[1], uc[2], u4l};
+            for (int a = 0; a < 4; a++) U[a] = gi[a][0] * ul[0] + gi[a][1] * ul[1] + gi[a][2] * ul[2] + gi[a][3] * ul[3];
+        }
+    }
+    int64_t o = off + id;
+    for (int ax = 0; ax < 3; ax++) out.x[ax][o] = ok ? X[ax] : 0.0;
+    for (int q = 0; q < 4; q++) out.u[q][o] = U[q];
+    out.sp[o] = ok ? (uint8_t)species : kDead;
+    if (ok) atomicAdd(&counters[C_LOAD_KEPT], 1ull);
+}
+
+void launch_load(const Grid &G, const Hole &h, double c, double r_rm, const double *xin, const double *ucin,
+                 int64_t n, int species, ParticlePtrs out, int64_t offset, unsigned long long *counters,
+                 hipStream_t s) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_load, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, G, h, c, r_rm, xin, ucin, n,
+                       species, out, offset, counters);
+}
+
+__global__ void k_zero_u64(unsigned long long *p, int64_t n) {
+    int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (id < n) p[id] = 0ull;
+}
+
+void launch_zero_u64(unsigned long long *p, int64_t n, hipStream_t s) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_zero_u64, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, n);
+}
+
+}  // namespace grpic
