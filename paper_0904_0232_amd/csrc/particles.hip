@@ -8,11 +8,13 @@
 namespace grpic {
 
 
-// Trilinear gather of the 16 mixed components at X (cloud-in-cell with
-// sqrt(-det g) = 1, Sec. 3.3).  The cell is floor(X) clamped to the grid; the
+// Lorentz term (q/m-free) L^a = F^a_b(X) u^b with F^a_b gathered trilinearly
+// from the nodes (cloud-in-cell with sqrt(-det g) = 1, Sec. 3.3): the
+// contraction with u is taken node by node, L = sum_n W_n (F_n u), so only four
+// accumulators stay live.  The cell is floor(X) clamped to the grid; the
 // offset is not clamped.
-__device__ __forceinline__ void gather16(const Grid &G, const double *__restrict__ node, const double X[3],
-                                         double F[16]) {
+__device__ __forceinline__ void gather_lorentz(const Grid &G, const double *__restrict__ node, const double X[3],
+                                               const double U[4], double L[4]) {
     int c[3];
     double w[3];
     for (int ax = 0; ax < 3; ax++) {
@@ -22,25 +24,23 @@ __device__ __forceinline__ void gather16(const Grid &G, const double *__restrict
         c[ax] = ci;
         w[ax] = X[ax] - (double)ci;
     }
-    for (int q = 0; q < 16; q++) F[q] = 0.0;
+    L[0] = L[1] = L[2] = L[3] = 0.0;
     const int64_t sj = G.nx + 1, sk = (int64_t)(G.nx + 1) * (G.ny + 1);
     const double *base = node + 16 * G.node(c[0], c[1], c[2]);
+#pragma unroll 1
+    for (int q = 0; q < 4; q++) {
+        const int dj = q & 1, dk = q >> 1;
+        const double wyz = (dj ? w[1] : 1.0 - w[1]) * (dk ? w[2] : 1.0 - w[2]);
+        const double2 *p = reinterpret_cast<const double2 *>(base + 16 * (dj * sj + dk * sk));
 #pragma unroll
-    for (int dk = 0; dk < 2; dk++) {
-        double wz = dk ? w[2] : 1.0 - w[2];
+        for (int di = 0; di < 2; di++) {
+            const double W = (di ? w[0] : 1.0 - w[0]) * wyz;
+            const double2 *pn = p + 8 * di;
 #pragma unroll
-        for (int dj = 0; dj < 2; dj++) {
-            double wyz = (dj ? w[1] : 1.0 - w[1]) * wz;
-#pragma unroll
-            for (int di = 0; di < 2; di++) {
-                double W = (di ? w[0] : 1.0 - w[0]) * wyz;
-                const double2 *p = reinterpret_cast<const double2 *>(base + 16 * (di + dj * sj + dk * sk));
-#pragma unroll
-                for (int q = 0; q < 8; q++) {
-                    double2 v = p[q];
-                    F[2 * q] += W * v.x;
-                    F[2 * q + 1] += W * v.y;
-                }
+            for (int a = 0; a < 4; a++) {
+                double2 f01 = pn[2 * a], f23 = pn[2 * a + 1];
+                double row = f01.x * U[0] + f01.y * U[1] + f23.x * U[2] + f23.y * U[3];
+                L[a] += W * row;
             }
         }
     }
@@ -49,19 +49,16 @@ __device__ __forceinline__ void gather16(const Grid &G, const double *__restrict
 // du^a/dtau = (q/m) F^a_b u^b - Gamma^a_{mn} u^m u^n  (Sec. 3.3)
 __device__ __forceinline__ void accel(const PushParams &P, const double *__restrict__ node, double qm,
                                       const double X[3], const double U[4], double A[4]) {
+    double L[4];
+    gather_lorentz(P.G, node, X, U, L);
     double Gm[4] = {0.0, 0.0, 0.0, 0.0};
     if (P.h.m != 0.0) {
         KSGrad kp;
         ks_grad(P.h.m, P.h.a, X[0] - P.h.cx, X[1] - P.h.cy, X[2] - P.h.cz, kp);
         gamma_uu(kp, U, Gm);
     }
-    double F[16];
-    gather16(P.G, node, X, F);
 #pragma unroll
-    for (int a = 0; a < 4; a++) {
-        double l = F[4 * a] * U[0] + F[4 * a + 1] * U[1] + F[4 * a + 2] * U[2] + F[4 * a + 3] * U[3];
-        A[a] = qm * l - Gm[a];
-    }
+    for (int a = 0; a < 4; a++) A[a] = qm * L[a] - Gm[a];
 }
 
 // Stage time-dilation factor: PAPER = 1/2 [u4/c + sqrt((u4/c)^2 + 2 a4 dt / c)]
@@ -79,7 +76,7 @@ __device__ __forceinline__ double stage_gamma(const PushParams &P, double u4, do
 
 // Classic RK4 in coordinate time on Y = (x, u): K_k = (u_k, A_k)/gamma_k,
 // stages at dt/2, dt/2, dt, combination 1:2:2:1 over 6.
-__global__ __launch_bounds__(256) void k_push(PushParams P, Species cS, const double *__restrict__ node,
+__global__ __launch_bounds__(256, 4) void k_push(PushParams P, Species cS, const double *__restrict__ node,
                                               ParticlePtrs in, ParticlePtrs out, unsigned long long *counters) {
     int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     int clamps = 0;
@@ -164,7 +161,26 @@ __device__ __forceinline__ double area_density(const DepCtx &D, int K, double X,
     return sqrt(1.0 + f * (1.0 - kK * kK));
 }
 
-__device__ __forceinline__ void dep_segment(const DepCtx &D, FieldPtrs &F, const double A[3], const double B[3],
+// Destinations of the fixed-point current: straight to the global int64
+// arrays, or into an LDS tile covering the block's particles.
+struct GlobalAcc {
+    unsigned long long *J[3];
+    Grid G;
+    __device__ __forceinline__ void add(int K, int i, int j, int k, long long v) const {
+        atomicAdd(&J[K][G.g(i, j, k)], (unsigned long long)v);
+    }
+};
+
+struct LdsAcc {
+    unsigned long long *sm;
+    int lo0, lo1, lo2, bx, by, V;
+    __device__ __forceinline__ void add(int K, int i, int j, int k, long long v) const {
+        atomicAdd(&sm[K * V + ((k - lo2) * by + (j - lo1)) * bx + (i - lo0)], (unsigned long long)v);
+    }
+};
+
+template <typename Acc>
+__device__ __forceinline__ void dep_segment(const DepCtx &D, const Acc &acc, const double A[3], const double B[3],
                                             const int cell[3], double Q) {
     double d[3], mid[3];
     for (int ax = 0; ax < 3; ax++) {
@@ -211,30 +227,29 @@ __device__ __forceinline__ void dep_segment(const DepCtx &D, FieldPtrs &F, const
         id[K] = cell[K];
         id[I] = cell[I];
         id[J] = cell[J];
-        const int64_t sI = I == 0 ? 1 : (I == 1 ? D.G.sx : D.G.sy);
-        const int64_t sJ = J == 0 ? 1 : (J == 1 ? D.G.sx : D.G.sy);
-        int64_t g0 = D.G.g(id[0], id[1], id[2]);
-        unsigned long long *Jk = F.Jint[K];
         double sc = flux * D.jscale;
-        atomicAdd(&Jk[g0], (unsigned long long)__double2ll_rn(sc * w00));
-        atomicAdd(&Jk[g0 + sI], (unsigned long long)__double2ll_rn(sc * w10));
-        atomicAdd(&Jk[g0 + sJ], (unsigned long long)__double2ll_rn(sc * w01));
-        atomicAdd(&Jk[g0 + sI + sJ], (unsigned long long)__double2ll_rn(sc * w11));
+        int e0[3] = {id[0], id[1], id[2]};
+        int eI[3] = {id[0], id[1], id[2]};
+        eI[I] += 1;
+        int eJ[3] = {id[0], id[1], id[2]};
+        eJ[J] += 1;
+        int eIJ[3] = {eI[0], eI[1], eI[2]};
+        eIJ[J] += 1;
+        acc.add(K, e0[0], e0[1], e0[2], __double2ll_rn(sc * w00));
+        acc.add(K, eI[0], eI[1], eI[2], __double2ll_rn(sc * w10));
+        acc.add(K, eJ[0], eJ[1], eJ[2], __double2ll_rn(sc * w01));
+        acc.add(K, eIJ[0], eIJ[1], eIJ[2], __double2ll_rn(sc * w11));
     }
 }
 
-__global__ __launch_bounds__(256) void k_deposit(DepCtx D, Species cS, double r_rm, double rscale, ParticlePtrs xo,
-                                                 ParticlePtrs xn, int64_t n, FieldPtrs F,
-                                                 unsigned long long *counters) {
-    int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (id >= n) return;
-    uint8_t sp = xo.sp[id];
-    if (sp == kDead) return;
-    double Q = cS.charge[sp];
-    double x1[3] = {xo.x[0][id], xo.x[1][id], xo.x[2][id]};
-    double x2[3] = {xn.x[0][id], xn.x[1][id], xn.x[2][id]};
-    double xr[3];
-    int c1[3], c2[3];
+constexpr int kDepBlock = 256;
+constexpr int kDepPPT = 4;      // particles per thread
+constexpr int kDepLds = 4096;   // int64 LDS entries of the current tile (32 KiB)
+
+// Zigzag split of one chord: relay point and the two cells; false when the
+// move is longer than a cell or leaves the ghost layer.
+__device__ __forceinline__ bool zigzag(const Grid &G, const double x1[3], const double x2[3], double xr[3],
+                                       int c1[3], int c2[3]) {
     bool ok = true;
     for (int ax = 0; ax < 3; ax++) {
         int i1 = (int)floor(x1[ax]), i2 = (int)floor(x2[ax]);
@@ -245,48 +260,154 @@ __global__ __launch_bounds__(256) void k_deposit(DepCtx D, Species cS, double r_
         xr[ax] = v < lo ? v : lo;
         c1[ax] = i1;
         c2[ax] = i2;
-        int nn = D.G.dim(ax);
-        if (c1[ax] < -1 || c1[ax] > nn || c2[ax] < -1 || c2[ax] > nn || !(fabs(x2[ax] - x1[ax]) < 1.0))
-            ok = false;
+        int nn = G.dim(ax);
+        if (c1[ax] < -1 || c1[ax] > nn || c2[ax] < -1 || c2[ax] > nn || !(fabs(x2[ax] - x1[ax]) < 1.0)) ok = false;
     }
-    if (ok && Q != 0.0) {
-        dep_segment(D, F, x1, xr, c1, Q);
-        dep_segment(D, F, xr, x2, c2, Q);
-    } else if (!ok) {
-        atomicOr(&counters[C_FLAGS], 1ull);
+    return ok;
+}
+
+__device__ __forceinline__ int wave_min(int v) {
+    for (int o = 32; o > 0; o >>= 1) {
+        int w = __shfl_xor(v, o, 64);
+        v = w < v ? w : v;
     }
-    // removal after the final move is deposited (paper silent; inside r_rm or outside the grid)
-    double r = ks_radius(D.h.a, x2[0] - D.h.cx, x2[1] - D.h.cy, x2[2] - D.h.cz);
-    bool outside = false;
+    return v;
+}
+__device__ __forceinline__ int wave_max(int v) {
+    for (int o = 32; o > 0; o >>= 1) {
+        int w = __shfl_xor(v, o, 64);
+        v = w > v ? w : v;
+    }
+    return v;
+}
+
+// One block deposits kDepBlock*kDepPPT consecutive particles.  When the
+// current they touch fits an LDS box (sorted particles: a few cells of one
+// tile), it is summed there with int64 LDS atomics and flushed once with
+// global atomics; otherwise the block writes global atomics directly.  Both
+// routes add the same integers, so the result does not depend on the route
+// or the order.  Removal follows the deposit of the final move.
+__global__ __launch_bounds__(kDepBlock) void k_deposit(DepCtx D, Species cS, double r_rm, double rscale,
+                                                       ParticlePtrs xo, ParticlePtrs xn, int64_t n, FieldPtrs F,
+                                                       unsigned long long *counters) {
+    __shared__ unsigned long long sm[kDepLds];
+    __shared__ int sred[6][kDepBlock / 64];
+    const int tid = threadIdx.x;
+    const int64_t base = (int64_t)blockIdx.x * (kDepBlock * kDepPPT);
+    double X1[kDepPPT][3], X2[kDepPPT][3];
+    uint8_t SP[kDepPPT];
+    int lo[3] = {1 << 30, 1 << 30, 1 << 30}, hi[3] = {-(1 << 30), -(1 << 30), -(1 << 30)};
+#pragma unroll
+    for (int p = 0; p < kDepPPT; p++) {
+        int64_t id = base + p * kDepBlock + tid;
+        SP[p] = id < n ? xo.sp[id] : kDead;
+        if (SP[p] != kDead) {
+            for (int ax = 0; ax < 3; ax++) {
+                X1[p][ax] = xo.x[ax][id];
+                X2[p][ax] = xn.x[ax][id];
+            }
+            double xr[3];
+            int c1[3], c2[3];
+            if (zigzag(D.G, X1[p], X2[p], xr, c1, c2) && cS.charge[SP[p]] != 0.0)
+                for (int ax = 0; ax < 3; ax++) {
+                    int a = c1[ax] < c2[ax] ? c1[ax] : c2[ax];
+                    int b = (c1[ax] > c2[ax] ? c1[ax] : c2[ax]) + 1;
+                    lo[ax] = a < lo[ax] ? a : lo[ax];
+                    hi[ax] = b > hi[ax] ? b : hi[ax];
+                }
+        }
+    }
     for (int ax = 0; ax < 3; ax++) {
-        double nn = (double)D.G.dim(ax);
-        if (!(x2[ax] >= 0.0 && x2[ax] < nn)) outside = true;
+        int a = wave_min(lo[ax]), b = wave_max(hi[ax]);
+        if ((tid & 63) == 0) {
+            sred[ax][tid >> 6] = a;
+            sred[3 + ax][tid >> 6] = b;
+        }
     }
-    if (r < r_rm) {
-        // keep the removed charge on the nodes for the Gauss diagnostic
-        int c[3];
-        double w[3];
-        bool inb = true;
+    __syncthreads();
+    int blo[3], bhi[3];
+    for (int ax = 0; ax < 3; ax++) {
+        blo[ax] = sred[ax][0];
+        bhi[ax] = sred[3 + ax][0];
+        for (int w = 1; w < kDepBlock / 64; w++) {
+            blo[ax] = sred[ax][w] < blo[ax] ? sred[ax][w] : blo[ax];
+            bhi[ax] = sred[3 + ax][w] > bhi[ax] ? sred[3 + ax][w] : bhi[ax];
+        }
+    }
+    const bool any = bhi[0] >= blo[0];
+    const int bx = any ? bhi[0] - blo[0] + 1 : 0, by = any ? bhi[1] - blo[1] + 1 : 0,
+              bz = any ? bhi[2] - blo[2] + 1 : 0;
+    const int64_t V64 = (int64_t)bx * by * bz;
+    const bool use_lds = any && 3 * V64 <= kDepLds;
+    const int V = use_lds ? (int)V64 : 0;
+    if (use_lds) {
+        for (int e = tid; e < 3 * V; e += kDepBlock) sm[e] = 0ull;
+        __syncthreads();
+    }
+    LdsAcc la{sm, blo[0], blo[1], blo[2], bx, by, V};
+    GlobalAcc ga{{F.Jint[0], F.Jint[1], F.Jint[2]}, D.G};
+#pragma unroll
+    for (int p = 0; p < kDepPPT; p++) {
+        if (SP[p] == kDead) continue;
+        int64_t id = base + p * kDepBlock + tid;
+        double Q = cS.charge[SP[p]];
+        double xr[3];
+        int c1[3], c2[3];
+        bool ok = zigzag(D.G, X1[p], X2[p], xr, c1, c2);
+        if (ok && Q != 0.0) {
+            if (use_lds) {
+                dep_segment(D, la, X1[p], xr, c1, Q);
+                dep_segment(D, la, xr, X2[p], c2, Q);
+            } else {
+                dep_segment(D, ga, X1[p], xr, c1, Q);
+                dep_segment(D, ga, xr, X2[p], c2, Q);
+            }
+        } else if (!ok) {
+            atomicOr(&counters[C_FLAGS], 1ull);
+        }
+        const double *x2 = X2[p];
+        double r = ks_radius(D.h.a, x2[0] - D.h.cx, x2[1] - D.h.cy, x2[2] - D.h.cz);
+        bool outside = false;
         for (int ax = 0; ax < 3; ax++) {
-            c[ax] = (int)floor(x2[ax]);
-            w[ax] = x2[ax] - (double)c[ax];
-            if (c[ax] < -1 || c[ax] > D.G.dim(ax)) inb = false;
+            double nn = (double)D.G.dim(ax);
+            if (!(x2[ax] >= 0.0 && x2[ax] < nn)) outside = true;
         }
-        if (inb && Q != 0.0) {
-            double sc = Q * rscale;
-            for (int dk = 0; dk < 2; dk++)
-                for (int dj = 0; dj < 2; dj++)
-                    for (int di = 0; di < 2; di++) {
-                        double W = (di ? w[0] : 1.0 - w[0]) * (dj ? w[1] : 1.0 - w[1]) * (dk ? w[2] : 1.0 - w[2]);
-                        atomicAdd(&F.rho_abs[D.G.g(c[0] + di, c[1] + dj, c[2] + dk)],
-                                  (unsigned long long)__double2ll_rn(sc * W));
-                    }
+        if (r < r_rm) {
+            // the removed charge stays on the nodes for the Gauss diagnostic
+            int c[3];
+            double w[3];
+            bool inb = true;
+            for (int ax = 0; ax < 3; ax++) {
+                c[ax] = (int)floor(x2[ax]);
+                w[ax] = x2[ax] - (double)c[ax];
+                if (c[ax] < -1 || c[ax] > D.G.dim(ax)) inb = false;
+            }
+            if (inb && Q != 0.0) {
+                double sc = Q * rscale;
+                for (int dk = 0; dk < 2; dk++)
+                    for (int dj = 0; dj < 2; dj++)
+                        for (int di = 0; di < 2; di++) {
+                            double W = (di ? w[0] : 1.0 - w[0]) * (dj ? w[1] : 1.0 - w[1]) * (dk ? w[2] : 1.0 - w[2]);
+                            atomicAdd(&F.rho_abs[D.G.g(c[0] + di, c[1] + dj, c[2] + dk)],
+                                      (unsigned long long)__double2ll_rn(sc * W));
+                        }
+            }
+            xo.sp[id] = kDead;
+            atomicAdd(&counters[C_REMOVED_HORIZON], 1ull);
+        } else if (outside) {
+            xo.sp[id] = kDead;
+            atomicAdd(&counters[C_REMOVED_OUTER], 1ull);
         }
-        xo.sp[id] = kDead;
-        atomicAdd(&counters[C_REMOVED_HORIZON], 1ull);
-    } else if (outside) {
-        xo.sp[id] = kDead;
-        atomicAdd(&counters[C_REMOVED_OUTER], 1ull);
+    }
+    if (use_lds) {
+        __syncthreads();
+        for (int e = tid; e < 3 * V; e += kDepBlock) {
+            unsigned long long v = sm[e];
+            if (v == 0ull) continue;
+            int K = e / V, l = e - K * V;
+            int li = l % bx, lj = (l / bx) % by, lk = l / (bx * by);
+            atomicAdd(&F.Jint[K][D.G.g(blo[0] + li, blo[1] + lj, blo[2] + lk)], v);
+        }
     }
 }
 
@@ -300,8 +421,9 @@ void launch_deposit(const Grid &G, const Hole &h, double dt, int deposit_mode, d
     D.inv_dt = 1.0 / dt;
     D.jscale = jscale;
     D.curved = deposit_mode == 0;
-    unsigned nb = (unsigned)((n + 255) / 256);
-    hipLaunchKernelGGL(k_deposit, dim3(nb), dim3(256), 0, s, D, S, r_rm, rscale, xold, xnew, n, F, counters);
+    const int64_t per = kDepBlock * kDepPPT;
+    unsigned nb = (unsigned)((n + per - 1) / per);
+    hipLaunchKernelGGL(k_deposit, dim3(nb), dim3(kDepBlock), 0, s, D, S, r_rm, rscale, xold, xnew, n, F, counters);
 }
 
 // ---------------------------------------------------------------------------
