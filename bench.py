@@ -30,6 +30,7 @@ sys.path.insert(0, ROOT)
 METRIC = "particle-steps/sec on 1 MI355X (FP32-mixed vs FP64) + serving p50/p99 latency"
 UNIT = "particle-steps/s"
 FP64_PEAK_TFLOPS = 78.6
+FP32_PEAK_TFLOPS = 157.3
 HBM_PEAK_GBS = 8000.0
 
 # Algorithmic FP64 operations of one particle-step of the pusher (one call of
@@ -96,6 +97,67 @@ def cpu_baseline(workload, sample_per_species):
     }
 
 
+def measure(workload, precision, steps, warmup, sort_every):
+    """Time `steps` cycles of one run; returns the figures of the timed region."""
+    import torch
+    from paper_0904_0232_amd import capi, inputs
+    from paper_0904_0232_amd import run as R
+
+    w = inputs.workload_params(workload)
+    parts = inputs.workload_particles(workload, seed=0)
+    ntot = sum(p[1].shape[1] for p in parts)
+    cfg = R.make_config(w["n"], m=w["m"], a=w["a"], dt=w["dt"], B0=(0.0, 0.0, w["B0"]), species=w["species"],
+                        r_rm=w["r_rm"], sort_every=sort_every, capacity=ntot,
+                        precision=capi.FP32_MIXED if precision == "fp32" else capi.FP64)
+    run = R.Run(cfg)
+    for sp, x, uc in parts:
+        run.load(sp, x, uc)
+    del parts
+    h = run.h
+    capi.grpic_step(h, warmup)
+    torch.cuda.synchronize()
+    ps0 = capi.grpic_particle_steps(h)
+    capi.grpic_set_timing(h, True)
+    capi.grpic_read_timing(h)  # reset
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    capi.grpic_step(h, steps)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    timers = capi.grpic_read_timing(h)
+    capi.grpic_set_timing(h, False)
+    ps1 = capi.grpic_particle_steps(h)
+    d = run.diag()
+    run.close()
+    wall = t1 - t0
+    psteps = ps1 - ps0
+    return {
+        "w": w, "ntot": ntot, "wall": wall, "psteps": psteps, "value": psteps / wall,
+        "ms_per_step": wall * 1e3 / steps, "timers": timers,
+        "kernel_ms_per_launch": {k: (v[0] / max(v[1], 1)) for k, v in timers.items()},
+        "live_end": int(sum(d["n_alive"])),
+    }
+
+
+def push_roofline(m, flops_per_ps, peak, traffic=None):
+    push_ms, push_n = m["timers"]["push"]
+    avg_push_s = push_ms / 1e3 / max(push_n, 1)
+    per_launch = m["psteps"] / max(push_n, 1)
+    achieved = flops_per_ps * per_launch / avg_push_s / 1e12
+    return {
+        "kernel": "k_push (gather + RK4 pusher)",
+        "bound": "alu",
+        "achieved": achieved,
+        "peak": peak,
+        "unit": "TFLOP/s",
+        "frac": achieved / peak,
+        "traffic": traffic,
+        "avg_launch_ms": avg_push_s * 1e3,
+        "flops_per_particle_step": flops_per_ps,
+        "particles_per_launch": per_launch,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -105,6 +167,9 @@ def main():
     ap.add_argument("--sort-every", type=int, default=10)
     ap.add_argument("--cpu-sample", type=int, default=1 << 20, help="particles per species for the oracle timing")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp32", action="store_true", help="skip the FP32-mixed measurement")
+    ap.add_argument("--scale", action="store_true",
+                    help="also time the 256^3 throughput workload (268M particles) in both precisions")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -114,63 +179,20 @@ def main():
         sys.exit(2)
 
     import torch
-    from paper_0904_0232_amd import capi, inputs
-    from paper_0904_0232_amd import run as R
-
     torch.cuda.set_device(0)
-    w = inputs.workload_params(args.workload)
-    parts = inputs.workload_particles(args.workload, seed=0)
-    ntot = sum(p[1].shape[1] for p in parts)
-    cfg = R.make_config(w["n"], m=w["m"], a=w["a"], dt=w["dt"], B0=(0.0, 0.0, w["B0"]), species=w["species"],
-                        r_rm=w["r_rm"], sort_every=args.sort_every, capacity=ntot)
-    run = R.Run(cfg)
-    for sp, x, uc in parts:
-        run.load(sp, x, uc)
-    h = run.h
-    capi.grpic_step(h, args.warmup)
-    torch.cuda.synchronize()
-    ps0 = capi.grpic_particle_steps(h)
-    capi.grpic_set_timing(h, True)
-    capi.grpic_read_timing(h)  # reset
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    capi.grpic_step(h, args.steps)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    timers = capi.grpic_read_timing(h)
-    capi.grpic_set_timing(h, False)
-    ps1 = capi.grpic_particle_steps(h)
-    wall = t1 - t0
-    psteps = ps1 - ps0
-    value = psteps / wall
-    d = run.diag()
 
-    push_ms, push_n = timers["push"]
-    avg_push_s = push_ms / 1e3 / max(push_n, 1)
-    per_launch = psteps / max(push_n, 1)
-    flops_per_launch = PUSH_FLOPS_PER_PARTICLE_STEP * per_launch
-    achieved = flops_per_launch / avg_push_s / 1e12
-    traffic = read_traffic(per_launch)
-    roofline = {
-        "kernel": "k_push (gather + RK4 pusher)",
-        "bound": "alu",
-        "achieved": achieved,
-        "peak": FP64_PEAK_TFLOPS,
-        "unit": "TFLOP/s",
-        "frac": achieved / FP64_PEAK_TFLOPS,
-        "traffic": traffic,
-        "avg_launch_ms": avg_push_s * 1e3,
-        "flops_per_particle_step": PUSH_FLOPS_PER_PARTICLE_STEP,
-    }
-    per_step = {k: (v[0] / max(v[1], 1)) for k, v in timers.items()}
+    m64 = measure(args.workload, "fp64", args.steps, args.warmup, args.sort_every)
+    w = m64["w"]
+    per_launch = m64["psteps"] / max(m64["timers"]["push"][1], 1)
+    roofline = push_roofline(m64, PUSH_FLOPS_PER_PARTICLE_STEP, FP64_PEAK_TFLOPS, read_traffic(per_launch))
     line = {
         "metric": METRIC,
-        "value": value,
+        "value": m64["value"],
         "unit": UNIT,
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": wall * 1e3 / args.steps,
+        "ms_per_step": m64["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -179,16 +201,30 @@ def main():
         "config": {
             "workload": "%s: Kerr a=%.2fm, m=%g cells, %d^3 grid, %d particles (%d ppc x 2 species), "
                         "uniform Maxwellian u_th=%gc, B_z=%g, dt=%g, curved deposit, paper gamma, "
-                        "sort every %d steps" % (args.workload, w["a_frac"], w["m"], w["n"], ntot, w["ppc"],
+                        "sort every %d steps" % (args.workload, w["a_frac"], w["m"], w["n"], m64["ntot"], w["ppc"],
                                                  w["u_th"], w["B0"], w["dt"], args.sort_every),
             "precision": "fp64",
-            "live_particles_end": int(sum(d["n_alive"])),
+            "live_particles_end": m64["live_end"],
         },
-        "kernel_ms_per_launch": per_step,
+        "kernel_ms_per_launch": m64["kernel_ms_per_launch"],
         "roofline": roofline,
         "cpu_baseline": None,
     }
-    run.close()
+    if not args.no_fp32:
+        m32 = measure(args.workload, "fp32", args.steps, args.warmup, args.sort_every)
+        line["fp32_mixed"] = {
+            "value": m32["value"], "unit": UNIT, "ms_per_step": m32["ms_per_step"], "dtype": "f32 (FP64 quartic, "
+            "near-horizon metric and diagnostics)", "kernel_ms_per_launch": m32["kernel_ms_per_launch"],
+            "speedup_vs_fp64": m32["value"] / m64["value"], "live_particles_end": m32["live_end"],
+            "roofline": push_roofline(m32, PUSH_FLOPS_PER_PARTICLE_STEP, FP32_PEAK_TFLOPS),
+        }
+    if args.scale:
+        scale = {}
+        for prec in ("fp32", "fp64"):
+            ms = measure("shell256", prec, 20, 2, args.sort_every)
+            scale[prec] = {"value": ms["value"], "ms_per_step": ms["ms_per_step"], "particles": ms["ntot"],
+                           "kernel_ms_per_launch": ms["kernel_ms_per_launch"], "steps": 20}
+        line["throughput_scale_shell256"] = scale
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(args.workload, args.cpu_sample)
     print(json.dumps(line), flush=True)

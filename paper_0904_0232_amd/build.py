@@ -15,7 +15,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libgrpic.so")
 
-SOURCES = ["api.hip", "fields.hip", "particles.hip", "sort.hip", "diag.hip"]
+SOURCES = ["api.hip", "fields.hip", "particles.hip", "particles32.hip", "sort.hip", "diag.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "--offload-arch=gfx950",

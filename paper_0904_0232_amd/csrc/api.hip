@@ -1,5 +1,6 @@
 // C ABI of the GRPIC hot path (declared in include/grpic.h): handle state,
-// allocation, the per-step driver and the host<->device copies.
+// allocation, the per-step driver and the host<->device copies, for the FP64
+// form and the FP32-mixed form.
 #include <math.h>
 #include <stdio.h>
 #include <stdlib.h>
@@ -16,13 +17,21 @@ using namespace grpic;
 
 struct grpic_s {
     grpic_config cfg;
+    bool mixed;  // FP32-mixed form
     hipStream_t stream;
     Grid G;
     Hole h;
     Species S;
-    FieldPtrs F;
+    Mixed M;
+    FieldPtrsT<double> F64;
+    FieldPtrsT<float> F32;
+    // FP64 particles
     double *px[2][3];
     double *pu[2][4];
+    // FP32-mixed particles
+    int32_t *pcell[2];
+    float *poff[2][3];
+    float *pu32[2][4];
     uint8_t *psp[2];
     int xc, uc;
     int64_t n_slots, cap;
@@ -54,23 +63,24 @@ int check_at(hipError_t e, const char *what, int line) {
 #define check(e) check_at((e), #e, __LINE__)
 #define FAILS(e) (check_at((e), #e, __LINE__) != GRPIC_OK)
 
-void *dev_alloc(grpic_t *h, size_t bytes) {
+// Errors left by earlier HIP calls of the host program (not this library)
+// must not be reported as ours: clear them on entry.
+void clear_foreign_error() { (void)hipGetLastError(); }
+
+void *raw_alloc(grpic_t *h, size_t bytes) {
     if (bytes == 0) bytes = 256;
     bytes = (bytes + 255) & ~(size_t)255;
     void *p = nullptr;
     if (h->cfg.alloc) {
         p = h->cfg.alloc(bytes, h->cfg.alloc_ctx);
-    } else {
-        if (FAILS(hipMalloc(&p, bytes))) p = nullptr;
+    } else if (FAILS(hipMalloc(&p, bytes))) {
+        p = nullptr;
     }
-    if (p)
-        h->allocs.push_back(p);
-    else
-        fprintf(stderr, "grpic: device allocation of %zu bytes failed\n", bytes);
+    if (!p) fprintf(stderr, "grpic: device allocation of %zu bytes failed\n", bytes);
     return p;
 }
 
-void dev_free(grpic_t *h, void *p) {
+void raw_free(grpic_t *h, void *p) {
     if (!p) return;
     if (h->cfg.alloc) {
         if (h->cfg.free) h->cfg.free(p, h->cfg.alloc_ctx);
@@ -79,13 +89,24 @@ void dev_free(grpic_t *h, void *p) {
     }
 }
 
-ParticlePtrs pp(grpic_t *h, int xb, int ub) {
-    ParticlePtrs P;
-    for (int q = 0; q < 3; q++) P.x[q] = h->px[xb][q];
-    for (int q = 0; q < 4; q++) P.u[q] = h->pu[ub][q];
-    P.sp = h->psp[ub];
-    return P;
+void *dev_alloc(grpic_t *h, size_t bytes) {
+    void *p = raw_alloc(h, bytes);
+    if (p) h->allocs.push_back(p);
+    return p;
 }
+
+// Scratch device buffer for one call (freed after the stream drained).
+struct Temp {
+    grpic_t *h;
+    void *p;
+    Temp(grpic_t *hh, size_t bytes) : h(hh), p(raw_alloc(hh, bytes)) {}
+    ~Temp() {
+        if (p) {
+            (void)hipStreamSynchronize(h->stream);
+            raw_free(h, p);
+        }
+    }
+};
 
 hipEvent_t take_event(grpic_t *h) {
     if (!h->ev_pool.empty()) {
@@ -116,14 +137,31 @@ struct TimedGroup {
     }
 };
 
+ParticlePtrs pp(grpic_t *h, int xb, int ub) {
+    ParticlePtrs P;
+    for (int q = 0; q < 3; q++) P.x[q] = h->px[xb][q];
+    for (int q = 0; q < 4; q++) P.u[q] = h->pu[ub][q];
+    P.sp = h->psp[ub];
+    return P;
+}
 
-// Errors left by earlier HIP calls of the host program (not this library)
-// must not be reported as ours: clear them on entry.
-void clear_foreign_error() { (void)hipGetLastError(); }
+ParticlePtrs32 pp32(grpic_t *h, int xb, int ub) {
+    ParticlePtrs32 P;
+    P.cell = h->pcell[xb];
+    for (int q = 0; q < 3; q++) P.off[q] = h->poff[xb][q];
+    for (int q = 0; q < 4; q++) P.u[q] = h->pu32[ub][q];
+    P.sp = h->psp[ub];
+    return P;
+}
+
+template <typename T> FieldPtrsT<T> &fields(grpic_t *h);
+template <> FieldPtrsT<double> &fields<double>(grpic_t *h) { return h->F64; }
+template <> FieldPtrsT<float> &fields<float>(grpic_t *h) { return h->F32; }
 
 int validate(const grpic_config *c) {
     if (!c) return GRPIC_EINVAL;
     if (c->nx < 4 || c->ny < 4 || c->nz < 4) return GRPIC_EINVAL;
+    if (c->nx > 1020 || c->ny > 1020 || c->nz > 1020) return GRPIC_EINVAL;  // packed cells hold 10 bits
     if ((int64_t)c->nx * c->ny * c->nz > (int64_t)1 << 30) return GRPIC_EINVAL;
     if (c->precision != GRPIC_FP64 && c->precision != GRPIC_FP32_MIXED) return GRPIC_EINVAL;
     if (c->gamma_mode != GRPIC_GAMMA_PAPER && c->gamma_mode != GRPIC_GAMMA_U4) return GRPIC_EINVAL;
@@ -145,100 +183,251 @@ int validate(const grpic_config *c) {
     return GRPIC_OK;
 }
 
-int enqueue_field_derivation_reference(grpic_t *h) {
-    FieldPtrs &F = h->F;
+template <typename T>
+bool alloc_fields(grpic_t *h, FieldPtrsT<T> &F) {
+    int64_t gs = h->G.gsize(), nn = h->G.nnodes();
+    bool ok = true;
+    auto A = [&](size_t bytes) -> void * {
+        void *p = dev_alloc(h, bytes);
+        if (!p) ok = false;
+        return p;
+    };
+    for (int c = 0; c < 3; c++) {
+        F.D[c] = (T *)A(gs * sizeof(T));
+        F.B[c] = (T *)A(gs * sizeof(T));
+        F.E[c] = (T *)A(gs * sizeof(T));
+        F.H[c] = (T *)A(gs * sizeof(T));
+        F.D0[c] = (T *)A(gs * sizeof(T));
+        F.B0[c] = (T *)A(gs * sizeof(T));
+        F.E0[c] = (T *)A(gs * sizeof(T));
+        F.H0[c] = (T *)A(gs * sizeof(T));
+        F.Dsave[c] = (T *)A(gs * sizeof(T));
+        F.Bsave[c] = (T *)A(gs * sizeof(T));
+        F.Jint[c] = (unsigned long long *)A(gs * 8);
+    }
+    F.rho_abs = (unsigned long long *)A(gs * 8);
+    F.mask = (uint8_t *)A(gs);
+    F.dS = (T *)A(21 * nn * sizeof(T));
+    F.gn = (T *)A(10 * nn * sizeof(T));
+    F.w = (T *)A(6 * nn * sizeof(T));
+    F.node = (T *)A(16 * nn * sizeof(T));
+    return ok;
+}
+
+template <typename T>
+int init_fields(grpic_t *h, FieldPtrsT<T> &F) {
     hipStream_t s = h->stream;
     int64_t gs = h->G.gsize();
-    for (int c = 0; c < 3; c++) {
-        if (FAILS(hipMemcpyAsync(F.D0[c], F.D[c], gs * 8, hipMemcpyDeviceToDevice, s))) return GRPIC_EDEVICE;
-        if (FAILS(hipMemcpyAsync(F.B0[c], F.B[c], gs * 8, hipMemcpyDeviceToDevice, s))) return GRPIC_EDEVICE;
+    int rc = GRPIC_OK;
+    for (int c = 0; c < 3 && !rc; c++) {
+        if (FAILS(hipMemsetAsync(F.E[c], 0, gs * sizeof(T), s))) rc = GRPIC_EDEVICE;
+        if (FAILS(hipMemsetAsync(F.H[c], 0, gs * sizeof(T), s))) rc = GRPIC_EDEVICE;
+        if (FAILS(hipMemsetAsync(F.Jint[c], 0, gs * 8, s))) rc = GRPIC_EDEVICE;
     }
-    launch_derived(h->G, F, false, true, true, s);
+    if (!rc && FAILS(hipMemsetAsync(F.rho_abs, 0, gs * 8, s))) rc = GRPIC_EDEVICE;
+    if (rc) return rc;
+    launch_bake<T>(h->G, h->h, F, s);
+    launch_init_fields<T>(h->G, h->h, F, h->cfg.B0, h->cfg.init_covariant, s);
+    // reference state: evolved values and their derived fields at t = 0
     for (int c = 0; c < 3; c++) {
-        if (FAILS(hipMemcpyAsync(F.E0[c], F.E[c], gs * 8, hipMemcpyDeviceToDevice, s))) return GRPIC_EDEVICE;
-        if (FAILS(hipMemcpyAsync(F.H0[c], F.H[c], gs * 8, hipMemcpyDeviceToDevice, s))) return GRPIC_EDEVICE;
+        if (FAILS(hipMemcpyAsync(F.D0[c], F.D[c], gs * sizeof(T), hipMemcpyDeviceToDevice, s))) return GRPIC_EDEVICE;
+        if (FAILS(hipMemcpyAsync(F.B0[c], F.B[c], gs * sizeof(T), hipMemcpyDeviceToDevice, s))) return GRPIC_EDEVICE;
+    }
+    launch_derived<T>(h->G, F, false, true, true, s);
+    for (int c = 0; c < 3; c++) {
+        if (FAILS(hipMemcpyAsync(F.E0[c], F.E[c], gs * sizeof(T), hipMemcpyDeviceToDevice, s))) return GRPIC_EDEVICE;
+        if (FAILS(hipMemcpyAsync(F.H0[c], F.H[c], gs * sizeof(T), hipMemcpyDeviceToDevice, s))) return GRPIC_EDEVICE;
     }
     return GRPIC_OK;
 }
 
+// Magnetic half-step to time n with E_cov^n made consistent with B^n, then
+// the node tensor from (D^n, B^n).
+template <typename T>
+int fields_to_n(grpic_t *h) {
+    FieldPtrsT<T> &F = fields<T>(h);
+    const grpic_config &c = h->cfg;
+    hipStream_t s = h->stream;
+    int64_t gs = h->G.gsize();
+    TimedGroup tg(h, GRPIC_TIMER_FIELDS);
+    for (int q = 0; q < 3; q++)
+        if (FAILS(hipMemcpyAsync(F.Bsave[q], F.B[q], gs * sizeof(T), hipMemcpyDeviceToDevice, s))) return GRPIC_EDEVICE;
+    const T *Bsave[3] = {F.Bsave[0], F.Bsave[1], F.Bsave[2]};
+    for (int it = 0; it < c.field_iters; it++) {
+        launch_derived<T>(h->G, F, true, true, false, s);
+        launch_bhalf<T>(h->G, F, Bsave, 0.5 * c.c * c.dt, s);
+    }
+    launch_node_tensor<T>(h->G, F, s);
+    return GRPIC_OK;
+}
+
+// Second magnetic half-step (same E_cov^n) and clearing of the current.
+template <typename T>
+void fields_mid(grpic_t *h) {
+    FieldPtrsT<T> &F = fields<T>(h);
+    TimedGroup tg(h, GRPIC_TIMER_FIELDS);
+    const T *Bcur[3] = {F.B[0], F.B[1], F.B[2]};
+    launch_bhalf<T>(h->G, F, Bcur, 0.5 * h->cfg.c * h->cfg.dt, h->stream);
+    for (int q = 0; q < 3; q++) launch_zero_u64(F.Jint[q], h->G.gsize(), h->stream);
+}
+
+// Electric step around D^{n+1/2}, then the relaxation layer.
+template <typename T>
+int fields_d(grpic_t *h) {
+    FieldPtrsT<T> &F = fields<T>(h);
+    const grpic_config &c = h->cfg;
+    hipStream_t s = h->stream;
+    int64_t gs = h->G.gsize();
+    TimedGroup tg(h, GRPIC_TIMER_FIELDS);
+    for (int q = 0; q < 3; q++)
+        if (FAILS(hipMemcpyAsync(F.Dsave[q], F.D[q], gs * sizeof(T), hipMemcpyDeviceToDevice, s))) return GRPIC_EDEVICE;
+    const T *Dsave[3] = {F.Dsave[0], F.Dsave[1], F.Dsave[2]};
+    double inv_js = 1.0 / h->jscale;
+    double fpc = 4.0 * M_PI / c.c;
+    for (int it = 0; it < c.field_iters; it++) {
+        launch_derived<T>(h->G, F, true, false, true, s);
+        double dtp = (it < c.field_iters - 1) ? 0.5 * c.dt : c.dt;
+        launch_dstep<T>(h->G, F, Dsave, c.c * dtp, fpc, inv_js, s);
+    }
+    launch_relax<T>(h->G, h->h, F, c.r_damp, c.damp_max, s);
+    return GRPIC_OK;
+}
+
+PushParams push_params(grpic_t *h) {
+    PushParams P;
+    P.G = h->G;
+    P.h = h->h;
+    P.c = h->cfg.c;
+    P.dt = h->cfg.dt;
+    P.gamma_mode = h->cfg.gamma_mode;
+    P.n = h->n_slots;
+    return P;
+}
+
+void push_particles(grpic_t *h) {
+    TimedGroup tg(h, GRPIC_TIMER_PUSH);
+    PushParams P = push_params(h);
+    if (h->mixed)
+        launch_push32(P, h->M, h->S, h->F32.node, pp32(h, h->xc, h->uc), pp32(h, 1 - h->xc, h->uc), h->counters,
+                      h->stream);
+    else
+        launch_push(P, h->S, h->F64.node, pp(h, h->xc, h->uc), pp(h, 1 - h->xc, h->uc), h->counters, h->stream);
+}
+
+void deposit_particles(grpic_t *h) {
+    TimedGroup tg(h, GRPIC_TIMER_DEPOSIT);
+    const grpic_config &c = h->cfg;
+    if (h->mixed)
+        launch_deposit32(h->G, h->h, h->M, c.dt, c.deposit_mode, c.r_rm, h->jscale, h->rscale, h->S,
+                         pp32(h, h->xc, h->uc), pp32(h, 1 - h->xc, h->uc), h->n_slots, h->F32, h->counters,
+                         h->stream);
+    else
+        launch_deposit(h->G, h->h, c.dt, c.deposit_mode, c.r_rm, h->jscale, h->rscale, h->S, pp(h, h->xc, h->uc),
+                       pp(h, 1 - h->xc, h->uc), h->n_slots, h->F64, h->counters, h->stream);
+}
+
 int do_sort(grpic_t *h) {
     TimedGroup tg(h, GRPIC_TIMER_SORT);
-    ParticlePtrs in = pp(h, h->xc, h->uc);
-    ParticlePtrs out = pp(h, 1 - h->xc, 1 - h->uc);
-    launch_sort(h->G, h->cfg.tile, h->n_slots, in, out, h->keys, h->keys_alt, h->idx, h->idx_alt, h->sort_temp,
-                h->sort_temp_bytes, h->key_bits, h->counters, h->stream);
+    if (h->mixed)
+        launch_sort32(h->G, h->cfg.tile, h->n_slots, pp32(h, h->xc, h->uc), pp32(h, 1 - h->xc, 1 - h->uc), h->keys,
+                      h->keys_alt, h->idx, h->idx_alt, h->sort_temp, h->sort_temp_bytes, h->key_bits, h->counters,
+                      h->stream);
+    else
+        launch_sort(h->G, h->cfg.tile, h->n_slots, pp(h, h->xc, h->uc), pp(h, 1 - h->xc, 1 - h->uc), h->keys,
+                    h->keys_alt, h->idx, h->idx_alt, h->sort_temp, h->sort_temp_bytes, h->key_bits, h->counters,
+                    h->stream);
     h->xc = 1 - h->xc;
     h->uc = 1 - h->uc;
     return check(hipGetLastError());
 }
 
-int one_step(grpic_t *h) {
-    const grpic_config &c = h->cfg;
-    FieldPtrs &F = h->F;
-    hipStream_t s = h->stream;
-    const Grid &G = h->G;
-    int64_t gs = G.gsize();
-    double hstep = 0.5 * c.c * c.dt;
-    // magnetic half-step to time n with E_cov^n made consistent with B^n
-    for (int q = 0; q < 3; q++)
-        if (FAILS(hipMemcpyAsync(F.Bsave[q], F.B[q], gs * 8, hipMemcpyDeviceToDevice, s)))
-            return GRPIC_EDEVICE;
-    const double *Bsave[3] = {F.Bsave[0], F.Bsave[1], F.Bsave[2]};
-    {
-        TimedGroup tg(h, GRPIC_TIMER_FIELDS);
-        for (int it = 0; it < c.field_iters; it++) {
-            launch_derived(G, F, true, true, false, s);
-            launch_bhalf(G, F, Bsave, hstep, s);
-        }
-        launch_node_tensor(G, F, s);
-    }
-    // particle push x_n -> x_{n+1}
-    PushParams P;
-    P.G = G;
-    P.h = h->h;
-    P.c = c.c;
-    P.dt = c.dt;
-    P.gamma_mode = c.gamma_mode;
-    P.n = h->n_slots;
-    ParticlePtrs cur = pp(h, h->xc, h->uc);
-    ParticlePtrs nxt = pp(h, 1 - h->xc, h->uc);
-    {
-        TimedGroup tg(h, GRPIC_TIMER_PUSH);
-        launch_push(P, h->S, F.node, cur, nxt, h->counters, s);
-    }
-    // second magnetic half-step with the same E_cov^n
-    const double *Bcur[3] = {F.B[0], F.B[1], F.B[2]};
-    {
-        TimedGroup tg(h, GRPIC_TIMER_FIELDS);
-        launch_bhalf(G, F, Bcur, hstep, s);
-        for (int q = 0; q < 3; q++) launch_zero_u64(F.Jint[q], gs, s);
-    }
-    // current of the chords
-    {
-        TimedGroup tg(h, GRPIC_TIMER_DEPOSIT);
-        launch_deposit(G, h->h, c.dt, c.deposit_mode, c.r_rm, h->jscale, h->rscale, h->S, cur, nxt, h->n_slots, F,
-                       h->counters, s);
-    }
-    // electric step around D^{n+1/2}
-    for (int q = 0; q < 3; q++)
-        if (FAILS(hipMemcpyAsync(F.Dsave[q], F.D[q], gs * 8, hipMemcpyDeviceToDevice, s)))
-            return GRPIC_EDEVICE;
-    const double *Dsave[3] = {F.Dsave[0], F.Dsave[1], F.Dsave[2]};
-    double inv_js = 1.0 / h->jscale;
-    double fpc = 4.0 * M_PI / c.c;
-    {
-        TimedGroup tg(h, GRPIC_TIMER_FIELDS);
-        for (int it = 0; it < c.field_iters; it++) {
-            launch_derived(G, F, true, false, true, s);
-            double dtp = (it < c.field_iters - 1) ? 0.5 * c.dt : c.dt;
-            launch_dstep(G, F, Dsave, c.c * dtp, fpc, inv_js, s);
-        }
-        launch_relax(G, h->h, F, c.r_damp, c.damp_max, s);
-    }
+template <typename T>
+int one_step_t(grpic_t *h) {
+    int rc = fields_to_n<T>(h);
+    if (rc) return rc;
+    push_particles(h);
+    fields_mid<T>(h);
+    deposit_particles(h);
+    rc = fields_d<T>(h);
+    if (rc) return rc;
     h->xc = 1 - h->xc;
     h->step_count++;
-    if (c.sort_every > 0 && h->step_count % c.sort_every == 0) return do_sort(h);
+    if (h->cfg.sort_every > 0 && h->step_count % h->cfg.sort_every == 0) return do_sort(h);
     return check(hipGetLastError());
+}
+
+int one_step(grpic_t *h) { return h->mixed ? one_step_t<float>(h) : one_step_t<double>(h); }
+
+// FP64 view of the particle state (the FP32-mixed form is widened into
+// tmp, which must hold 7 n doubles).
+ParticlePtrs f64_view(grpic_t *h, double *tmp) {
+    if (!h->mixed) return pp(h, h->xc, h->uc);
+    int64_t n = h->n_slots;
+    launch_to_f64(pp32(h, h->xc, h->uc), tmp, tmp + 3 * n, n, h->stream);
+    ParticlePtrs P;
+    for (int q = 0; q < 3; q++) P.x[q] = tmp + q * n;
+    for (int q = 0; q < 4; q++) P.u[q] = tmp + (3 + q) * n;
+    P.sp = h->psp[h->uc];
+    return P;
+}
+
+template <typename T>
+int copy_field_out(grpic_t *h, const T *src, double *out, int64_t count) {
+    if (sizeof(T) == sizeof(double)) {
+        int rc = check(hipMemcpyAsync(out, src, count * 8, hipMemcpyDeviceToHost, h->stream));
+        return rc ? rc : check(hipStreamSynchronize(h->stream));
+    }
+    std::vector<T> tmp(count);
+    int rc = check(hipMemcpyAsync(tmp.data(), src, count * sizeof(T), hipMemcpyDeviceToHost, h->stream));
+    if (!rc) rc = check(hipStreamSynchronize(h->stream));
+    for (int64_t i = 0; i < count && !rc; i++) out[i] = (double)tmp[i];
+    return rc;
+}
+
+template <typename T>
+int copy_field_in(grpic_t *h, T *dst, const double *in, int64_t count) {
+    if (sizeof(T) == sizeof(double)) {
+        int rc = check(hipMemcpyAsync(dst, in, count * 8, hipMemcpyHostToDevice, h->stream));
+        return rc ? rc : check(hipStreamSynchronize(h->stream));
+    }
+    std::vector<T> tmp(count);
+    for (int64_t i = 0; i < count; i++) tmp[i] = (T)in[i];
+    int rc = check(hipMemcpyAsync(dst, tmp.data(), count * sizeof(T), hipMemcpyHostToDevice, h->stream));
+    if (!rc) rc = check(hipStreamSynchronize(h->stream));
+    return rc;
+}
+
+template <typename T>
+int dump_fields_t(grpic_t *h, int which, double *out) {
+    FieldPtrsT<T> &F = fields<T>(h);
+    int64_t gs = h->G.gsize();
+    int rc = GRPIC_OK;
+    if (which == 4) {
+        std::vector<long long> tmp(gs);
+        for (int q = 0; q < 3 && !rc; q++) {
+            rc = check(hipMemcpyAsync(tmp.data(), F.Jint[q], gs * 8, hipMemcpyDeviceToHost, h->stream));
+            if (!rc) rc = check(hipStreamSynchronize(h->stream));
+            for (int64_t i = 0; i < gs && !rc; i++) out[q * gs + i] = (double)tmp[i] / h->jscale;
+        }
+        return rc;
+    }
+    for (int q = 0; q < 3 && !rc; q++) {
+        T *src = which == 0 ? F.D[q] : which == 1 ? F.B[q] : which == 2 ? F.E[q] : F.H[q];
+        rc = copy_field_out<T>(h, src, out + q * gs, gs);
+    }
+    return rc;
+}
+
+template <typename T>
+int restore_fields_t(grpic_t *h, const double *D, const double *B) {
+    FieldPtrsT<T> &F = fields<T>(h);
+    int64_t gs = h->G.gsize();
+    int rc = GRPIC_OK;
+    for (int q = 0; q < 3 && !rc; q++) {
+        rc = copy_field_in<T>(h, F.D[q], D + q * gs, gs);
+        if (!rc) rc = copy_field_in<T>(h, F.B[q], B + q * gs, gs);
+    }
+    return rc;
 }
 
 }  // namespace
@@ -293,7 +482,7 @@ void grpic_destroy(grpic_t *h) {
             (void)hipEventDestroy(pr.first);
             (void)hipEventDestroy(pr.second);
         }
-    for (void *p : h->allocs) dev_free(h, p);
+    for (void *p : h->allocs) raw_free(h, p);
     delete h;
 }
 
@@ -303,10 +492,10 @@ int grpic_create(const grpic_config *cfg, void *stream, grpic_t **out) {
     *out = nullptr;
     int rc = validate(cfg);
     if (rc) return rc;
-    if (cfg->precision != GRPIC_FP64) return GRPIC_EINVAL;  // FP32-mixed lives in its own entry
     grpic_t *h = new (std::nothrow) grpic_s();
     if (!h) return GRPIC_ENOMEM;
     h->cfg = *cfg;
+    h->mixed = cfg->precision == GRPIC_FP32_MIXED;
     h->stream = (hipStream_t)stream;
     h->G.nx = cfg->nx;
     h->G.ny = cfg->ny;
@@ -319,6 +508,8 @@ int grpic_create(const grpic_config *cfg, void *stream, grpic_t **out) {
     h->h.cy = cfg->center[1];
     h->h.cz = cfg->center[2];
     h->h.r_exc = cfg->r_exc;
+    // FP64 metric and Christoffel symbols within 4 m of the horizon
+    h->M.r_fp64 = cfg->m + sqrt(fmax(cfg->m * cfg->m - cfg->a * cfg->a, 0.0)) + 4.0 * cfg->m;
     double qmax = 0.0;
     for (int s = 0; s < kMaxSpecies; s++) {
         bool on = s < cfg->nspecies;
@@ -331,41 +522,25 @@ int grpic_create(const grpic_config *cfg, void *stream, grpic_t **out) {
     h->rscale = ldexp(1.0, cfg->fp_bits) / qmax;
     h->jscale = ldexp(1.0, cfg->fp_bits) * cfg->dt / qmax;
     h->cap = cfg->capacity;
-    h->n_slots = 0;
-    h->xc = h->uc = 0;
 
     const Grid &G = h->G;
     int64_t gs = G.gsize(), nn = G.nnodes();
-    FieldPtrs &F = h->F;
-    bool ok = true;
+    bool ok = h->mixed ? alloc_fields<float>(h, h->F32) : alloc_fields<double>(h, h->F64);
     auto A = [&](size_t bytes) -> void * {
         void *p = dev_alloc(h, bytes);
         if (!p) ok = false;
         return p;
     };
-    for (int c = 0; c < 3; c++) {
-        F.D[c] = (double *)A(gs * 8);
-        F.B[c] = (double *)A(gs * 8);
-        F.E[c] = (double *)A(gs * 8);
-        F.H[c] = (double *)A(gs * 8);
-        F.D0[c] = (double *)A(gs * 8);
-        F.B0[c] = (double *)A(gs * 8);
-        F.E0[c] = (double *)A(gs * 8);
-        F.H0[c] = (double *)A(gs * 8);
-        F.Dsave[c] = (double *)A(gs * 8);
-        F.Bsave[c] = (double *)A(gs * 8);
-        F.Jint[c] = (unsigned long long *)A(gs * 8);
-    }
-    F.rho_abs = (unsigned long long *)A(gs * 8);
-    F.mask = (uint8_t *)A(gs);
-    F.dS = (double *)A(21 * nn * 8);
-    F.gn = (double *)A(10 * nn * 8);
-    F.w = (double *)A(6 * nn * 8);
-    F.node = (double *)A(16 * nn * 8);
     int64_t cap = h->cap > 0 ? h->cap : 1;
     for (int b = 0; b < 2; b++) {
-        for (int q = 0; q < 3; q++) h->px[b][q] = (double *)A(cap * 8);
-        for (int q = 0; q < 4; q++) h->pu[b][q] = (double *)A(cap * 8);
+        if (h->mixed) {
+            h->pcell[b] = (int32_t *)A(cap * 4);
+            for (int q = 0; q < 3; q++) h->poff[b][q] = (float *)A(cap * 4);
+            for (int q = 0; q < 4; q++) h->pu32[b][q] = (float *)A(cap * 4);
+        } else {
+            for (int q = 0; q < 3; q++) h->px[b][q] = (double *)A(cap * 8);
+            for (int q = 0; q < 4; q++) h->pu[b][q] = (double *)A(cap * 8);
+        }
         h->psp[b] = (uint8_t *)A(cap);
     }
     h->counters = (unsigned long long *)A(C_NCOUNTERS * 8);
@@ -392,19 +567,9 @@ int grpic_create(const grpic_config *cfg, void *stream, grpic_t **out) {
     hipStream_t s = h->stream;
     rc = GRPIC_OK;
     if (FAILS(hipMemsetAsync(h->counters, 0, C_NCOUNTERS * 8, s))) rc = GRPIC_EDEVICE;
-    for (int c = 0; c < 3 && !rc; c++) {
-        if (FAILS(hipMemsetAsync(F.E[c], 0, gs * 8, s))) rc = GRPIC_EDEVICE;
-        if (FAILS(hipMemsetAsync(F.H[c], 0, gs * 8, s))) rc = GRPIC_EDEVICE;
-        if (FAILS(hipMemsetAsync(F.Jint[c], 0, gs * 8, s))) rc = GRPIC_EDEVICE;
-    }
-    if (!rc && FAILS(hipMemsetAsync(F.rho_abs, 0, gs * 8, s))) rc = GRPIC_EDEVICE;
     for (int b = 0; b < 2 && !rc; b++)
         if (FAILS(hipMemsetAsync(h->psp[b], GRPIC_DEAD, cap, s))) rc = GRPIC_EDEVICE;
-    if (!rc) {
-        launch_bake(G, h->h, F, s);
-        launch_init_fields(G, h->h, F, cfg->B0, cfg->init_covariant, s);
-        rc = enqueue_field_derivation_reference(h);
-    }
+    if (!rc) rc = h->mixed ? init_fields<float>(h, h->F32) : init_fields<double>(h, h->F64);
     if (!rc) rc = check(hipGetLastError());
     if (!rc) rc = check(hipStreamSynchronize(s));
     if (rc) {
@@ -424,33 +589,27 @@ int grpic_load_particles(grpic_t *h, int32_t species, int64_t n, const double *x
     if (kept) *kept = 0;
     if (n == 0) return GRPIC_OK;
     hipStream_t s = h->stream;
-    double *stage = nullptr;
-    size_t bytes = (size_t)6 * n * 8;
-    if (h->cfg.alloc)
-        stage = (double *)h->cfg.alloc(bytes, h->cfg.alloc_ctx);
-    else if (FAILS(hipMalloc((void **)&stage, bytes)))
-        stage = nullptr;
-    if (!stage) return GRPIC_ENOMEM;
+    Temp stage(h, (size_t)6 * n * 8);
+    if (!stage.p) return GRPIC_ENOMEM;
+    double *st = (double *)stage.p;
     int rc = GRPIC_OK;
     unsigned long long before = 0, after = 0;
-    if (FAILS(hipMemcpyAsync(stage, x, 3 * n * 8, hipMemcpyHostToDevice, s))) rc = GRPIC_EDEVICE;
-    if (!rc && FAILS(hipMemcpyAsync(stage + 3 * n, ucov, 3 * n * 8, hipMemcpyHostToDevice, s)))
-        rc = GRPIC_EDEVICE;
+    if (FAILS(hipMemcpyAsync(st, x, 3 * n * 8, hipMemcpyHostToDevice, s))) rc = GRPIC_EDEVICE;
+    if (!rc && FAILS(hipMemcpyAsync(st + 3 * n, ucov, 3 * n * 8, hipMemcpyHostToDevice, s))) rc = GRPIC_EDEVICE;
     if (!rc && FAILS(hipMemcpyAsync(&before, h->counters + C_LOAD_KEPT, 8, hipMemcpyDeviceToHost, s)))
         rc = GRPIC_EDEVICE;
     if (!rc) {
-        launch_load(h->G, h->h, h->cfg.c, h->cfg.r_rm, stage, stage + 3 * n, n, species, pp(h, h->xc, h->uc),
-                    h->n_slots, h->counters, s);
+        if (h->mixed)
+            launch_load32(h->G, h->h, h->cfg.c, h->cfg.r_rm, st, st + 3 * n, n, species, pp32(h, h->xc, h->uc),
+                          h->n_slots, h->counters, s);
+        else
+            launch_load(h->G, h->h, h->cfg.c, h->cfg.r_rm, st, st + 3 * n, n, species, pp(h, h->xc, h->uc),
+                        h->n_slots, h->counters, s);
         rc = check(hipGetLastError());
     }
     if (!rc && FAILS(hipMemcpyAsync(&after, h->counters + C_LOAD_KEPT, 8, hipMemcpyDeviceToHost, s)))
         rc = GRPIC_EDEVICE;
     if (!rc) rc = check(hipStreamSynchronize(s));
-    if (h->cfg.alloc) {
-        if (h->cfg.free) h->cfg.free(stage, h->cfg.alloc_ctx);
-    } else {
-        (void)hipFree(stage);
-    }
     if (rc) return rc;
     h->n_slots += n;
     if (kept) *kept = (int64_t)(after - before);
@@ -474,16 +633,12 @@ int grpic_step(grpic_t *h, int32_t nsteps) {
 int grpic_push_only(grpic_t *h, int32_t nsteps) {
     clear_foreign_error();
     if (!h || nsteps < 0) return GRPIC_EINVAL;
-    launch_node_tensor(h->G, h->F, h->stream);
+    if (h->mixed)
+        launch_node_tensor<float>(h->G, h->F32, h->stream);
+    else
+        launch_node_tensor<double>(h->G, h->F64, h->stream);
     for (int i = 0; i < nsteps; i++) {
-        PushParams P;
-        P.G = h->G;
-        P.h = h->h;
-        P.c = h->cfg.c;
-        P.dt = h->cfg.dt;
-        P.gamma_mode = h->cfg.gamma_mode;
-        P.n = h->n_slots;
-        launch_push(P, h->S, h->F.node, pp(h, h->xc, h->uc), pp(h, 1 - h->xc, h->uc), h->counters, h->stream);
+        push_particles(h);
         h->xc = 1 - h->xc;
     }
     return check(hipGetLastError());
@@ -500,12 +655,13 @@ int grpic_dump_particles(grpic_t *h, double *x, double *u, uint8_t *sp) {
     if (!h) return GRPIC_EINVAL;
     int64_t n = h->n_slots;
     hipStream_t s = h->stream;
+    Temp tmp(h, h->mixed ? (size_t)7 * (n > 0 ? n : 1) * 8 : 8);
+    if (!tmp.p) return GRPIC_ENOMEM;
+    ParticlePtrs P = f64_view(h, (double *)tmp.p);
     int rc = GRPIC_OK;
-    for (int q = 0; q < 3 && x && !rc; q++)
-        rc = check(hipMemcpyAsync(x + q * n, h->px[h->xc][q], n * 8, hipMemcpyDeviceToHost, s));
-    for (int q = 0; q < 4 && u && !rc; q++)
-        rc = check(hipMemcpyAsync(u + q * n, h->pu[h->uc][q], n * 8, hipMemcpyDeviceToHost, s));
-    if (sp && !rc) rc = check(hipMemcpyAsync(sp, h->psp[h->uc], n, hipMemcpyDeviceToHost, s));
+    for (int q = 0; q < 3 && x && !rc; q++) rc = check(hipMemcpyAsync(x + q * n, P.x[q], n * 8, hipMemcpyDeviceToHost, s));
+    for (int q = 0; q < 4 && u && !rc; q++) rc = check(hipMemcpyAsync(u + q * n, P.u[q], n * 8, hipMemcpyDeviceToHost, s));
+    if (sp && !rc) rc = check(hipMemcpyAsync(sp, P.sp, n, hipMemcpyDeviceToHost, s));
     if (!rc) rc = check(hipStreamSynchronize(s));
     return rc;
 }
@@ -514,10 +670,20 @@ int grpic_restore_particles(grpic_t *h, int64_t n, const double *x, const double
     if (!h || n < 0 || n > h->cap || (n > 0 && (!x || !u || !sp))) return GRPIC_EINVAL;
     hipStream_t s = h->stream;
     int rc = GRPIC_OK;
-    for (int q = 0; q < 3 && !rc; q++)
-        rc = check(hipMemcpyAsync(h->px[h->xc][q], x + q * n, n * 8, hipMemcpyHostToDevice, s));
-    for (int q = 0; q < 4 && !rc; q++)
-        rc = check(hipMemcpyAsync(h->pu[h->uc][q], u + q * n, n * 8, hipMemcpyHostToDevice, s));
+    if (h->mixed) {
+        Temp tmp(h, (size_t)7 * (n > 0 ? n : 1) * 8);
+        if (!tmp.p) return GRPIC_ENOMEM;
+        double *t = (double *)tmp.p;
+        rc = check(hipMemcpyAsync(t, x, 3 * n * 8, hipMemcpyHostToDevice, s));
+        if (!rc) rc = check(hipMemcpyAsync(t + 3 * n, u, 4 * n * 8, hipMemcpyHostToDevice, s));
+        if (!rc) launch_from_f64(t, t + 3 * n, pp32(h, h->xc, h->uc), n, s);
+        if (!rc) rc = check(hipStreamSynchronize(s));
+    } else {
+        for (int q = 0; q < 3 && !rc; q++)
+            rc = check(hipMemcpyAsync(h->px[h->xc][q], x + q * n, n * 8, hipMemcpyHostToDevice, s));
+        for (int q = 0; q < 4 && !rc; q++)
+            rc = check(hipMemcpyAsync(h->pu[h->uc][q], u + q * n, n * 8, hipMemcpyHostToDevice, s));
+    }
     if (!rc) rc = check(hipMemcpyAsync(h->psp[h->uc], sp, n, hipMemcpyHostToDevice, s));
     if (!rc) rc = check(hipStreamSynchronize(s));
     if (!rc) h->n_slots = n;
@@ -528,44 +694,18 @@ int64_t grpic_field_size(const grpic_t *h) { return h ? h->G.gsize() : 0; }
 
 int grpic_dump_fields(grpic_t *h, int32_t which, double *out) {
     if (!h || !out || which < 0 || which > 4) return GRPIC_EINVAL;
-    int64_t gs = h->G.gsize();
-    hipStream_t s = h->stream;
-    int rc = GRPIC_OK;
-    if (which == 4) {
-        std::vector<long long> tmp(gs);
-        for (int q = 0; q < 3 && !rc; q++) {
-            rc = check(hipMemcpyAsync(tmp.data(), h->F.Jint[q], gs * 8, hipMemcpyDeviceToHost, s));
-            if (!rc) rc = check(hipStreamSynchronize(s));
-            for (int64_t i = 0; i < gs && !rc; i++) out[q * gs + i] = (double)tmp[i] / h->jscale;
-        }
-        return rc;
-    }
-    for (int q = 0; q < 3 && !rc; q++) {
-        double *src = which == 0 ? h->F.D[q] : which == 1 ? h->F.B[q] : which == 2 ? h->F.E[q] : h->F.H[q];
-        rc = check(hipMemcpyAsync(out + q * gs, src, gs * 8, hipMemcpyDeviceToHost, s));
-    }
-    if (!rc) rc = check(hipStreamSynchronize(s));
-    return rc;
+    return h->mixed ? dump_fields_t<float>(h, which, out) : dump_fields_t<double>(h, which, out);
 }
 
 int grpic_restore_fields(grpic_t *h, const double *D, const double *B) {
     if (!h || !D || !B) return GRPIC_EINVAL;
-    int64_t gs = h->G.gsize();
-    hipStream_t s = h->stream;
-    int rc = GRPIC_OK;
-    for (int q = 0; q < 3 && !rc; q++) {
-        rc = check(hipMemcpyAsync(h->F.D[q], D + q * gs, gs * 8, hipMemcpyHostToDevice, s));
-        if (!rc) rc = check(hipMemcpyAsync(h->F.B[q], B + q * gs, gs * 8, hipMemcpyHostToDevice, s));
-    }
-    if (!rc) rc = check(hipStreamSynchronize(s));
-    return rc;
+    return h->mixed ? restore_fields_t<float>(h, D, B) : restore_fields_t<double>(h, D, B);
 }
 
 int grpic_dump_nodes(grpic_t *h, double *out) {
     if (!h || !out) return GRPIC_EINVAL;
-    int rc = check(hipMemcpyAsync(out, h->F.node, h->G.nnodes() * 16 * 8, hipMemcpyDeviceToHost, h->stream));
-    if (!rc) rc = check(hipStreamSynchronize(h->stream));
-    return rc;
+    int64_t cnt = h->G.nnodes() * 16;
+    return h->mixed ? copy_field_out<float>(h, h->F32.node, out, cnt) : copy_field_out<double>(h, h->F64.node, out, cnt);
 }
 
 int grpic_sort(grpic_t *h, uint32_t *keys_out, int64_t *perm_out) {
@@ -596,11 +736,22 @@ int grpic_diagnostics(grpic_t *h, grpic_diag *out) {
     if (!h || !out) return GRPIC_EINVAL;
     memset(out, 0, sizeof(*out));
     hipStream_t s = h->stream;
-    // derived fields of the current state (frozen points keep their initial values)
-    launch_derived(h->G, h->F, true, true, true, s);
+    int64_t n = h->n_slots;
+    Temp tmp(h, h->mixed ? (size_t)7 * (n > 0 ? n : 1) * 8 : 8);
+    if (!tmp.p) return GRPIC_ENOMEM;
+    ParticlePtrs P = f64_view(h, (double *)tmp.p);
     DiagOut d;
-    int rc = run_diag(h->G, h->h, h->cfg.c, h->rscale, h->S, pp(h, h->xc, h->uc), h->n_slots, h->F,
-                      h->cfg.r_damp, h->cfg.damp_max, h->rho_scratch, h->red, h->red_cap, d, s);
+    int rc;
+    // derived fields of the current state (frozen points keep their initial values)
+    if (h->mixed) {
+        launch_derived<float>(h->G, h->F32, true, true, true, s);
+        rc = run_diag<float>(h->G, h->h, h->cfg.c, h->rscale, h->S, P, n, h->F32, h->cfg.r_damp, h->cfg.damp_max,
+                             h->rho_scratch, h->red, h->red_cap, d, s);
+    } else {
+        launch_derived<double>(h->G, h->F64, true, true, true, s);
+        rc = run_diag<double>(h->G, h->h, h->cfg.c, h->rscale, h->S, P, n, h->F64, h->cfg.r_damp, h->cfg.damp_max,
+                              h->rho_scratch, h->red, h->red_cap, d, s);
+    }
     if (rc) return GRPIC_EDEVICE;
     unsigned long long cnt[C_NCOUNTERS];
     rc = check(hipMemcpyAsync(cnt, h->counters, sizeof(cnt), hipMemcpyDeviceToHost, s));

@@ -103,7 +103,8 @@ __device__ __forceinline__ bool relaxed_e(const Grid &G, const Hole &h, double r
 // Field sums over index (i,j,k) in [0,n]^3: 0 sum -E_cov D over E points,
 // 1 sum B H over B points, 2 max Gauss residual at checked nodes.
 constexpr int kNVf = 3;
-__global__ __launch_bounds__(kDiagBlock) void k_diag_fields(Grid G, Hole h, FieldPtrs F, double rscale, double r_damp,
+template <typename T>
+__global__ __launch_bounds__(kDiagBlock) void k_diag_fields(Grid G, Hole h, FieldPtrsT<T> F, double rscale, double r_damp,
                                                             double damp_max, const unsigned long long *rho,
                                                             double *out) {
     int64_t nn = G.nnodes();
@@ -116,8 +117,8 @@ __global__ __launch_bounds__(kDiagBlock) void k_diag_fields(Grid G, Hole h, Fiel
         int k = (int)(t / (G.ny + 1));
         int64_t gi = G.g(i, j, k);
         for (int c = 0; c < 3; c++) {
-            if (in_dom(G, 0, c, i, j, k)) v[0] += -F.E[c][gi] * F.D[c][gi];
-            if (in_dom(G, 1, c, i, j, k)) v[1] += F.B[c][gi] * F.H[c][gi];
+            if (in_dom(G, 0, c, i, j, k)) v[0] += -(double)F.E[c][gi] * (double)F.D[c][gi];
+            if (in_dom(G, 1, c, i, j, k)) v[1] += (double)F.B[c][gi] * (double)F.H[c][gi];
         }
         if (i >= 1 && i <= G.nx - 1 && j >= 1 && j <= G.ny - 1 && k >= 1 && k <= G.nz - 1) {
             int64_t st[3] = {1, G.sx, G.sy};
@@ -130,7 +131,7 @@ __global__ __launch_bounds__(kDiagBlock) void k_diag_fields(Grid G, Hole h, Fiel
                 if (relaxed_e(G, h, r_damp, damp_max, c, i, j, k) ||
                     relaxed_e(G, h, r_damp, damp_max, c, im[0], im[1], im[2]))
                     ok = false;
-                div += F.D[c][gi] - F.D[c][gi - st[c]];
+                div += (double)F.D[c][gi] - (double)F.D[c][gi - st[c]];
             }
             if (ok) {
                 double q = ((double)(long long)rho[gi] + (double)(long long)F.rho_abs[gi]) / rscale;
@@ -141,8 +142,9 @@ __global__ __launch_bounds__(kDiagBlock) void k_diag_fields(Grid G, Hole h, Fiel
     block_reduce<kNVf>(v, 1u << 2, out);
 }
 
+template <typename T>
 int run_diag(const Grid &G, const Hole &h, double c, double rscale, const Species &S, ParticlePtrs P, int64_t n,
-             FieldPtrs &F, double r_damp, double damp_max, unsigned long long *rho_scratch, double *red_scratch,
+             FieldPtrsT<T> &F, double r_damp, double damp_max, unsigned long long *rho_scratch, double *red_scratch,
              int64_t red_cap, DiagOut &out, hipStream_t s) {
     int64_t nbp = n > 0 ? (n + kDiagBlock - 1) / kDiagBlock : 0;
     int64_t nbf = (G.nnodes() + kDiagBlock - 1) / kDiagBlock;
@@ -153,7 +155,7 @@ int run_diag(const Grid &G, const Hole &h, double c, double rscale, const Specie
     if (nbp > 0)
         hipLaunchKernelGGL(k_diag_particles, dim3((unsigned)nbp), dim3(kDiagBlock), 0, s, G, h, c, rscale, S, P, n,
                            rho_scratch, pp);
-    hipLaunchKernelGGL(k_diag_fields, dim3((unsigned)nbf), dim3(kDiagBlock), 0, s, G, h, F, rscale, r_damp,
+    hipLaunchKernelGGL(k_diag_fields<T>, dim3((unsigned)nbf), dim3(kDiagBlock), 0, s, G, h, F, rscale, r_damp,
                        damp_max, rho_scratch, pf);
     std::vector<double> hp(nbp * kNVp), hf(nbf * kNVf);
     if (nbp > 0 && hipMemcpyAsync(hp.data(), pp, hp.size() * sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess)
@@ -188,5 +190,12 @@ int run_diag(const Grid &G, const Hole &h, double c, double rscale, const Specie
     out.gauss_max = fa[2];
     return 0;
 }
+
+template int run_diag<double>(const Grid &, const Hole &, double, double, const Species &, ParticlePtrs, int64_t,
+                              FieldPtrsT<double> &, double, double, unsigned long long *, double *, int64_t,
+                              DiagOut &, hipStream_t);
+template int run_diag<float>(const Grid &, const Hole &, double, double, const Species &, ParticlePtrs, int64_t,
+                             FieldPtrsT<float> &, double, double, unsigned long long *, double *, int64_t, DiagOut &,
+                             hipStream_t);
 
 }  // namespace grpic

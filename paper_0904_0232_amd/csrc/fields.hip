@@ -15,7 +15,9 @@
 // with P the average of the six components onto the nodes (1/2 of the two
 // E points along c, 1/4 of the four B points) and P^T its transpose, so the
 // discrete map is symmetric and reduces to Yee's identity at m = 0.
-// (S - I) and g are baked per node once (the metric is stationary).
+// (S - I) and g are baked per node once (the metric is stationary), in FP64,
+// and stored in the field type T: double for the FP64 form, float for the
+// FP32-mixed form (whose field arithmetic is then FP32).
 #include "grpic_dev.h"
 #include "grpic_impl.h"
 
@@ -34,7 +36,8 @@ __device__ __forceinline__ int sym6(int i, int j) {
 // Bake: per node the curvature part dS = S - I of the constitutive map and
 // the covariant metric g (for lowering the node tensor).
 // Variable order v = (D^0, D^1, D^2, B_0, B_1, B_2).
-__global__ void k_bake_nodes(Grid G, Hole h, double *__restrict__ dS, double *__restrict__ gn) {
+template <typename T>
+__global__ void k_bake_nodes(Grid G, Hole h, T *__restrict__ dS, T *__restrict__ gn) {
     int64_t nn = G.nnodes();
     int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (id >= nn) return;
@@ -44,7 +47,7 @@ __global__ void k_bake_nodes(Grid G, Hole h, double *__restrict__ dS, double *__
     int k = (int)(t / (G.ny + 1));
     Sym4 g, gi;
     grid_metric(h, (double)i, (double)j, (double)k, g, gi);
-    for (int q = 0; q < 10; q++) gn[q * nn + id] = g.v[q];
+    for (int q = 0; q < 10; q++) gn[q * nn + id] = (T)g.v[q];
     // M over the pairs: M[A][B] = gi^{mu al} gi^{nu be} - gi^{mu be} gi^{nu al}
     double M[6][6];
     for (int A = 0; A < 6; A++)
@@ -82,7 +85,7 @@ __global__ void k_bake_nodes(Grid G, Hole h, double *__restrict__ dS, double *__
             S[3 + r][3 + c] = s;
         }
     for (int r = 0; r < 6; r++)
-        for (int c = r; c < 6; c++) dS[sym6(r, c) * nn + id] = S[r][c] - (r == c ? 1.0 : 0.0);
+        for (int c = r; c < 6; c++) dS[sym6(r, c) * nn + id] = (T)(S[r][c] - (r == c ? 1.0 : 0.0));
 }
 
 // Update masks: bit c set if E_c at this index is updated, bit 3+c for B_c.
@@ -119,33 +122,35 @@ __global__ void k_masks(Grid G, Hole h, uint8_t *__restrict__ mask) {
 }
 
 // Node averages of the evolved pair.
-__device__ __forceinline__ void node_pair(const Grid &G, const FieldPtrs &F, const double *const D[3],
-                                          const double *const B[3], int i, int j, int k, double v[6]) {
-    v[0] = 0.5 * (D[0][G.g(i - 1, j, k)] + D[0][G.g(i, j, k)]);
-    v[1] = 0.5 * (D[1][G.g(i, j - 1, k)] + D[1][G.g(i, j, k)]);
-    v[2] = 0.5 * (D[2][G.g(i, j, k - 1)] + D[2][G.g(i, j, k)]);
-    v[3] = 0.25 * (B[0][G.g(i, j - 1, k - 1)] + B[0][G.g(i, j, k - 1)] + B[0][G.g(i, j - 1, k)] +
+template <typename T>
+__device__ __forceinline__ void node_pair(const Grid &G, const T *const D[3], const T *const B[3], int i, int j, int k,
+                                          T v[6]) {
+    const T h = (T)0.5, q = (T)0.25;
+    v[0] = h * (D[0][G.g(i - 1, j, k)] + D[0][G.g(i, j, k)]);
+    v[1] = h * (D[1][G.g(i, j - 1, k)] + D[1][G.g(i, j, k)]);
+    v[2] = h * (D[2][G.g(i, j, k - 1)] + D[2][G.g(i, j, k)]);
+    v[3] = q * (B[0][G.g(i, j - 1, k - 1)] + B[0][G.g(i, j, k - 1)] + B[0][G.g(i, j - 1, k)] +
                    B[0][G.g(i, j, k)]);
-    v[4] = 0.25 * (B[1][G.g(i - 1, j, k - 1)] + B[1][G.g(i, j, k - 1)] + B[1][G.g(i - 1, j, k)] +
+    v[4] = q * (B[1][G.g(i - 1, j, k - 1)] + B[1][G.g(i, j, k - 1)] + B[1][G.g(i - 1, j, k)] +
                    B[1][G.g(i, j, k)]);
-    v[5] = 0.25 * (B[2][G.g(i - 1, j - 1, k)] + B[2][G.g(i, j - 1, k)] + B[2][G.g(i - 1, j, k)] +
+    v[5] = q * (B[2][G.g(i - 1, j - 1, k)] + B[2][G.g(i, j - 1, k)] + B[2][G.g(i - 1, j, k)] +
                    B[2][G.g(i, j, k)]);
 }
 
-__device__ __forceinline__ void apply_dS(const double *__restrict__ dS, int64_t nn, int64_t id,
-                                         const double v[6], double w[6]) {
-    for (int r = 0; r < 6; r++) w[r] = 0.0;
+template <typename T>
+__device__ __forceinline__ void apply_dS(const T *__restrict__ dS, int64_t nn, int64_t id, const T v[6], T w[6]) {
+    for (int r = 0; r < 6; r++) w[r] = (T)0;
     for (int r = 0; r < 6; r++)
         for (int c = r; c < 6; c++) {
-            double s = dS[sym6(r, c) * nn + id];
+            T s = dS[sym6(r, c) * nn + id];
             w[r] += s * v[c];
             if (c != r) w[c] += s * v[r];
         }
 }
 
 // w = (S - I) P (D, B) at every node.
-__global__ void k_node_w(Grid G, FieldPtrs F, const double *__restrict__ B0p, const double *__restrict__ B1p,
-                         const double *__restrict__ B2p, double *__restrict__ w) {
+template <typename T>
+__global__ void k_node_w(Grid G, FieldPtrsT<T> F, T *__restrict__ w) {
     int64_t nn = G.nnodes();
     int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (id >= nn) return;
@@ -153,11 +158,11 @@ __global__ void k_node_w(Grid G, FieldPtrs F, const double *__restrict__ B0p, co
     int64_t t = id / (G.nx + 1);
     int j = (int)(t % (G.ny + 1));
     int k = (int)(t / (G.ny + 1));
-    const double *D[3] = {F.D[0], F.D[1], F.D[2]};
-    const double *B[3] = {B0p, B1p, B2p};
-    double v[6], o[6];
-    node_pair(G, F, D, B, i, j, k, v);
-    apply_dS(F.dS, nn, id, v, o);
+    const T *D[3] = {F.D[0], F.D[1], F.D[2]};
+    const T *B[3] = {F.B[0], F.B[1], F.B[2]};
+    T v[6], o[6];
+    node_pair<T>(G, D, B, i, j, k, v);
+    apply_dS<T>(F.dS, nn, id, v, o);
     for (int q = 0; q < 6; q++) w[q * nn + id] = o[q];
 }
 
@@ -173,7 +178,8 @@ __device__ __forceinline__ bool in_domain(const Grid &G, int kind, int c, int i,
 
 // E_cov at every in-domain E point: -(D + P^T w) where updated, else the
 // initial value.  Thread per index (i,j,k) in [0,n]^3, all three components.
-__global__ void k_ecov(Grid G, FieldPtrs F, const double *__restrict__ w, bool use_ref) {
+template <typename T>
+__global__ void k_ecov(Grid G, FieldPtrsT<T> F, const T *__restrict__ w, bool use_ref) {
     int64_t nn = G.nnodes();
     int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (id >= nn) return;
@@ -187,11 +193,11 @@ __global__ void k_ecov(Grid G, FieldPtrs F, const double *__restrict__ w, bool u
     int64_t step[3] = {1, (int64_t)(G.nx + 1), (int64_t)(G.nx + 1) * (G.ny + 1)};
     for (int c = 0; c < 3; c++) {
         if (!in_domain(G, 0, c, i, j, k)) continue;
-        double val;
+        T val;
         if (use_ref && !(mk & (1u << c))) {
             val = F.E0[c][gi];
         } else {
-            double corr = 0.5 * (w[c * nn + n0] + w[c * nn + n0 + step[c]]);
+            T corr = (T)0.5 * (w[c * nn + n0] + w[c * nn + n0 + step[c]]);
             val = -(F.D[c][gi] + corr);
         }
         F.E[c][gi] = val;
@@ -199,7 +205,8 @@ __global__ void k_ecov(Grid G, FieldPtrs F, const double *__restrict__ w, bool u
 }
 
 // H at every in-domain B point: B + P^T w where updated, else the initial value.
-__global__ void k_hfield(Grid G, FieldPtrs F, const double *__restrict__ w, bool use_ref) {
+template <typename T>
+__global__ void k_hfield(Grid G, FieldPtrsT<T> F, const T *__restrict__ w, bool use_ref) {
     int64_t nn = G.nnodes();
     int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (id >= nn) return;
@@ -213,13 +220,13 @@ __global__ void k_hfield(Grid G, FieldPtrs F, const double *__restrict__ w, bool
     int64_t step[3] = {1, (int64_t)(G.nx + 1), (int64_t)(G.nx + 1) * (G.ny + 1)};
     for (int c = 0; c < 3; c++) {
         if (!in_domain(G, 1, c, i, j, k)) continue;
-        double val;
+        T val;
         if (use_ref && !(mk & (1u << (3 + c)))) {
             val = F.H0[c][gi];
         } else {
             int a1 = (c + 1) % 3, a2 = (c + 2) % 3;
-            const double *wc = w + (3 + c) * nn;
-            double corr = 0.25 * (wc[n0] + wc[n0 + step[a1]] + wc[n0 + step[a2]] + wc[n0 + step[a1] + step[a2]]);
+            const T *wc = w + (3 + c) * nn;
+            T corr = (T)0.25 * (wc[n0] + wc[n0 + step[a1]] + wc[n0 + step[a2]] + wc[n0 + step[a1] + step[a2]]);
             val = F.B[c][gi] + corr;
         }
         F.H[c][gi] = val;
@@ -229,8 +236,9 @@ __global__ void k_hfield(Grid G, FieldPtrs F, const double *__restrict__ w, bool
 // Magnetic half-step (Sec. 3.1) for the pair (al, be) of component c:
 //   Bout_c = Bin_c - h [ (E_be(x + e_al) - E_be(x)) - (E_al(x + e_be) - E_al(x)) ],  h = c dt / 2.
 // Points that are not updated copy Bin (when Bin and Bout differ).
-__global__ void k_bhalf(Grid G, FieldPtrs F, const double *__restrict__ Bin0, const double *__restrict__ Bin1,
-                        const double *__restrict__ Bin2, double hstep) {
+template <typename T>
+__global__ void k_bhalf(Grid G, FieldPtrsT<T> F, const T *__restrict__ Bin0, const T *__restrict__ Bin1,
+                        const T *__restrict__ Bin2, T hstep) {
     int64_t nn = G.nnodes();
     int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (id >= nn) return;
@@ -240,15 +248,15 @@ __global__ void k_bhalf(Grid G, FieldPtrs F, const double *__restrict__ Bin0, co
     int k = (int)(t / (G.ny + 1));
     int64_t gi = G.g(i, j, k);
     uint8_t mk = F.mask[gi];
-    const double *Bin[3] = {Bin0, Bin1, Bin2};
+    const T *Bin[3] = {Bin0, Bin1, Bin2};
     int64_t st[3] = {1, G.sx, G.sy};
     for (int c = 0; c < 3; c++) {
         if (!in_domain(G, 1, c, i, j, k)) continue;
-        double b = Bin[c][gi];
+        T b = Bin[c][gi];
         if (mk & (1u << (3 + c))) {
             int al = (c + 1) % 3, be = (c + 2) % 3;
-            double d1 = F.E[be][gi + st[al]] - F.E[be][gi];
-            double d2 = F.E[al][gi + st[be]] - F.E[al][gi];
+            T d1 = F.E[be][gi + st[al]] - F.E[be][gi];
+            T d2 = F.E[al][gi + st[be]] - F.E[al][gi];
             b -= (d1 - d2) * hstep;
         }
         F.B[c][gi] = b;
@@ -259,8 +267,9 @@ __global__ void k_bhalf(Grid G, FieldPtrs F, const double *__restrict__ Bin0, co
 //   Dout_c = Din_c + dx4 [ (4 pi / c) J_c - sum_k d_k F^{c k} ],
 // F^{c,c+1} = H[c+2], F^{c,c+2} = -H[c+1], backward differences; J from the
 // int64 accumulator.
-__global__ void k_dstep(Grid G, FieldPtrs F, const double *__restrict__ Din0, const double *__restrict__ Din1,
-                        const double *__restrict__ Din2, double dx4, double four_pi_over_c, double inv_jscale) {
+template <typename T>
+__global__ void k_dstep(Grid G, FieldPtrsT<T> F, const T *__restrict__ Din0, const T *__restrict__ Din1,
+                        const T *__restrict__ Din2, T dx4, T four_pi_over_c, double inv_jscale) {
     int64_t nn = G.nnodes();
     int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (id >= nn) return;
@@ -270,16 +279,16 @@ __global__ void k_dstep(Grid G, FieldPtrs F, const double *__restrict__ Din0, co
     int k = (int)(t / (G.ny + 1));
     int64_t gi = G.g(i, j, k);
     uint8_t mk = F.mask[gi];
-    const double *Din[3] = {Din0, Din1, Din2};
+    const T *Din[3] = {Din0, Din1, Din2};
     int64_t st[3] = {1, G.sx, G.sy};
     for (int c = 0; c < 3; c++) {
         if (!in_domain(G, 0, c, i, j, k)) continue;
-        double d = Din[c][gi];
+        T d = Din[c][gi];
         if (mk & (1u << c)) {
             int c1 = (c + 1) % 3, c2 = (c + 2) % 3;
             // + d_{c1} H[c2] - d_{c2} H[c1]
-            double div = (F.H[c2][gi] - F.H[c2][gi - st[c1]]) - (F.H[c1][gi] - F.H[c1][gi - st[c2]]);
-            double Jc = (double)(long long)F.Jint[c][gi] * inv_jscale;
+            T div = (F.H[c2][gi] - F.H[c2][gi - st[c1]]) - (F.H[c1][gi] - F.H[c1][gi - st[c2]]);
+            T Jc = (T)((double)(long long)F.Jint[c][gi] * inv_jscale);
             d += dx4 * (four_pi_over_c * Jc - div);
         }
         F.D[c][gi] = d;
@@ -288,7 +297,8 @@ __global__ void k_dstep(Grid G, FieldPtrs F, const double *__restrict__ Din0, co
 
 // Relaxation layer inside the horizon: updated points with r_exc <= r < r_damp
 // move toward their initial values by damp_max ((r_damp - r)/(r_damp - r_exc))^2.
-__global__ void k_relax(Grid G, Hole h, FieldPtrs F, double r_damp, double damp_max, int i0, int j0, int k0,
+template <typename T>
+__global__ void k_relax(Grid G, Hole h, FieldPtrsT<T> F, double r_damp, double damp_max, int i0, int j0, int k0,
                         int bx, int by, int bz) {
     int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     int64_t tot = (int64_t)bx * by * bz;
@@ -309,14 +319,15 @@ __global__ void k_relax(Grid G, Hole h, FieldPtrs F, double r_damp, double damp_
             if (!(r < r_damp)) continue;
             double tt = (r_damp - r) / (r_damp - h.r_exc);
             double sg = damp_max * tt * tt;
-            double *Fp = kind == 0 ? F.D[c] : F.B[c];
-            const double *F0 = kind == 0 ? F.D0[c] : F.B0[c];
-            Fp[gi] -= sg * (Fp[gi] - F0[gi]);
+            T *Fp = kind == 0 ? F.D[c] : F.B[c];
+            const T *F0 = kind == 0 ? F.D0[c] : F.B0[c];
+            Fp[gi] -= (T)sg * (Fp[gi] - F0[gi]);
         }
 }
 
 // Node tensor F^a_b = F^{ag} g_{gb} from the node pair completed by S.
-__global__ void k_node_tensor(Grid G, FieldPtrs F, double *__restrict__ out) {
+template <typename T>
+__global__ void k_node_tensor(Grid G, FieldPtrsT<T> F, T *__restrict__ out) {
     int64_t nn = G.nnodes();
     int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (id >= nn) return;
@@ -324,15 +335,15 @@ __global__ void k_node_tensor(Grid G, FieldPtrs F, double *__restrict__ out) {
     int64_t t = id / (G.nx + 1);
     int j = (int)(t % (G.ny + 1));
     int k = (int)(t / (G.ny + 1));
-    const double *D[3] = {F.D[0], F.D[1], F.D[2]};
-    const double *B[3] = {F.B[0], F.B[1], F.B[2]};
-    double v[6], w[6];
-    node_pair(G, F, D, B, i, j, k, v);
-    apply_dS(F.dS, nn, id, v, w);
+    const T *D[3] = {F.D[0], F.D[1], F.D[2]};
+    const T *B[3] = {F.B[0], F.B[1], F.B[2]};
+    T v[6], w[6];
+    node_pair<T>(G, D, B, i, j, k, v);
+    apply_dS<T>(F.dS, nn, id, v, w);
     // contravariant components: F^{c4} = v_D, F^{s} = v_B + w_B
-    double Fu[4][4];
-    for (int a = 0; a < 4; a++) Fu[a][a] = 0.0;
-    double Hs[3] = {v[3] + w[3], v[4] + w[4], v[5] + w[5]};
+    T Fu[4][4];
+    for (int a = 0; a < 4; a++) Fu[a][a] = (T)0;
+    T Hs[3] = {v[3] + w[3], v[4] + w[4], v[5] + w[5]};
     Fu[1][2] = Hs[0]; Fu[2][1] = -Hs[0];
     Fu[2][0] = Hs[1]; Fu[0][2] = -Hs[1];
     Fu[0][1] = Hs[2]; Fu[1][0] = -Hs[2];
@@ -340,12 +351,12 @@ __global__ void k_node_tensor(Grid G, FieldPtrs F, double *__restrict__ out) {
         Fu[c][3] = v[c];
         Fu[3][c] = -v[c];
     }
-    double g[10];
+    T g[10];
     for (int q = 0; q < 10; q++) g[q] = F.gn[q * nn + id];
-    double *o = out + 16 * id;
+    T *o = out + 16 * id;
     for (int a = 0; a < 4; a++)
         for (int b = 0; b < 4; b++) {
-            double s = 0.0;
+            T s = (T)0;
             for (int c = 0; c < 4; c++) s += Fu[a][c] * g[sym4(c, b)];
             o[a * 4 + b] = s;
         }
@@ -353,7 +364,8 @@ __global__ void k_node_tensor(Grid G, FieldPtrs F, double *__restrict__ out) {
 
 // Initial fields: uniform F (contravariant or covariant B0) lowered/raised
 // with the point metric at every ghosted point.
-__global__ void k_init_fields(Grid G, Hole h, FieldPtrs F, double b0, double b1, double b2, int covariant) {
+template <typename T>
+__global__ void k_init_fields(Grid G, Hole h, FieldPtrsT<T> F, double b0, double b1, double b2, int covariant) {
     int64_t gs = G.gsize();
     int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (id >= gs) return;
@@ -370,52 +382,57 @@ __global__ void k_init_fields(Grid G, Hole h, FieldPtrs F, double b0, double b1,
             double Z = k + ((kind == 0 ? c == 2 : c != 2) ? 0.5 : 0.0);
             Sym4 g, gi;
             grid_metric(h, X, Y, Z, g, gi);
-            const Sym4 &T = covariant ? gi : g;
+            const Sym4 &Mt = covariant ? gi : g;
             int al = kind == 1 ? kPair[c][0] : kPair[3 + c][0];
             int be = kind == 1 ? kPair[c][1] : kPair[3 + c][1];
             double v = 0.0;
             for (int mu = 0; mu < 4; mu++)
-                for (int nu = 0; nu < 4; nu++) v += T.v[sym4(al, mu)] * T.v[sym4(be, nu)] * Fm[mu][nu];
+                for (int nu = 0; nu < 4; nu++) v += Mt.v[sym4(al, mu)] * Mt.v[sym4(be, nu)] * Fm[mu][nu];
             if (kind == 1)
-                F.B[c][id] = covariant ? Bc[c] : v;
+                F.B[c][id] = (T)(covariant ? Bc[c] : v);
             else
-                F.D[c][id] = covariant ? v : 0.0;
+                F.D[c][id] = (T)(covariant ? v : 0.0);
         }
 }
 
 // ---------------------------------------------------------------------------
 static inline unsigned nblk(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
 
-void launch_bake(const Grid &G, const Hole &h, FieldPtrs &F, hipStream_t s) {
-    hipLaunchKernelGGL(k_bake_nodes, dim3(nblk(G.nnodes(), 128)), dim3(128), 0, s, G, h, F.dS, F.gn);
+template <typename T> void launch_bake(const Grid &G, const Hole &h, FieldPtrsT<T> &F, hipStream_t s) {
+    hipLaunchKernelGGL(k_bake_nodes<T>, dim3(nblk(G.nnodes(), 128)), dim3(128), 0, s, G, h, F.dS, F.gn);
     hipLaunchKernelGGL(k_masks, dim3(nblk(G.gsize(), 256)), dim3(256), 0, s, G, h, F.mask);
 }
 
-void launch_init_fields(const Grid &G, const Hole &h, FieldPtrs &F, const double B0[3], int covariant,
+template <typename T>
+void launch_init_fields(const Grid &G, const Hole &h, FieldPtrsT<T> &F, const double B0[3], int covariant,
                         hipStream_t s) {
-    hipLaunchKernelGGL(k_init_fields, dim3(nblk(G.gsize(), 128)), dim3(128), 0, s, G, h, F, B0[0], B0[1],
-                       B0[2], covariant);
+    hipLaunchKernelGGL(k_init_fields<T>, dim3(nblk(G.gsize(), 128)), dim3(128), 0, s, G, h, F, B0[0], B0[1], B0[2],
+                       covariant);
 }
 
-void launch_derived(const Grid &G, FieldPtrs &F, bool use_ref, bool do_e, bool do_h, hipStream_t s) {
+template <typename T>
+void launch_derived(const Grid &G, FieldPtrsT<T> &F, bool use_ref, bool do_e, bool do_h, hipStream_t s) {
     unsigned nb = nblk(G.nnodes(), 256);
-    hipLaunchKernelGGL(k_node_w, dim3(nb), dim3(256), 0, s, G, F, F.B[0], F.B[1], F.B[2], F.w);
-    if (do_e) hipLaunchKernelGGL(k_ecov, dim3(nb), dim3(256), 0, s, G, F, F.w, use_ref);
-    if (do_h) hipLaunchKernelGGL(k_hfield, dim3(nb), dim3(256), 0, s, G, F, F.w, use_ref);
+    hipLaunchKernelGGL(k_node_w<T>, dim3(nb), dim3(256), 0, s, G, F, F.w);
+    if (do_e) hipLaunchKernelGGL(k_ecov<T>, dim3(nb), dim3(256), 0, s, G, F, F.w, use_ref);
+    if (do_h) hipLaunchKernelGGL(k_hfield<T>, dim3(nb), dim3(256), 0, s, G, F, F.w, use_ref);
 }
 
-void launch_bhalf(const Grid &G, FieldPtrs &F, const double *const Bin[3], double hstep, hipStream_t s) {
-    hipLaunchKernelGGL(k_bhalf, dim3(nblk(G.nnodes(), 256)), dim3(256), 0, s, G, F, Bin[0], Bin[1], Bin[2],
-                       hstep);
+template <typename T>
+void launch_bhalf(const Grid &G, FieldPtrsT<T> &F, const T *const Bin[3], double hstep, hipStream_t s) {
+    hipLaunchKernelGGL(k_bhalf<T>, dim3(nblk(G.nnodes(), 256)), dim3(256), 0, s, G, F, Bin[0], Bin[1], Bin[2],
+                       (T)hstep);
 }
 
-void launch_dstep(const Grid &G, FieldPtrs &F, const double *const Din[3], double dx4, double fpc,
-                  double inv_jscale, hipStream_t s) {
-    hipLaunchKernelGGL(k_dstep, dim3(nblk(G.nnodes(), 256)), dim3(256), 0, s, G, F, Din[0], Din[1], Din[2],
-                       dx4, fpc, inv_jscale);
+template <typename T>
+void launch_dstep(const Grid &G, FieldPtrsT<T> &F, const T *const Din[3], double dx4, double fpc, double inv_jscale,
+                  hipStream_t s) {
+    hipLaunchKernelGGL(k_dstep<T>, dim3(nblk(G.nnodes(), 256)), dim3(256), 0, s, G, F, Din[0], Din[1], Din[2],
+                       (T)dx4, (T)fpc, inv_jscale);
 }
 
-void launch_relax(const Grid &G, const Hole &h, FieldPtrs &F, double r_damp, double damp_max, hipStream_t s) {
+template <typename T>
+void launch_relax(const Grid &G, const Hole &h, FieldPtrsT<T> &F, double r_damp, double damp_max, hipStream_t s) {
     if (!(r_damp > h.r_exc) || !(damp_max > 0.0) || h.m == 0.0) return;
     // bounding box of the oblate region r < r_damp: |x|,|y| <= sqrt(r^2+a^2), |z| <= r
     double ext_xy = sqrt(r_damp * r_damp + h.a * h.a) + 1.0, ext_z = r_damp + 1.0;
@@ -426,12 +443,25 @@ void launch_relax(const Grid &G, const Hole &h, FieldPtrs &F, double r_damp, dou
     i1 = i1 > G.nx ? G.nx : i1; j1 = j1 > G.ny ? G.ny : j1; k1 = k1 > G.nz ? G.nz : k1;
     if (i1 < i0 || j1 < j0 || k1 < k0) return;
     int bx = i1 - i0 + 1, by = j1 - j0 + 1, bz = k1 - k0 + 1;
-    hipLaunchKernelGGL(k_relax, dim3(nblk((int64_t)bx * by * bz, 128)), dim3(128), 0, s, G, h, F, r_damp,
+    hipLaunchKernelGGL(k_relax<T>, dim3(nblk((int64_t)bx * by * bz, 128)), dim3(128), 0, s, G, h, F, r_damp,
                        damp_max, i0, j0, k0, bx, by, bz);
 }
 
-void launch_node_tensor(const Grid &G, FieldPtrs &F, hipStream_t s) {
-    hipLaunchKernelGGL(k_node_tensor, dim3(nblk(G.nnodes(), 128)), dim3(128), 0, s, G, F, F.node);
+template <typename T> void launch_node_tensor(const Grid &G, FieldPtrsT<T> &F, hipStream_t s) {
+    hipLaunchKernelGGL(k_node_tensor<T>, dim3(nblk(G.nnodes(), 128)), dim3(128), 0, s, G, F, F.node);
 }
+
+#define GRPIC_FIELD_INSTANTIATE(T)                                                                          \
+    template void launch_bake<T>(const Grid &, const Hole &, FieldPtrsT<T> &, hipStream_t);                 \
+    template void launch_init_fields<T>(const Grid &, const Hole &, FieldPtrsT<T> &, const double *, int,   \
+                                        hipStream_t);                                                       \
+    template void launch_derived<T>(const Grid &, FieldPtrsT<T> &, bool, bool, bool, hipStream_t);          \
+    template void launch_bhalf<T>(const Grid &, FieldPtrsT<T> &, const T *const *, double, hipStream_t);    \
+    template void launch_dstep<T>(const Grid &, FieldPtrsT<T> &, const T *const *, double, double, double,  \
+                                  hipStream_t);                                                             \
+    template void launch_relax<T>(const Grid &, const Hole &, FieldPtrsT<T> &, double, double, hipStream_t); \
+    template void launch_node_tensor<T>(const Grid &, FieldPtrsT<T> &, hipStream_t);
+GRPIC_FIELD_INSTANTIATE(double)
+GRPIC_FIELD_INSTANTIATE(float)
 
 }  // namespace grpic

@@ -116,37 +116,41 @@ __device__ __forceinline__ bool grid_excised(const Hole &h, double X, double Y, 
     return ks_radius(h.a, X - h.cx, Y - h.cy, Z - h.cz) < h.r_exc;
 }
 
-// Kerr-Schild point with the gradients the pusher needs:
+// Kerr-Schild point with the gradients the pusher needs, in type T, from a
+// radius r already solved (in FP64):
 //   d_i r = x_i r^3/(r^4+a^2 z^2) (x, y),  z r (r^2+a^2)/(r^4+a^2 z^2) (z);
 //   d_i f = f (3 d_i r / r - d_i S4 / S4),  S4 = r^4 + a^2 z^2;
 //   dk[j][i] = d_i k_j.
-struct KSGrad {
-    double r, f, k[3];
-    double df[3];
-    double dk[3][3];
+template <typename T>
+struct KSGradT {
+    T r, f, k[3];
+    T df[3];
+    T dk[3][3];
 };
+using KSGrad = KSGradT<double>;
 
-__device__ __forceinline__ void ks_grad(double m, double a, double x, double y, double z, KSGrad &o) {
-    double r = ks_radius(a, x, y, z);
-    double rr = r * r;
-    double a2 = a * a;
-    double S4 = rr * rr + a2 * z * z;
-    double iS4 = 1.0 / S4;
-    double iden = 1.0 / (rr + a2);
-    double ir = 1.0 / r;
-    double f = 2.0 * m * r * rr * iS4;
-    double k0 = (r * x - a * y) * iden;
-    double k1 = (r * y + a * x) * iden;
-    double k2 = z * ir;
-    double c = r * rr * iS4;
-    double dr[3] = {x * c, y * c, z * r * (rr + a2) * iS4};
-    double f3r = 3.0 * f * ir;
-    double f4 = 4.0 * f * rr * r * iS4;
+template <typename T>
+__device__ __forceinline__ void ks_grad_r(T m, T a, T x, T y, T z, T r, KSGradT<T> &o) {
+    const T one = (T)1;
+    T rr = r * r;
+    T a2 = a * a;
+    T S4 = rr * rr + a2 * z * z;
+    T iS4 = one / S4;
+    T iden = one / (rr + a2);
+    T ir = one / r;
+    T f = (T)2 * m * r * rr * iS4;
+    T k0 = (r * x - a * y) * iden;
+    T k1 = (r * y + a * x) * iden;
+    T k2 = z * ir;
+    T c = r * rr * iS4;
+    T dr[3] = {x * c, y * c, z * r * (rr + a2) * iS4};
+    T f3r = (T)3 * f * ir;
+    T f4 = (T)4 * f * rr * r * iS4;
     for (int i = 0; i < 3; i++) o.df[i] = (f3r - f4) * dr[i];
-    o.df[2] -= f * 2.0 * a2 * z * iS4;
-    double two_r = 2.0 * r;
+    o.df[2] -= f * (T)2 * a2 * z * iS4;
+    T two_r = (T)2 * r;
     for (int i = 0; i < 3; i++) {
-        double dd = two_r * dr[i];
+        T dd = two_r * dr[i];
         o.dk[0][i] = (dr[i] * x - k0 * dd) * iden;
         o.dk[1][i] = (dr[i] * y - k1 * dd) * iden;
         o.dk[2][i] = -k2 * dr[i] * ir;
@@ -163,27 +167,32 @@ __device__ __forceinline__ void ks_grad(double m, double a, double x, double y, 
     o.k[2] = k2;
 }
 
+__device__ __forceinline__ void ks_grad(double m, double a, double x, double y, double z, KSGrad &o) {
+    ks_grad_r<double>(m, a, x, y, z, ks_radius(a, x, y, z), o);
+}
+
 // G^a = Gamma^a_{mn} u^m u^n for g = eta + f k k (stationary, k_4 = 1):
 //   G_b = s (Df k_b + f Dk_b) + f q k_b - s^2/2 d_b f - f s w_b   (b spatial)
 //   G_4 = s Df + f q
 // with s = k.u, D = u^i d_i, Dk_j = u^i d_i k_j, q = u^j Dk_j,
 // w_b = u^j d_b k_j, then G^a = g^{ab} G_b = eta^{ab} G_b - f k^a (k^b G_b).
-__device__ __forceinline__ void gamma_uu(const KSGrad &p, const double u[4], double G[4]) {
-    const double f = p.f;
-    double s = p.k[0] * u[0] + p.k[1] * u[1] + p.k[2] * u[2] + u[3];
-    double Df = p.df[0] * u[0] + p.df[1] * u[1] + p.df[2] * u[2];
-    double Dk[3], w[3];
+template <typename T>
+__device__ __forceinline__ void gamma_uu(const KSGradT<T> &p, const T u[4], T G[4]) {
+    const T f = p.f;
+    T s = p.k[0] * u[0] + p.k[1] * u[1] + p.k[2] * u[2] + u[3];
+    T Df = p.df[0] * u[0] + p.df[1] * u[1] + p.df[2] * u[2];
+    T Dk[3], w[3];
     for (int j = 0; j < 3; j++) Dk[j] = p.dk[j][0] * u[0] + p.dk[j][1] * u[1] + p.dk[j][2] * u[2];
     for (int b = 0; b < 3; b++) w[b] = p.dk[0][b] * u[0] + p.dk[1][b] * u[1] + p.dk[2][b] * u[2];
-    double q = Dk[0] * u[0] + Dk[1] * u[1] + Dk[2] * u[2];
-    double Gl[4];
-    double hs2 = 0.5 * s * s;
-    double fs = f * s;
-    double sDf_fq = s * Df + f * q;
+    T q = Dk[0] * u[0] + Dk[1] * u[1] + Dk[2] * u[2];
+    T Gl[4];
+    T hs2 = (T)0.5 * s * s;
+    T fs = f * s;
+    T sDf_fq = s * Df + f * q;
     for (int b = 0; b < 3; b++) Gl[b] = sDf_fq * p.k[b] + fs * Dk[b] - hs2 * p.df[b] - fs * w[b];
     Gl[3] = sDf_fq;
-    double kG = p.k[0] * Gl[0] + p.k[1] * Gl[1] + p.k[2] * Gl[2] - Gl[3];
-    double fkG = f * kG;
+    T kG = p.k[0] * Gl[0] + p.k[1] * Gl[1] + p.k[2] * Gl[2] - Gl[3];
+    T fkG = f * kG;
     G[0] = Gl[0] - fkG * p.k[0];
     G[1] = Gl[1] - fkG * p.k[1];
     G[2] = Gl[2] - fkG * p.k[2];

@@ -7,22 +7,44 @@
 
 namespace grpic {
 
-// Device pointers of the field state (FP64).  Every array of a staggered
+// Device pointers of the field state, stored in T (double for the FP64
+// form, float for the FP32-mixed form).  Every array of a staggered
 // component has Grid::gsize() entries; node arrays have Grid::nnodes().
-struct FieldPtrs {
-    double *D[3], *B[3];    // evolved: F^{c4} at E points, covariant pairs at B points
-    double *E[3], *H[3];    // derived: F_{c4} at E points, contravariant pairs at B points
-    double *D0[3], *B0[3];  // initial evolved values (frozen points, relaxation target)
-    double *E0[3], *H0[3];  // initial derived values (frozen points)
-    double *Dsave[3], *Bsave[3];  // D^n and B^{n-1/2} during the fixed-point passes
+template <typename T>
+struct FieldPtrsT {
+    T *D[3], *B[3];         // evolved: F^{c4} at E points, covariant pairs at B points
+    T *E[3], *H[3];         // derived: F_{c4} at E points, contravariant pairs at B points
+    T *D0[3], *B0[3];       // initial evolved values (frozen points, relaxation target)
+    T *E0[3], *H0[3];       // initial derived values (frozen points)
+    T *Dsave[3], *Bsave[3]; // D^n and B^{n-1/2} during the fixed-point passes
     unsigned long long *Jint[3];  // int64 fixed-point current on E points
     unsigned long long *rho_abs;  // int64 fixed-point charge removed at the horizon (nodes, ghosted)
     uint8_t *mask;          // update bits per ghosted index
-    double *dS;             // [21][nnodes] packed S - I
-    double *gn;             // [10][nnodes] packed g_ab
-    double *w;              // [6][nnodes] scratch (S - I) P v
-    double *node;           // [nnodes][16] mixed tensor F^a_b
+    T *dS;                  // [21][nnodes] packed S - I
+    T *gn;                  // [10][nnodes] packed g_ab
+    T *w;                   // [6][nnodes] scratch (S - I) P v
+    T *node;                // [nnodes][16] mixed tensor F^a_b
 };
+using FieldPtrs = FieldPtrsT<double>;
+
+// FP32-mixed particle storage: packed cell (i+1) | (j+1) << 10 | (k+1) << 20,
+// FP32 offset inside the cell, FP32 contravariant four-velocity.
+struct ParticlePtrs32 {
+    int32_t *cell;
+    float *off[3];
+    float *u[4];
+    uint8_t *sp;
+};
+
+__host__ __device__ inline int32_t pack_cell(int i, int j, int k) {
+    return (int32_t)((uint32_t)(i + 1) | ((uint32_t)(j + 1) << 10) | ((uint32_t)(k + 1) << 20));
+}
+__host__ __device__ inline void unpack_cell(int32_t c, int &i, int &j, int &k) {
+    uint32_t u = (uint32_t)c;
+    i = (int)(u & 1023u) - 1;
+    j = (int)((u >> 10) & 1023u) - 1;
+    k = (int)((u >> 20) & 1023u) - 1;
+}
 
 // FP64 particle storage (SoA), two buffers for the sort and for x_n/x_{n+1}.
 struct ParticlePtrs {
@@ -57,16 +79,21 @@ struct PushParams {
     int64_t n;  // slots to process
 };
 
-// field kernels
-void launch_bake(const Grid &G, const Hole &h, FieldPtrs &F, hipStream_t s);
-void launch_init_fields(const Grid &G, const Hole &h, FieldPtrs &F, const double B0[3], int covariant,
+// field kernels (T = double or float)
+template <typename T> void launch_bake(const Grid &G, const Hole &h, FieldPtrsT<T> &F, hipStream_t s);
+template <typename T>
+void launch_init_fields(const Grid &G, const Hole &h, FieldPtrsT<T> &F, const double B0[3], int covariant,
                         hipStream_t s);
-void launch_derived(const Grid &G, FieldPtrs &F, bool use_ref, bool do_e, bool do_h, hipStream_t s);
-void launch_bhalf(const Grid &G, FieldPtrs &F, const double *const Bin[3], double hstep, hipStream_t s);
-void launch_dstep(const Grid &G, FieldPtrs &F, const double *const Din[3], double dx4, double fpc,
+template <typename T>
+void launch_derived(const Grid &G, FieldPtrsT<T> &F, bool use_ref, bool do_e, bool do_h, hipStream_t s);
+template <typename T>
+void launch_bhalf(const Grid &G, FieldPtrsT<T> &F, const T *const Bin[3], double hstep, hipStream_t s);
+template <typename T>
+void launch_dstep(const Grid &G, FieldPtrsT<T> &F, const T *const Din[3], double dx4, double fpc,
                   double inv_jscale, hipStream_t s);
-void launch_relax(const Grid &G, const Hole &h, FieldPtrs &F, double r_damp, double damp_max, hipStream_t s);
-void launch_node_tensor(const Grid &G, FieldPtrs &F, hipStream_t s);
+template <typename T>
+void launch_relax(const Grid &G, const Hole &h, FieldPtrsT<T> &F, double r_damp, double damp_max, hipStream_t s);
+template <typename T> void launch_node_tensor(const Grid &G, FieldPtrsT<T> &F, hipStream_t s);
 
 // particle kernels
 void launch_push(const PushParams &P, const Species &S, const double *node, ParticlePtrs in, ParticlePtrs out,
@@ -79,19 +106,39 @@ void launch_load(const Grid &G, const Hole &h, double c, double r_rm, const doub
                  hipStream_t s);
 void launch_zero_u64(unsigned long long *p, int64_t n, hipStream_t s);
 
+// FP32-mixed particle kernels
+struct Mixed {
+    double r_fp64;  // metric and Christoffel symbols in FP64 when r < r_fp64
+};
+void launch_push32(const PushParams &P, const Mixed &M, const Species &S, const float *node, ParticlePtrs32 in,
+                   ParticlePtrs32 out, unsigned long long *counters, hipStream_t s);
+void launch_deposit32(const Grid &G, const Hole &h, const Mixed &M, double dt, int deposit_mode, double r_rm,
+                      double jscale, double rscale, const Species &S, ParticlePtrs32 xold, ParticlePtrs32 xnew,
+                      int64_t n, FieldPtrsT<float> &F, unsigned long long *counters, hipStream_t s);
+void launch_load32(const Grid &G, const Hole &h, double c, double r_rm, const double *xin, const double *ucin,
+                   int64_t n, int species, ParticlePtrs32 out, int64_t offset, unsigned long long *counters,
+                   hipStream_t s);
+void launch_to_f64(ParticlePtrs32 in, double *x, double *u, int64_t n, hipStream_t s);
+void launch_from_f64(const double *x, const double *u, ParticlePtrs32 out, int64_t n, hipStream_t s);
+
 // sort
 size_t sort_temp_bytes(int64_t capacity);
 void launch_sort(const Grid &G, int tile, int64_t n, ParticlePtrs in, ParticlePtrs out, uint32_t *keys,
                  uint32_t *keys_alt, uint32_t *idx, uint32_t *idx_alt, void *temp, size_t temp_bytes,
                  int key_bits, unsigned long long *counters, hipStream_t s);
+void launch_sort32(const Grid &G, int tile, int64_t n, ParticlePtrs32 in, ParticlePtrs32 out, uint32_t *keys,
+                   uint32_t *keys_alt, uint32_t *idx, uint32_t *idx_alt, void *temp, size_t temp_bytes,
+                   int key_bits, unsigned long long *counters, hipStream_t s);
 
 // diagnostics: fills host-side partial sums (see diag.hip)
 struct DiagOut {
     int64_t n_alive[kMaxSpecies];
     double charge_total, energy_particles, lz_particles, energy_field, gauss_max, shell_max;
 };
+// P: FP64 particle view (the FP32-mixed form is widened into scratch first)
+template <typename T>
 int run_diag(const Grid &G, const Hole &h, double c, double rscale, const Species &S, ParticlePtrs P, int64_t n,
-             FieldPtrs &F, double r_damp, double damp_max, unsigned long long *rho_scratch, double *red_scratch,
+             FieldPtrsT<T> &F, double r_damp, double damp_max, unsigned long long *rho_scratch, double *red_scratch,
              int64_t red_cap, DiagOut &out, hipStream_t s);
 
 }  // namespace grpic

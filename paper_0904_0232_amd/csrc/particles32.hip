@@ -1,0 +1,557 @@
+// FP32-mixed particle kernels.  A particle is a packed int32 cell
+// (i+1 | (j+1) << 10 | (k+1) << 20), an FP32 offset inside that cell and an
+// FP32 contravariant four-velocity: 32 bytes plus the species byte.
+// Gather, Lorentz term, RK4 stages and deposition weights run in FP32 on
+// offsets relative to the particle's cell (so the position error does not
+// grow with the grid size); the radius quartic is always solved in FP64 from
+// the exact cell + offset, and within r_fp64 (r_+ + 4 m) of the hole the
+// metric gradients and the Christoffel contraction are evaluated in FP64.
+#include "grpic_dev.h"
+#include "grpic_impl.h"
+
+namespace grpic {
+
+__device__ __forceinline__ void hole_rel(const Hole &h, int i, int j, int k, const float X[3], double &x, double &y,
+                                         double &z) {
+    x = ((double)i - h.cx) + (double)X[0];
+    y = ((double)j - h.cy) + (double)X[1];
+    z = ((double)k - h.cz) + (double)X[2];
+}
+
+// L^a = F^a_b u^b gathered from the FP32 node tensor; X is the offset
+// relative to cell (i,j,k) and may leave [0,1) by up to a cell.
+__device__ __forceinline__ void gather_lorentz32(const Grid &G, const float *__restrict__ node, int i, int j, int k,
+                                                 const float X[3], const float U[4], float L[4]) {
+    const int base[3] = {i, j, k};
+    int c[3];
+    float w[3];
+    for (int ax = 0; ax < 3; ax++) {
+        int n = G.dim(ax);
+        float fl = floorf(X[ax]);
+        int ci = base[ax] + (int)fl;
+        ci = ci < 0 ? 0 : (ci > n - 1 ? n - 1 : ci);
+        c[ax] = ci;
+        w[ax] = (float)(base[ax] - ci) + X[ax];
+    }
+    L[0] = L[1] = L[2] = L[3] = 0.0f;
+    const int64_t sj = G.nx + 1, sk = (int64_t)(G.nx + 1) * (G.ny + 1);
+    const float *b0 = node + 16 * G.node(c[0], c[1], c[2]);
+#pragma unroll 1
+    for (int q = 0; q < 4; q++) {
+        const int dj = q & 1, dk = q >> 1;
+        const float wyz = (dj ? w[1] : 1.0f - w[1]) * (dk ? w[2] : 1.0f - w[2]);
+        const float4 *p = reinterpret_cast<const float4 *>(b0 + 16 * (dj * sj + dk * sk));
+#pragma unroll
+        for (int di = 0; di < 2; di++) {
+            const float W = (di ? w[0] : 1.0f - w[0]) * wyz;
+#pragma unroll
+            for (int a = 0; a < 4; a++) {
+                float4 f = p[4 * di + a];
+                float row = f.x * U[0] + f.y * U[1] + f.z * U[2] + f.w * U[3];
+                L[a] += W * row;
+            }
+        }
+    }
+}
+
+__device__ __forceinline__ void accel32(const PushParams &P, const Mixed &M, const float *__restrict__ node, float qm,
+                                        int i, int j, int k, const float X[3], const float U[4], float A[4]) {
+    float L[4];
+    gather_lorentz32(P.G, node, i, j, k, X, U, L);
+    float Gm[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+    if (P.h.m != 0.0) {
+        double x, y, z;
+        hole_rel(P.h, i, j, k, X, x, y, z);
+        double r = ks_radius(P.h.a, x, y, z);
+        if (r < M.r_fp64) {
+            KSGradT<double> kp;
+            ks_grad_r<double>(P.h.m, P.h.a, x, y, z, r, kp);
+            double Ud[4] = {U[0], U[1], U[2], U[3]}, Gd[4];
+            gamma_uu<double>(kp, Ud, Gd);
+            for (int a = 0; a < 4; a++) Gm[a] = (float)Gd[a];
+        } else {
+            KSGradT<float> kp;
+            ks_grad_r<float>((float)P.h.m, (float)P.h.a, (float)x, (float)y, (float)z, (float)r, kp);
+            gamma_uu<float>(kp, U, Gm);
+        }
+    }
+#pragma unroll
+    for (int a = 0; a < 4; a++) A[a] = qm * L[a] - Gm[a];
+}
+
+__device__ __forceinline__ float stage_gamma32(const PushParams &P, float u4, float a4, int &clamps) {
+    const float c = (float)P.c;
+    float uc = u4 / c;
+    if (P.gamma_mode == 1) return uc;
+    float disc = uc * uc + 4.0f * a4 * (float)(P.dt / (2.0 * P.c));
+    if (disc < 0.0f) {
+        disc = 0.0f;
+        clamps++;
+    }
+    return 0.5f * (uc + sqrtf(disc));
+}
+
+// The same RK4 in coordinate time as the FP64 pusher, on offsets relative
+// to the particle's cell; the cell is re-based after the step.
+__global__ __launch_bounds__(256, 4) void k_push32(PushParams P, Mixed M, Species cS, const float *__restrict__ node,
+                                                   ParticlePtrs32 in, ParticlePtrs32 out,
+                                                   unsigned long long *counters) {
+    int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int clamps = 0;
+    uint8_t sp = id < P.n ? in.sp[id] : kDead;
+    unsigned long long live = __ballot(sp != kDead);
+    if ((threadIdx.x & 63) == 0 && live) atomicAdd(&counters[C_PUSHED], (unsigned long long)__popcll(live));
+    if (sp != kDead) {
+        const float qm = (float)cS.qm[sp];
+        int i, j, k;
+        unpack_cell(in.cell[id], i, j, k);
+        float X0[3] = {in.off[0][id], in.off[1][id], in.off[2][id]};
+        float U0[4] = {in.u[0][id], in.u[1][id], in.u[2][id], in.u[3][id]};
+        float Xs[3] = {X0[0], X0[1], X0[2]};
+        float Us[4] = {U0[0], U0[1], U0[2], U0[3]};
+        float Sx[3] = {0.0f, 0.0f, 0.0f}, Su[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+        const float dt = (float)P.dt;
+#pragma unroll 1
+        for (int st = 0; st < 4; st++) {
+            float A[4];
+            accel32(P, M, node, qm, i, j, k, Xs, Us, A);
+            float gam = stage_gamma32(P, Us[3], A[3], clamps);
+            float ig = 1.0f / gam;
+            float Kx[3] = {Us[0] * ig, Us[1] * ig, Us[2] * ig};
+            float Ku[4] = {A[0] * ig, A[1] * ig, A[2] * ig, A[3] * ig};
+            float wgt = (st == 0 || st == 3) ? 1.0f : 2.0f;
+            for (int q = 0; q < 3; q++) Sx[q] += wgt * Kx[q];
+            for (int q = 0; q < 4; q++) Su[q] += wgt * Ku[q];
+            if (st < 3) {
+                float fac = (st < 2 ? 0.5f : 1.0f) * dt;
+                for (int q = 0; q < 3; q++) Xs[q] = X0[q] + fac * Kx[q];
+                for (int q = 0; q < 4; q++) Us[q] = U0[q] + fac * Ku[q];
+            }
+        }
+        const float h6 = (float)(P.dt / 6.0);
+        int cc[3] = {i, j, k};
+        for (int q = 0; q < 3; q++) {
+            float xo = X0[q] + h6 * Sx[q];
+            float fl = floorf(xo);
+            int nc = cc[q] + (int)fl;
+            // a cell outside the ghost layer cannot be packed; the particle is
+            // removed as outside by the deposition kernel either way
+            nc = nc < -1 ? -1 : (nc > 1022 ? 1022 : nc);
+            xo -= fl;
+            cc[q] = nc;
+            out.off[q][id] = xo;
+        }
+        out.cell[id] = pack_cell(cc[0], cc[1], cc[2]);
+        for (int q = 0; q < 4; q++) out.u[q][id] = U0[q] + h6 * Su[q];
+    }
+    if (clamps) atomicAdd(&counters[C_GAMMA_CLAMPS], (unsigned long long)clamps);
+}
+
+void launch_push32(const PushParams &P, const Mixed &M, const Species &S, const float *node, ParticlePtrs32 in,
+                   ParticlePtrs32 out, unsigned long long *counters, hipStream_t s) {
+    if (P.n <= 0) return;
+    unsigned nb = (unsigned)((P.n + 255) / 256);
+    hipLaunchKernelGGL(k_push32, dim3(nb), dim3(256), 0, s, P, M, S, node, in, out, counters);
+}
+
+// ---------------------------------------------------------------------------
+// Deposition in FP32 coordinates local to the old cell (Sec. 4, same zigzag
+// and weights as the FP64 kernel), int64 fixed-point accumulation.
+
+struct Dep32 {
+    Grid G;
+    Hole h;
+    double r_fp64;
+    float inv_dt;
+    double jscale;
+    int curved;
+};
+
+// Area density sqrt(1 + f (1 - k_K^2)) at a point given as cell + local offset.
+__device__ __forceinline__ float area_density32(const Dep32 &D, int K, const int base[3], const float P3[3]) {
+    if (D.h.m == 0.0) return 1.0f;
+    double x = ((double)base[0] - D.h.cx) + (double)P3[0];
+    double y = ((double)base[1] - D.h.cy) + (double)P3[1];
+    double z = ((double)base[2] - D.h.cz) + (double)P3[2];
+    double a = D.h.a;
+    double r = ks_radius(a, x, y, z);
+    if (r < D.h.r_exc) return 1.0f;
+    if (r < D.r_fp64) {
+        double rr = r * r;
+        double f = 2.0 * D.h.m * r * rr / (rr * rr + a * a * z * z);
+        double kK = K == 0 ? (r * x - a * y) / (rr + a * a) : (K == 1 ? (r * y + a * x) / (rr + a * a) : z / r);
+        return (float)sqrt(1.0 + f * (1.0 - kK * kK));
+    }
+    float rf = (float)r, af = (float)a, xf = (float)x, yf = (float)y, zf = (float)z;
+    float rr = rf * rf;
+    float f = 2.0f * (float)D.h.m * rf * rr / (rr * rr + af * af * zf * zf);
+    float kK = K == 0 ? (rf * xf - af * yf) / (rr + af * af) : (K == 1 ? (rf * yf + af * xf) / (rr + af * af) : zf / rf);
+    return sqrtf(1.0f + f * (1.0f - kK * kK));
+}
+
+struct GlobalAcc32 {
+    unsigned long long *J[3];
+    Grid G;
+    __device__ __forceinline__ void add(int K, int i, int j, int k, long long v) const {
+        atomicAdd(&J[K][G.g(i, j, k)], (unsigned long long)v);
+    }
+};
+
+struct LdsAcc32 {
+    unsigned long long *sm;
+    int lo0, lo1, lo2, bx, by, V;
+    __device__ __forceinline__ void add(int K, int i, int j, int k, long long v) const {
+        atomicAdd(&sm[K * V + ((k - lo2) * by + (j - lo1)) * bx + (i - lo0)], (unsigned long long)v);
+    }
+};
+
+// One segment A -> B, local to cell `base` + `cell` (cell relative to base).
+template <typename Acc>
+__device__ __forceinline__ void dep_segment32(const Dep32 &D, const Acc &acc, const int base[3], const float A[3],
+                                              const float B[3], const int cell[3], float Q) {
+    float d[3], mid[3];
+    for (int ax = 0; ax < 3; ax++) {
+        d[ax] = B[ax] - A[ax];
+        mid[ax] = 0.5f * (A[ax] + B[ax]);
+    }
+#pragma unroll
+    for (int K = 0; K < 3; K++) {
+        const int I = (K + 1) % 3, J = (K + 2) % 3;
+        float flux = Q * d[K] * D.inv_dt;
+        if (flux == 0.0f) continue;
+        float t = d[I] * d[J] * (1.0f / 12.0f);
+        float loI = (float)cell[I], loJ = (float)cell[J];
+        float w00, w10, w01, w11;
+        float xi = mid[I] - loI, eta = mid[J] - loJ;
+        if (!D.curved) {
+            w00 = (1.0f - xi) * (1.0f - eta);
+            w10 = xi * (1.0f - eta);
+            w01 = (1.0f - xi) * eta;
+            w11 = xi * eta;
+        } else {
+            float area[2][2];
+            for (int bj = 0; bj < 2; bj++)
+                for (int bi = 0; bi < 2; bi++) {
+                    float i0 = bi ? loI : mid[I], i1 = bi ? mid[I] : loI + 1.0f;
+                    float j0 = bj ? loJ : mid[J], j1 = bj ? mid[J] : loJ + 1.0f;
+                    float P3[3];
+                    P3[K] = mid[K];
+                    P3[I] = 0.5f * (i0 + i1);
+                    P3[J] = 0.5f * (j0 + j1);
+                    area[bi][bj] = area_density32(D, K, base, P3) * ((i1 - i0) * (j1 - j0));
+                }
+            float inv = 1.0f / (area[0][0] + area[1][0] + area[0][1] + area[1][1]);
+            w00 = area[0][0] * inv;
+            w10 = area[1][0] * inv;
+            w01 = area[0][1] * inv;
+            w11 = area[1][1] * inv;
+        }
+        w00 += t;
+        w11 += t;
+        w10 -= t;
+        w01 -= t;
+        int e0[3] = {base[0] + cell[0], base[1] + cell[1], base[2] + cell[2]};
+        int eI[3] = {e0[0], e0[1], e0[2]};
+        eI[I] += 1;
+        int eJ[3] = {e0[0], e0[1], e0[2]};
+        eJ[J] += 1;
+        int eIJ[3] = {eI[0], eI[1], eI[2]};
+        eIJ[J] += 1;
+        double sc = (double)flux * D.jscale;
+        acc.add(K, e0[0], e0[1], e0[2], __double2ll_rn(sc * (double)w00));
+        acc.add(K, eI[0], eI[1], eI[2], __double2ll_rn(sc * (double)w10));
+        acc.add(K, eJ[0], eJ[1], eJ[2], __double2ll_rn(sc * (double)w01));
+        acc.add(K, eIJ[0], eIJ[1], eIJ[2], __double2ll_rn(sc * (double)w11));
+    }
+}
+
+// Zigzag in coordinates local to the old cell: x1 in [0,1), x2 = (cell2 -
+// cell1) + off2.  Cells returned relative to the old cell; false when the
+// move exceeds a cell or leaves the ghost layer.
+__device__ __forceinline__ bool zigzag32(const Grid &G, const int base[3], const float x1[3], const float x2[3],
+                                         float xr[3], int c1[3], int c2[3]) {
+    bool ok = true;
+    for (int ax = 0; ax < 3; ax++) {
+        int i1 = (int)floorf(x1[ax]), i2 = (int)floorf(x2[ax]);
+        float lo = (float)((i1 < i2 ? i1 : i2) + 1);
+        float hi = (float)(i1 > i2 ? i1 : i2);
+        float mid = 0.5f * (x1[ax] + x2[ax]);
+        float v = mid > hi ? mid : hi;
+        xr[ax] = v < lo ? v : lo;
+        c1[ax] = i1;
+        c2[ax] = i2;
+        int nn = G.dim(ax);
+        int g1 = base[ax] + i1, g2 = base[ax] + i2;
+        if (g1 < -1 || g1 > nn || g2 < -1 || g2 > nn || !(fabsf(x2[ax] - x1[ax]) < 1.0f)) ok = false;
+    }
+    return ok;
+}
+
+__device__ __forceinline__ int wave_min32(int v) {
+    for (int o = 32; o > 0; o >>= 1) {
+        int w = __shfl_xor(v, o, 64);
+        v = w < v ? w : v;
+    }
+    return v;
+}
+__device__ __forceinline__ int wave_max32(int v) {
+    for (int o = 32; o > 0; o >>= 1) {
+        int w = __shfl_xor(v, o, 64);
+        v = w > v ? w : v;
+    }
+    return v;
+}
+
+constexpr int kDep32Block = 256;
+constexpr int kDep32PPT = 4;
+constexpr int kDep32Lds = 4096;
+
+__global__ __launch_bounds__(kDep32Block) void k_deposit32(Dep32 D, Species cS, double r_rm, double rscale,
+                                                           ParticlePtrs32 xo, ParticlePtrs32 xn, int64_t n,
+                                                           FieldPtrsT<float> F, unsigned long long *counters) {
+    __shared__ unsigned long long sm[kDep32Lds];
+    __shared__ int sred[6][kDep32Block / 64];
+    const int tid = threadIdx.x;
+    const int64_t base = (int64_t)blockIdx.x * (kDep32Block * kDep32PPT);
+    float X1[kDep32PPT][3], X2[kDep32PPT][3];
+    int B1[kDep32PPT][3];
+    uint8_t SP[kDep32PPT];
+    int lo[3] = {1 << 30, 1 << 30, 1 << 30}, hi[3] = {-(1 << 30), -(1 << 30), -(1 << 30)};
+#pragma unroll
+    for (int p = 0; p < kDep32PPT; p++) {
+        int64_t id = base + p * kDep32Block + tid;
+        SP[p] = id < n ? xo.sp[id] : kDead;
+        if (SP[p] != kDead) {
+            int c2[3];
+            unpack_cell(xo.cell[id], B1[p][0], B1[p][1], B1[p][2]);
+            unpack_cell(xn.cell[id], c2[0], c2[1], c2[2]);
+            for (int ax = 0; ax < 3; ax++) {
+                X1[p][ax] = xo.off[ax][id];
+                X2[p][ax] = (float)(c2[ax] - B1[p][ax]) + xn.off[ax][id];
+            }
+            float xr[3];
+            int l1[3], l2[3];
+            if (zigzag32(D.G, B1[p], X1[p], X2[p], xr, l1, l2) && cS.charge[SP[p]] != 0.0)
+                for (int ax = 0; ax < 3; ax++) {
+                    int a = B1[p][ax] + (l1[ax] < l2[ax] ? l1[ax] : l2[ax]);
+                    int b = B1[p][ax] + (l1[ax] > l2[ax] ? l1[ax] : l2[ax]) + 1;
+                    lo[ax] = a < lo[ax] ? a : lo[ax];
+                    hi[ax] = b > hi[ax] ? b : hi[ax];
+                }
+        }
+    }
+    for (int ax = 0; ax < 3; ax++) {
+        int a = wave_min32(lo[ax]), b = wave_max32(hi[ax]);
+        if ((tid & 63) == 0) {
+            sred[ax][tid >> 6] = a;
+            sred[3 + ax][tid >> 6] = b;
+        }
+    }
+    __syncthreads();
+    int blo[3], bhi[3];
+    for (int ax = 0; ax < 3; ax++) {
+        blo[ax] = sred[ax][0];
+        bhi[ax] = sred[3 + ax][0];
+        for (int w = 1; w < kDep32Block / 64; w++) {
+            blo[ax] = sred[ax][w] < blo[ax] ? sred[ax][w] : blo[ax];
+            bhi[ax] = sred[3 + ax][w] > bhi[ax] ? sred[3 + ax][w] : bhi[ax];
+        }
+    }
+    const bool any = bhi[0] >= blo[0];
+    const int bx = any ? bhi[0] - blo[0] + 1 : 0, by = any ? bhi[1] - blo[1] + 1 : 0,
+              bz = any ? bhi[2] - blo[2] + 1 : 0;
+    const int64_t V64 = (int64_t)bx * by * bz;
+    const bool use_lds = any && 3 * V64 <= kDep32Lds;
+    const int V = use_lds ? (int)V64 : 0;
+    if (use_lds) {
+        for (int e = tid; e < 3 * V; e += kDep32Block) sm[e] = 0ull;
+        __syncthreads();
+    }
+    LdsAcc32 la{sm, blo[0], blo[1], blo[2], bx, by, V};
+    GlobalAcc32 ga{{F.Jint[0], F.Jint[1], F.Jint[2]}, D.G};
+#pragma unroll
+    for (int p = 0; p < kDep32PPT; p++) {
+        if (SP[p] == kDead) continue;
+        int64_t id = base + p * kDep32Block + tid;
+        float Q = (float)cS.charge[SP[p]];
+        float xr[3];
+        int l1[3], l2[3];
+        bool ok = zigzag32(D.G, B1[p], X1[p], X2[p], xr, l1, l2);
+        if (ok && Q != 0.0f) {
+            if (use_lds) {
+                dep_segment32(D, la, B1[p], X1[p], xr, l1, Q);
+                dep_segment32(D, la, B1[p], xr, X2[p], l2, Q);
+            } else {
+                dep_segment32(D, ga, B1[p], X1[p], xr, l1, Q);
+                dep_segment32(D, ga, B1[p], xr, X2[p], l2, Q);
+            }
+        } else if (!ok) {
+            atomicOr(&counters[C_FLAGS], 1ull);
+        }
+        // removal after the final move is deposited
+        int c2[3];
+        unpack_cell(xn.cell[id], c2[0], c2[1], c2[2]);
+        bool outside = false;
+        for (int ax = 0; ax < 3; ax++)
+            if (c2[ax] < 0 || c2[ax] > D.G.dim(ax) - 1) outside = true;
+        float o2[3] = {xn.off[0][id], xn.off[1][id], xn.off[2][id]};
+        double x, y, z;
+        hole_rel(D.h, c2[0], c2[1], c2[2], o2, x, y, z);
+        double r = ks_radius(D.h.a, x, y, z);
+        if (r < r_rm) {
+            bool inb = true;
+            for (int ax = 0; ax < 3; ax++)
+                if (c2[ax] < -1 || c2[ax] > D.G.dim(ax)) inb = false;
+            if (inb && Q != 0.0f) {
+                double sc = (double)cS.charge[SP[p]] * rscale;
+                for (int dk = 0; dk < 2; dk++)
+                    for (int dj = 0; dj < 2; dj++)
+                        for (int di = 0; di < 2; di++) {
+                            double W = (di ? (double)o2[0] : 1.0 - (double)o2[0]) *
+                                       (dj ? (double)o2[1] : 1.0 - (double)o2[1]) *
+                                       (dk ? (double)o2[2] : 1.0 - (double)o2[2]);
+                            atomicAdd(&F.rho_abs[D.G.g(c2[0] + di, c2[1] + dj, c2[2] + dk)],
+                                      (unsigned long long)__double2ll_rn(sc * W));
+                        }
+            }
+            xo.sp[id] = kDead;
+            atomicAdd(&counters[C_REMOVED_HORIZON], 1ull);
+        } else if (outside) {
+            xo.sp[id] = kDead;
+            atomicAdd(&counters[C_REMOVED_OUTER], 1ull);
+        }
+    }
+    if (use_lds) {
+        __syncthreads();
+        for (int e = tid; e < 3 * V; e += kDep32Block) {
+            unsigned long long v = sm[e];
+            if (v == 0ull) continue;
+            int K = e / V, l = e - K * V;
+            int li = l % bx, lj = (l / bx) % by, lk = l / (bx * by);
+            atomicAdd(&F.Jint[K][D.G.g(blo[0] + li, blo[1] + lj, blo[2] + lk)], v);
+        }
+    }
+}
+
+void launch_deposit32(const Grid &G, const Hole &h, const Mixed &M, double dt, int deposit_mode, double r_rm,
+                      double jscale, double rscale, const Species &S, ParticlePtrs32 xold, ParticlePtrs32 xnew,
+                      int64_t n, FieldPtrsT<float> &F, unsigned long long *counters, hipStream_t s) {
+    if (n <= 0) return;
+    Dep32 D;
+    D.G = G;
+    D.h = h;
+    D.r_fp64 = M.r_fp64;
+    D.inv_dt = (float)(1.0 / dt);
+    D.jscale = jscale;
+    D.curved = deposit_mode == 0;
+    const int64_t per = kDep32Block * kDep32PPT;
+    hipLaunchKernelGGL(k_deposit32, dim3((unsigned)((n + per - 1) / per)), dim3(kDep32Block), 0, s, D, S, r_rm,
+                       rscale, xold, xnew, n, F, counters);
+}
+
+// ---------------------------------------------------------------------------
+// Load: FP64 mass shell (as in the FP64 form), then cell + FP32 offset.
+__global__ void k_load32(Grid G, Hole h, double c, double r_rm, const double *__restrict__ xin,
+                         const double *__restrict__ ucin, int64_t n, int species, ParticlePtrs32 out, int64_t off,
+                         unsigned long long *counters) {
+    int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (id >= n) return;
+    double X[3] = {xin[id], xin[n + id], xin[2 * n + id]};
+    double uc[3] = {ucin[id], ucin[n + id], ucin[2 * n + id]};
+    bool ok = true;
+    for (int ax = 0; ax < 3; ax++) {
+        if (!isfinite(X[ax]) || !isfinite(uc[ax])) ok = false;
+        if (!(X[ax] >= 0.0 && X[ax] < (double)G.dim(ax))) ok = false;
+    }
+    double U[4] = {0.0, 0.0, 0.0, c};
+    if (ok) {
+        double x = X[0] - h.cx, y = X[1] - h.cy, z = X[2] - h.cz;
+        double f = 0.0, k[3] = {0.0, 0.0, 0.0};
+        if (h.m != 0.0) {
+            double r = ks_radius(h.a, x, y, z);
+            if (r < r_rm) ok = false;
+            if (ok) {
+                KSPoint<double> p;
+                ks_point(h.m, h.a, x, y, z, p);
+                f = p.f;
+                k[0] = p.k0;
+                k[1] = p.k1;
+                k[2] = p.k2;
+            }
+        }
+        if (ok) {
+            double ku[4] = {k[0], k[1], k[2], -1.0};
+            const double eta[4] = {1.0, 1.0, 1.0, -1.0};
+            double gi[4][4];
+            for (int a = 0; a < 4; a++)
+                for (int b = 0; b < 4; b++) gi[a][b] = (a == b ? eta[a] : 0.0) - f * ku[a] * ku[b];
+            double A = gi[3][3];
+            double B = gi[3][0] * uc[0] + gi[3][1] * uc[1] + gi[3][2] * uc[2];
+            double C = c * c;
+            for (int i = 0; i < 3; i++)
+                for (int j = 0; j < 3; j++) C += gi[i][j] * uc[i] * uc[j];
+            double disc = B * B - A * C;
+            disc = disc < 0.0 ? 0.0 : disc;
+            double sq = sqrt(disc);
+            double u4l = (B <= 0.0) ? (sq - B) / A : -C / (sq + B);
+            double ul[4] = {uc[0], uc[1], uc[2], u4l};
+            for (int a = 0; a < 4; a++) U[a] = gi[a][0] * ul[0] + gi[a][1] * ul[1] + gi[a][2] * ul[2] + gi[a][3] * ul[3];
+        }
+    }
+    int64_t o = off + id;
+    int ci[3] = {0, 0, 0};
+    for (int ax = 0; ax < 3; ax++) {
+        double fl = ok ? floor(X[ax]) : 0.0;
+        ci[ax] = (int)fl;
+        out.off[ax][o] = ok ? (float)(X[ax] - fl) : 0.0f;
+    }
+    out.cell[o] = pack_cell(ci[0], ci[1], ci[2]);
+    for (int q = 0; q < 4; q++) out.u[q][o] = (float)U[q];
+    out.sp[o] = ok ? (uint8_t)species : kDead;
+    if (ok) atomicAdd(&counters[C_LOAD_KEPT], 1ull);
+}
+
+void launch_load32(const Grid &G, const Hole &h, double c, double r_rm, const double *xin, const double *ucin,
+                   int64_t n, int species, ParticlePtrs32 out, int64_t offset, unsigned long long *counters,
+                   hipStream_t s) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_load32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, G, h, c, r_rm, xin, ucin, n,
+                       species, out, offset, counters);
+}
+
+// Widening to FP64 (x = cell + offset exactly, u converted) and back.
+__global__ void k_to_f64(ParticlePtrs32 in, double *x, double *u, int64_t n) {
+    int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (id >= n) return;
+    int c[3];
+    unpack_cell(in.cell[id], c[0], c[1], c[2]);
+    for (int q = 0; q < 3; q++) x[q * n + id] = (double)c[q] + (double)in.off[q][id];
+    for (int q = 0; q < 4; q++) u[q * n + id] = (double)in.u[q][id];
+}
+
+__global__ void k_from_f64(const double *x, const double *u, ParticlePtrs32 out, int64_t n) {
+    int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (id >= n) return;
+    int c[3];
+    for (int q = 0; q < 3; q++) {
+        double v = x[q * n + id];
+        double fl = floor(v);
+        c[q] = (int)fl;
+        c[q] = c[q] < -1 ? -1 : (c[q] > 1022 ? 1022 : c[q]);
+        out.off[q][id] = (float)(v - (double)c[q]);
+    }
+    out.cell[id] = pack_cell(c[0], c[1], c[2]);
+    for (int q = 0; q < 4; q++) out.u[q][id] = (float)u[q * n + id];
+}
+
+void launch_to_f64(ParticlePtrs32 in, double *x, double *u, int64_t n, hipStream_t s) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_to_f64, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, in, x, u, n);
+}
+
+void launch_from_f64(const double *x, const double *u, ParticlePtrs32 out, int64_t n, hipStream_t s) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_from_f64, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, x, u, out, n);
+}
+
+}  // namespace grpic
