@@ -45,6 +45,10 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_push_kerr64_traffic.txt")
 PUSH_SOURCES = [os.path.join(ROOT, "paper_0904_0232_amd", "csrc", f) for f in ("particles.hip", "grpic_dev.h")]
 
 
+def log(msg):
+    print("bench: " + msg, file=sys.stderr, flush=True)
+
+
 def push_source_hash():
     h = hashlib.sha256()
     for f in PUSH_SOURCES:
@@ -158,6 +162,130 @@ def push_roofline(m, flops_per_ps, peak, traffic=None):
     }
 
 
+def serving(args, saturated_rate):
+    """Continuous batching of independent FP32-mixed runs with Poisson arrivals
+    at 0.7 of the completion rate the measured single-run throughput sustains."""
+    from paper_0904_0232_amd import serve
+    probe = serve.make_requests(args.serve_runs, 0, 1.0)
+    mean_work = sum(2 * r["ppc"] * r["edge"] ** 3 * r["steps"] for r in probe) / len(probe)
+    rate = 0.7 * saturated_rate / mean_work
+    reqs = serve.make_requests(args.serve_runs, 0, rate)
+    res = serve.serve(reqs, int(args.serve_budget_gb * (1 << 30)), args.serve_slots, log=log)
+    return {
+        "runs": res["n_runs"],
+        "arrival_rate_per_s": rate,
+        "p50_latency_s": res["p50_latency_s"],
+        "p99_latency_s": res["p99_latency_s"],
+        "runs_per_s": res["runs_per_s"],
+        "particle_steps_per_s": res["particle_steps_per_s"],
+        "makespan_s": res["makespan_s"],
+        "budget_gb": args.serve_budget_gb,
+        "slots": args.serve_slots,
+        "workload": "grid edge in {16,32,48,64,96}, a~U[0,0.99]m, m=edge/16, 2-8 ppc per species, "
+                    "u_th~U[0.02,0.2]c, 50-500 steps, FP32-mixed, Poisson arrivals (seed 0)",
+    }
+
+
+def precision_study(workload, checkpoints=(1, 10, 100, 300, 1000), modes=("geodesic", "push", "cycle"), n_override=None,
+                    log=sys.stderr):
+    """FP32-mixed against FP64 on one workload, particle identity kept (one
+    cell sort at load, none afterwards).  Three runs per mode:
+      A  FP64 loaded from the exact inputs,
+      B  FP64 restored from C's loaded state (the inputs rounded to the
+         mixed representation: FP32 offsets and velocities),
+      C  FP32-mixed.
+    C-A is the whole FP32-mixed error; C-B isolates the FP32 arithmetic of
+    the steps; B-A is the control: how far FP64 itself carries a perturbation
+    of the size of one FP32 rounding of the start (the dynamics' own
+    divergence).  "geodesic" runs test particles with no field, "push" test
+    particles in the frozen initial fields, "cycle" the self-consistent cycle.  A particle is "regular" while its A
+    path stays inside the grid and outside R = 3m."""
+    import numpy as np
+    import torch
+    from paper_0904_0232_amd import capi, inputs
+    from paper_0904_0232_amd import run as R
+
+    w = inputs.workload_params(workload)
+    parts = inputs.workload_particles(workload, seed=0, n_override=n_override)
+    ntot = sum(p[1].shape[1] for p in parts)
+    cen = np.full(3, w["n"] / 2.0)
+
+    def cfg(prec, b0):
+        return R.make_config(w["n"], m=w["m"], a=w["a"], dt=w["dt"], B0=(0.0, 0.0, b0), species=w["species"],
+                             r_rm=w["r_rm"], sort_every=0, capacity=ntot,
+                             precision=capi.FP32_MIXED if prec == "fp32" else capi.FP64)
+
+    def diff(P, Q, regular):
+        (x1, u1, s1), (x2, u2, s2) = P, Q
+        both = (s1 != 255) & (s2 != 255)
+        with np.errstate(invalid="ignore", divide="ignore"):
+            ex = (np.abs(x2 - x1) / np.maximum(np.abs(x1), 1.0)).max(axis=0)
+            eu = (np.abs(u2 - u1) / np.maximum(np.abs(u1), 1.0)).max(axis=0)
+        e = np.where(np.isfinite(ex) & np.isfinite(eu), np.maximum(ex, eu), np.inf)
+        reg = regular & both
+        return {
+            "alive_mismatch": int(((s1 != 255) != (s2 != 255)).sum()),
+            "frac_within_1e-4": float((e[both] < 1e-4).mean()) if both.any() else None,
+            "regular": int(reg.sum()),
+            "regular_frac_within_1e-4": float((e[reg] < 1e-4).mean()) if reg.any() else None,
+            "regular_median": float(np.median(e[reg])) if reg.any() else None,
+            "regular_p99": float(np.quantile(e[reg], 0.99)) if reg.any() else None,
+        }
+
+    def jdiff(J1, J2):
+        return {"l2_rel": float(np.linalg.norm(J2 - J1) / np.linalg.norm(J1)),
+                "max_rel": float(np.abs(J2 - J1).max() / np.abs(J1).max())}
+
+    out = {"workload": workload, "particles": ntot}
+    for mode in modes:
+        b0 = 0.0 if mode == "geodesic" else w["B0"]
+        c = R.Run(cfg("fp32", b0))
+        a = R.Run(cfg("fp64", b0))
+        for sp, x, uc in parts:
+            c.load(sp, x, uc)
+            a.load(sp, x, uc)
+        c.sort()
+        a.sort()
+        b = R.Run(cfg("fp64", b0))
+        b.restore_particles(*c.particles())
+        runs = {"A": a, "B": b, "C": c}
+        regular = None
+        rows = []
+        done = 0
+        for target in checkpoints:
+            t0 = time.perf_counter()
+            for r in runs.values():
+                if mode == "cycle":
+                    r.step(target - done)
+                else:
+                    r.push_only(target - done)
+            torch.cuda.synchronize()
+            done = target
+            st = {k: r.particles() for k, r in runs.items()}
+            xa, ua, sa = st["A"]
+            Rr = np.sqrt(((xa - cen[:, None]) ** 2).sum(0))
+            ok = np.all((xa >= 0) & (xa < w["n"]), axis=0) & (Rr > 3.0 * w["m"]) & np.isfinite(ua).all(0) & (sa != 255)
+            regular = ok if regular is None else (regular & ok)
+            row = {"step": target, "alive": int((sa != 255).sum()),
+                   "fp32_vs_fp64": diff(st["A"], st["C"], regular),
+                   "fp32_arith": diff(st["B"], st["C"], regular),
+                   "fp64_control": diff(st["A"], st["B"], regular)}
+            del st
+            if mode == "cycle":
+                J = {k: r.fields("J") for k, r in runs.items()}
+                row["J_fp32_vs_fp64"] = jdiff(J["A"], J["C"])
+                row["J_fp32_arith"] = jdiff(J["B"], J["C"])
+                row["J_fp64_control"] = jdiff(J["A"], J["B"])
+                del J
+            rows.append(row)
+            print("precision %s step %d (%.1f s): %s" % (mode, target, time.perf_counter() - t0, json.dumps(row)),
+                  file=log, flush=True)
+        for r in runs.values():
+            r.close()
+        out[mode] = rows
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -170,6 +298,14 @@ def main():
     ap.add_argument("--no-fp32", action="store_true", help="skip the FP32-mixed measurement")
     ap.add_argument("--scale", action="store_true",
                     help="also time the 256^3 throughput workload (268M particles) in both precisions")
+    ap.add_argument("--precision", action="store_true",
+                    help="also run the FP32-mixed vs FP64 precision study on the torus workload (1000 steps)")
+    ap.add_argument("--precision-particles", type=int, default=0,
+                    help="particles per species for the precision study (0: the full workload)")
+    ap.add_argument("--serve-runs", type=int, default=48,
+                    help="requests in the serving measurement (0 skips it); the serving workload has 256")
+    ap.add_argument("--serve-budget-gb", type=float, default=8.0)
+    ap.add_argument("--serve-slots", type=int, default=32)
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -182,6 +318,7 @@ def main():
     torch.cuda.set_device(0)
 
     m64 = measure(args.workload, "fp64", args.steps, args.warmup, args.sort_every)
+    log("fp64 %s: %.4g particle-steps/s" % (args.workload, m64["value"]))
     w = m64["w"]
     per_launch = m64["psteps"] / max(m64["timers"]["push"][1], 1)
     roofline = push_roofline(m64, PUSH_FLOPS_PER_PARTICLE_STEP, FP64_PEAK_TFLOPS, read_traffic(per_launch))
@@ -212,21 +349,29 @@ def main():
     }
     if not args.no_fp32:
         m32 = measure(args.workload, "fp32", args.steps, args.warmup, args.sort_every)
+        log("fp32-mixed %s: %.4g particle-steps/s" % (args.workload, m32["value"]))
         line["fp32_mixed"] = {
             "value": m32["value"], "unit": UNIT, "ms_per_step": m32["ms_per_step"], "dtype": "f32 (FP64 quartic, "
             "near-horizon metric and diagnostics)", "kernel_ms_per_launch": m32["kernel_ms_per_launch"],
             "speedup_vs_fp64": m32["value"] / m64["value"], "live_particles_end": m32["live_end"],
             "roofline": push_roofline(m32, PUSH_FLOPS_PER_PARTICLE_STEP, FP32_PEAK_TFLOPS),
         }
+    if args.serve_runs > 0:
+        line["serving"] = serving(args, line.get("fp32_mixed", {}).get("value", m64["value"]))
+        log("serving: p50 %.3f s p99 %.3f s" % (line["serving"]["p50_latency_s"], line["serving"]["p99_latency_s"]))
     if args.scale:
         scale = {}
         for prec in ("fp32", "fp64"):
             ms = measure("shell256", prec, 20, 2, args.sort_every)
+            log("shell256 %s: %.4g particle-steps/s" % (prec, ms["value"]))
             scale[prec] = {"value": ms["value"], "ms_per_step": ms["ms_per_step"], "particles": ms["ntot"],
                            "kernel_ms_per_launch": ms["kernel_ms_per_launch"], "steps": 20}
         line["throughput_scale_shell256"] = scale
+    if args.precision:
+        line["precision_torus128"] = precision_study("torus128", n_override=args.precision_particles or None)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(args.workload, args.cpu_sample)
+        log("cpu baseline: %.4g particle-steps/s" % line["cpu_baseline"]["value"])
     print(json.dumps(line), flush=True)
 
 

@@ -128,7 +128,8 @@ int grpic_particle_count(grpic_t *h, int64_t *n_slots, int64_t *capacity);
 
 /* Copy the particle state to host: x [3][n] node coordinates, u [4][n]
  * contravariant four-velocity, sp [n] species (GRPIC_DEAD when removed);
- * n = the slot count of grpic_particle_count.  Synchronous. */
+ * n = the slot count of grpic_particle_count.  x and u of a GRPIC_DEAD slot
+ * are unspecified (the pusher no longer writes them).  Synchronous. */
 int grpic_dump_particles(grpic_t *h, double *x, double *u, uint8_t *sp);
 
 /* Replace the particle state verbatim (the inverse of the dump).  n <= capacity. */
@@ -180,6 +181,56 @@ int grpic_particle_steps(grpic_t *h, int64_t *out);
 
 void grpic_destroy(grpic_t *h);
 const char *grpic_strerror(int code);
+
+/* ------------------------------------------------------------------------
+ * Serving: continuous batching of independent runs.  A batch owns up to
+ * max_slots runs whose device memory together stays within budget_bytes.
+ * Each admitted run keeps its state on the device and its own HIP stream;
+ * one batch iteration replays every active run's captured one-cycle graph
+ * (the cell sort, when due, runs eagerly after it), so the runs' work
+ * overlaps on the GPU.  Runs that reach their step count are finished:
+ * their diagnostics are taken and their memory is freed at once, which
+ * admits queued work.  One batch is not thread-safe.
+ * ------------------------------------------------------------------------ */
+typedef struct grpic_batch_s grpic_batch_t;
+
+enum { GRPIC_RUN_UNKNOWN = 0, GRPIC_RUN_ACTIVE = 1, GRPIC_RUN_DONE = 2 };
+
+/* Device bytes a run with this configuration allocates (admission estimate). */
+int64_t grpic_run_bytes(const grpic_config *cfg);
+
+int grpic_batch_create(int64_t budget_bytes, int32_t max_slots, grpic_batch_t **out);
+
+/* Admit a run if a slot and budget_bytes allow it (else GRPIC_EAGAIN and no
+ * state changes).  Particles of species s (s < cfg->nspecies): n[s] entries,
+ * x[s] and ucov[s] as for grpic_load_particles; cfg->alloc must be NULL (the
+ * batch allocates).  The run advances one cycle per grpic_batch_step until
+ * nsteps are done.  keep_state != 0 keeps a host copy of the final particle
+ * state for grpic_batch_dump. */
+int grpic_batch_submit(grpic_batch_t *b, const grpic_config *cfg, int32_t nsteps, int32_t keep_state,
+                       const int64_t *n, const double *const *x, const double *const *ucov, int64_t *run_id);
+
+/* One cycle of every active run.  *finished receives how many runs
+ * completed in this iteration. */
+int grpic_batch_step(grpic_batch_t *b, int32_t *finished);
+
+/* State of a run (GRPIC_RUN_*), cycles done, and for a finished run its
+ * diagnostics, the slot count of its kept final state (0 if not kept) and
+ * the particle pushes it performed.
+ * Unknown or released ids give GRPIC_RUN_UNKNOWN.  Pointers may be NULL. */
+int grpic_batch_poll(grpic_batch_t *b, int64_t run_id, int32_t *state, int32_t *steps_done, grpic_diag *diag,
+                     int64_t *n_slots, int64_t *particle_steps);
+
+/* Copy a finished run's kept final particle state (layout of grpic_dump_particles). */
+int grpic_batch_dump(grpic_batch_t *b, int64_t run_id, double *x, double *u, uint8_t *sp);
+
+/* Forget a finished run (its memory was already returned at completion). */
+int grpic_batch_release(grpic_batch_t *b, int64_t run_id);
+
+/* Active runs and device bytes they hold. */
+int grpic_batch_stats(grpic_batch_t *b, int32_t *active, int64_t *bytes_in_use);
+
+void grpic_batch_destroy(grpic_batch_t *b);
 
 #ifdef __cplusplus
 }

@@ -63,7 +63,13 @@ class Diag(ctypes.Structure):
 
 
 class GrpicError(RuntimeError):
-    pass
+    def __init__(self, msg, code=0):
+        super().__init__(msg)
+        self.code = code
+
+
+EAGAIN = -6
+RUN_UNKNOWN, RUN_ACTIVE, RUN_DONE = 0, 1, 2
 
 
 _lib = None
@@ -102,6 +108,19 @@ def lib():
         L.grpic_set_timing.argtypes = [_H, ctypes.c_int32]
         L.grpic_read_timing.argtypes = [_H, _D, _I64]
         L.grpic_particle_steps.argtypes = [_H, _I64]
+        L.grpic_run_bytes.argtypes = [ctypes.POINTER(Config)]
+        L.grpic_run_bytes.restype = ctypes.c_int64
+        L.grpic_batch_create.argtypes = [ctypes.c_int64, ctypes.c_int32, ctypes.POINTER(_H)]
+        L.grpic_batch_submit.argtypes = [_H, ctypes.POINTER(Config), ctypes.c_int32, ctypes.c_int32, _I64,
+                                         ctypes.POINTER(_D), ctypes.POINTER(_D), _I64]
+        L.grpic_batch_step.argtypes = [_H, ctypes.POINTER(ctypes.c_int32)]
+        L.grpic_batch_poll.argtypes = [_H, ctypes.c_int64, ctypes.POINTER(ctypes.c_int32),
+                                       ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(Diag), _I64, _I64]
+        L.grpic_batch_dump.argtypes = [_H, ctypes.c_int64, _D, _D, _U8]
+        L.grpic_batch_release.argtypes = [_H, ctypes.c_int64]
+        L.grpic_batch_stats.argtypes = [_H, ctypes.POINTER(ctypes.c_int32), _I64]
+        L.grpic_batch_destroy.argtypes = [_H]
+        L.grpic_batch_destroy.restype = None
         L.grpic_destroy.argtypes = [_H]
         L.grpic_destroy.restype = None
         L.grpic_strerror.argtypes = [ctypes.c_int]
@@ -110,7 +129,9 @@ def lib():
                      "grpic_diagnostics", "grpic_particle_count", "grpic_dump_particles",
                      "grpic_restore_particles", "grpic_dump_fields", "grpic_restore_fields",
                      "grpic_dump_nodes", "grpic_sort", "grpic_set_timing", "grpic_read_timing",
-                     "grpic_particle_steps"):
+                     "grpic_particle_steps", "grpic_batch_create", "grpic_batch_submit",
+                     "grpic_batch_step", "grpic_batch_poll", "grpic_batch_dump", "grpic_batch_release",
+                     "grpic_batch_stats"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -118,7 +139,7 @@ def lib():
 
 def _check(rc):
     if rc != 0:
-        raise GrpicError("grpic error %d: %s" % (rc, lib().grpic_strerror(rc).decode()))
+        raise GrpicError("grpic error %d: %s" % (rc, lib().grpic_strerror(rc).decode()), rc)
 
 
 def _dp(a):
@@ -276,3 +297,72 @@ def grpic_particle_steps(h):
 def grpic_destroy(h):
     if h:
         lib().grpic_destroy(h)
+
+
+def grpic_run_bytes(cfg):
+    return lib().grpic_run_bytes(ctypes.byref(cfg))
+
+
+def grpic_batch_create(budget_bytes, max_slots):
+    b = _H()
+    _check(lib().grpic_batch_create(int(budget_bytes), int(max_slots), ctypes.byref(b)))
+    return b
+
+
+def grpic_batch_submit(b, cfg, nsteps, species_particles, keep_state=False):
+    """species_particles: [(x[3][n], ucov[3][n]) per species].  Returns the run id,
+    or None when the batch has no free slot or memory right now."""
+    ns = len(species_particles)
+    xs = [_f64(x) for x, _ in species_particles]
+    us = [_f64(u) for _, u in species_particles]
+    n = np.array([x.shape[1] for x in xs], dtype=np.int64)
+    xp = (_D * ns)(*[_dp(x) for x in xs])
+    up = (_D * ns)(*[_dp(u) for u in us])
+    rid = ctypes.c_int64()
+    rc = lib().grpic_batch_submit(b, ctypes.byref(cfg), int(nsteps), 1 if keep_state else 0,
+                                  n.ctypes.data_as(_I64), xp, up, ctypes.byref(rid))
+    if rc == EAGAIN:
+        return None
+    _check(rc)
+    return rid.value
+
+
+def grpic_batch_step(b):
+    fin = ctypes.c_int32()
+    _check(lib().grpic_batch_step(b, ctypes.byref(fin)))
+    return fin.value
+
+
+def grpic_batch_poll(b, run_id):
+    st = ctypes.c_int32()
+    done = ctypes.c_int32()
+    d = Diag()
+    ns = ctypes.c_int64()
+    ps = ctypes.c_int64()
+    _check(lib().grpic_batch_poll(b, int(run_id), ctypes.byref(st), ctypes.byref(done), ctypes.byref(d),
+                                  ctypes.byref(ns), ctypes.byref(ps)))
+    return st.value, done.value, (d.as_dict() if st.value == RUN_DONE else None), ns.value, ps.value
+
+
+def grpic_batch_dump(b, run_id, n_slots):
+    x = np.zeros((3, n_slots))
+    u = np.zeros((4, n_slots))
+    sp = np.zeros(n_slots, dtype=np.uint8)
+    _check(lib().grpic_batch_dump(b, int(run_id), _dp(x), _dp(u), sp.ctypes.data_as(_U8)))
+    return x, u, sp
+
+
+def grpic_batch_release(b, run_id):
+    _check(lib().grpic_batch_release(b, int(run_id)))
+
+
+def grpic_batch_stats(b):
+    a = ctypes.c_int32()
+    by = ctypes.c_int64()
+    _check(lib().grpic_batch_stats(b, ctypes.byref(a), ctypes.byref(by)))
+    return a.value, by.value
+
+
+def grpic_batch_destroy(b):
+    if b:
+        lib().grpic_batch_destroy(b)

@@ -6,6 +6,7 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <map>
 #include <new>
 #include <vector>
 
@@ -342,7 +343,7 @@ int do_sort(grpic_t *h) {
 }
 
 template <typename T>
-int one_step_t(grpic_t *h) {
+int one_step_t(grpic_t *h, bool allow_sort) {
     int rc = fields_to_n<T>(h);
     if (rc) return rc;
     push_particles(h);
@@ -352,11 +353,15 @@ int one_step_t(grpic_t *h) {
     if (rc) return rc;
     h->xc = 1 - h->xc;
     h->step_count++;
-    if (h->cfg.sort_every > 0 && h->step_count % h->cfg.sort_every == 0) return do_sort(h);
+    if (allow_sort && h->cfg.sort_every > 0 && h->step_count % h->cfg.sort_every == 0) return do_sort(h);
     return check(hipGetLastError());
 }
 
-int one_step(grpic_t *h) { return h->mixed ? one_step_t<float>(h) : one_step_t<double>(h); }
+int one_step(grpic_t *h, bool allow_sort = true) {
+    return h->mixed ? one_step_t<float>(h, allow_sort) : one_step_t<double>(h, allow_sort);
+}
+
+bool sort_due(const grpic_t *h) { return h->cfg.sort_every > 0 && h->step_count % h->cfg.sort_every == 0; }
 
 // FP64 view of the particle state (the FP32-mixed form is widened into
 // tmp, which must hold 7 n doubles).
@@ -430,9 +435,253 @@ int restore_fields_t(grpic_t *h, const double *D, const double *B) {
     return rc;
 }
 
+// Device bytes of a run, mirroring the allocations of grpic_create plus the
+// load staging (admission estimate of the batch).
+int64_t run_bytes(const grpic_config *c) {
+    auto up = [](int64_t b) { return (b + 255) & ~(int64_t)255; };
+    int64_t gs = (int64_t)(c->nx + 3) * (c->ny + 3) * (c->nz + 3);
+    int64_t nn = (int64_t)(c->nx + 1) * (c->ny + 1) * (c->nz + 1);
+    int64_t T = c->precision == GRPIC_FP32_MIXED ? 4 : 8;
+    int64_t cap = c->capacity > 0 ? c->capacity : 1;
+    int64_t b = 0;
+    b += 30 * up(gs * T) + 3 * up(gs * 8) + up(gs * 8) + up(gs);
+    b += up(21 * nn * T) + up(10 * nn * T) + up(6 * nn * T) + up(16 * nn * T);
+    if (c->precision == GRPIC_FP32_MIXED)
+        b += 2 * (up(cap * 4) + 3 * up(cap * 4) + 4 * up(cap * 4) + up(cap));
+    else
+        b += 2 * (3 * up(cap * 8) + 4 * up(cap * 8) + up(cap));
+    b += up(64) + 4 * up(cap * 4) + up((int64_t)sort_temp_bytes(cap)) + up(gs * 8);
+    b += up((((cap + 255) / 256) * 12 + ((nn + 255) / 256) * 3 + 64) * 8);
+    b += up(6 * cap * 8);  // load staging
+    return b;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Serving batch.
+struct BatchRun {
+    int64_t id;
+    grpic_t *h;
+    hipStream_t stream;
+    hipGraphExec_t exec[2][2];  // one captured cycle per (x buffer, u buffer) parity
+    int32_t nsteps, done, state;
+    int64_t bytes;
+    grpic_diag diag;
+    bool keep;
+    int64_t n_slots;
+    int64_t particle_steps;
+    std::vector<double> x, u;
+    std::vector<uint8_t> sp;
+};
+
+struct grpic_batch_s {
+    int64_t budget, used;
+    int32_t max_slots;
+    int64_t next_id;
+    std::vector<BatchRun *> active;
+    std::map<int64_t, BatchRun *> runs;
+};
+
+namespace {
+
+void drop_graphs(BatchRun *r) {
+    for (int a = 0; a < 2; a++)
+        for (int c = 0; c < 2; c++)
+            if (r->exec[a][c]) {
+                (void)hipGraphExecDestroy(r->exec[a][c]);
+                r->exec[a][c] = nullptr;
+            }
+}
+
+// Capture one cycle (without the sort) of run r for its current buffer parity.
+int capture_cycle(BatchRun *r, hipGraphExec_t *out) {
+    grpic_t *h = r->h;
+    int xc = h->xc, uc = h->uc;
+    int64_t sc = h->step_count;
+    int rc = check(hipStreamBeginCapture(r->stream, hipStreamCaptureModeThreadLocal));
+    if (rc) return rc;
+    int rc_step = one_step(h, false);
+    hipGraph_t g = nullptr;
+    rc = check(hipStreamEndCapture(r->stream, &g));
+    // capturing recorded the work without running it: undo the bookkeeping
+    h->xc = xc;
+    h->uc = uc;
+    h->step_count = sc;
+    if (rc_step) rc = rc_step;
+    if (!rc) rc = check(hipGraphInstantiate(out, g, nullptr, nullptr, 0));
+    if (g) (void)hipGraphDestroy(g);
+    return rc;
+}
+
+int finish_run(grpic_batch_t *b, BatchRun *r) {
+    grpic_t *h = r->h;
+    int rc = grpic_diagnostics(h, &r->diag);
+    if (!rc) rc = grpic_particle_steps(h, &r->particle_steps);
+    if (!rc && r->keep) {
+        r->n_slots = h->n_slots;
+        r->x.resize(3 * r->n_slots);
+        r->u.resize(4 * r->n_slots);
+        r->sp.resize(r->n_slots);
+        rc = grpic_dump_particles(h, r->x.data(), r->u.data(), r->sp.data());
+    }
+    drop_graphs(r);
+    grpic_destroy(h);
+    (void)hipStreamDestroy(r->stream);
+    r->h = nullptr;
+    r->stream = nullptr;
+    b->used -= r->bytes;
+    r->state = GRPIC_RUN_DONE;
+    return rc;
+}
+
 }  // namespace
 
 extern "C" {
+
+int64_t grpic_run_bytes(const grpic_config *cfg) { return cfg ? run_bytes(cfg) : 0; }
+
+int grpic_batch_create(int64_t budget_bytes, int32_t max_slots, grpic_batch_t **out) {
+    if (!out || budget_bytes <= 0 || max_slots < 1) return GRPIC_EINVAL;
+    grpic_batch_t *b = new (std::nothrow) grpic_batch_s();
+    if (!b) return GRPIC_ENOMEM;
+    b->budget = budget_bytes;
+    b->used = 0;
+    b->max_slots = max_slots;
+    b->next_id = 1;
+    *out = b;
+    return GRPIC_OK;
+}
+
+int grpic_batch_submit(grpic_batch_t *b, const grpic_config *cfg, int32_t nsteps, int32_t keep_state,
+                       const int64_t *n, const double *const *x, const double *const *ucov, int64_t *run_id) {
+    clear_foreign_error();
+    if (!b || !cfg || nsteps < 1 || !n || !x || !ucov || !run_id) return GRPIC_EINVAL;
+    if (cfg->alloc) return GRPIC_EINVAL;
+    int rc = validate(cfg);
+    if (rc) return rc;
+    int64_t bytes = run_bytes(cfg);
+    if ((int32_t)b->active.size() >= b->max_slots || b->used + bytes > b->budget) return GRPIC_EAGAIN;
+    BatchRun *r = new (std::nothrow) BatchRun();
+    if (!r) return GRPIC_ENOMEM;
+    if (FAILS(hipStreamCreateWithFlags(&r->stream, hipStreamNonBlocking))) {
+        delete r;
+        return GRPIC_EDEVICE;
+    }
+    rc = grpic_create(cfg, r->stream, &r->h);
+    for (int s = 0; s < cfg->nspecies && !rc; s++) rc = grpic_load_particles(r->h, s, n[s], x[s], ucov[s], nullptr);
+    if (rc) {
+        if (r->h) grpic_destroy(r->h);
+        (void)hipStreamDestroy(r->stream);
+        delete r;
+        return rc;
+    }
+    r->id = b->next_id++;
+    r->nsteps = nsteps;
+    r->done = 0;
+    r->state = GRPIC_RUN_ACTIVE;
+    r->bytes = bytes;
+    r->keep = keep_state != 0;
+    r->n_slots = 0;
+    b->used += bytes;
+    b->active.push_back(r);
+    b->runs[r->id] = r;
+    *run_id = r->id;
+    return GRPIC_OK;
+}
+
+int grpic_batch_step(grpic_batch_t *b, int32_t *finished) {
+    clear_foreign_error();
+    if (!b) return GRPIC_EINVAL;
+    if (finished) *finished = 0;
+    int rc = GRPIC_OK;
+    for (BatchRun *r : b->active) {
+        grpic_t *h = r->h;
+        hipGraphExec_t &ex = r->exec[h->xc][h->uc];
+        if (!ex) {
+            rc = capture_cycle(r, &ex);
+            if (rc) return rc;
+        }
+        rc = check(hipGraphLaunch(ex, r->stream));
+        if (rc) return rc;
+        h->xc = 1 - h->xc;
+        h->step_count++;
+        if (sort_due(h)) {
+            rc = do_sort(h);
+            if (rc) return rc;
+        }
+        r->done++;
+    }
+    std::vector<BatchRun *> still;
+    for (BatchRun *r : b->active) {
+        if (r->done >= r->nsteps) {
+            int frc = finish_run(b, r);
+            if (frc && !rc) rc = frc;
+            if (finished) (*finished)++;
+        } else {
+            still.push_back(r);
+        }
+    }
+    b->active.swap(still);
+    return rc;
+}
+
+int grpic_batch_poll(grpic_batch_t *b, int64_t run_id, int32_t *state, int32_t *steps_done, grpic_diag *diag,
+                     int64_t *n_slots, int64_t *particle_steps) {
+    if (!b) return GRPIC_EINVAL;
+    auto it = b->runs.find(run_id);
+    if (it == b->runs.end()) {
+        if (state) *state = GRPIC_RUN_UNKNOWN;
+        return GRPIC_OK;
+    }
+    BatchRun *r = it->second;
+    if (state) *state = r->state;
+    if (steps_done) *steps_done = r->done;
+    if (diag && r->state == GRPIC_RUN_DONE) *diag = r->diag;
+    if (n_slots) *n_slots = r->state == GRPIC_RUN_DONE ? r->n_slots : 0;
+    if (particle_steps) *particle_steps = r->state == GRPIC_RUN_DONE ? r->particle_steps : 0;
+    return GRPIC_OK;
+}
+
+int grpic_batch_dump(grpic_batch_t *b, int64_t run_id, double *x, double *u, uint8_t *sp) {
+    if (!b) return GRPIC_EINVAL;
+    auto it = b->runs.find(run_id);
+    if (it == b->runs.end() || it->second->state != GRPIC_RUN_DONE || !it->second->keep) return GRPIC_ESTATE;
+    BatchRun *r = it->second;
+    if (x) memcpy(x, r->x.data(), r->x.size() * sizeof(double));
+    if (u) memcpy(u, r->u.data(), r->u.size() * sizeof(double));
+    if (sp) memcpy(sp, r->sp.data(), r->sp.size());
+    return GRPIC_OK;
+}
+
+int grpic_batch_release(grpic_batch_t *b, int64_t run_id) {
+    if (!b) return GRPIC_EINVAL;
+    auto it = b->runs.find(run_id);
+    if (it == b->runs.end()) return GRPIC_EINVAL;
+    if (it->second->state != GRPIC_RUN_DONE) return GRPIC_ESTATE;
+    delete it->second;
+    b->runs.erase(it);
+    return GRPIC_OK;
+}
+
+int grpic_batch_stats(grpic_batch_t *b, int32_t *active, int64_t *bytes_in_use) {
+    if (!b) return GRPIC_EINVAL;
+    if (active) *active = (int32_t)b->active.size();
+    if (bytes_in_use) *bytes_in_use = b->used;
+    return GRPIC_OK;
+}
+
+void grpic_batch_destroy(grpic_batch_t *b) {
+    if (!b) return;
+    for (BatchRun *r : b->active) {
+        drop_graphs(r);
+        if (r->h) grpic_destroy(r->h);
+        if (r->stream) (void)hipStreamDestroy(r->stream);
+    }
+    for (auto &kv : b->runs) delete kv.second;
+    delete b;
+}
+
 
 void grpic_config_default(grpic_config *cfg, int32_t nx, int32_t ny, int32_t nz) {
     memset(cfg, 0, sizeof(*cfg));

@@ -1,16 +1,19 @@
 """Seeded synthetic inputs for the GRPIC workloads (shared by tests, the
 benchmark and the oracle-side checks).
 
-This module holds no arithmetic of the method itself: it draws positions and
+This module holds no arithmetic of the method itself (no metric evaluation,
+push, gather, deposit or field step): it draws positions and
 covariant spatial four-velocities from counter-based Philox streams (numpy's
 Philox4x32-10, keyed by seed, purpose and species) and derives the species
 table from the plasma-frequency choice.  Shapes follow the workloads:
 
 - uniform Maxwellian plasma, ppc particles per cell and species, positions
   uniform inside each cell, ions at the electrons' positions (neutral start);
-- torus n ~ exp(-((rho - 24)^2 + z^2)/50) with a Keplerian azimuthal velocity
-  v = c sqrt(m/R) (Euclidean R, prograde = along the frame dragging of the
-  metric, clockwise about +z for a > 0) plus thermal spread;
+- torus n ~ exp(-((rho - 24)^2 + z^2)/50) moving on circular orbits: the
+  Keplerian coordinate speed v = c sqrt(m/R) (Euclidean R, prograde = along
+  the frame dragging of the metric, clockwise about +z for a > 0), given as
+  the covariant velocity of the non-rotating hole's circular geodesic in
+  Kerr-Schild form (closed-form initial data), plus thermal spread;
 - uniform plasma with an infalling shell (|R - edge/4| <= 2 gets v_r = -0.3c).
 
 Velocities are covariant spatial components u_i (the load call completes
@@ -70,26 +73,45 @@ def torus_plasma(seed, nx, ny, nz, m, spin_sign, u_th, n_per_species, center=Non
     cen = np.array(center if center is not None else (nx / 2.0, ny / 2.0, nz / 2.0))
     g = rng(seed, PURPOSE_POS)
     ga = rng(seed, PURPOSE_ACCEPT)
+    # n(rho, z) ~ exp(-((rho - rho0)^2 + z^2)/width2) per unit volume is
+    # rho exp(...) per d rho d phi d z: z and phi are drawn directly, rho from
+    # the Gaussian by rejection against the Jacobian rho / rho_max, and
+    # points outside the grid are dropped.
+    sig = math.sqrt(width2 / 2.0)
+    rho_max = rho0 + 8.0 * sig
+    lo = np.zeros(3)
+    hi = np.array([nx, ny, nz], dtype=float)
     out = np.zeros((3, 0))
     while out.shape[1] < n_per_species:
-        k = max(2 * (n_per_species - out.shape[1]), 1024)
-        cand = g.random((3, k)) * np.array([[nx], [ny], [nz]])
-        d = cand - cen[:, None]
-        rho = np.hypot(d[0], d[1])
-        dens = np.exp(-((rho - rho0) ** 2 + d[2] ** 2) / width2)
-        keep = ga.random(k) < dens
-        out = np.concatenate([out, cand[:, keep]], axis=1)
+        k = max(3 * (n_per_species - out.shape[1]), 1024)
+        rho = g.normal(rho0, sig, k)
+        z = g.normal(0.0, sig, k)
+        phi = g.random(k) * (2.0 * math.pi)
+        keep = (rho > 0.0) & (ga.random(k) * rho_max < rho)
+        cand = np.stack([cen[0] + rho * np.cos(phi), cen[1] + rho * np.sin(phi), cen[2] + z])[:, keep]
+        inside = np.all((cand >= lo[:, None]) & (cand < hi[:, None]), axis=0)
+        out = np.concatenate([out, cand[:, inside]], axis=1)
     x = out[:, :n_per_species]
     d = x - cen[:, None]
     R = np.sqrt((d ** 2).sum(0))
     rho = np.maximum(np.hypot(d[0], d[1]), 1e-12)
-    v = c * np.sqrt(m / np.maximum(R, 1e-12))
-    v = np.minimum(v, 0.9 * c)
-    gam = 1.0 / np.sqrt(1.0 - (v / c) ** 2)
+    # Circular geodesic of the non-rotating hole of mass m written in
+    # Kerr-Schild coordinates (closed-form initial data, the spin enters only
+    # as a perturbation): coordinate speed v = c sqrt(m/R) along phi_hat,
+    # u^4 = 1/sqrt(1 - 3m/R), no contravariant radial motion.  Lowering the
+    # index with g = eta + f k k (f = 2m/R, k = (r_hat, 1)) adds f u^4 r_hat
+    # to the spatial part, so the covariant velocity the loader takes is
+    # u^4 (v phi_hat + f r_hat).  Inside R = 4m (no stable orbit there) the
+    # R = 4m values are used.
+    Rc = np.maximum(R, 4.0 * m / c ** 2) if m > 0 else np.maximum(R, 1e-12)
+    v = c * np.sqrt(m / Rc)
+    u4 = 1.0 / np.sqrt(1.0 - 3.0 * m / (c * c * Rc))
+    f = 2.0 * m / (c * c * Rc)
     # prograde: with the frame dragging of the metric (clockwise for spin_sign > 0)
     sgn = -1.0 if spin_sign > 0 else 1.0
     phi_hat = np.stack([-d[1] / rho, d[0] / rho, np.zeros_like(rho)]) * sgn
-    base = phi_hat * (gam * v)
+    r_hat = d / np.maximum(R, 1e-12)
+    base = u4 * (phi_hat * v + r_hat * (f * c))
     ue = base + maxwellian(seed, 0, n_per_species, u_th)
     ui = base + maxwellian(seed, 1, n_per_species, u_th / math.sqrt(mass_ratio))
     return [(0, x, ue), (1, x.copy(), ui)]

@@ -15,13 +15,13 @@ from common import alive, gpu_run, oracle_sim, params, rel_err, say
 pytestmark = pytest.mark.gpu
 
 
-def _run(P, capacity, precision, sort_every=0):
+def _run(P, capacity, precision, sort_every=0, fp_bits=50):
     from paper_0904_0232_amd import capi
     from paper_0904_0232_amd import run as R
     cfg = R.make_config(P["n"], m=P["m"], a=P["a"], dt=P["dt"], B0=P["B0"], species=P["species"],
                         r_rm=P["r_rm"], gamma_mode=P["gamma_mode"], deposit_mode=P["deposit_mode"],
                         field_iters=P["field_iters"], damp_max=P["damp_max"], sort_every=sort_every,
-                        capacity=capacity, fp_bits=50,
+                        capacity=capacity, fp_bits=fp_bits,
                         precision=capi.FP32_MIXED if precision == "fp32" else capi.FP64)
     return R.Run(cfg)
 
@@ -128,36 +128,82 @@ def test_mixed_sort_keys_bit_exact():
     assert np.array_equal(perm, po)
 
 
-def test_mixed_torus_test_particles_1000_steps():
-    """The 128^3 Kerr a=0.5m torus workload (Keplerian disk around an m=4
-    hole), sampled to 20,000 particles per species, in test-particle mode
-    (frozen initial fields, no removal) for 1000 RK4 steps: FP32-mixed
-    against FP64 from the same loaded state.  Particles whose FP64 path came
-    within 3 m of the hole or left the grid are not tracked."""
+def _torus_runs(nps, B0, start_same):
+    """FP64 and FP32-mixed runs of the 128^3 torus workload (Kerr a = 0.5m,
+    m = 4) with nps particles per species, in the same slot order.  With
+    start_same the FP64 run starts from the mixed run's loaded state (the
+    inputs rounded to FP32 offsets and velocities), so differences come from
+    the FP32 arithmetic of the steps alone."""
     from paper_0904_0232_amd import inputs
     w = inputs.workload_params("torus128")
-    P = params(w["n"], m=w["m"], a=w["a"], dt=w["dt"], B0=(0.0, 0.0, w["B0"]), species=w["species"])
-    parts = inputs.workload_particles("torus128", seed=0, n_override=20000)
-    r64, r32 = _pair(parts, P=P)
+    P = params(w["n"], m=w["m"], a=w["a"], dt=w["dt"], B0=(0.0, 0.0, B0), species=w["species"], r_rm=w["r_rm"])
+    parts = inputs.workload_particles("torus128", seed=0, n_override=nps)
+    cap = 2 * nps
+    # 44 fraction bits: the densest torus cells sum ~10^4 contributions
+    r64, r32 = _run(P, cap, "fp64", fp_bits=44), _run(P, cap, "fp32", fp_bits=44)
+    for sp, x, uc in parts:
+        r32.load(sp, x, uc)
+        if not start_same:
+            r64.load(sp, x, uc)
+    r32.sort()
+    if start_same:
+        r64.restore_particles(*r32.particles())
+    else:
+        r64.sort()
+    return w, r64, r32
+
+
+def test_mixed_torus_geodesic_1000_steps():
+    """Test particles of the torus workload on geodesics (no field) for 1000
+    RK4 steps, FP32-mixed against FP64 from the same start.  Particles whose
+    FP64 path leaves the grid or comes within 3m of the hole (plunging orbits
+    from inside the marginally stable radius, which amplify any difference)
+    are not counted as regular."""
+    w, r64, r32 = _torus_runs(20000, 0.0, True)
     cen = np.full(3, w["n"] / 2.0)
-    tracked = None
+    regular = None
     for block in range(10):
         r64.push_only(100)
         r32.push_only(100)
         x6, u6, s6 = r64.particles()
         R = np.sqrt(((x6 - cen[:, None]) ** 2).sum(0))
         ok = np.all((x6 >= 0) & (x6 < w["n"]), axis=0) & (R > 3.0 * w["m"]) & np.isfinite(u6).all(0)
-        tracked = ok if tracked is None else (tracked & ok)
+        regular = ok if regular is None else (regular & ok)
     x3, u3, s3 = r32.particles()
-    ex = (np.abs(x3 - x6) / np.maximum(np.abs(x6), 1.0)).max(axis=0)[tracked]
-    eu = (np.abs(u3 - u6) / np.maximum(np.abs(u6), 1.0)).max(axis=0)[tracked]
-    frac = float(((ex < 1e-4) & (eu < 1e-4)).mean())
-    say("torus test particles, 1000 steps: %d of %d tracked, x err median %.2e p99 %.2e max %.2e, "
-        "u err median %.2e p99 %.2e max %.2e, fraction within 1e-4: %.4f"
-        % (tracked.sum(), tracked.size, np.median(ex), np.quantile(ex, 0.99), ex.max(), np.median(eu),
-           np.quantile(eu, 0.99), eu.max(), frac))
-    assert tracked.sum() > 0.5 * tracked.size
+    ex = (np.abs(x3 - x6) / np.maximum(np.abs(x6), 1.0)).max(axis=0)[regular]
+    eu = (np.abs(u3 - u6) / np.maximum(np.abs(u6), 1.0)).max(axis=0)[regular]
+    e = np.maximum(ex, eu)
+    frac = float((e < 1e-4).mean())
+    say("torus geodesics, 1000 steps: %d of %d regular, error median %.2e p90 %.2e p99 %.2e, "
+        "fraction within 1e-4: %.4f" % (regular.sum(), regular.size, np.median(e), np.quantile(e, 0.9),
+                                         np.quantile(e, 0.99), frac))
+    assert regular.sum() > 0.5 * regular.size
+    assert np.median(e) < 1e-5
     assert frac > 0.95
+
+
+def test_mixed_torus_current_one_step():
+    """One self-consistent cycle of the torus workload (1M particles per
+    species, field B_z = 0.1): the FP32-mixed current against FP64 from the
+    same start, within 1e-5 of max|J|.  From the exact inputs instead, a few
+    particles within an FP32 rounding of a cell face take the other crossing
+    decision, and the zigzag relay point jumps there; electrons and ions
+    nearly cancel in this co-rotating plasma, so that shows in the max norm
+    (printed, bounded only in L2)."""
+    for same in (True, False):
+        w, r64, r32 = _torus_runs(1 << 20, 0.1, same)
+        r64.step(1)
+        r32.step(1)
+        J6, J3 = r64.fields("J"), r32.fields("J")
+        emax = np.abs(J3 - J6).max() / np.abs(J6).max()
+        el2 = np.linalg.norm(J3 - J6) / np.linalg.norm(J6)
+        say("torus one cycle, %s start: J max-rel %.2e, L2-rel %.2e" % ("same" if same else "exact-input", emax, el2))
+        if same:
+            assert emax < 1e-5
+        else:
+            assert el2 < 1e-5
+        r64.close()
+        r32.close()
 
 
 def test_mixed_gyration_closed_form():
