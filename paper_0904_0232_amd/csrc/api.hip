@@ -450,7 +450,7 @@ int64_t run_bytes(const grpic_config *c) {
         b += 2 * (up(cap * 4) + 3 * up(cap * 4) + 4 * up(cap * 4) + up(cap));
     else
         b += 2 * (3 * up(cap * 8) + 4 * up(cap * 8) + up(cap));
-    b += up(64) + 4 * up(cap * 4) + up((int64_t)sort_temp_bytes(cap)) + up(gs * 8);
+    b += up(kCounterWords * 8) + 4 * up(cap * 4) + up((int64_t)sort_temp_bytes(cap)) + up(gs * 8);
     b += up((((cap + 255) / 256) * 12 + ((nn + 255) / 256) * 3 + 64) * 8);
     b += up(6 * cap * 8);  // load staging
     return b;
@@ -792,7 +792,7 @@ int grpic_create(const grpic_config *cfg, void *stream, grpic_t **out) {
         }
         h->psp[b] = (uint8_t *)A(cap);
     }
-    h->counters = (unsigned long long *)A(C_NCOUNTERS * 8);
+    h->counters = (unsigned long long *)A(kCounterWords * 8);
     h->keys = (uint32_t *)A(cap * 4);
     h->keys_alt = (uint32_t *)A(cap * 4);
     h->idx = (uint32_t *)A(cap * 4);
@@ -815,7 +815,7 @@ int grpic_create(const grpic_config *cfg, void *stream, grpic_t **out) {
 
     hipStream_t s = h->stream;
     rc = GRPIC_OK;
-    if (FAILS(hipMemsetAsync(h->counters, 0, C_NCOUNTERS * 8, s))) rc = GRPIC_EDEVICE;
+    if (FAILS(hipMemsetAsync(h->counters, 0, kCounterWords * 8, s))) rc = GRPIC_EDEVICE;
     for (int b = 0; b < 2 && !rc; b++)
         if (FAILS(hipMemsetAsync(h->psp[b], GRPIC_DEAD, cap, s))) rc = GRPIC_EDEVICE;
     if (!rc) rc = h->mixed ? init_fields<float>(h, h->F32) : init_fields<double>(h, h->F64);
@@ -1047,10 +1047,12 @@ int grpic_read_timing(grpic_t *h, double *ms, int64_t *launches) {
 
 int grpic_particle_steps(grpic_t *h, int64_t *out) {
     if (!h || !out) return GRPIC_EINVAL;
-    unsigned long long v = 0;
-    int rc = check(hipMemcpyAsync(&v, h->counters + C_PUSHED, 8, hipMemcpyDeviceToHost, h->stream));
+    std::vector<unsigned long long> v(kCounterWords);
+    int rc = check(hipMemcpyAsync(v.data(), h->counters, kCounterWords * 8, hipMemcpyDeviceToHost, h->stream));
     if (!rc) rc = check(hipStreamSynchronize(h->stream));
-    *out = (int64_t)v;
+    unsigned long long sum = 0;
+    for (int s = 0; s < kPushedSlots; s++) sum += v[pushed_index((unsigned)s)];
+    *out = (int64_t)sum;
     return rc;
 }
 

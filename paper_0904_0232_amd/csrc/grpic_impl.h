@@ -67,9 +67,16 @@ enum Counter {
     C_REMOVED_OUTER = 3,
     C_FLAGS = 4,
     C_LOAD_KEPT = 5,
-    C_PUSHED = 6,      // live particles pushed, summed over steps
     C_NCOUNTERS = 8
 };
+
+// The particle-step counter (live particles pushed, summed over steps) gets
+// one increment per wave of every push: it is spread over kPushedSlots cache
+// lines after the first, so same-address atomics do not serialise the push.
+// The counter is the sum of the slots.
+constexpr int kPushedSlots = 64;
+constexpr int kCounterWords = 16 * (1 + kPushedSlots);
+__host__ __device__ inline int pushed_index(unsigned block) { return 16 * (1 + (int)(block & (kPushedSlots - 1))); }
 
 struct PushParams {
     Grid G;

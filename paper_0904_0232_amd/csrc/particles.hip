@@ -7,35 +7,48 @@
 
 namespace grpic {
 
-
-// Lorentz term (q/m-free) L^a = F^a_b(X) u^b with F^a_b gathered trilinearly
-// from the nodes (cloud-in-cell with sqrt(-det g) = 1, Sec. 3.3): the
-// contraction with u is taken node by node, L = sum_n W_n (F_n u), so only four
-// accumulators stay live.  The cell is floor(X) clamped to the grid; the
-// offset is not clamped.
-__device__ __forceinline__ void gather_lorentz(const Grid &G, const double *__restrict__ node, const double X[3],
-                                               const double U[4], double L[4]) {
-    int c[3];
-    double w[3];
-    for (int ax = 0; ax < 3; ax++) {
-        int n = G.dim(ax);
-        int ci = (int)floor(X[ax]);
-        ci = ci < 0 ? 0 : (ci > n - 1 ? n - 1 : ci);
-        c[ax] = ci;
-        w[ax] = X[ax] - (double)ci;
+__device__ __forceinline__ int wave_min(int v) {
+    for (int o = 32; o > 0; o >>= 1) {
+        int w = __shfl_xor(v, o, 64);
+        v = w < v ? w : v;
     }
-    L[0] = L[1] = L[2] = L[3] = 0.0;
-    const int64_t sj = G.nx + 1, sk = (int64_t)(G.nx + 1) * (G.ny + 1);
-    const double *base = node + 16 * G.node(c[0], c[1], c[2]);
+    return v;
+}
+__device__ __forceinline__ int wave_max(int v) {
+    for (int o = 32; o > 0; o >>= 1) {
+        int w = __shfl_xor(v, o, 64);
+        v = w > v ? w : v;
+    }
+    return v;
+}
+
+
+// Node tensor rows in LDS: 16 doubles per node padded to 18, so nodes one
+// apart start 4 banks apart.
+constexpr int kNodeStride2 = 9;  // double2 per staged node
+
+// A block's copy of the node tensor over the node box [lo, lo + n) (x
+// fastest), or use = false (the block reads global memory).
+struct NodeBox {
+    const double2 *lds;
+    int lo[3], n[3];
+    bool use;
+};
+
+// L^a += sum over the 8 nodes of W_n (F_n u)^a, nodes addressed from the
+// (0,0,0) node `p` with strides (in double2) si, sj, sk; the contraction with
+// u is taken node by node, so only four accumulators stay live.
+__device__ __forceinline__ void gather_rows(const double2 *p, int64_t si, int64_t sj, int64_t sk, const double w[3],
+                                            const double U[4], double L[4]) {
 #pragma unroll 1
     for (int q = 0; q < 4; q++) {
         const int dj = q & 1, dk = q >> 1;
         const double wyz = (dj ? w[1] : 1.0 - w[1]) * (dk ? w[2] : 1.0 - w[2]);
-        const double2 *p = reinterpret_cast<const double2 *>(base + 16 * (dj * sj + dk * sk));
+        const double2 *pq = p + dj * sj + dk * sk;
 #pragma unroll
         for (int di = 0; di < 2; di++) {
             const double W = (di ? w[0] : 1.0 - w[0]) * wyz;
-            const double2 *pn = p + 8 * di;
+            const double2 *pn = pq + di * si;
 #pragma unroll
             for (int a = 0; a < 4; a++) {
                 double2 f01 = pn[2 * a], f23 = pn[2 * a + 1];
@@ -46,11 +59,40 @@ __device__ __forceinline__ void gather_lorentz(const Grid &G, const double *__re
     }
 }
 
+// Cell of a gather: floor(X) clamped to the grid (the offset is not clamped).
+__device__ __forceinline__ void gather_cell(const Grid &G, const double X[3], int c[3]) {
+    for (int ax = 0; ax < 3; ax++) {
+        int n = G.dim(ax);
+        int ci = (int)floor(X[ax]);
+        c[ax] = ci < 0 ? 0 : (ci > n - 1 ? n - 1 : ci);
+    }
+}
+
+// Lorentz term (q/m-free) L^a = F^a_b(X) u^b with F^a_b gathered trilinearly
+// from the nodes of cell c (cloud-in-cell with sqrt(-det g) = 1, Sec. 3.3),
+// from the block's LDS box when it holds one, else from global memory; the
+// arithmetic is the same.
+__device__ __forceinline__ void gather_lorentz(const Grid &G, const double *__restrict__ node, const NodeBox &B,
+                                               const int c[3], const double X[3], const double U[4], double L[4]) {
+    double w[3];
+    for (int ax = 0; ax < 3; ax++) w[ax] = X[ax] - (double)c[ax];
+    L[0] = L[1] = L[2] = L[3] = 0.0;
+    if (B.use) {
+        const int64_t l = ((int64_t)(c[2] - B.lo[2]) * B.n[1] + (c[1] - B.lo[1])) * B.n[0] + (c[0] - B.lo[0]);
+        gather_rows(B.lds + kNodeStride2 * l, kNodeStride2, kNodeStride2 * B.n[0],
+                    (int64_t)kNodeStride2 * B.n[0] * B.n[1], w, U, L);
+    } else {
+        const int64_t sj = G.nx + 1, sk = (int64_t)(G.nx + 1) * (G.ny + 1);
+        gather_rows(reinterpret_cast<const double2 *>(node) + 8 * G.node(c[0], c[1], c[2]), 8, 8 * sj, 8 * sk, w, U,
+                    L);
+    }
+}
+
 // du^a/dtau = (q/m) F^a_b u^b - Gamma^a_{mn} u^m u^n  (Sec. 3.3)
-__device__ __forceinline__ void accel(const PushParams &P, const double *__restrict__ node, double qm,
-                                      const double X[3], const double U[4], double A[4]) {
+__device__ __forceinline__ void accel(const PushParams &P, const double *__restrict__ node, const NodeBox &B,
+                                      const int c[3], double qm, const double X[3], const double U[4], double A[4]) {
     double L[4];
-    gather_lorentz(P.G, node, X, U, L);
+    gather_lorentz(P.G, node, B, c, X, U, L);
     double Gm[4] = {0.0, 0.0, 0.0, 0.0};
     if (P.h.m != 0.0) {
         KSGrad kp;
@@ -74,44 +116,106 @@ __device__ __forceinline__ double stage_gamma(const PushParams &P, double u4, do
     return 0.5 * (uc + sqrt(disc));
 }
 
+constexpr int kPushBlock = 256;
+constexpr int kPushLdsNodes = 256;  // 36 KB of padded node tensor per block
+
+// Stage the nodes of the cells the block's live lanes gather from (cell c of
+// each live lane, nodes c .. c+1) into LDS when the box fits.  Every thread
+// of the block calls this; it synchronises the block twice (before the box
+// is overwritten and after it is filled).
+__device__ __forceinline__ void stage_nodes(const Grid &G, const double *__restrict__ node, bool live, const int c[3],
+                                            double2 *snode, int (*sred)[kPushBlock / 64], NodeBox &B) {
+    const int tid = threadIdx.x;
+    for (int ax = 0; ax < 3; ax++) {
+        int a = wave_min(live ? c[ax] : (1 << 30)), b = wave_max(live ? c[ax] : -(1 << 30));
+        if ((tid & 63) == 0) {
+            sred[ax][tid >> 6] = a;
+            sred[3 + ax][tid >> 6] = b;
+        }
+    }
+    __syncthreads();  // also: every wave has finished reading the previous box
+    int count = 1;
+    for (int ax = 0; ax < 3; ax++) {
+        int a = sred[ax][0], b = sred[3 + ax][0];
+        for (int w = 1; w < kPushBlock / 64; w++) {
+            a = sred[ax][w] < a ? sred[ax][w] : a;
+            b = sred[3 + ax][w] > b ? sred[3 + ax][w] : b;
+        }
+        B.lo[ax] = a;
+        B.n[ax] = b >= a ? b - a + 2 : 0;  // nodes a .. b+1
+        count = (B.n[ax] > 0 && count <= kPushLdsNodes) ? count * B.n[ax] : 0;
+    }
+    B.use = count > 0 && count <= kPushLdsNodes;  // count = 0: no live lane
+    if (B.use) {
+        const double2 *src = reinterpret_cast<const double2 *>(node);
+        const int nb0 = B.n[0], nb01 = B.n[0] * B.n[1];
+        for (int e = tid; e < count * 8; e += kPushBlock) {
+            const int l = e >> 3, part = e & 7;
+            const int lk = l / nb01, r = l - lk * nb01, lj = r / nb0, li = r - lj * nb0;
+            snode[kNodeStride2 * l + part] = src[8 * G.node(B.lo[0] + li, B.lo[1] + lj, B.lo[2] + lk) + part];
+        }
+    }
+    __syncthreads();
+}
+
 // Classic RK4 in coordinate time on Y = (x, u): K_k = (u_k, A_k)/gamma_k,
 // stages at dt/2, dt/2, dt, combination 1:2:2:1 over 6.
-__global__ __launch_bounds__(256, 4) void k_push(PushParams P, Species cS, const double *__restrict__ node,
-                                              ParticlePtrs in, ParticlePtrs out, unsigned long long *counters) {
-    int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+//
+// Before each stage the block copies the node tensor of the box of cells its
+// particles gather from into LDS: cell-sorted particles of one block cover a
+// few cells, so each node is read from L2/HBM once per block and stage
+// instead of once per particle.
+__global__ __launch_bounds__(kPushBlock, 4) void k_push(PushParams P, Species cS, const double *__restrict__ node,
+                                                     ParticlePtrs in, ParticlePtrs out,
+                                                     unsigned long long *counters) {
+    __shared__ double2 snode[kPushLdsNodes * kNodeStride2];
+    __shared__ int sred[6][kPushBlock / 64];
+    const int tid = threadIdx.x;
+    const int64_t id = (int64_t)blockIdx.x * kPushBlock + tid;
     int clamps = 0;
-    uint8_t sp = id < P.n ? in.sp[id] : kDead;
-    unsigned long long live = __ballot(sp != kDead);
-    if ((threadIdx.x & 63) == 0 && live) atomicAdd(&counters[C_PUSHED], (unsigned long long)__popcll(live));
-    {
-        if (sp != kDead) {
-            double qm = cS.qm[sp];
-            double X0[3] = {in.x[0][id], in.x[1][id], in.x[2][id]};
-            double U0[4] = {in.u[0][id], in.u[1][id], in.u[2][id], in.u[3][id]};
-            double Xs[3] = {X0[0], X0[1], X0[2]};
-            double Us[4] = {U0[0], U0[1], U0[2], U0[3]};
-            double Sx[3] = {0.0, 0.0, 0.0}, Su[4] = {0.0, 0.0, 0.0, 0.0};
+    const uint8_t sp = id < P.n ? in.sp[id] : kDead;
+    const bool live = sp != kDead;
+    const unsigned long long ballot = __ballot(live);
+    if ((tid & 63) == 0 && ballot)
+        atomicAdd(&counters[pushed_index(blockIdx.x)], (unsigned long long)__popcll(ballot));
+    double X0[3] = {0.0, 0.0, 0.0}, U0[4] = {0.0, 0.0, 0.0, 0.0};
+    double qm = 0.0;
+    if (live) {
+        qm = cS.qm[sp];
+        for (int q = 0; q < 3; q++) X0[q] = in.x[q][id];
+        for (int q = 0; q < 4; q++) U0[q] = in.u[q][id];
+    }
+    double Xs[3] = {X0[0], X0[1], X0[2]};
+    double Us[4] = {U0[0], U0[1], U0[2], U0[3]};
+    double Sx[3] = {0.0, 0.0, 0.0}, Su[4] = {0.0, 0.0, 0.0, 0.0};
+    NodeBox B;
+    B.lds = snode;
 #pragma unroll 1
-            for (int st = 0; st < 4; st++) {
-                double A[4];
-                accel(P, node, qm, Xs, Us, A);
-                double gam = stage_gamma(P, Us[3], A[3], clamps);
-                double ig = 1.0 / gam;
-                double Kx[3] = {Us[0] * ig, Us[1] * ig, Us[2] * ig};
-                double Ku[4] = {A[0] * ig, A[1] * ig, A[2] * ig, A[3] * ig};
-                double wgt = (st == 0 || st == 3) ? 1.0 : 2.0;
-                for (int q = 0; q < 3; q++) Sx[q] += wgt * Kx[q];
-                for (int q = 0; q < 4; q++) Su[q] += wgt * Ku[q];
-                if (st < 3) {
-                    double fac = (st < 2 ? 0.5 : 1.0) * P.dt;
-                    for (int q = 0; q < 3; q++) Xs[q] = X0[q] + fac * Kx[q];
-                    for (int q = 0; q < 4; q++) Us[q] = U0[q] + fac * Ku[q];
-                }
+    for (int st = 0; st < 4; st++) {
+        int c[3];
+        gather_cell(P.G, Xs, c);
+        stage_nodes(P.G, node, live, c, snode, sred, B);
+        if (live) {
+            double A[4];
+            accel(P, node, B, c, qm, Xs, Us, A);
+            double gam = stage_gamma(P, Us[3], A[3], clamps);
+            double ig = 1.0 / gam;
+            double Kx[3] = {Us[0] * ig, Us[1] * ig, Us[2] * ig};
+            double Ku[4] = {A[0] * ig, A[1] * ig, A[2] * ig, A[3] * ig};
+            double wgt = (st == 0 || st == 3) ? 1.0 : 2.0;
+            for (int q = 0; q < 3; q++) Sx[q] += wgt * Kx[q];
+            for (int q = 0; q < 4; q++) Su[q] += wgt * Ku[q];
+            if (st < 3) {
+                double fac = (st < 2 ? 0.5 : 1.0) * P.dt;
+                for (int q = 0; q < 3; q++) Xs[q] = X0[q] + fac * Kx[q];
+                for (int q = 0; q < 4; q++) Us[q] = U0[q] + fac * Ku[q];
             }
-            double h6 = P.dt / 6.0;
-            for (int q = 0; q < 3; q++) out.x[q][id] = X0[q] + h6 * Sx[q];
-            for (int q = 0; q < 4; q++) out.u[q][id] = U0[q] + h6 * Su[q];
         }
+    }
+    if (live) {
+        double h6 = P.dt / 6.0;
+        for (int q = 0; q < 3; q++) out.x[q][id] = X0[q] + h6 * Sx[q];
+        for (int q = 0; q < 4; q++) out.u[q][id] = U0[q] + h6 * Su[q];
     }
     if (clamps) atomicAdd(&counters[C_GAMMA_CLAMPS], (unsigned long long)clamps);
 }
@@ -119,8 +223,8 @@ __global__ __launch_bounds__(256, 4) void k_push(PushParams P, Species cS, const
 void launch_push(const PushParams &P, const Species &S, const double *node, ParticlePtrs in, ParticlePtrs out,
                  unsigned long long *counters, hipStream_t s) {
     if (P.n <= 0) return;
-    unsigned nb = (unsigned)((P.n + 255) / 256);
-    hipLaunchKernelGGL(k_push, dim3(nb), dim3(256), 0, s, P, S, node, in, out, counters);
+    unsigned nb = (unsigned)((P.n + kPushBlock - 1) / kPushBlock);
+    hipLaunchKernelGGL(k_push, dim3(nb), dim3(kPushBlock), 0, s, P, S, node, in, out, counters);
 }
 
 // ---------------------------------------------------------------------------
@@ -264,21 +368,6 @@ __device__ __forceinline__ bool zigzag(const Grid &G, const double x1[3], const 
         if (c1[ax] < -1 || c1[ax] > nn || c2[ax] < -1 || c2[ax] > nn || !(fabs(x2[ax] - x1[ax]) < 1.0)) ok = false;
     }
     return ok;
-}
-
-__device__ __forceinline__ int wave_min(int v) {
-    for (int o = 32; o > 0; o >>= 1) {
-        int w = __shfl_xor(v, o, 64);
-        v = w < v ? w : v;
-    }
-    return v;
-}
-__device__ __forceinline__ int wave_max(int v) {
-    for (int o = 32; o > 0; o >>= 1) {
-        int w = __shfl_xor(v, o, 64);
-        v = w > v ? w : v;
-    }
-    return v;
 }
 
 // One block deposits kDepBlock*kDepPPT consecutive particles.  When the

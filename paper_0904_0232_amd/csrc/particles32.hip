@@ -11,6 +11,21 @@
 
 namespace grpic {
 
+__device__ __forceinline__ int wave_min32(int v) {
+    for (int o = 32; o > 0; o >>= 1) {
+        int w = __shfl_xor(v, o, 64);
+        v = w < v ? w : v;
+    }
+    return v;
+}
+__device__ __forceinline__ int wave_max32(int v) {
+    for (int o = 32; o > 0; o >>= 1) {
+        int w = __shfl_xor(v, o, 64);
+        v = w > v ? w : v;
+    }
+    return v;
+}
+
 __device__ __forceinline__ void hole_rel(const Hole &h, int i, int j, int k, const float X[3], double &x, double &y,
                                          double &z) {
     x = ((double)i - h.cx) + (double)X[0];
@@ -18,35 +33,34 @@ __device__ __forceinline__ void hole_rel(const Hole &h, int i, int j, int k, con
     z = ((double)k - h.cz) + (double)X[2];
 }
 
-// L^a = F^a_b u^b gathered from the FP32 node tensor; X is the offset
-// relative to cell (i,j,k) and may leave [0,1) by up to a cell.
-__device__ __forceinline__ void gather_lorentz32(const Grid &G, const float *__restrict__ node, int i, int j, int k,
-                                                 const float X[3], const float U[4], float L[4]) {
-    const int base[3] = {i, j, k};
-    int c[3];
-    float w[3];
-    for (int ax = 0; ax < 3; ax++) {
-        int n = G.dim(ax);
-        float fl = floorf(X[ax]);
-        int ci = base[ax] + (int)fl;
-        ci = ci < 0 ? 0 : (ci > n - 1 ? n - 1 : ci);
-        c[ax] = ci;
-        w[ax] = (float)(base[ax] - ci) + X[ax];
-    }
-    L[0] = L[1] = L[2] = L[3] = 0.0f;
-    const int64_t sj = G.nx + 1, sk = (int64_t)(G.nx + 1) * (G.ny + 1);
-    const float *b0 = node + 16 * G.node(c[0], c[1], c[2]);
+// FP32 node tensor rows in LDS: 16 floats per node padded to 20, so nodes one
+// apart start 4 banks apart.
+constexpr int kNode32Stride4 = 5;  // float4 per staged node
+
+// A block's LDS copy of the FP32 node tensor over the node box [lo, lo + n)
+// (x fastest), or use = false.
+struct NodeBox32 {
+    const float4 *lds;
+    int lo[3], n[3];
+    bool use;
+};
+
+// L^a += sum over the 8 nodes of W_n (F_n u)^a from the (0,0,0) node p and
+// strides (in float4) si, sj, sk.
+__device__ __forceinline__ void gather_rows32(const float4 *p, int64_t si, int64_t sj, int64_t sk, const float w[3],
+                                              const float U[4], float L[4]) {
 #pragma unroll 1
     for (int q = 0; q < 4; q++) {
         const int dj = q & 1, dk = q >> 1;
         const float wyz = (dj ? w[1] : 1.0f - w[1]) * (dk ? w[2] : 1.0f - w[2]);
-        const float4 *p = reinterpret_cast<const float4 *>(b0 + 16 * (dj * sj + dk * sk));
+        const float4 *pq = p + dj * sj + dk * sk;
 #pragma unroll
         for (int di = 0; di < 2; di++) {
             const float W = (di ? w[0] : 1.0f - w[0]) * wyz;
+            const float4 *pn = pq + di * si;
 #pragma unroll
             for (int a = 0; a < 4; a++) {
-                float4 f = p[4 * di + a];
+                float4 f = pn[a];
                 float row = f.x * U[0] + f.y * U[1] + f.z * U[2] + f.w * U[3];
                 L[a] += W * row;
             }
@@ -54,10 +68,42 @@ __device__ __forceinline__ void gather_lorentz32(const Grid &G, const float *__r
     }
 }
 
-__device__ __forceinline__ void accel32(const PushParams &P, const Mixed &M, const float *__restrict__ node, float qm,
-                                        int i, int j, int k, const float X[3], const float U[4], float A[4]) {
+// Gather cell of offset X relative to cell `base`: base + floor(X), clamped
+// to the grid.
+__device__ __forceinline__ void gather_cell32(const Grid &G, const int base[3], const float X[3], int c[3]) {
+    for (int ax = 0; ax < 3; ax++) {
+        int n = G.dim(ax);
+        int ci = base[ax] + (int)floorf(X[ax]);
+        c[ax] = ci < 0 ? 0 : (ci > n - 1 ? n - 1 : ci);
+    }
+}
+
+// L^a = F^a_b u^b gathered from the FP32 node tensor at offset X relative to
+// cell `base` (X may leave [0,1) by up to a cell), from the nodes of the
+// gather cell c, read from the block's LDS box when it holds one.
+__device__ __forceinline__ void gather_lorentz32(const Grid &G, const float *__restrict__ node, const NodeBox32 &B,
+                                                 const int base[3], const int c[3], const float X[3],
+                                                 const float U[4], float L[4]) {
+    float w[3];
+    for (int ax = 0; ax < 3; ax++) w[ax] = (float)(base[ax] - c[ax]) + X[ax];
+    L[0] = L[1] = L[2] = L[3] = 0.0f;
+    if (B.use) {
+        const int64_t l = ((int64_t)(c[2] - B.lo[2]) * B.n[1] + (c[1] - B.lo[1])) * B.n[0] + (c[0] - B.lo[0]);
+        gather_rows32(B.lds + kNode32Stride4 * l, kNode32Stride4, kNode32Stride4 * B.n[0],
+                      (int64_t)kNode32Stride4 * B.n[0] * B.n[1], w, U, L);
+    } else {
+        const int64_t sj = G.nx + 1, sk = (int64_t)(G.nx + 1) * (G.ny + 1);
+        gather_rows32(reinterpret_cast<const float4 *>(node) + 4 * G.node(c[0], c[1], c[2]), 4, 4 * sj, 4 * sk, w,
+                      U, L);
+    }
+}
+
+__device__ __forceinline__ void accel32(const PushParams &P, const Mixed &M, const float *__restrict__ node,
+                                        const NodeBox32 &B, const int c[3], float qm, int i, int j, int k,
+                                        const float X[3], const float U[4], float A[4]) {
     float L[4];
-    gather_lorentz32(P.G, node, i, j, k, X, U, L);
+    const int base[3] = {i, j, k};
+    gather_lorentz32(P.G, node, B, base, c, X, U, L);
     float Gm[4] = {0.0f, 0.0f, 0.0f, 0.0f};
     if (P.h.m != 0.0) {
         double x, y, z;
@@ -91,30 +137,87 @@ __device__ __forceinline__ float stage_gamma32(const PushParams &P, float u4, fl
     return 0.5f * (uc + sqrtf(disc));
 }
 
+constexpr int kPush32Block = 256;
+constexpr int kPush32LdsNodes = 448;  // 35 KB of padded FP32 node tensor per block
+
+// Stage the FP32 nodes of the cells the block's live lanes gather from into
+// LDS when the box fits (as the FP64 pusher does).  Every thread of the block
+// calls this; it synchronises the block twice.
+__device__ __forceinline__ void stage_nodes32(const Grid &G, const float *__restrict__ node, bool live, const int c[3],
+                                              float4 *snode, int (*sred)[kPush32Block / 64], NodeBox32 &B) {
+    const int tid = threadIdx.x;
+    for (int ax = 0; ax < 3; ax++) {
+        int a = wave_min32(live ? c[ax] : (1 << 30)), b = wave_max32(live ? c[ax] : -(1 << 30));
+        if ((tid & 63) == 0) {
+            sred[ax][tid >> 6] = a;
+            sred[3 + ax][tid >> 6] = b;
+        }
+    }
+    __syncthreads();  // also: every wave has finished reading the previous box
+    int count = 1;
+    for (int ax = 0; ax < 3; ax++) {
+        int a = sred[ax][0], b = sred[3 + ax][0];
+        for (int w = 1; w < kPush32Block / 64; w++) {
+            a = sred[ax][w] < a ? sred[ax][w] : a;
+            b = sred[3 + ax][w] > b ? sred[3 + ax][w] : b;
+        }
+        B.lo[ax] = a;
+        B.n[ax] = b >= a ? b - a + 2 : 0;  // nodes a .. b+1
+        count = (B.n[ax] > 0 && count <= kPush32LdsNodes) ? count * B.n[ax] : 0;
+    }
+    B.use = count > 0 && count <= kPush32LdsNodes;  // count = 0: no live lane
+    if (B.use) {
+        const float4 *src = reinterpret_cast<const float4 *>(node);
+        const int nb0 = B.n[0], nb01 = B.n[0] * B.n[1];
+        for (int e = tid; e < count * 4; e += kPush32Block) {
+            const int l = e >> 2, part = e & 3;
+            const int lk = l / nb01, r = l - lk * nb01, lj = r / nb0, li = r - lj * nb0;
+            snode[kNode32Stride4 * l + part] = src[4 * G.node(B.lo[0] + li, B.lo[1] + lj, B.lo[2] + lk) + part];
+        }
+    }
+    __syncthreads();
+}
+
 // The same RK4 in coordinate time as the FP64 pusher, on offsets relative
-// to the particle's cell; the cell is re-based after the step.
-__global__ __launch_bounds__(256, 4) void k_push32(PushParams P, Mixed M, Species cS, const float *__restrict__ node,
-                                                   ParticlePtrs32 in, ParticlePtrs32 out,
-                                                   unsigned long long *counters) {
-    int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+// to the particle's cell; the cell is re-based after the step.  The nodes of
+// each stage are staged in LDS per block, as in the FP64 pusher.
+__global__ __launch_bounds__(kPush32Block, 4) void k_push32(PushParams P, Mixed M, Species cS,
+                                                           const float *__restrict__ node, ParticlePtrs32 in,
+                                                           ParticlePtrs32 out, unsigned long long *counters) {
+    __shared__ float4 snode[kPush32LdsNodes * kNode32Stride4];
+    __shared__ int sred[6][kPush32Block / 64];
+    const int tid = threadIdx.x;
+    const int64_t id = (int64_t)blockIdx.x * kPush32Block + tid;
     int clamps = 0;
-    uint8_t sp = id < P.n ? in.sp[id] : kDead;
-    unsigned long long live = __ballot(sp != kDead);
-    if ((threadIdx.x & 63) == 0 && live) atomicAdd(&counters[C_PUSHED], (unsigned long long)__popcll(live));
-    if (sp != kDead) {
-        const float qm = (float)cS.qm[sp];
-        int i, j, k;
+    const uint8_t sp = id < P.n ? in.sp[id] : kDead;
+    const bool alive = sp != kDead;
+    const unsigned long long live = __ballot(alive);
+    if ((tid & 63) == 0 && live)
+        atomicAdd(&counters[pushed_index(blockIdx.x)], (unsigned long long)__popcll(live));
+    int i = 0, j = 0, k = 0;
+    float qm = 0.0f;
+    float X0[3] = {0.0f, 0.0f, 0.0f}, U0[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+    if (alive) {
+        qm = (float)cS.qm[sp];
         unpack_cell(in.cell[id], i, j, k);
-        float X0[3] = {in.off[0][id], in.off[1][id], in.off[2][id]};
-        float U0[4] = {in.u[0][id], in.u[1][id], in.u[2][id], in.u[3][id]};
-        float Xs[3] = {X0[0], X0[1], X0[2]};
-        float Us[4] = {U0[0], U0[1], U0[2], U0[3]};
-        float Sx[3] = {0.0f, 0.0f, 0.0f}, Su[4] = {0.0f, 0.0f, 0.0f, 0.0f};
-        const float dt = (float)P.dt;
+        for (int q = 0; q < 3; q++) X0[q] = in.off[q][id];
+        for (int q = 0; q < 4; q++) U0[q] = in.u[q][id];
+    }
+    const int base[3] = {i, j, k};
+    float Xs[3] = {X0[0], X0[1], X0[2]};
+    float Us[4] = {U0[0], U0[1], U0[2], U0[3]};
+    float Sx[3] = {0.0f, 0.0f, 0.0f}, Su[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+    const float dt = (float)P.dt;
+    NodeBox32 B;
+    B.lds = snode;
 #pragma unroll 1
-        for (int st = 0; st < 4; st++) {
+    for (int st = 0; st < 4; st++) {
+        int c[3];
+        gather_cell32(P.G, base, Xs, c);
+        stage_nodes32(P.G, node, alive, c, snode, sred, B);
+        if (alive) {
             float A[4];
-            accel32(P, M, node, qm, i, j, k, Xs, Us, A);
+            accel32(P, M, node, B, c, qm, i, j, k, Xs, Us, A);
             float gam = stage_gamma32(P, Us[3], A[3], clamps);
             float ig = 1.0f / gam;
             float Kx[3] = {Us[0] * ig, Us[1] * ig, Us[2] * ig};
@@ -128,6 +231,8 @@ __global__ __launch_bounds__(256, 4) void k_push32(PushParams P, Mixed M, Specie
                 for (int q = 0; q < 4; q++) Us[q] = U0[q] + fac * Ku[q];
             }
         }
+    }
+    if (alive) {
         const float h6 = (float)(P.dt / 6.0);
         int cc[3] = {i, j, k};
         for (int q = 0; q < 3; q++) {
@@ -150,8 +255,8 @@ __global__ __launch_bounds__(256, 4) void k_push32(PushParams P, Mixed M, Specie
 void launch_push32(const PushParams &P, const Mixed &M, const Species &S, const float *node, ParticlePtrs32 in,
                    ParticlePtrs32 out, unsigned long long *counters, hipStream_t s) {
     if (P.n <= 0) return;
-    unsigned nb = (unsigned)((P.n + 255) / 256);
-    hipLaunchKernelGGL(k_push32, dim3(nb), dim3(256), 0, s, P, M, S, node, in, out, counters);
+    unsigned nb = (unsigned)((P.n + kPush32Block - 1) / kPush32Block);
+    hipLaunchKernelGGL(k_push32, dim3(nb), dim3(kPush32Block), 0, s, P, M, S, node, in, out, counters);
 }
 
 // ---------------------------------------------------------------------------
@@ -285,21 +390,6 @@ __device__ __forceinline__ bool zigzag32(const Grid &G, const int base[3], const
         if (g1 < -1 || g1 > nn || g2 < -1 || g2 > nn || !(fabsf(x2[ax] - x1[ax]) < 1.0f)) ok = false;
     }
     return ok;
-}
-
-__device__ __forceinline__ int wave_min32(int v) {
-    for (int o = 32; o > 0; o >>= 1) {
-        int w = __shfl_xor(v, o, 64);
-        v = w < v ? w : v;
-    }
-    return v;
-}
-__device__ __forceinline__ int wave_max32(int v) {
-    for (int o = 32; o > 0; o >>= 1) {
-        int w = __shfl_xor(v, o, 64);
-        v = w > v ? w : v;
-    }
-    return v;
 }
 
 constexpr int kDep32Block = 256;
