@@ -199,6 +199,12 @@ __device__ __forceinline__ void gamma_uu(const KSGradT<T> &p, const T u[4], T G[
     G[3] = -Gl[3] + fkG;
 }
 
+// l / d for 0 <= l < 2^20 and d >= 1 through the float reciprocal inv_d = 1/d:
+// (l + 1/2)/d lies at least 1/(2d) from an integer while the float rounding
+// moves it by less than (l + 1/2)/d * 2^-22, so the truncation is the exact
+// quotient.
+__device__ __forceinline__ int small_div(int l, float inv_d) { return (int)(((float)l + 0.5f) * inv_d); }
+
 // Fixed-point conversion of one current or charge contribution.
 __device__ __forceinline__ unsigned long long to_fixed(double v, double scale) {
     return (unsigned long long)(long long)__double2ll_rn(v * scale);

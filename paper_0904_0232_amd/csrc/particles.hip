@@ -7,20 +7,10 @@
 
 namespace grpic {
 
-__device__ __forceinline__ int wave_min(int v) {
-    for (int o = 32; o > 0; o >>= 1) {
-        int w = __shfl_xor(v, o, 64);
-        v = w < v ? w : v;
-    }
-    return v;
-}
-__device__ __forceinline__ int wave_max(int v) {
-    for (int o = 32; o > 0; o >>= 1) {
-        int w = __shfl_xor(v, o, 64);
-        v = w > v ? w : v;
-    }
-    return v;
-}
+// Wavefront min / max (DPP reductions of the device library); the result is
+// the same in every lane.
+__device__ __forceinline__ int wave_min(int v) { return __ockl_wfred_min_i32(v); }
+__device__ __forceinline__ int wave_max(int v) { return __ockl_wfred_max_i32(v); }
 
 
 // Node tensor rows in LDS: 16 doubles per node padded to 18, so nodes one
@@ -149,9 +139,10 @@ __device__ __forceinline__ void stage_nodes(const Grid &G, const double *__restr
     if (B.use) {
         const double2 *src = reinterpret_cast<const double2 *>(node);
         const int nb0 = B.n[0], nb01 = B.n[0] * B.n[1];
+        const float inv0 = 1.0f / (float)nb0, inv01 = 1.0f / (float)nb01;
         for (int e = tid; e < count * 8; e += kPushBlock) {
             const int l = e >> 3, part = e & 7;
-            const int lk = l / nb01, r = l - lk * nb01, lj = r / nb0, li = r - lj * nb0;
+            const int lk = small_div(l, inv01), r = l - lk * nb01, lj = small_div(r, inv0), li = r - lj * nb0;
             snode[kNodeStride2 * l + part] = src[8 * G.node(B.lo[0] + li, B.lo[1] + lj, B.lo[2] + lk) + part];
         }
     }
@@ -247,22 +238,29 @@ struct DepCtx {
     int curved;
 };
 
+// sqrt(1 + f (1 - k_K^2)) with f = 2 m r^3 / (r^4 + a^2 z^2), folded into
+// one division:  for K = 0, 1, 1 - k_K^2 = (D - n)(D + n) / D^2 with
+// D = r^2 + a^2 and n = r x - a y (K = 0) or r y + a x (K = 1); for K = 2,
+// 1 - k_K^2 = (r^2 - z^2) / r^2.
 __device__ __forceinline__ double area_density(const DepCtx &D, int K, double X, double Y, double Z) {
     if (D.h.m == 0.0) return 1.0;
-    double x = X - D.h.cx, y = Y - D.h.cy, z = Z - D.h.cz;
-    double a = D.h.a;
-    double r = ks_radius(a, x, y, z);
+    const double x = X - D.h.cx, y = Y - D.h.cy, z = Z - D.h.cz;
+    const double a = D.h.a;
+    const double r = ks_radius(a, x, y, z);
     if (r < D.h.r_exc) return 1.0;
-    double rr = r * r;
-    double f = 2.0 * D.h.m * r * rr / (rr * rr + a * a * z * z);
-    double kK;
-    if (K == 0)
-        kK = (r * x - a * y) / (rr + a * a);
-    else if (K == 1)
-        kK = (r * y + a * x) / (rr + a * a);
-    else
-        kK = z / r;
-    return sqrt(1.0 + f * (1.0 - kK * kK));
+    const double rr = r * r;
+    const double S4 = rr * rr + a * a * z * z;
+    double num, den;
+    if (K == 2) {
+        num = 2.0 * D.h.m * r * ((r - z) * (r + z));
+        den = S4;
+    } else {
+        const double Dn = rr + a * a;
+        const double nK = K == 0 ? r * x - a * y : r * y + a * x;
+        num = 2.0 * D.h.m * r * rr * ((Dn - nK) * (Dn + nK));
+        den = S4 * (Dn * Dn);
+    }
+    return sqrt(1.0 + num / den);
 }
 
 // Destinations of the fixed-point current: straight to the global int64
@@ -283,9 +281,10 @@ struct LdsAcc {
     }
 };
 
-template <typename Acc>
-__device__ __forceinline__ void dep_segment(const DepCtx &D, const Acc &acc, const double A[3], const double B[3],
-                                            const int cell[3], double Q) {
+// Fixed-point contributions of one segment A -> B inside `cell`, added to
+// v[K][bi + 2 bj] (the K-edge at cell + bi e_I + bj e_J, I = K+1, J = K+2).
+__device__ __forceinline__ void dep_segment(const DepCtx &D, const double A[3], const double B[3], const int cell[3],
+                                            double Q, long long v[3][4]) {
     double d[3], mid[3];
     for (int ax = 0; ax < 3; ax++) {
         d[ax] = B[ax] - A[ax];
@@ -327,23 +326,46 @@ __device__ __forceinline__ void dep_segment(const DepCtx &D, const Acc &acc, con
         w11 += t;
         w10 -= t;
         w01 -= t;
-        int id[3];
-        id[K] = cell[K];
-        id[I] = cell[I];
-        id[J] = cell[J];
         double sc = flux * D.jscale;
-        int e0[3] = {id[0], id[1], id[2]};
-        int eI[3] = {id[0], id[1], id[2]};
-        eI[I] += 1;
-        int eJ[3] = {id[0], id[1], id[2]};
-        eJ[J] += 1;
-        int eIJ[3] = {eI[0], eI[1], eI[2]};
-        eIJ[J] += 1;
-        acc.add(K, e0[0], e0[1], e0[2], __double2ll_rn(sc * w00));
-        acc.add(K, eI[0], eI[1], eI[2], __double2ll_rn(sc * w10));
-        acc.add(K, eJ[0], eJ[1], eJ[2], __double2ll_rn(sc * w01));
-        acc.add(K, eIJ[0], eIJ[1], eIJ[2], __double2ll_rn(sc * w11));
+        v[K][0] += __double2ll_rn(sc * w00);
+        v[K][1] += __double2ll_rn(sc * w10);
+        v[K][2] += __double2ll_rn(sc * w01);
+        v[K][3] += __double2ll_rn(sc * w11);
     }
+}
+
+// Add the twelve edge sums of one cell to the accumulator (zeros skipped).
+template <typename Acc>
+__device__ __forceinline__ void dep_flush(const Acc &acc, const int cell[3], long long v[3][4]) {
+#pragma unroll
+    for (int K = 0; K < 3; K++) {
+        const int I = (K + 1) % 3, J = (K + 2) % 3;
+#pragma unroll
+        for (int c = 0; c < 4; c++) {
+            if (v[K][c] != 0) {
+                int id[3] = {cell[0], cell[1], cell[2]};
+                id[I] += c & 1;
+                id[J] += c >> 1;
+                acc.add(K, id[0], id[1], id[2], v[K][c]);
+            }
+            v[K][c] = 0;
+        }
+    }
+}
+
+// Both segments of one chord: summed in registers first when they lie in
+// the same cell (integer sums, so the totals are unchanged).
+template <typename Acc>
+__device__ __forceinline__ void dep_chord(const DepCtx &D, const Acc &acc, const double X1[3], const double xr[3],
+                                          const double X2[3], const int c1[3], const int c2[3], double Q) {
+    long long v[3][4];
+#pragma unroll
+    for (int K = 0; K < 3; K++)
+        for (int c = 0; c < 4; c++) v[K][c] = 0;
+    dep_segment(D, X1, xr, c1, Q, v);
+    if (c1[0] != c2[0] || c1[1] != c2[1] || c1[2] != c2[2]) dep_flush(acc, c1, v);
+    dep_segment(D, xr, X2, c2, Q, v);
+    dep_flush(acc, c2, v);
 }
 
 constexpr int kDepBlock = 256;
@@ -383,7 +405,6 @@ __global__ __launch_bounds__(kDepBlock) void k_deposit(DepCtx D, Species cS, dou
     __shared__ int sred[6][kDepBlock / 64];
     const int tid = threadIdx.x;
     const int64_t base = (int64_t)blockIdx.x * (kDepBlock * kDepPPT);
-    double X1[kDepPPT][3], X2[kDepPPT][3];
     uint8_t SP[kDepPPT];
     int lo[3] = {1 << 30, 1 << 30, 1 << 30}, hi[3] = {-(1 << 30), -(1 << 30), -(1 << 30)};
 #pragma unroll
@@ -391,13 +412,14 @@ __global__ __launch_bounds__(kDepBlock) void k_deposit(DepCtx D, Species cS, dou
         int64_t id = base + p * kDepBlock + tid;
         SP[p] = id < n ? xo.sp[id] : kDead;
         if (SP[p] != kDead) {
+            double X1[3], X2[3];
             for (int ax = 0; ax < 3; ax++) {
-                X1[p][ax] = xo.x[ax][id];
-                X2[p][ax] = xn.x[ax][id];
+                X1[ax] = xo.x[ax][id];
+                X2[ax] = xn.x[ax][id];
             }
             double xr[3];
             int c1[3], c2[3];
-            if (zigzag(D.G, X1[p], X2[p], xr, c1, c2) && cS.charge[SP[p]] != 0.0)
+            if (zigzag(D.G, X1, X2, xr, c1, c2) && cS.charge[SP[p]] != 0.0)
                 for (int ax = 0; ax < 3; ax++) {
                     int a = c1[ax] < c2[ax] ? c1[ax] : c2[ax];
                     int b = (c1[ax] > c2[ax] ? c1[ax] : c2[ax]) + 1;
@@ -435,26 +457,28 @@ __global__ __launch_bounds__(kDepBlock) void k_deposit(DepCtx D, Species cS, dou
     }
     LdsAcc la{sm, blo[0], blo[1], blo[2], bx, by, V};
     GlobalAcc ga{{F.Jint[0], F.Jint[1], F.Jint[2]}, D.G};
-#pragma unroll
+#pragma unroll 1
     for (int p = 0; p < kDepPPT; p++) {
         if (SP[p] == kDead) continue;
         int64_t id = base + p * kDepBlock + tid;
         double Q = cS.charge[SP[p]];
+        double X1[3], X2[3];
+        for (int ax = 0; ax < 3; ax++) {
+            X1[ax] = xo.x[ax][id];
+            X2[ax] = xn.x[ax][id];
+        }
         double xr[3];
         int c1[3], c2[3];
-        bool ok = zigzag(D.G, X1[p], X2[p], xr, c1, c2);
+        bool ok = zigzag(D.G, X1, X2, xr, c1, c2);
         if (ok && Q != 0.0) {
-            if (use_lds) {
-                dep_segment(D, la, X1[p], xr, c1, Q);
-                dep_segment(D, la, xr, X2[p], c2, Q);
-            } else {
-                dep_segment(D, ga, X1[p], xr, c1, Q);
-                dep_segment(D, ga, xr, X2[p], c2, Q);
-            }
+            if (use_lds)
+                dep_chord(D, la, X1, xr, X2, c1, c2, Q);
+            else
+                dep_chord(D, ga, X1, xr, X2, c1, c2, Q);
         } else if (!ok) {
             atomicOr(&counters[C_FLAGS], 1ull);
         }
-        const double *x2 = X2[p];
+        const double *x2 = X2;
         double r = ks_radius(D.h.a, x2[0] - D.h.cx, x2[1] - D.h.cy, x2[2] - D.h.cz);
         bool outside = false;
         for (int ax = 0; ax < 3; ax++) {
@@ -490,11 +514,12 @@ __global__ __launch_bounds__(kDepBlock) void k_deposit(DepCtx D, Species cS, dou
     }
     if (use_lds) {
         __syncthreads();
+        const float inv_bx = 1.0f / (float)bx, inv_bxy = 1.0f / (float)(bx * by);
         for (int e = tid; e < 3 * V; e += kDepBlock) {
             unsigned long long v = sm[e];
             if (v == 0ull) continue;
-            int K = e / V, l = e - K * V;
-            int li = l % bx, lj = (l / bx) % by, lk = l / (bx * by);
+            const int K = e >= 2 * V ? 2 : (e >= V ? 1 : 0), l = e - K * V;
+            const int lk = small_div(l, inv_bxy), r = l - lk * bx * by, lj = small_div(r, inv_bx), li = r - lj * bx;
             atomicAdd(&F.Jint[K][D.G.g(blo[0] + li, blo[1] + lj, blo[2] + lk)], v);
         }
     }

@@ -11,20 +11,10 @@
 
 namespace grpic {
 
-__device__ __forceinline__ int wave_min32(int v) {
-    for (int o = 32; o > 0; o >>= 1) {
-        int w = __shfl_xor(v, o, 64);
-        v = w < v ? w : v;
-    }
-    return v;
-}
-__device__ __forceinline__ int wave_max32(int v) {
-    for (int o = 32; o > 0; o >>= 1) {
-        int w = __shfl_xor(v, o, 64);
-        v = w > v ? w : v;
-    }
-    return v;
-}
+// Wavefront min / max (DPP reductions of the device library); the result is
+// the same in every lane.
+__device__ __forceinline__ int wave_min32(int v) { return __ockl_wfred_min_i32(v); }
+__device__ __forceinline__ int wave_max32(int v) { return __ockl_wfred_max_i32(v); }
 
 __device__ __forceinline__ void hole_rel(const Hole &h, int i, int j, int k, const float X[3], double &x, double &y,
                                          double &z) {
@@ -169,9 +159,10 @@ __device__ __forceinline__ void stage_nodes32(const Grid &G, const float *__rest
     if (B.use) {
         const float4 *src = reinterpret_cast<const float4 *>(node);
         const int nb0 = B.n[0], nb01 = B.n[0] * B.n[1];
+        const float inv0 = 1.0f / (float)nb0, inv01 = 1.0f / (float)nb01;
         for (int e = tid; e < count * 4; e += kPush32Block) {
             const int l = e >> 2, part = e & 3;
-            const int lk = l / nb01, r = l - lk * nb01, lj = r / nb0, li = r - lj * nb0;
+            const int lk = small_div(l, inv01), r = l - lk * nb01, lj = small_div(r, inv0), li = r - lj * nb0;
             snode[kNode32Stride4 * l + part] = src[4 * G.node(B.lo[0] + li, B.lo[1] + lj, B.lo[2] + lk) + part];
         }
     }
@@ -272,26 +263,41 @@ struct Dep32 {
     int curved;
 };
 
-// Area density sqrt(1 + f (1 - k_K^2)) at a point given as cell + local offset.
+// Area density sqrt(1 + f (1 - k_K^2)) at a point given as cell + local
+// offset, folded into one division as in the FP64 kernel; FP64 within r_fp64.
 __device__ __forceinline__ float area_density32(const Dep32 &D, int K, const int base[3], const float P3[3]) {
     if (D.h.m == 0.0) return 1.0f;
-    double x = ((double)base[0] - D.h.cx) + (double)P3[0];
-    double y = ((double)base[1] - D.h.cy) + (double)P3[1];
-    double z = ((double)base[2] - D.h.cz) + (double)P3[2];
-    double a = D.h.a;
-    double r = ks_radius(a, x, y, z);
+    const double x = ((double)base[0] - D.h.cx) + (double)P3[0];
+    const double y = ((double)base[1] - D.h.cy) + (double)P3[1];
+    const double z = ((double)base[2] - D.h.cz) + (double)P3[2];
+    const double a = D.h.a;
+    const double r = ks_radius(a, x, y, z);
     if (r < D.h.r_exc) return 1.0f;
     if (r < D.r_fp64) {
-        double rr = r * r;
-        double f = 2.0 * D.h.m * r * rr / (rr * rr + a * a * z * z);
-        double kK = K == 0 ? (r * x - a * y) / (rr + a * a) : (K == 1 ? (r * y + a * x) / (rr + a * a) : z / r);
-        return (float)sqrt(1.0 + f * (1.0 - kK * kK));
+        const double rr = r * r, S4 = rr * rr + a * a * z * z;
+        double num, den;
+        if (K == 2) {
+            num = 2.0 * D.h.m * r * ((r - z) * (r + z));
+            den = S4;
+        } else {
+            const double Dn = rr + a * a, nK = K == 0 ? r * x - a * y : r * y + a * x;
+            num = 2.0 * D.h.m * r * rr * ((Dn - nK) * (Dn + nK));
+            den = S4 * (Dn * Dn);
+        }
+        return (float)sqrt(1.0 + num / den);
     }
-    float rf = (float)r, af = (float)a, xf = (float)x, yf = (float)y, zf = (float)z;
-    float rr = rf * rf;
-    float f = 2.0f * (float)D.h.m * rf * rr / (rr * rr + af * af * zf * zf);
-    float kK = K == 0 ? (rf * xf - af * yf) / (rr + af * af) : (K == 1 ? (rf * yf + af * xf) / (rr + af * af) : zf / rf);
-    return sqrtf(1.0f + f * (1.0f - kK * kK));
+    const float rf = (float)r, af = (float)a, xf = (float)x, yf = (float)y, zf = (float)z, mf = (float)D.h.m;
+    const float rr = rf * rf, S4 = rr * rr + af * af * zf * zf;
+    float num, den;
+    if (K == 2) {
+        num = 2.0f * mf * rf * ((rf - zf) * (rf + zf));
+        den = S4;
+    } else {
+        const float Dn = rr + af * af, nK = K == 0 ? rf * xf - af * yf : rf * yf + af * xf;
+        num = 2.0f * mf * rf * rr * ((Dn - nK) * (Dn + nK));
+        den = S4 * (Dn * Dn);
+    }
+    return sqrtf(1.0f + num / den);
 }
 
 struct GlobalAcc32 {
@@ -311,9 +317,10 @@ struct LdsAcc32 {
 };
 
 // One segment A -> B, local to cell `base` + `cell` (cell relative to base).
-template <typename Acc>
-__device__ __forceinline__ void dep_segment32(const Dep32 &D, const Acc &acc, const int base[3], const float A[3],
-                                              const float B[3], const int cell[3], float Q) {
+// Its fixed-point contributions are added to v[K][bi + 2 bj] (the K-edge at
+// base + cell + bi e_I + bj e_J).
+__device__ __forceinline__ void dep_segment32(const Dep32 &D, const int base[3], const float A[3], const float B[3],
+                                              const int cell[3], float Q, long long v[3][4]) {
     float d[3], mid[3];
     for (int ax = 0; ax < 3; ax++) {
         d[ax] = B[ax] - A[ax];
@@ -355,19 +362,48 @@ __device__ __forceinline__ void dep_segment32(const Dep32 &D, const Acc &acc, co
         w11 += t;
         w10 -= t;
         w01 -= t;
-        int e0[3] = {base[0] + cell[0], base[1] + cell[1], base[2] + cell[2]};
-        int eI[3] = {e0[0], e0[1], e0[2]};
-        eI[I] += 1;
-        int eJ[3] = {e0[0], e0[1], e0[2]};
-        eJ[J] += 1;
-        int eIJ[3] = {eI[0], eI[1], eI[2]};
-        eIJ[J] += 1;
         double sc = (double)flux * D.jscale;
-        acc.add(K, e0[0], e0[1], e0[2], __double2ll_rn(sc * (double)w00));
-        acc.add(K, eI[0], eI[1], eI[2], __double2ll_rn(sc * (double)w10));
-        acc.add(K, eJ[0], eJ[1], eJ[2], __double2ll_rn(sc * (double)w01));
-        acc.add(K, eIJ[0], eIJ[1], eIJ[2], __double2ll_rn(sc * (double)w11));
+        v[K][0] += __double2ll_rn(sc * (double)w00);
+        v[K][1] += __double2ll_rn(sc * (double)w10);
+        v[K][2] += __double2ll_rn(sc * (double)w01);
+        v[K][3] += __double2ll_rn(sc * (double)w11);
     }
+}
+
+// Add the twelve edge sums of cell base + cell to the accumulator (zeros
+// skipped) and clear them.
+template <typename Acc>
+__device__ __forceinline__ void dep_flush32(const Acc &acc, const int base[3], const int cell[3], long long v[3][4]) {
+#pragma unroll
+    for (int K = 0; K < 3; K++) {
+        const int I = (K + 1) % 3, J = (K + 2) % 3;
+#pragma unroll
+        for (int c = 0; c < 4; c++) {
+            if (v[K][c] != 0) {
+                int id[3] = {base[0] + cell[0], base[1] + cell[1], base[2] + cell[2]};
+                id[I] += c & 1;
+                id[J] += c >> 1;
+                acc.add(K, id[0], id[1], id[2], v[K][c]);
+            }
+            v[K][c] = 0;
+        }
+    }
+}
+
+// Both segments of one chord, summed in registers first when they lie in the
+// same cell.
+template <typename Acc>
+__device__ __forceinline__ void dep_chord32(const Dep32 &D, const Acc &acc, const int base[3], const float X1[3],
+                                            const float xr[3], const float X2[3], const int l1[3], const int l2[3],
+                                            float Q) {
+    long long v[3][4];
+#pragma unroll
+    for (int K = 0; K < 3; K++)
+        for (int c = 0; c < 4; c++) v[K][c] = 0;
+    dep_segment32(D, base, X1, xr, l1, Q, v);
+    if (l1[0] != l2[0] || l1[1] != l2[1] || l1[2] != l2[2]) dep_flush32(acc, base, l1, v);
+    dep_segment32(D, base, xr, X2, l2, Q, v);
+    dep_flush32(acc, base, l2, v);
 }
 
 // Zigzag in coordinates local to the old cell: x1 in [0,1), x2 = (cell2 -
@@ -392,6 +428,18 @@ __device__ __forceinline__ bool zigzag32(const Grid &G, const int base[3], const
     return ok;
 }
 
+// Old cell, old offset and the new position relative to the old cell.
+__device__ __forceinline__ void load_chord32(const ParticlePtrs32 &xo, const ParticlePtrs32 &xn, int64_t id, int B1[3],
+                                             float X1[3], float X2[3]) {
+    int c2[3];
+    unpack_cell(xo.cell[id], B1[0], B1[1], B1[2]);
+    unpack_cell(xn.cell[id], c2[0], c2[1], c2[2]);
+    for (int ax = 0; ax < 3; ax++) {
+        X1[ax] = xo.off[ax][id];
+        X2[ax] = (float)(c2[ax] - B1[ax]) + xn.off[ax][id];
+    }
+}
+
 constexpr int kDep32Block = 256;
 constexpr int kDep32PPT = 4;
 constexpr int kDep32Lds = 4096;
@@ -403,8 +451,6 @@ __global__ __launch_bounds__(kDep32Block) void k_deposit32(Dep32 D, Species cS, 
     __shared__ int sred[6][kDep32Block / 64];
     const int tid = threadIdx.x;
     const int64_t base = (int64_t)blockIdx.x * (kDep32Block * kDep32PPT);
-    float X1[kDep32PPT][3], X2[kDep32PPT][3];
-    int B1[kDep32PPT][3];
     uint8_t SP[kDep32PPT];
     int lo[3] = {1 << 30, 1 << 30, 1 << 30}, hi[3] = {-(1 << 30), -(1 << 30), -(1 << 30)};
 #pragma unroll
@@ -412,19 +458,15 @@ __global__ __launch_bounds__(kDep32Block) void k_deposit32(Dep32 D, Species cS, 
         int64_t id = base + p * kDep32Block + tid;
         SP[p] = id < n ? xo.sp[id] : kDead;
         if (SP[p] != kDead) {
-            int c2[3];
-            unpack_cell(xo.cell[id], B1[p][0], B1[p][1], B1[p][2]);
-            unpack_cell(xn.cell[id], c2[0], c2[1], c2[2]);
-            for (int ax = 0; ax < 3; ax++) {
-                X1[p][ax] = xo.off[ax][id];
-                X2[p][ax] = (float)(c2[ax] - B1[p][ax]) + xn.off[ax][id];
-            }
+            int B1[3];
+            float X1[3], X2[3];
+            load_chord32(xo, xn, id, B1, X1, X2);
             float xr[3];
             int l1[3], l2[3];
-            if (zigzag32(D.G, B1[p], X1[p], X2[p], xr, l1, l2) && cS.charge[SP[p]] != 0.0)
+            if (zigzag32(D.G, B1, X1, X2, xr, l1, l2) && cS.charge[SP[p]] != 0.0)
                 for (int ax = 0; ax < 3; ax++) {
-                    int a = B1[p][ax] + (l1[ax] < l2[ax] ? l1[ax] : l2[ax]);
-                    int b = B1[p][ax] + (l1[ax] > l2[ax] ? l1[ax] : l2[ax]) + 1;
+                    int a = B1[ax] + (l1[ax] < l2[ax] ? l1[ax] : l2[ax]);
+                    int b = B1[ax] + (l1[ax] > l2[ax] ? l1[ax] : l2[ax]) + 1;
                     lo[ax] = a < lo[ax] ? a : lo[ax];
                     hi[ax] = b > hi[ax] ? b : hi[ax];
                 }
@@ -459,22 +501,22 @@ __global__ __launch_bounds__(kDep32Block) void k_deposit32(Dep32 D, Species cS, 
     }
     LdsAcc32 la{sm, blo[0], blo[1], blo[2], bx, by, V};
     GlobalAcc32 ga{{F.Jint[0], F.Jint[1], F.Jint[2]}, D.G};
-#pragma unroll
+#pragma unroll 1
     for (int p = 0; p < kDep32PPT; p++) {
         if (SP[p] == kDead) continue;
         int64_t id = base + p * kDep32Block + tid;
         float Q = (float)cS.charge[SP[p]];
+        int B1[3];
+        float X1[3], X2[3];
+        load_chord32(xo, xn, id, B1, X1, X2);
         float xr[3];
         int l1[3], l2[3];
-        bool ok = zigzag32(D.G, B1[p], X1[p], X2[p], xr, l1, l2);
+        bool ok = zigzag32(D.G, B1, X1, X2, xr, l1, l2);
         if (ok && Q != 0.0f) {
-            if (use_lds) {
-                dep_segment32(D, la, B1[p], X1[p], xr, l1, Q);
-                dep_segment32(D, la, B1[p], xr, X2[p], l2, Q);
-            } else {
-                dep_segment32(D, ga, B1[p], X1[p], xr, l1, Q);
-                dep_segment32(D, ga, B1[p], xr, X2[p], l2, Q);
-            }
+            if (use_lds)
+                dep_chord32(D, la, B1, X1, xr, X2, l1, l2, Q);
+            else
+                dep_chord32(D, ga, B1, X1, xr, X2, l1, l2, Q);
         } else if (!ok) {
             atomicOr(&counters[C_FLAGS], 1ull);
         }
@@ -513,11 +555,12 @@ __global__ __launch_bounds__(kDep32Block) void k_deposit32(Dep32 D, Species cS, 
     }
     if (use_lds) {
         __syncthreads();
+        const float inv_bx = 1.0f / (float)bx, inv_bxy = 1.0f / (float)(bx * by);
         for (int e = tid; e < 3 * V; e += kDep32Block) {
             unsigned long long v = sm[e];
             if (v == 0ull) continue;
-            int K = e / V, l = e - K * V;
-            int li = l % bx, lj = (l / bx) % by, lk = l / (bx * by);
+            const int K = e >= 2 * V ? 2 : (e >= V ? 1 : 0), l = e - K * V;
+            const int lk = small_div(l, inv_bxy), r = l - lk * bx * by, lj = small_div(r, inv_bx), li = r - lj * bx;
             atomicAdd(&F.Jint[K][D.G.g(blo[0] + li, blo[1] + lj, blo[2] + lk)], v);
         }
     }
