@@ -183,14 +183,18 @@ void grpic_destroy(grpic_t *h);
 const char *grpic_strerror(int code);
 
 /* ------------------------------------------------------------------------
- * Serving: continuous batching of independent runs.  A batch owns up to
- * max_slots runs whose device memory together stays within budget_bytes.
- * Each admitted run keeps its state on the device and its own HIP stream;
- * one batch iteration replays every active run's captured one-cycle graph
- * (the cell sort, when due, runs eagerly after it), so the runs' work
- * overlaps on the GPU.  Runs that reach their step count are finished:
- * their diagnostics are taken and their memory is freed at once, which
- * admits queued work.  One batch is not thread-safe.
+ * Serving: continuous batching of independent FP32-mixed runs.  A batch
+ * owns up to max_slots (at most 64) runs whose device memory together stays
+ * within budget_bytes.  Each admitted run keeps its state on the device.
+ * One batch iteration advances every active run by one cycle with a single
+ * set of batched launches (one per stage of the cycle, each covering the
+ * particles or grid points of all runs), captured once as a HIP graph and
+ * replayed; a run table in device memory, rewritten before each replay,
+ * tells the launches which runs are active and where their state is.  The
+ * cell sort, when due, runs per run after the replay.  Runs that reach
+ * their step count are finished: their diagnostics are taken and their
+ * memory is freed at once, which admits queued work.  All work of a batch
+ * runs on its own HIP stream.  One batch is not thread-safe.
  * ------------------------------------------------------------------------ */
 typedef struct grpic_batch_s grpic_batch_t;
 
@@ -199,12 +203,14 @@ enum { GRPIC_RUN_UNKNOWN = 0, GRPIC_RUN_ACTIVE = 1, GRPIC_RUN_DONE = 2 };
 /* Device bytes a run with this configuration allocates (admission estimate). */
 int64_t grpic_run_bytes(const grpic_config *cfg);
 
+/* GRPIC_EINVAL unless 1 <= max_slots <= 64 and budget_bytes > 0. */
 int grpic_batch_create(int64_t budget_bytes, int32_t max_slots, grpic_batch_t **out);
 
 /* Admit a run if a slot and budget_bytes allow it (else GRPIC_EAGAIN and no
  * state changes).  Particles of species s (s < cfg->nspecies): n[s] entries,
- * x[s] and ucov[s] as for grpic_load_particles; cfg->alloc must be NULL (the
- * batch allocates).  The run advances one cycle per grpic_batch_step until
+ * x[s] and ucov[s] as for grpic_load_particles; cfg->precision must be
+ * GRPIC_FP32_MIXED and cfg->alloc NULL (the batch allocates), else
+ * GRPIC_EINVAL.  Waits for the batch's queued work.  The run advances one cycle per grpic_batch_step until
  * nsteps are done.  keep_state != 0 keeps a host copy of the final particle
  * state for grpic_batch_dump. */
 int grpic_batch_submit(grpic_batch_t *b, const grpic_config *cfg, int32_t nsteps, int32_t keep_state,

@@ -24,6 +24,10 @@ FLAGS = [
     "-fPIC",
     # packed FP32 instructions are kept out of every kernel
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # multiply-add fusion only inside one source expression, so the same
+    # device function rounds the same way in every kernel that inlines it
+    # (single-run and batched launches give bit-identical results)
+    "-ffp-contract=on",
     "-Wno-unused-command-line-argument",
     "-I" + os.path.join(ROOT, "include"),
 ]

@@ -459,12 +459,14 @@ int64_t run_bytes(const grpic_config *c) {
 }  // namespace
 
 // ---------------------------------------------------------------------------
-// Serving batch.
+// Serving batch (FP32-mixed runs).  Every iteration rewrites the run table in
+// device memory (one host-to-device copy from a pinned double buffer) and
+// replays one captured graph of persistent batched launches that advance
+// every active run by one cycle; cell sorts that fall due run per run after
+// the replay, and finished runs are reduced and freed.
 struct BatchRun {
     int64_t id;
     grpic_t *h;
-    hipStream_t stream;
-    hipGraphExec_t exec[2][2];  // one captured cycle per (x buffer, u buffer) parity
     int32_t nsteps, done, state;
     int64_t bytes;
     grpic_diag diag;
@@ -479,38 +481,88 @@ struct grpic_batch_s {
     int64_t budget, used;
     int32_t max_slots;
     int64_t next_id;
+    hipStream_t stream;
+    BatchTable *d_table;       // device
+    BatchTable *h_table[2];    // pinned host staging, used in turn
+    hipEvent_t copied[2];      // the copy out of h_table[k] has completed
+    bool copy_pending[2];
+    int ring;
+    hipGraphExec_t exec;       // one iteration for up to exec_iters fixed-point passes
+    int exec_iters;
     std::vector<BatchRun *> active;
     std::map<int64_t, BatchRun *> runs;
 };
 
 namespace {
 
-void drop_graphs(BatchRun *r) {
-    for (int a = 0; a < 2; a++)
-        for (int c = 0; c < 2; c++)
-            if (r->exec[a][c]) {
-                (void)hipGraphExecDestroy(r->exec[a][c]);
-                r->exec[a][c] = nullptr;
-            }
+// Persistent grids: blocks per CU that the kernels' registers and LDS allow,
+// times the 256 compute units.
+constexpr int kBatchGridField = 256 * 8;
+constexpr int kBatchGridPush = 256 * 4;
+constexpr int kBatchGridDep = 256 * 3;
+
+void fill_table_entry(grpic_t *h, BatchRun32 &R) {
+    const grpic_config &c = h->cfg;
+    R.G = h->G;
+    R.h = h->h;
+    R.F = h->F32;
+    R.hstep = (float)(0.5 * c.c * c.dt);
+    R.c = c.c;
+    R.dt = c.dt;
+    R.fpc = (float)(4.0 * M_PI / c.c);
+    R.inv_jscale = 1.0 / h->jscale;
+    R.field_iters = c.field_iters;
+    relax_box_of(h->G, h->h, c.r_damp, c.damp_max, R.relax_box);
+    R.r_damp = c.r_damp;
+    R.damp_max = c.damp_max;
+    R.P = push_params(h);
+    R.M = h->M;
+    R.S = h->S;
+    R.cur = pp32(h, h->xc, h->uc);
+    R.nxt = pp32(h, 1 - h->xc, h->uc);
+    R.counters = h->counters;
+    R.D = make_dep32(h->G, h->h, h->M, c.dt, c.deposit_mode, h->jscale);
+    R.r_rm = c.r_rm;
+    R.rscale = h->rscale;
 }
 
-// Capture one cycle (without the sort) of run r for its current buffer parity.
-int capture_cycle(BatchRun *r, hipGraphExec_t *out) {
-    grpic_t *h = r->h;
-    int xc = h->xc, uc = h->uc;
-    int64_t sc = h->step_count;
-    int rc = check(hipStreamBeginCapture(r->stream, hipStreamCaptureModeThreadLocal));
+// Enqueue one batched iteration (captured into a graph by the caller).
+void enqueue_iteration(grpic_batch_t *b, int iters) {
+    const BatchTable *T = b->d_table;
+    hipStream_t s = b->stream;
+    launch_batch_field(BF_SAVE_B, T, 0, kBatchGridField, s);
+    for (int it = 0; it < iters; it++) {
+        launch_batch_field(BF_NODE_W, T, it, kBatchGridField, s);
+        launch_batch_field(BF_ECOV, T, it, kBatchGridField, s);
+        launch_batch_field(BF_BHALF_SAVED, T, it, kBatchGridField, s);
+    }
+    launch_batch_field(BF_NODE_TENSOR, T, 0, kBatchGridField, s);
+    launch_batch_push32(T, kBatchGridPush, s);
+    launch_batch_field(BF_BHALF_CUR, T, 0, kBatchGridField, s);
+    launch_batch_field(BF_ZERO_J, T, 0, kBatchGridField, s);
+    launch_batch_deposit32(T, kBatchGridDep, s);
+    launch_batch_field(BF_SAVE_D, T, 0, kBatchGridField, s);
+    for (int it = 0; it < iters; it++) {
+        launch_batch_field(BF_NODE_W, T, it, kBatchGridField, s);
+        launch_batch_field(BF_HFIELD, T, it, kBatchGridField, s);
+        launch_batch_field(BF_DSTEP, T, it, kBatchGridField, s);
+    }
+    launch_batch_field(BF_RELAX, T, 0, kBatchGridField, s);
+}
+
+int capture_iteration(grpic_batch_t *b, int iters) {
+    if (b->exec) {
+        (void)hipGraphExecDestroy(b->exec);
+        b->exec = nullptr;
+    }
+    int rc = check(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
     if (rc) return rc;
-    int rc_step = one_step(h, false);
+    enqueue_iteration(b, iters);
     hipGraph_t g = nullptr;
-    rc = check(hipStreamEndCapture(r->stream, &g));
-    // capturing recorded the work without running it: undo the bookkeeping
-    h->xc = xc;
-    h->uc = uc;
-    h->step_count = sc;
-    if (rc_step) rc = rc_step;
-    if (!rc) rc = check(hipGraphInstantiate(out, g, nullptr, nullptr, 0));
+    rc = check(hipStreamEndCapture(b->stream, &g));
+    if (!rc) rc = check(hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0));
     if (g) (void)hipGraphDestroy(g);
+    if (!rc) b->exec_iters = iters;
     return rc;
 }
 
@@ -525,11 +577,8 @@ int finish_run(grpic_batch_t *b, BatchRun *r) {
         r->sp.resize(r->n_slots);
         rc = grpic_dump_particles(h, r->x.data(), r->u.data(), r->sp.data());
     }
-    drop_graphs(r);
     grpic_destroy(h);
-    (void)hipStreamDestroy(r->stream);
     r->h = nullptr;
-    r->stream = nullptr;
     b->used -= r->bytes;
     r->state = GRPIC_RUN_DONE;
     return rc;
@@ -542,13 +591,24 @@ extern "C" {
 int64_t grpic_run_bytes(const grpic_config *cfg) { return cfg ? run_bytes(cfg) : 0; }
 
 int grpic_batch_create(int64_t budget_bytes, int32_t max_slots, grpic_batch_t **out) {
-    if (!out || budget_bytes <= 0 || max_slots < 1) return GRPIC_EINVAL;
+    clear_foreign_error();
+    if (!out || budget_bytes <= 0 || max_slots < 1 || max_slots > kMaxBatchRuns) return GRPIC_EINVAL;
     grpic_batch_t *b = new (std::nothrow) grpic_batch_s();
     if (!b) return GRPIC_ENOMEM;
     b->budget = budget_bytes;
-    b->used = 0;
     b->max_slots = max_slots;
     b->next_id = 1;
+    int rc = GRPIC_OK;
+    if (FAILS(hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking))) rc = GRPIC_EDEVICE;
+    if (!rc && FAILS(hipMalloc((void **)&b->d_table, sizeof(BatchTable)))) rc = GRPIC_ENOMEM;
+    for (int k = 0; k < 2 && !rc; k++) {
+        if (FAILS(hipHostMalloc((void **)&b->h_table[k], sizeof(BatchTable), hipHostMallocDefault))) rc = GRPIC_ENOMEM;
+        if (!rc && FAILS(hipEventCreateWithFlags(&b->copied[k], hipEventDisableTiming))) rc = GRPIC_EDEVICE;
+    }
+    if (rc) {
+        grpic_batch_destroy(b);
+        return rc;
+    }
     *out = b;
     return GRPIC_OK;
 }
@@ -557,22 +617,17 @@ int grpic_batch_submit(grpic_batch_t *b, const grpic_config *cfg, int32_t nsteps
                        const int64_t *n, const double *const *x, const double *const *ucov, int64_t *run_id) {
     clear_foreign_error();
     if (!b || !cfg || nsteps < 1 || !n || !x || !ucov || !run_id) return GRPIC_EINVAL;
-    if (cfg->alloc) return GRPIC_EINVAL;
+    if (cfg->alloc || cfg->precision != GRPIC_FP32_MIXED) return GRPIC_EINVAL;
     int rc = validate(cfg);
     if (rc) return rc;
     int64_t bytes = run_bytes(cfg);
     if ((int32_t)b->active.size() >= b->max_slots || b->used + bytes > b->budget) return GRPIC_EAGAIN;
     BatchRun *r = new (std::nothrow) BatchRun();
     if (!r) return GRPIC_ENOMEM;
-    if (FAILS(hipStreamCreateWithFlags(&r->stream, hipStreamNonBlocking))) {
-        delete r;
-        return GRPIC_EDEVICE;
-    }
-    rc = grpic_create(cfg, r->stream, &r->h);
+    rc = grpic_create(cfg, b->stream, &r->h);
     for (int s = 0; s < cfg->nspecies && !rc; s++) rc = grpic_load_particles(r->h, s, n[s], x[s], ucov[s], nullptr);
     if (rc) {
         if (r->h) grpic_destroy(r->h);
-        (void)hipStreamDestroy(r->stream);
         delete r;
         return rc;
     }
@@ -594,16 +649,41 @@ int grpic_batch_step(grpic_batch_t *b, int32_t *finished) {
     clear_foreign_error();
     if (!b) return GRPIC_EINVAL;
     if (finished) *finished = 0;
-    int rc = GRPIC_OK;
+    if (b->active.empty()) return GRPIC_OK;
+    // run table of this iteration, staged in the host buffer whose previous
+    // copy has completed
+    const int k = b->ring;
+    if (b->copy_pending[k] && FAILS(hipEventSynchronize(b->copied[k]))) return GRPIC_EDEVICE;
+    BatchTable *T = b->h_table[k];
+    const int nr = (int)b->active.size();
+    T->nruns = nr;
+    int64_t off[BK_NKINDS] = {0, 0, 0, 0, 0};
+    int iters = 1;
+    for (int i = 0; i < nr; i++) {
+        grpic_t *h = b->active[i]->h;
+        BatchRun32 &R = T->run[i];
+        fill_table_entry(h, R);
+        for (int kd = 0; kd < BK_NKINDS; kd++) {
+            R.off[kd] = off[kd];
+            off[kd] += batch_blocks(kd, h->G, R.relax_box, h->n_slots);
+        }
+        iters = h->cfg.field_iters > iters ? h->cfg.field_iters : iters;
+    }
+    for (int kd = 0; kd < BK_NKINDS; kd++) T->total[kd] = off[kd];
+    const size_t bytes = offsetof(BatchTable, run) + (size_t)nr * sizeof(BatchRun32);
+    int rc = check(hipMemcpyAsync(b->d_table, T, bytes, hipMemcpyHostToDevice, b->stream));
+    if (!rc) rc = check(hipEventRecord(b->copied[k], b->stream));
+    if (rc) return rc;
+    b->copy_pending[k] = true;
+    b->ring = 1 - k;
+    if (!b->exec || b->exec_iters != iters) {
+        rc = capture_iteration(b, iters);
+        if (rc) return rc;
+    }
+    rc = check(hipGraphLaunch(b->exec, b->stream));
+    if (rc) return rc;
     for (BatchRun *r : b->active) {
         grpic_t *h = r->h;
-        hipGraphExec_t &ex = r->exec[h->xc][h->uc];
-        if (!ex) {
-            rc = capture_cycle(r, &ex);
-            if (rc) return rc;
-        }
-        rc = check(hipGraphLaunch(ex, r->stream));
-        if (rc) return rc;
         h->xc = 1 - h->xc;
         h->step_count++;
         if (sort_due(h)) {
@@ -673,15 +753,19 @@ int grpic_batch_stats(grpic_batch_t *b, int32_t *active, int64_t *bytes_in_use) 
 
 void grpic_batch_destroy(grpic_batch_t *b) {
     if (!b) return;
-    for (BatchRun *r : b->active) {
-        drop_graphs(r);
+    if (b->stream) (void)hipStreamSynchronize(b->stream);
+    for (BatchRun *r : b->active)
         if (r->h) grpic_destroy(r->h);
-        if (r->stream) (void)hipStreamDestroy(r->stream);
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    for (int k = 0; k < 2; k++) {
+        if (b->h_table[k]) (void)hipHostFree(b->h_table[k]);
+        if (b->copied[k]) (void)hipEventDestroy(b->copied[k]);
     }
+    if (b->d_table) (void)hipFree(b->d_table);
+    if (b->stream) (void)hipStreamDestroy(b->stream);
     for (auto &kv : b->runs) delete kv.second;
     delete b;
 }
-
 
 void grpic_config_default(grpic_config *cfg, int32_t nx, int32_t ny, int32_t nz) {
     memset(cfg, 0, sizeof(*cfg));

@@ -148,22 +148,29 @@ __device__ __forceinline__ void apply_dS(const T *__restrict__ dS, int64_t nn, i
         }
 }
 
-// w = (S - I) P (D, B) at every node.
-template <typename T>
-__global__ void k_node_w(Grid G, FieldPtrsT<T> F, T *__restrict__ w) {
-    int64_t nn = G.nnodes();
-    int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (id >= nn) return;
-    int i = (int)(id % (G.nx + 1));
+__device__ __forceinline__ void node_ijk(const Grid &G, int64_t id, int &i, int &j, int &k) {
+    i = (int)(id % (G.nx + 1));
     int64_t t = id / (G.nx + 1);
-    int j = (int)(t % (G.ny + 1));
-    int k = (int)(t / (G.ny + 1));
+    j = (int)(t % (G.ny + 1));
+    k = (int)(t / (G.ny + 1));
+}
+
+// Per-index bodies of the field kernels.  A single run launches one thread
+// per index; the serving batch runs the same bodies for the indices of many
+// runs from one launch (see the batched kernels below).
+
+// w = (S - I) P (D, B) at node id.
+template <typename T>
+__device__ __forceinline__ void node_w_at(const Grid &G, const FieldPtrsT<T> &F, int64_t id) {
+    const int64_t nn = G.nnodes();
+    int i, j, k;
+    node_ijk(G, id, i, j, k);
     const T *D[3] = {F.D[0], F.D[1], F.D[2]};
     const T *B[3] = {F.B[0], F.B[1], F.B[2]};
     T v[6], o[6];
     node_pair<T>(G, D, B, i, j, k, v);
     apply_dS<T>(F.dS, nn, id, v, o);
-    for (int q = 0; q < 6; q++) w[q * nn + id] = o[q];
+    for (int q = 0; q < 6; q++) F.w[q * nn + id] = o[q];
 }
 
 __device__ __forceinline__ bool in_domain(const Grid &G, int kind, int c, int i, int j, int k) {
@@ -176,17 +183,13 @@ __device__ __forceinline__ bool in_domain(const Grid &G, int kind, int c, int i,
     return true;
 }
 
-// E_cov at every in-domain E point: -(D + P^T w) where updated, else the
-// initial value.  Thread per index (i,j,k) in [0,n]^3, all three components.
+// E_cov at the in-domain E points of index id: -(D + P^T w) where updated,
+// else the initial value (all three components).
 template <typename T>
-__global__ void k_ecov(Grid G, FieldPtrsT<T> F, const T *__restrict__ w, bool use_ref) {
-    int64_t nn = G.nnodes();
-    int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (id >= nn) return;
-    int i = (int)(id % (G.nx + 1));
-    int64_t t = id / (G.nx + 1);
-    int j = (int)(t % (G.ny + 1));
-    int k = (int)(t / (G.ny + 1));
+__device__ __forceinline__ void ecov_at(const Grid &G, const FieldPtrsT<T> &F, bool use_ref, int64_t id) {
+    const int64_t nn = G.nnodes();
+    int i, j, k;
+    node_ijk(G, id, i, j, k);
     int64_t gi = G.g(i, j, k);
     uint8_t mk = F.mask[gi];
     int64_t n0 = G.node(i, j, k);
@@ -197,23 +200,20 @@ __global__ void k_ecov(Grid G, FieldPtrsT<T> F, const T *__restrict__ w, bool us
         if (use_ref && !(mk & (1u << c))) {
             val = F.E0[c][gi];
         } else {
-            T corr = (T)0.5 * (w[c * nn + n0] + w[c * nn + n0 + step[c]]);
+            T corr = (T)0.5 * (F.w[c * nn + n0] + F.w[c * nn + n0 + step[c]]);
             val = -(F.D[c][gi] + corr);
         }
         F.E[c][gi] = val;
     }
 }
 
-// H at every in-domain B point: B + P^T w where updated, else the initial value.
+// H at the in-domain B points of index id: B + P^T w where updated, else the
+// initial value.
 template <typename T>
-__global__ void k_hfield(Grid G, FieldPtrsT<T> F, const T *__restrict__ w, bool use_ref) {
-    int64_t nn = G.nnodes();
-    int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (id >= nn) return;
-    int i = (int)(id % (G.nx + 1));
-    int64_t t = id / (G.nx + 1);
-    int j = (int)(t % (G.ny + 1));
-    int k = (int)(t / (G.ny + 1));
+__device__ __forceinline__ void hfield_at(const Grid &G, const FieldPtrsT<T> &F, bool use_ref, int64_t id) {
+    const int64_t nn = G.nnodes();
+    int i, j, k;
+    node_ijk(G, id, i, j, k);
     int64_t gi = G.g(i, j, k);
     uint8_t mk = F.mask[gi];
     int64_t n0 = G.node(i, j, k);
@@ -225,7 +225,7 @@ __global__ void k_hfield(Grid G, FieldPtrsT<T> F, const T *__restrict__ w, bool 
             val = F.H0[c][gi];
         } else {
             int a1 = (c + 1) % 3, a2 = (c + 2) % 3;
-            const T *wc = w + (3 + c) * nn;
+            const T *wc = F.w + (3 + c) * nn;
             T corr = (T)0.25 * (wc[n0] + wc[n0 + step[a1]] + wc[n0 + step[a2]] + wc[n0 + step[a1] + step[a2]]);
             val = F.B[c][gi] + corr;
         }
@@ -237,18 +237,12 @@ __global__ void k_hfield(Grid G, FieldPtrsT<T> F, const T *__restrict__ w, bool 
 //   Bout_c = Bin_c - h [ (E_be(x + e_al) - E_be(x)) - (E_al(x + e_be) - E_al(x)) ],  h = c dt / 2.
 // Points that are not updated copy Bin (when Bin and Bout differ).
 template <typename T>
-__global__ void k_bhalf(Grid G, FieldPtrsT<T> F, const T *__restrict__ Bin0, const T *__restrict__ Bin1,
-                        const T *__restrict__ Bin2, T hstep) {
-    int64_t nn = G.nnodes();
-    int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (id >= nn) return;
-    int i = (int)(id % (G.nx + 1));
-    int64_t t = id / (G.nx + 1);
-    int j = (int)(t % (G.ny + 1));
-    int k = (int)(t / (G.ny + 1));
+__device__ __forceinline__ void bhalf_at(const Grid &G, const FieldPtrsT<T> &F, const T *const Bin[3], T hstep,
+                                         int64_t id) {
+    int i, j, k;
+    node_ijk(G, id, i, j, k);
     int64_t gi = G.g(i, j, k);
     uint8_t mk = F.mask[gi];
-    const T *Bin[3] = {Bin0, Bin1, Bin2};
     int64_t st[3] = {1, G.sx, G.sy};
     for (int c = 0; c < 3; c++) {
         if (!in_domain(G, 1, c, i, j, k)) continue;
@@ -268,18 +262,12 @@ __global__ void k_bhalf(Grid G, FieldPtrsT<T> F, const T *__restrict__ Bin0, con
 // F^{c,c+1} = H[c+2], F^{c,c+2} = -H[c+1], backward differences; J from the
 // int64 accumulator.
 template <typename T>
-__global__ void k_dstep(Grid G, FieldPtrsT<T> F, const T *__restrict__ Din0, const T *__restrict__ Din1,
-                        const T *__restrict__ Din2, T dx4, T four_pi_over_c, double inv_jscale) {
-    int64_t nn = G.nnodes();
-    int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (id >= nn) return;
-    int i = (int)(id % (G.nx + 1));
-    int64_t t = id / (G.nx + 1);
-    int j = (int)(t % (G.ny + 1));
-    int k = (int)(t / (G.ny + 1));
+__device__ __forceinline__ void dstep_at(const Grid &G, const FieldPtrsT<T> &F, const T *const Din[3], T dx4,
+                                         T four_pi_over_c, double inv_jscale, int64_t id) {
+    int i, j, k;
+    node_ijk(G, id, i, j, k);
     int64_t gi = G.g(i, j, k);
     uint8_t mk = F.mask[gi];
-    const T *Din[3] = {Din0, Din1, Din2};
     int64_t st[3] = {1, G.sx, G.sy};
     for (int c = 0; c < 3; c++) {
         if (!in_domain(G, 0, c, i, j, k)) continue;
@@ -297,16 +285,14 @@ __global__ void k_dstep(Grid G, FieldPtrsT<T> F, const T *__restrict__ Din0, con
 
 // Relaxation layer inside the horizon: updated points with r_exc <= r < r_damp
 // move toward their initial values by damp_max ((r_damp - r)/(r_damp - r_exc))^2.
+// id runs over the box [i0, i0 + bx) x [j0, j0 + by) x [k0, k0 + bz).
 template <typename T>
-__global__ void k_relax(Grid G, Hole h, FieldPtrsT<T> F, double r_damp, double damp_max, int i0, int j0, int k0,
-                        int bx, int by, int bz) {
-    int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    int64_t tot = (int64_t)bx * by * bz;
-    if (id >= tot) return;
-    int i = i0 + (int)(id % bx);
-    int64_t t = id / bx;
-    int j = j0 + (int)(t % by);
-    int k = k0 + (int)(t / by);
+__device__ __forceinline__ void relax_at(const Grid &G, const Hole &h, const FieldPtrsT<T> &F, double r_damp,
+                                         double damp_max, const int box[6], int64_t id) {
+    int i = box[0] + (int)(id % box[3]);
+    int64_t t = id / box[3];
+    int j = box[1] + (int)(t % box[4]);
+    int k = box[2] + (int)(t / box[4]);
     int64_t gi = G.g(i, j, k);
     uint8_t mk = F.mask[gi];
     for (int kind = 0; kind < 2; kind++)
@@ -327,14 +313,10 @@ __global__ void k_relax(Grid G, Hole h, FieldPtrsT<T> F, double r_damp, double d
 
 // Node tensor F^a_b = F^{ag} g_{gb} from the node pair completed by S.
 template <typename T>
-__global__ void k_node_tensor(Grid G, FieldPtrsT<T> F, T *__restrict__ out) {
-    int64_t nn = G.nnodes();
-    int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (id >= nn) return;
-    int i = (int)(id % (G.nx + 1));
-    int64_t t = id / (G.nx + 1);
-    int j = (int)(t % (G.ny + 1));
-    int k = (int)(t / (G.ny + 1));
+__device__ __forceinline__ void node_tensor_at(const Grid &G, const FieldPtrsT<T> &F, int64_t id) {
+    const int64_t nn = G.nnodes();
+    int i, j, k;
+    node_ijk(G, id, i, j, k);
     const T *D[3] = {F.D[0], F.D[1], F.D[2]};
     const T *B[3] = {F.B[0], F.B[1], F.B[2]};
     T v[6], w[6];
@@ -353,13 +335,56 @@ __global__ void k_node_tensor(Grid G, FieldPtrsT<T> F, T *__restrict__ out) {
     }
     T g[10];
     for (int q = 0; q < 10; q++) g[q] = F.gn[q * nn + id];
-    T *o = out + 16 * id;
+    T *o = F.node + 16 * id;
     for (int a = 0; a < 4; a++)
         for (int b = 0; b < 4; b++) {
             T s = (T)0;
             for (int c = 0; c < 4; c++) s += Fu[a][c] * g[sym4(c, b)];
             o[a * 4 + b] = s;
         }
+}
+
+// Single-run kernels: one thread per index.
+template <typename T>
+__global__ void k_node_w(Grid G, FieldPtrsT<T> F) {
+    int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (id < G.nnodes()) node_w_at<T>(G, F, id);
+}
+template <typename T>
+__global__ void k_ecov(Grid G, FieldPtrsT<T> F, bool use_ref) {
+    int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (id < G.nnodes()) ecov_at<T>(G, F, use_ref, id);
+}
+template <typename T>
+__global__ void k_hfield(Grid G, FieldPtrsT<T> F, bool use_ref) {
+    int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (id < G.nnodes()) hfield_at<T>(G, F, use_ref, id);
+}
+template <typename T>
+__global__ void k_bhalf(Grid G, FieldPtrsT<T> F, const T *__restrict__ Bin0, const T *__restrict__ Bin1,
+                        const T *__restrict__ Bin2, T hstep) {
+    int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const T *Bin[3] = {Bin0, Bin1, Bin2};
+    if (id < G.nnodes()) bhalf_at<T>(G, F, Bin, hstep, id);
+}
+template <typename T>
+__global__ void k_dstep(Grid G, FieldPtrsT<T> F, const T *__restrict__ Din0, const T *__restrict__ Din1,
+                        const T *__restrict__ Din2, T dx4, T four_pi_over_c, double inv_jscale) {
+    int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const T *Din[3] = {Din0, Din1, Din2};
+    if (id < G.nnodes()) dstep_at<T>(G, F, Din, dx4, four_pi_over_c, inv_jscale, id);
+}
+template <typename T>
+__global__ void k_relax(Grid G, Hole h, FieldPtrsT<T> F, double r_damp, double damp_max, int i0, int j0, int k0,
+                        int bx, int by, int bz) {
+    int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int box[6] = {i0, j0, k0, bx, by, bz};
+    if (id < (int64_t)bx * by * bz) relax_at<T>(G, h, F, r_damp, damp_max, box, id);
+}
+template <typename T>
+__global__ void k_node_tensor(Grid G, FieldPtrsT<T> F) {
+    int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (id < G.nnodes()) node_tensor_at<T>(G, F, id);
 }
 
 // Initial fields: uniform F (contravariant or covariant B0) lowered/raised
@@ -413,9 +438,9 @@ void launch_init_fields(const Grid &G, const Hole &h, FieldPtrsT<T> &F, const do
 template <typename T>
 void launch_derived(const Grid &G, FieldPtrsT<T> &F, bool use_ref, bool do_e, bool do_h, hipStream_t s) {
     unsigned nb = nblk(G.nnodes(), 256);
-    hipLaunchKernelGGL(k_node_w<T>, dim3(nb), dim3(256), 0, s, G, F, F.w);
-    if (do_e) hipLaunchKernelGGL(k_ecov<T>, dim3(nb), dim3(256), 0, s, G, F, F.w, use_ref);
-    if (do_h) hipLaunchKernelGGL(k_hfield<T>, dim3(nb), dim3(256), 0, s, G, F, F.w, use_ref);
+    hipLaunchKernelGGL(k_node_w<T>, dim3(nb), dim3(256), 0, s, G, F);
+    if (do_e) hipLaunchKernelGGL(k_ecov<T>, dim3(nb), dim3(256), 0, s, G, F, use_ref);
+    if (do_h) hipLaunchKernelGGL(k_hfield<T>, dim3(nb), dim3(256), 0, s, G, F, use_ref);
 }
 
 template <typename T>
@@ -431,10 +456,12 @@ void launch_dstep(const Grid &G, FieldPtrsT<T> &F, const T *const Din[3], double
                        (T)dx4, (T)fpc, inv_jscale);
 }
 
-template <typename T>
-void launch_relax(const Grid &G, const Hole &h, FieldPtrsT<T> &F, double r_damp, double damp_max, hipStream_t s) {
+// Index box of the relaxation layer: the bounding box of the oblate region
+// r < r_damp (|x|,|y| <= sqrt(r^2+a^2), |z| <= r) clipped to the grid;
+// bx = by = bz = 0 when there is no layer.
+void relax_box_of(const Grid &G, const Hole &h, double r_damp, double damp_max, int box[6]) {
+    for (int q = 0; q < 6; q++) box[q] = 0;
     if (!(r_damp > h.r_exc) || !(damp_max > 0.0) || h.m == 0.0) return;
-    // bounding box of the oblate region r < r_damp: |x|,|y| <= sqrt(r^2+a^2), |z| <= r
     double ext_xy = sqrt(r_damp * r_damp + h.a * h.a) + 1.0, ext_z = r_damp + 1.0;
     int i0 = (int)floor(h.cx - ext_xy), i1 = (int)ceil(h.cx + ext_xy);
     int j0 = (int)floor(h.cy - ext_xy), j1 = (int)ceil(h.cy + ext_xy);
@@ -442,13 +469,91 @@ void launch_relax(const Grid &G, const Hole &h, FieldPtrsT<T> &F, double r_damp,
     i0 = i0 < 0 ? 0 : i0; j0 = j0 < 0 ? 0 : j0; k0 = k0 < 0 ? 0 : k0;
     i1 = i1 > G.nx ? G.nx : i1; j1 = j1 > G.ny ? G.ny : j1; k1 = k1 > G.nz ? G.nz : k1;
     if (i1 < i0 || j1 < j0 || k1 < k0) return;
-    int bx = i1 - i0 + 1, by = j1 - j0 + 1, bz = k1 - k0 + 1;
-    hipLaunchKernelGGL(k_relax<T>, dim3(nblk((int64_t)bx * by * bz, 128)), dim3(128), 0, s, G, h, F, r_damp,
-                       damp_max, i0, j0, k0, bx, by, bz);
+    box[0] = i0; box[1] = j0; box[2] = k0;
+    box[3] = i1 - i0 + 1; box[4] = j1 - j0 + 1; box[5] = k1 - k0 + 1;
+}
+
+template <typename T>
+void launch_relax(const Grid &G, const Hole &h, FieldPtrsT<T> &F, double r_damp, double damp_max, hipStream_t s) {
+    int box[6];
+    relax_box_of(G, h, r_damp, damp_max, box);
+    if (box[3] == 0) return;
+    hipLaunchKernelGGL(k_relax<T>, dim3(nblk((int64_t)box[3] * box[4] * box[5], 128)), dim3(128), 0, s, G, h, F,
+                       r_damp, damp_max, box[0], box[1], box[2], box[3], box[4], box[5]);
+}
+
+// ---------------------------------------------------------------------------
+// Serving batch: one persistent launch per field stage over the logical
+// blocks of every active run (FP32 fields).  Stages of the fixed-point
+// passes skip runs with fewer passes than `it + 1`.
+template <int OP>
+__global__ __launch_bounds__(kBatchBlock) void k_batch_field(const BatchTable *__restrict__ T, int it) {
+    constexpr int kind = (OP == BF_SAVE_B || OP == BF_ZERO_J || OP == BF_SAVE_D) ? BK_GRID
+                         : (OP == BF_RELAX ? BK_RELAX : BK_NODE);
+    constexpr bool pass = OP == BF_NODE_W || OP == BF_ECOV || OP == BF_BHALF_SAVED || OP == BF_HFIELD ||
+                          OP == BF_DSTEP;
+    const int64_t total = T->total[kind];
+    for (int64_t lb = blockIdx.x; lb < total; lb += gridDim.x) {
+        const BatchRun32 &R = T->run[batch_run_of(T, kind, lb)];
+        if (pass && it >= R.field_iters) continue;
+        const int64_t id = (lb - R.off[kind]) * kBatchBlock + threadIdx.x;
+        const Grid &G = R.G;
+        const FieldPtrsT<float> &F = R.F;
+        if (kind == BK_GRID) {
+            if (id >= G.gsize()) continue;
+            for (int q = 0; q < 3; q++) {
+                if (OP == BF_SAVE_B) F.Bsave[q][id] = F.B[q][id];
+                if (OP == BF_SAVE_D) F.Dsave[q][id] = F.D[q][id];
+                if (OP == BF_ZERO_J) F.Jint[q][id] = 0ull;
+            }
+        } else if (kind == BK_RELAX) {
+            if (id < (int64_t)R.relax_box[3] * R.relax_box[4] * R.relax_box[5])
+                relax_at<float>(G, R.h, F, R.r_damp, R.damp_max, R.relax_box, id);
+        } else {
+            if (id >= G.nnodes()) continue;
+            if (OP == BF_NODE_W) node_w_at<float>(G, F, id);
+            if (OP == BF_ECOV) ecov_at<float>(G, F, true, id);
+            if (OP == BF_HFIELD) hfield_at<float>(G, F, true, id);
+            if (OP == BF_NODE_TENSOR) node_tensor_at<float>(G, F, id);
+            if (OP == BF_BHALF_SAVED || OP == BF_BHALF_CUR) {
+                const float *Bin[3] = {F.Bsave[0], F.Bsave[1], F.Bsave[2]};
+                if (OP == BF_BHALF_CUR) {
+                    Bin[0] = F.B[0];
+                    Bin[1] = F.B[1];
+                    Bin[2] = F.B[2];
+                }
+                bhalf_at<float>(G, F, Bin, R.hstep, id);
+            }
+            if (OP == BF_DSTEP) {
+                const float *Din[3] = {F.Dsave[0], F.Dsave[1], F.Dsave[2]};
+                const double dtp = (it < R.field_iters - 1) ? 0.5 * R.dt : R.dt;
+                dstep_at<float>(G, F, Din, (float)(R.c * dtp), R.fpc, R.inv_jscale, id);
+            }
+        }
+    }
+}
+
+void launch_batch_field(int op, const BatchTable *table, int it, int grid, hipStream_t s) {
+    switch (op) {
+#define GRPIC_BF(OP) \
+    case OP: hipLaunchKernelGGL(k_batch_field<OP>, dim3(grid), dim3(kBatchBlock), 0, s, table, it); break;
+        GRPIC_BF(BF_SAVE_B)
+        GRPIC_BF(BF_NODE_W)
+        GRPIC_BF(BF_ECOV)
+        GRPIC_BF(BF_BHALF_SAVED)
+        GRPIC_BF(BF_NODE_TENSOR)
+        GRPIC_BF(BF_BHALF_CUR)
+        GRPIC_BF(BF_ZERO_J)
+        GRPIC_BF(BF_SAVE_D)
+        GRPIC_BF(BF_HFIELD)
+        GRPIC_BF(BF_DSTEP)
+        GRPIC_BF(BF_RELAX)
+#undef GRPIC_BF
+    }
 }
 
 template <typename T> void launch_node_tensor(const Grid &G, FieldPtrsT<T> &F, hipStream_t s) {
-    hipLaunchKernelGGL(k_node_tensor<T>, dim3(nblk(G.nnodes(), 128)), dim3(128), 0, s, G, F, F.node);
+    hipLaunchKernelGGL(k_node_tensor<T>, dim3(nblk(G.nnodes(), 128)), dim3(128), 0, s, G, F);
 }
 
 #define GRPIC_FIELD_INSTANTIATE(T)                                                                          \

@@ -122,11 +122,82 @@ void launch_push32(const PushParams &P, const Mixed &M, const Species &S, const 
 void launch_deposit32(const Grid &G, const Hole &h, const Mixed &M, double dt, int deposit_mode, double r_rm,
                       double jscale, double rscale, const Species &S, ParticlePtrs32 xold, ParticlePtrs32 xnew,
                       int64_t n, FieldPtrsT<float> &F, unsigned long long *counters, hipStream_t s);
+struct Dep32 {
+    Grid G;
+    Hole h;
+    double r_fp64;
+    float inv_dt;
+    double jscale;
+    int curved;
+};
 void launch_load32(const Grid &G, const Hole &h, double c, double r_rm, const double *xin, const double *ucin,
                    int64_t n, int species, ParticlePtrs32 out, int64_t offset, unsigned long long *counters,
                    hipStream_t s);
 void launch_to_f64(ParticlePtrs32 in, double *x, double *u, int64_t n, hipStream_t s);
 void launch_from_f64(const double *x, const double *u, ParticlePtrs32 out, int64_t n, hipStream_t s);
+
+// ---------------------------------------------------------------------------
+// Serving batch (FP32-mixed form): one launch per cycle stage covers every
+// active run.  The launches are persistent: a fixed grid whose blocks walk
+// the logical blocks of all runs, each run owning a contiguous range of
+// logical blocks per kind of work, so a logical block belongs to one run.
+// The run table lives in device memory and is rewritten before every
+// iteration, so a captured iteration replays unchanged while runs come and
+// go and their buffers swap.
+enum BatchKind { BK_NODE = 0, BK_GRID, BK_RELAX, BK_PUSH, BK_DEP, BK_NKINDS };
+constexpr int kBatchBlock = 256;     // threads per block of the field kinds
+constexpr int kMaxBatchRuns = 64;
+
+struct BatchRun32 {
+    int64_t off[BK_NKINDS];  // first logical block of this run per kind
+    Grid G;
+    Hole h;
+    FieldPtrsT<float> F;
+    float hstep;             // c dt / 2
+    double c, dt;
+    float fpc;               // 4 pi / c
+    double inv_jscale;
+    int field_iters;
+    int relax_box[6];        // i0, j0, k0, bx, by, bz (bx = 0: no relaxation)
+    double r_damp, damp_max;
+    PushParams P;            // P.n = particle slots
+    Mixed M;
+    Species S;
+    ParticlePtrs32 cur, nxt;  // state at time n and the buffers of time n+1
+    unsigned long long *counters;
+    Dep32 D;
+    double r_rm, rscale;
+};
+
+struct BatchTable {
+    int nruns;
+    int64_t total[BK_NKINDS];  // logical blocks per kind over all runs
+    BatchRun32 run[kMaxBatchRuns];
+};
+
+// Stage identifiers of the batched field launches.
+enum BatchFieldOp { BF_SAVE_B, BF_NODE_W, BF_ECOV, BF_BHALF_SAVED, BF_NODE_TENSOR, BF_BHALF_CUR, BF_ZERO_J,
+                    BF_SAVE_D, BF_HFIELD, BF_DSTEP, BF_RELAX };
+// The run owning logical block lb of a kind: the last run whose first block
+// is <= lb (runs are stored in increasing block order).
+__device__ __forceinline__ int batch_run_of(const BatchTable *__restrict__ T, int kind, int64_t lb) {
+    int lo = 0, hi = T->nruns - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (T->run[mid].off[kind] <= lb)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    return lo;
+}
+Dep32 make_dep32(const Grid &G, const Hole &h, const Mixed &M, double dt, int deposit_mode, double jscale);
+void launch_batch_field(int op, const BatchTable *table, int it, int grid, hipStream_t s);
+void launch_batch_push32(const BatchTable *table, int grid, hipStream_t s);
+void launch_batch_deposit32(const BatchTable *table, int grid, hipStream_t s);
+// logical blocks of one run per kind (field kinds in kBatchBlock threads)
+int64_t batch_blocks(int kind, const Grid &G, const int relax_box[6], int64_t n_slots);
+void relax_box_of(const Grid &G, const Hole &h, double r_damp, double damp_max, int box[6]);
 
 // sort
 size_t sort_temp_bytes(int64_t capacity);

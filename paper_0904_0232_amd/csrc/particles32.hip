@@ -172,19 +172,21 @@ __device__ __forceinline__ void stage_nodes32(const Grid &G, const float *__rest
 // The same RK4 in coordinate time as the FP64 pusher, on offsets relative
 // to the particle's cell; the cell is re-based after the step.  The nodes of
 // each stage are staged in LDS per block, as in the FP64 pusher.
-__global__ __launch_bounds__(kPush32Block, 4) void k_push32(PushParams P, Mixed M, Species cS,
-                                                           const float *__restrict__ node, ParticlePtrs32 in,
-                                                           ParticlePtrs32 out, unsigned long long *counters) {
-    __shared__ float4 snode[kPush32LdsNodes * kNode32Stride4];
-    __shared__ int sred[6][kPush32Block / 64];
+// Block `blk` of the push (particles blk * kPush32Block ...); LDS scratch
+// snode and sred come from the calling kernel.  Every thread of the block
+// calls this.
+__device__ __forceinline__ void push32_block(const PushParams &P, const Mixed &M, const Species &cS,
+                                             const float *__restrict__ node, const ParticlePtrs32 &in,
+                                             const ParticlePtrs32 &out, unsigned long long *counters, int64_t blk,
+                                             float4 *snode, int (*sred)[kPush32Block / 64]) {
     const int tid = threadIdx.x;
-    const int64_t id = (int64_t)blockIdx.x * kPush32Block + tid;
+    const int64_t id = blk * kPush32Block + tid;
     int clamps = 0;
     const uint8_t sp = id < P.n ? in.sp[id] : kDead;
     const bool alive = sp != kDead;
     const unsigned long long live = __ballot(alive);
     if ((tid & 63) == 0 && live)
-        atomicAdd(&counters[pushed_index(blockIdx.x)], (unsigned long long)__popcll(live));
+        atomicAdd(&counters[pushed_index((unsigned)blk)], (unsigned long long)__popcll(live));
     int i = 0, j = 0, k = 0;
     float qm = 0.0f;
     float X0[3] = {0.0f, 0.0f, 0.0f}, U0[4] = {0.0f, 0.0f, 0.0f, 0.0f};
@@ -243,6 +245,14 @@ __global__ __launch_bounds__(kPush32Block, 4) void k_push32(PushParams P, Mixed 
     if (clamps) atomicAdd(&counters[C_GAMMA_CLAMPS], (unsigned long long)clamps);
 }
 
+__global__ __launch_bounds__(kPush32Block, 4) void k_push32(PushParams P, Mixed M, Species cS,
+                                                           const float *__restrict__ node, ParticlePtrs32 in,
+                                                           ParticlePtrs32 out, unsigned long long *counters) {
+    __shared__ float4 snode[kPush32LdsNodes * kNode32Stride4];
+    __shared__ int sred[6][kPush32Block / 64];
+    push32_block(P, M, cS, node, in, out, counters, blockIdx.x, snode, sred);
+}
+
 void launch_push32(const PushParams &P, const Mixed &M, const Species &S, const float *node, ParticlePtrs32 in,
                    ParticlePtrs32 out, unsigned long long *counters, hipStream_t s) {
     if (P.n <= 0) return;
@@ -254,14 +264,6 @@ void launch_push32(const PushParams &P, const Mixed &M, const Species &S, const 
 // Deposition in FP32 coordinates local to the old cell (Sec. 4, same zigzag
 // and weights as the FP64 kernel), int64 fixed-point accumulation.
 
-struct Dep32 {
-    Grid G;
-    Hole h;
-    double r_fp64;
-    float inv_dt;
-    double jscale;
-    int curved;
-};
 
 // Area density sqrt(1 + f (1 - k_K^2)) at a point given as cell + local
 // offset, folded into one division as in the FP64 kernel; FP64 within r_fp64.
@@ -444,13 +446,15 @@ constexpr int kDep32Block = 256;
 constexpr int kDep32PPT = 4;
 constexpr int kDep32Lds = 4096;
 
-__global__ __launch_bounds__(kDep32Block) void k_deposit32(Dep32 D, Species cS, double r_rm, double rscale,
-                                                           ParticlePtrs32 xo, ParticlePtrs32 xn, int64_t n,
-                                                           FieldPtrsT<float> F, unsigned long long *counters) {
-    __shared__ unsigned long long sm[kDep32Lds];
-    __shared__ int sred[6][kDep32Block / 64];
+// Block `blk` of the deposit (particles blk * kDep32Block * kDep32PPT ...);
+// LDS scratch sm and sred come from the calling kernel.  Every thread of the
+// block calls this.
+__device__ __forceinline__ void deposit32_block(const Dep32 &D, const Species &cS, double r_rm, double rscale,
+                                                const ParticlePtrs32 &xo, const ParticlePtrs32 &xn, int64_t n,
+                                                const FieldPtrsT<float> &F, unsigned long long *counters, int64_t blk,
+                                                unsigned long long *sm, int (*sred)[kDep32Block / 64]) {
     const int tid = threadIdx.x;
-    const int64_t base = (int64_t)blockIdx.x * (kDep32Block * kDep32PPT);
+    const int64_t base = blk * (kDep32Block * kDep32PPT);
     uint8_t SP[kDep32PPT];
     int lo[3] = {1 << 30, 1 << 30, 1 << 30}, hi[3] = {-(1 << 30), -(1 << 30), -(1 << 30)};
 #pragma unroll
@@ -566,10 +570,15 @@ __global__ __launch_bounds__(kDep32Block) void k_deposit32(Dep32 D, Species cS, 
     }
 }
 
-void launch_deposit32(const Grid &G, const Hole &h, const Mixed &M, double dt, int deposit_mode, double r_rm,
-                      double jscale, double rscale, const Species &S, ParticlePtrs32 xold, ParticlePtrs32 xnew,
-                      int64_t n, FieldPtrsT<float> &F, unsigned long long *counters, hipStream_t s) {
-    if (n <= 0) return;
+__global__ __launch_bounds__(kDep32Block) void k_deposit32(Dep32 D, Species cS, double r_rm, double rscale,
+                                                           ParticlePtrs32 xo, ParticlePtrs32 xn, int64_t n,
+                                                           FieldPtrsT<float> F, unsigned long long *counters) {
+    __shared__ unsigned long long sm[kDep32Lds];
+    __shared__ int sred[6][kDep32Block / 64];
+    deposit32_block(D, cS, r_rm, rscale, xo, xn, n, F, counters, blockIdx.x, sm, sred);
+}
+
+Dep32 make_dep32(const Grid &G, const Hole &h, const Mixed &M, double dt, int deposit_mode, double jscale) {
     Dep32 D;
     D.G = G;
     D.h = h;
@@ -577,6 +586,60 @@ void launch_deposit32(const Grid &G, const Hole &h, const Mixed &M, double dt, i
     D.inv_dt = (float)(1.0 / dt);
     D.jscale = jscale;
     D.curved = deposit_mode == 0;
+    return D;
+}
+
+// ---------------------------------------------------------------------------
+// Serving batch: persistent push and deposit over the logical blocks of all
+// active runs (the run table is in device memory).
+__global__ __launch_bounds__(kPush32Block, 4) void k_batch_push32(const BatchTable *__restrict__ T) {
+    __shared__ float4 snode[kPush32LdsNodes * kNode32Stride4];
+    __shared__ int sred[6][kPush32Block / 64];
+    const int64_t total = T->total[BK_PUSH];
+    for (int64_t lb = blockIdx.x; lb < total; lb += gridDim.x) {
+        __syncthreads();  // the previous logical block is done with the LDS scratch
+        const BatchRun32 &R = T->run[batch_run_of(T, BK_PUSH, lb)];
+        push32_block(R.P, R.M, R.S, R.F.node, R.cur, R.nxt, R.counters, lb - R.off[BK_PUSH], snode, sred);
+    }
+}
+
+__global__ __launch_bounds__(kDep32Block) void k_batch_deposit32(const BatchTable *__restrict__ T) {
+    __shared__ unsigned long long sm[kDep32Lds];
+    __shared__ int sred[6][kDep32Block / 64];
+    const int64_t total = T->total[BK_DEP];
+    for (int64_t lb = blockIdx.x; lb < total; lb += gridDim.x) {
+        __syncthreads();  // the previous logical block is done with the LDS scratch
+        const BatchRun32 &R = T->run[batch_run_of(T, BK_DEP, lb)];
+        deposit32_block(R.D, R.S, R.r_rm, R.rscale, R.cur, R.nxt, R.P.n, R.F, R.counters, lb - R.off[BK_DEP], sm,
+                        sred);
+    }
+}
+
+void launch_batch_push32(const BatchTable *table, int grid, hipStream_t s) {
+    hipLaunchKernelGGL(k_batch_push32, dim3(grid), dim3(kPush32Block), 0, s, table);
+}
+
+void launch_batch_deposit32(const BatchTable *table, int grid, hipStream_t s) {
+    hipLaunchKernelGGL(k_batch_deposit32, dim3(grid), dim3(kDep32Block), 0, s, table);
+}
+
+int64_t batch_blocks(int kind, const Grid &G, const int relax_box[6], int64_t n_slots) {
+    auto up = [](int64_t a, int64_t b) { return (a + b - 1) / b; };
+    switch (kind) {
+    case BK_NODE: return up(G.nnodes(), kBatchBlock);
+    case BK_GRID: return up(G.gsize(), kBatchBlock);
+    case BK_RELAX: return up((int64_t)relax_box[3] * relax_box[4] * relax_box[5], kBatchBlock);
+    case BK_PUSH: return up(n_slots, kPush32Block);
+    case BK_DEP: return up(n_slots, (int64_t)kDep32Block * kDep32PPT);
+    }
+    return 0;
+}
+
+void launch_deposit32(const Grid &G, const Hole &h, const Mixed &M, double dt, int deposit_mode, double r_rm,
+                      double jscale, double rscale, const Species &S, ParticlePtrs32 xold, ParticlePtrs32 xnew,
+                      int64_t n, FieldPtrsT<float> &F, unsigned long long *counters, hipStream_t s) {
+    if (n <= 0) return;
+    const Dep32 D = make_dep32(G, h, M, dt, deposit_mode, jscale);
     const int64_t per = kDep32Block * kDep32PPT;
     hipLaunchKernelGGL(k_deposit32, dim3((unsigned)((n + per - 1) / per)), dim3(kDep32Block), 0, s, D, S, r_rm,
                        rscale, xold, xnew, n, F, counters);

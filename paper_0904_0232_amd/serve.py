@@ -77,6 +77,7 @@ def serve(requests, budget_bytes, max_slots, keep_ids=(), prefetch=4, log=None):
     t0 = time.perf_counter()
     total_psteps = 0
     iterations = 0
+    t_inputs = t_submit = t_step = 0.0  # host time waiting for inputs, admitting, stepping
     try:
         while pending or waiting or active:
             now = time.perf_counter() - t0
@@ -89,9 +90,13 @@ def serve(requests, budget_bytes, max_slots, keep_ids=(), prefetch=4, log=None):
                     if q["id"] not in futures:
                         futures[q["id"]] = pool.submit(request_particles, q)
                 r = waiting[0]
+                ta = time.perf_counter()
                 parts = futures[r["id"]].result()
+                tb = time.perf_counter()
                 rid = capi.grpic_batch_submit(b, request_config(r), r["steps"], parts,
                                               keep_state=r["id"] in keep_ids)
+                t_inputs += tb - ta
+                t_submit += time.perf_counter() - tb
                 if rid is None:
                     break
                 waiting.popleft()
@@ -99,7 +104,9 @@ def serve(requests, budget_bytes, max_slots, keep_ids=(), prefetch=4, log=None):
                 active[rid] = r
                 records[r["id"]] = dict(r, admitted=time.perf_counter() - t0)
             if active:
+                ta = time.perf_counter()
                 fin = capi.grpic_batch_step(b)
+                t_step += time.perf_counter() - ta
                 iterations += 1
                 if fin:
                     tnow = time.perf_counter() - t0
@@ -133,4 +140,5 @@ def serve(requests, budget_bytes, max_slots, keep_ids=(), prefetch=4, log=None):
         "particle_steps": total_psteps,
         "particle_steps_per_s": total_psteps / makespan if makespan > 0 else 0.0,
         "runs_per_s": len(records) / makespan if makespan > 0 else 0.0,
+        "host_s": {"waiting_for_inputs": t_inputs, "admitting": t_submit, "stepping": t_step},
     }

@@ -54,6 +54,8 @@ def test_batch_graph_replay_equals_eager_steps():
         say("nsteps %d: batch %d slots, eager %d slots, energy %.12e vs %.12e" %
             (nsteps, ns, xe.shape[1], diag_b["energy_particles"], diag_e["energy_particles"]))
         live = spe != O.DEAD  # x and u of removed slots are unspecified
+        say("   batch vs eager, live slots: max |dx| %.3e, max |du| %.3e" %
+            (np.abs(xb[:, live] - xe[:, live]).max(), np.abs(ub[:, live] - ue[:, live]).max()))
         assert np.array_equal(spb, spe)
         assert np.array_equal(xb[:, live], xe[:, live]) and np.array_equal(ub[:, live], ue[:, live])
         for k in ("n_alive", "energy_particles", "lz_particles", "energy_field", "gauss_residual_max"):
