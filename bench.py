@@ -162,15 +162,23 @@ def push_roofline(m, flops_per_ps, peak, traffic=None):
     }
 
 
-def serving(args, saturated_rate):
-    """Continuous batching of independent FP32-mixed runs with Poisson arrivals
-    at 0.7 of the completion rate the measured single-run throughput sustains."""
+def serving(args):
+    """Continuous batching of independent FP32-mixed runs with Poisson
+    arrivals.  A saturated probe (32 requests arriving at once) measures the
+    loop's own capacity in particle-steps/s; the measured workload then
+    arrives at 0.7 of that capacity."""
     from paper_0904_0232_amd import serve
-    probe = serve.make_requests(args.serve_runs, 0, 1.0)
-    mean_work = sum(2 * r["ppc"] * r["edge"] ** 3 * r["steps"] for r in probe) / len(probe)
-    rate = 0.7 * saturated_rate / mean_work
+    budget = int(args.serve_budget_gb * (1 << 30))
+
+    def work(reqs):
+        return sum(2 * r["ppc"] * r["edge"] ** 3 * r["steps"] for r in reqs) / len(reqs)
+
+    probe = serve.serve(serve.make_requests(32, 1, 1e6), budget, args.serve_slots)
+    capacity = probe["particle_steps_per_s"]
+    log("serving probe: %.4g particle-steps/s saturated" % capacity)
+    rate = 0.7 * capacity / work(serve.make_requests(args.serve_runs, 0, 1.0))
     reqs = serve.make_requests(args.serve_runs, 0, rate)
-    res = serve.serve(reqs, int(args.serve_budget_gb * (1 << 30)), args.serve_slots, log=log)
+    res = serve.serve(reqs, budget, args.serve_slots)
     return {
         "runs": res["n_runs"],
         "arrival_rate_per_s": rate,
@@ -178,11 +186,15 @@ def serving(args, saturated_rate):
         "p99_latency_s": res["p99_latency_s"],
         "runs_per_s": res["runs_per_s"],
         "particle_steps_per_s": res["particle_steps_per_s"],
+        "saturated_particle_steps_per_s": capacity,
         "makespan_s": res["makespan_s"],
+        "iterations": res["iterations"],
+        "host_s": res["host_s"],
         "budget_gb": args.serve_budget_gb,
         "slots": args.serve_slots,
         "workload": "grid edge in {16,32,48,64,96}, a~U[0,0.99]m, m=edge/16, 2-8 ppc per species, "
-                    "u_th~U[0.02,0.2]c, 50-500 steps, FP32-mixed, Poisson arrivals (seed 0)",
+                    "u_th~U[0.02,0.2]c, 50-500 steps, FP32-mixed, Poisson arrivals at 0.7 of the saturated "
+                    "capacity (seed 0)",
     }
 
 
@@ -302,10 +314,9 @@ def main():
                     help="also run the FP32-mixed vs FP64 precision study on the torus workload (1000 steps)")
     ap.add_argument("--precision-particles", type=int, default=0,
                     help="particles per species for the precision study (0: the full workload)")
-    ap.add_argument("--serve-runs", type=int, default=48,
-                    help="requests in the serving measurement (0 skips it); the serving workload has 256")
-    ap.add_argument("--serve-budget-gb", type=float, default=8.0)
-    ap.add_argument("--serve-slots", type=int, default=32)
+    ap.add_argument("--serve-runs", type=int, default=256, help="requests in the serving measurement (0 skips it)")
+    ap.add_argument("--serve-budget-gb", type=float, default=64.0)
+    ap.add_argument("--serve-slots", type=int, default=64)
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -357,7 +368,7 @@ def main():
             "roofline": push_roofline(m32, PUSH_FLOPS_PER_PARTICLE_STEP, FP32_PEAK_TFLOPS),
         }
     if args.serve_runs > 0:
-        line["serving"] = serving(args, line.get("fp32_mixed", {}).get("value", m64["value"]))
+        line["serving"] = serving(args)
         log("serving: p50 %.3f s p99 %.3f s" % (line["serving"]["p50_latency_s"], line["serving"]["p99_latency_s"]))
     if args.scale:
         scale = {}

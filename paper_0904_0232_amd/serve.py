@@ -61,7 +61,7 @@ def percentile(v, q):
     return float(np.percentile(np.asarray(v, dtype=float), q)) if len(v) else float("nan")
 
 
-def serve(requests, budget_bytes, max_slots, keep_ids=(), prefetch=4, log=None):
+def serve(requests, budget_bytes, max_slots, keep_ids=(), prefetch=8, log=None):
     """Run the request loop to completion.  Returns per-request records and totals."""
     b = capi.grpic_batch_create(budget_bytes, max_slots)
     pool = ThreadPoolExecutor(max_workers=prefetch)
@@ -84,9 +84,14 @@ def serve(requests, budget_bytes, max_slots, keep_ids=(), prefetch=4, log=None):
             while pending and pending[0]["arrival"] <= now:
                 r = pending.popleft()
                 waiting.append(r)
+            # a request carries its particles: the payloads of the next few
+            # requests in arrival order are drawn ahead on host threads, so
+            # they are ready when the requests arrive
+            for q in itertools.islice(itertools.chain(waiting, pending), prefetch):
+                if q["id"] not in futures:
+                    futures[q["id"]] = pool.submit(request_particles, q)
             while waiting:
-                # inputs of the next few queued requests are drawn ahead on host threads
-                for q in itertools.islice(waiting, prefetch):
+                for q in itertools.islice(itertools.chain(waiting, pending), prefetch):
                     if q["id"] not in futures:
                         futures[q["id"]] = pool.submit(request_particles, q)
                 r = waiting[0]
