@@ -42,6 +42,37 @@ struct Hole {
     double r_exc;
 };
 
+// Square root and quotient from the hardware reciprocal (square-root)
+// estimates refined by two Newton steps, plus a residual correction for the
+// quotient: a few ulps instead of the correctly rounded result, at about
+// half the instructions.  sqrt_nr takes x >= 0 (0 gives 0); div_nr takes a
+// finite non-zero normal d.
+__device__ __forceinline__ double sqrt_nr(double x) {
+    double y = __builtin_amdgcn_rsq(x);
+    const double h = 0.5 * x;
+    y = y * fma(-h * y, y, 1.5);
+    y = y * fma(-h * y, y, 1.5);
+    return x > 0.0 ? x * y : 0.0;
+}
+__device__ __forceinline__ double rcp_nr(double d) {
+    double r = __builtin_amdgcn_rcp(d);
+    r = fma(fma(-d, r, 1.0), r, r);
+    return fma(fma(-d, r, 1.0), r, r);
+}
+__device__ __forceinline__ double div_nr(double n, double d) {
+    const double r = rcp_nr(d);
+    const double q = n * r;
+    return fma(fma(-d, q, n), r, q);
+}
+// 1/d in the pusher's type: the refined FP64 estimate, or the FP32 hardware
+// reciprocal with one Newton step.
+template <typename T> __device__ __forceinline__ T recip(T d);
+template <> __device__ __forceinline__ double recip<double>(double d) { return rcp_nr(d); }
+template <> __device__ __forceinline__ float recip<float>(float d) {
+    const float r = __builtin_amdgcn_rcpf(d);
+    return fmaf(fmaf(-d, r, 1.0f), r, r);
+}
+
 // Radius from the quartic, always in FP64: the cancellation-free root for
 // r^2 on each side of R^2 = a^2.
 __device__ __forceinline__ double ks_radius(double a, double x, double y, double z) {
@@ -51,6 +82,14 @@ __device__ __forceinline__ double ks_radius(double a, double x, double y, double
     double s = sqrt(b * b + 4.0 * a2z2);
     double r2 = (b >= 0.0) ? 0.5 * (b + s) : (2.0 * a2z2) / (s - b);
     return sqrt(r2);
+}
+
+// The same root with the refined square roots and quotient (the hot paths:
+// every RK4 stage and every deposit face point).
+__device__ __forceinline__ double ks_radius_nr(double a, double x, double y, double z) {
+    const double b = x * x + y * y + z * z - a * a, a2z2 = a * a * z * z;
+    const double s = sqrt_nr(b * b + 4.0 * a2z2);
+    return sqrt_nr(b >= 0.0 ? 0.5 * (b + s) : div_nr(2.0 * a2z2, s - b));
 }
 
 // f and the spatial part of k at a hole-relative point (m > 0, r > 0).
@@ -135,9 +174,9 @@ __device__ __forceinline__ void ks_grad_r(T m, T a, T x, T y, T z, T r, KSGradT<
     T rr = r * r;
     T a2 = a * a;
     T S4 = rr * rr + a2 * z * z;
-    T iS4 = one / S4;
-    T iden = one / (rr + a2);
-    T ir = one / r;
+    T iS4 = recip<T>(S4);
+    T iden = recip<T>(rr + a2);
+    T ir = recip<T>(r);
     T f = (T)2 * m * r * rr * iS4;
     T k0 = (r * x - a * y) * iden;
     T k1 = (r * y + a * x) * iden;
@@ -168,7 +207,7 @@ __device__ __forceinline__ void ks_grad_r(T m, T a, T x, T y, T z, T r, KSGradT<
 }
 
 __device__ __forceinline__ void ks_grad(double m, double a, double x, double y, double z, KSGrad &o) {
-    ks_grad_r<double>(m, a, x, y, z, ks_radius(a, x, y, z), o);
+    ks_grad_r<double>(m, a, x, y, z, ks_radius_nr(a, x, y, z), o);
 }
 
 // G^a = Gamma^a_{mn} u^m u^n for g = eta + f k k (stationary, k_4 = 1):

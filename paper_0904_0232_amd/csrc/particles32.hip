@@ -98,7 +98,7 @@ __device__ __forceinline__ void accel32(const PushParams &P, const Mixed &M, con
     if (P.h.m != 0.0) {
         double x, y, z;
         hole_rel(P.h, i, j, k, X, x, y, z);
-        double r = ks_radius(P.h.a, x, y, z);
+        double r = ks_radius_nr(P.h.a, x, y, z);
         if (r < M.r_fp64) {
             KSGradT<double> kp;
             ks_grad_r<double>(P.h.m, P.h.a, x, y, z, r, kp);
@@ -212,7 +212,7 @@ __device__ __forceinline__ void push32_block(const PushParams &P, const Mixed &M
             float A[4];
             accel32(P, M, node, B, c, qm, i, j, k, Xs, Us, A);
             float gam = stage_gamma32(P, Us[3], A[3], clamps);
-            float ig = 1.0f / gam;
+            float ig = recip<float>(gam);
             float Kx[3] = {Us[0] * ig, Us[1] * ig, Us[2] * ig};
             float Ku[4] = {A[0] * ig, A[1] * ig, A[2] * ig, A[3] * ig};
             float wgt = (st == 0 || st == 3) ? 1.0f : 2.0f;
@@ -273,7 +273,7 @@ __device__ __forceinline__ float area_density32(const Dep32 &D, int K, const int
     const double y = ((double)base[1] - D.h.cy) + (double)P3[1];
     const double z = ((double)base[2] - D.h.cz) + (double)P3[2];
     const double a = D.h.a;
-    const double r = ks_radius(a, x, y, z);
+    const double r = ks_radius_nr(a, x, y, z);
     if (r < D.h.r_exc) return 1.0f;
     if (r < D.r_fp64) {
         const double rr = r * r, S4 = rr * rr + a * a * z * z;
@@ -286,7 +286,7 @@ __device__ __forceinline__ float area_density32(const Dep32 &D, int K, const int
             num = 2.0 * D.h.m * r * rr * ((Dn - nK) * (Dn + nK));
             den = S4 * (Dn * Dn);
         }
-        return (float)sqrt(1.0 + num / den);
+        return (float)sqrt_nr(1.0 + div_nr(num, den));
     }
     const float rf = (float)r, af = (float)a, xf = (float)x, yf = (float)y, zf = (float)z, mf = (float)D.h.m;
     const float rr = rf * rf, S4 = rr * rr + af * af * zf * zf;
