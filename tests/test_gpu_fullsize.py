@@ -1,0 +1,127 @@
+"""Parity at the full sizes of the torus (128^3, 33,554,432 particles) and
+throughput (256^3, 268,435,456 particles) workloads, in the launch
+configuration the benchmark times, in both precisions.
+
+The oracle cannot redo a whole 256^3 cycle in seconds, so the full-size runs
+are pinned two ways:
+
+- sampled particles, one test-particle step (the node tensor of the initial
+  fields, as grpic_push_only uses): the oracle runs on a 20^3 window of the
+  big grid, placed by giving it the hole centre in window coordinates; the
+  initial fields and their node tensor are local, so the window's interior
+  reproduces the big grid's exactly.  Windows sit near the hole, in the bulk
+  of the plasma and further out;
+- one full cycle from the same state: the total current per direction
+  equals sum q dx / dt over the particles' own moves (true for any
+  transverse weights, at any size).
+
+Tolerances: FP64 1e-12 relative per step (as the other parity tests);
+FP32-mixed 1e-5 relative against the FP64 oracle.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+from common import rel_err, say
+
+pytestmark = [pytest.mark.gpu, pytest.mark.slow]
+
+W = 20          # window edge in cells
+MARGIN = 3      # sampled particles start and end this far inside the window
+PER_WINDOW = 1500
+
+_inputs = {}
+
+
+def _workload(name):
+    from paper_0904_0232_amd import inputs
+    if name not in _inputs:
+        _inputs.clear()
+        say("generating the %s inputs" % name)
+        _inputs[name] = inputs.workload_particles(name, seed=0)
+    return inputs.workload_params(name), _inputs[name]
+
+
+def _run(w, ntot, precision):
+    from paper_0904_0232_amd import capi
+    from paper_0904_0232_amd import run as R
+    cfg = R.make_config(w["n"], m=w["m"], a=w["a"], dt=w["dt"], B0=(0.0, 0.0, w["B0"]), species=w["species"],
+                        r_rm=w["r_rm"], sort_every=0, capacity=ntot,
+                        precision=capi.FP32_MIXED if precision == "fp32" else capi.FP64)
+    return R.Run(cfg)
+
+
+def _windows(w):
+    """Window origins: centred at R = r_+ + 5, in the bulk and further out
+    (torus: R = 24 and 34 in the equatorial plane, where its particles are;
+    uniform plasmas: n/4 and 0.4 n), along x, y and a third direction."""
+    n, c0 = w["n"], w["n"] / 2.0
+    if w["plasma"] == "torus":
+        far = ((24.0, (0.0, 1.0, 0.0)), (34.0, (-1.0, -1.0, 0.0)))
+    else:
+        far = ((n / 4.0, (0.0, 1.0, 0.0)), (0.4 * n, (1.0, 1.0, 1.0)))
+    out = []
+    for R, d in ((w["r_plus"] + 5.0, (1.0, 0.0, 0.0)),) + far:
+        d = np.array(d) / np.linalg.norm(d)
+        cen = c0 + R * d
+        out.append(np.floor(cen - W / 2.0).astype(int))
+    return out
+
+
+@pytest.mark.parametrize("name,precision", [("torus128", "fp64"), ("torus128", "fp32"),
+                                            ("shell256", "fp64"), ("shell256", "fp32")])
+def test_full_size(name, precision):
+    w, parts = _workload(name)
+    ntot = sum(p[1].shape[1] for p in parts)
+    say("case %s %s: %d particles, %d^3 grid" % (name, precision, ntot, w["n"]))
+    r = _run(w, ntot, precision)
+    kept = sum(r.load(sp, x, uc) for sp, x, uc in parts)
+    x0, u0, sp0 = r.particles()
+    say("  loaded %d live of %d" % (kept, ntot))
+    live = sp0 != O.DEAD
+
+    # sampled test-particle step against oracle windows
+    r.push_only(1)
+    x1, u1, _ = r.particles()
+    tol = 1e-12 if precision == "fp64" else 1e-5
+    g = np.random.default_rng(7)
+    for o in _windows(w):
+        inside = live.copy()
+        for ax in range(3):
+            lo, hi = o[ax] + MARGIN, o[ax] + W - MARGIN
+            inside &= (x0[ax] >= lo) & (x0[ax] < hi) & (x1[ax] >= lo) & (x1[ax] < hi)
+        idx = np.nonzero(inside)[0]
+        assert idx.size > 0, ("empty window", o)
+        pick = np.sort(g.choice(idx, min(PER_WINDOW, idx.size), replace=False))
+        cen = tuple(w["n"] / 2.0 - o)
+        p = O.make_params(W, m=w["m"], a=w["a"], dt=w["dt"], center=cen, r_rm=w["r_rm"],
+                          species=w["species"])
+        s = O.Sim(p, pick.size)
+        s.init_fields([0.0, 0.0, w["B0"]])
+        s.compute_nodes()
+        s.set_particles(x0[:, pick] - o[:, None], u0[:, pick], sp0[pick])
+        s.push_only(1)
+        xs, us, _ = s.particles()
+        ex = rel_err(x1[:, pick] - o[:, None], xs, 1.0)
+        eu = rel_err(u1[:, pick], us, 1.0)
+        Rw = np.linalg.norm(o + W / 2.0 - w["n"] / 2.0)
+        say("  window at R=%.1f: %d particles, push err x %.2e u %.2e" % (Rw, pick.size, ex, eu))
+        assert ex < tol and eu < tol
+    del x1, u1
+
+    # one full cycle from the loaded state: total current per direction
+    r.restore_particles(x0, u0, sp0)
+    del u0
+    r.step(1)
+    x1, _, _ = r.particles()
+    J = r.fields("J")
+    qs = np.array([q for q, _ in w["species"]])
+    qlive = qs[sp0[live]]
+    jtol = 1e-12 if precision == "fp64" else 1e-6
+    for K in range(3):
+        ref = float((qlive * (x1[K, live] - x0[K, live])).sum()) / w["dt"]
+        floor = live.sum() * 24 * 0.5 * np.abs(qs).max() / w["dt"] * 2.0 ** -44
+        got = float(J[K].sum())
+        say("  full cycle: sum J_%d %.6e, sum q dx/dt %.6e" % (K, got, ref))
+        assert abs(got - ref) <= jtol * float(np.abs(J[K]).sum()) + floor, K
+    r.close()
