@@ -208,8 +208,6 @@ bool alloc_fields(grpic_t *h, FieldPtrsT<T> &F) {
     }
     F.rho_abs = (unsigned long long *)A(gs * 8);
     F.mask = (uint8_t *)A(gs);
-    F.dS = (T *)A(21 * nn * sizeof(T));
-    F.gn = (T *)A(10 * nn * sizeof(T));
     F.w = (T *)A(6 * nn * sizeof(T));
     F.node = (T *)A(16 * nn * sizeof(T));
     return ok;
@@ -234,7 +232,7 @@ int init_fields(grpic_t *h, FieldPtrsT<T> &F) {
         if (FAILS(hipMemcpyAsync(F.D0[c], F.D[c], gs * sizeof(T), hipMemcpyDeviceToDevice, s))) return GRPIC_EDEVICE;
         if (FAILS(hipMemcpyAsync(F.B0[c], F.B[c], gs * sizeof(T), hipMemcpyDeviceToDevice, s))) return GRPIC_EDEVICE;
     }
-    launch_derived<T>(h->G, F, false, true, true, s);
+    launch_derived<T>(h->G, h->h, F, false, true, true, s);
     for (int c = 0; c < 3; c++) {
         if (FAILS(hipMemcpyAsync(F.E0[c], F.E[c], gs * sizeof(T), hipMemcpyDeviceToDevice, s))) return GRPIC_EDEVICE;
         if (FAILS(hipMemcpyAsync(F.H0[c], F.H[c], gs * sizeof(T), hipMemcpyDeviceToDevice, s))) return GRPIC_EDEVICE;
@@ -249,16 +247,14 @@ int fields_to_n(grpic_t *h) {
     FieldPtrsT<T> &F = fields<T>(h);
     const grpic_config &c = h->cfg;
     hipStream_t s = h->stream;
-    int64_t gs = h->G.gsize();
     TimedGroup tg(h, GRPIC_TIMER_FIELDS);
-    for (int q = 0; q < 3; q++)
-        if (FAILS(hipMemcpyAsync(F.Bsave[q], F.B[q], gs * sizeof(T), hipMemcpyDeviceToDevice, s))) return GRPIC_EDEVICE;
+    launch_save<T>(h->G, F, 0, s);
     const T *Bsave[3] = {F.Bsave[0], F.Bsave[1], F.Bsave[2]};
     for (int it = 0; it < c.field_iters; it++) {
-        launch_derived<T>(h->G, F, true, true, false, s);
+        launch_derived<T>(h->G, h->h, F, true, true, false, s);
         launch_bhalf<T>(h->G, F, Bsave, 0.5 * c.c * c.dt, s);
     }
-    launch_node_tensor<T>(h->G, F, s);
+    launch_node_tensor<T>(h->G, h->h, F, s);
     return GRPIC_OK;
 }
 
@@ -269,7 +265,7 @@ void fields_mid(grpic_t *h) {
     TimedGroup tg(h, GRPIC_TIMER_FIELDS);
     const T *Bcur[3] = {F.B[0], F.B[1], F.B[2]};
     launch_bhalf<T>(h->G, F, Bcur, 0.5 * h->cfg.c * h->cfg.dt, h->stream);
-    for (int q = 0; q < 3; q++) launch_zero_u64(F.Jint[q], h->G.gsize(), h->stream);
+    launch_zero3_u64(F.Jint, h->G.gsize(), h->stream);
 }
 
 // Electric step around D^{n+1/2}, then the relaxation layer.
@@ -278,15 +274,13 @@ int fields_d(grpic_t *h) {
     FieldPtrsT<T> &F = fields<T>(h);
     const grpic_config &c = h->cfg;
     hipStream_t s = h->stream;
-    int64_t gs = h->G.gsize();
     TimedGroup tg(h, GRPIC_TIMER_FIELDS);
-    for (int q = 0; q < 3; q++)
-        if (FAILS(hipMemcpyAsync(F.Dsave[q], F.D[q], gs * sizeof(T), hipMemcpyDeviceToDevice, s))) return GRPIC_EDEVICE;
+    launch_save<T>(h->G, F, 1, s);
     const T *Dsave[3] = {F.Dsave[0], F.Dsave[1], F.Dsave[2]};
     double inv_js = 1.0 / h->jscale;
     double fpc = 4.0 * M_PI / c.c;
     for (int it = 0; it < c.field_iters; it++) {
-        launch_derived<T>(h->G, F, true, false, true, s);
+        launch_derived<T>(h->G, h->h, F, true, false, true, s);
         double dtp = (it < c.field_iters - 1) ? 0.5 * c.dt : c.dt;
         launch_dstep<T>(h->G, F, Dsave, c.c * dtp, fpc, inv_js, s);
     }
@@ -445,7 +439,7 @@ int64_t run_bytes(const grpic_config *c) {
     int64_t cap = c->capacity > 0 ? c->capacity : 1;
     int64_t b = 0;
     b += 30 * up(gs * T) + 3 * up(gs * 8) + up(gs * 8) + up(gs);
-    b += up(21 * nn * T) + up(10 * nn * T) + up(6 * nn * T) + up(16 * nn * T);
+    b += up(6 * nn * T) + up(16 * nn * T);
     if (c->precision == GRPIC_FP32_MIXED)
         b += 2 * (up(cap * 4) + 3 * up(cap * 4) + 4 * up(cap * 4) + up(cap));
     else
@@ -967,9 +961,9 @@ int grpic_push_only(grpic_t *h, int32_t nsteps) {
     clear_foreign_error();
     if (!h || nsteps < 0) return GRPIC_EINVAL;
     if (h->mixed)
-        launch_node_tensor<float>(h->G, h->F32, h->stream);
+        launch_node_tensor<float>(h->G, h->h, h->F32, h->stream);
     else
-        launch_node_tensor<double>(h->G, h->F64, h->stream);
+        launch_node_tensor<double>(h->G, h->h, h->F64, h->stream);
     for (int i = 0; i < nsteps; i++) {
         push_particles(h);
         h->xc = 1 - h->xc;
@@ -1077,11 +1071,11 @@ int grpic_diagnostics(grpic_t *h, grpic_diag *out) {
     int rc;
     // derived fields of the current state (frozen points keep their initial values)
     if (h->mixed) {
-        launch_derived<float>(h->G, h->F32, true, true, true, s);
+        launch_derived<float>(h->G, h->h, h->F32, true, true, true, s);
         rc = run_diag<float>(h->G, h->h, h->cfg.c, h->rscale, h->S, P, n, h->F32, h->cfg.r_damp, h->cfg.damp_max,
                              h->rho_scratch, h->red, h->red_cap, d, s);
     } else {
-        launch_derived<double>(h->G, h->F64, true, true, true, s);
+        launch_derived<double>(h->G, h->h, h->F64, true, true, true, s);
         rc = run_diag<double>(h->G, h->h, h->cfg.c, h->rscale, h->S, P, n, h->F64, h->cfg.r_damp, h->cfg.damp_max,
                               h->rho_scratch, h->red, h->red_cap, d, s);
     }

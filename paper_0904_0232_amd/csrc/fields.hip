@@ -15,44 +15,46 @@
 // with P the average of the six components onto the nodes (1/2 of the two
 // E points along c, 1/4 of the four B points) and P^T its transpose, so the
 // discrete map is symmetric and reduces to Yee's identity at m = 0.
-// (S - I) and g are baked per node once (the metric is stationary), in FP64,
-// and stored in the field type T: double for the FP64 form, float for the
-// FP32-mixed form (whose field arithmetic is then FP32).
+// (S - I) and g are evaluated per node in FP64 in each node pass (the metric
+// is stationary) and rounded to the field type T: double for the FP64 form,
+// float for the FP32-mixed form (whose field arithmetic is then FP32).
 #include "grpic_dev.h"
 #include "grpic_impl.h"
 
 namespace grpic {
 
 // Pairs: s = {23, 31, 12}, t = {14, 24, 34} (0-based: (1,2),(2,0),(0,1),(0,3),(1,3),(2,3)).
+__host__ __device__ constexpr int pair_index(int A, int e) {
+    return A == 0 ? (e ? 2 : 1) : A == 1 ? (e ? 0 : 2) : A == 2 ? (e ? 1 : 0) : (e ? 3 : A - 3);
+}
 __constant__ int kPair[6][2] = {{1, 2}, {2, 0}, {0, 1}, {0, 3}, {1, 3}, {2, 3}};
 
 // packed symmetric 6x6: index of (i,j)
-__device__ __forceinline__ int sym6(int i, int j) {
-    int lo = i < j ? i : j, hi = i < j ? j : i;
-    return lo * 6 - (lo * (lo - 1)) / 2 + (hi - lo);
+__host__ __device__ constexpr int sym6(int i, int j) {
+    return (i < j ? i : j) * 6 - ((i < j ? i : j) * ((i < j ? i : j) - 1)) / 2 + ((i < j ? j : i) - (i < j ? i : j));
 }
 
 // ---------------------------------------------------------------------------
-// Bake: per node the curvature part dS = S - I of the constitutive map and
-// the covariant metric g (for lowering the node tensor).
+// Per node: the curvature part dS = S - I of the constitutive map (packed
+// symmetric, 21 values) and the covariant metric g (packed, 10 values), in
+// FP64 from the metric at the node.  The metric is stationary, but computing
+// these in the node passes costs less than streaming 31 stored values per
+// node through every pass.
 // Variable order v = (D^0, D^1, D^2, B_0, B_1, B_2).
-template <typename T>
-__global__ void k_bake_nodes(Grid G, Hole h, T *__restrict__ dS, T *__restrict__ gn) {
-    int64_t nn = G.nnodes();
-    int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (id >= nn) return;
-    int i = (int)(id % (G.nx + 1));
-    int64_t t = id / (G.nx + 1);
-    int j = (int)(t % (G.ny + 1));
-    int k = (int)(t / (G.ny + 1));
+__device__ __forceinline__ void node_constitutive(const Hole &h, int i, int j, int k, double dS[21],
+                                                  double gout[10]) {
     Sym4 g, gi;
     grid_metric(h, (double)i, (double)j, (double)k, g, gi);
-    for (int q = 0; q < 10; q++) gn[q * nn + id] = (T)g.v[q];
+    for (int q = 0; q < 10; q++) gout[q] = g.v[q];
     // M over the pairs: M[A][B] = gi^{mu al} gi^{nu be} - gi^{mu be} gi^{nu al}
+    // (loops unrolled so that every index is a constant and the matrices stay
+    // in registers)
     double M[6][6];
+#pragma unroll
     for (int A = 0; A < 6; A++)
+#pragma unroll
         for (int B = 0; B < 6; B++) {
-            int mu = kPair[A][0], nu = kPair[A][1], al = kPair[B][0], be = kPair[B][1];
+            const int mu = pair_index(A, 0), nu = pair_index(A, 1), al = pair_index(B, 0), be = pair_index(B, 1);
             M[A][B] = gi.v[sym4(mu, al)] * gi.v[sym4(nu, be)] - gi.v[sym4(mu, be)] * gi.v[sym4(nu, al)];
         }
     // Minv = M_tt^{-1} by the adjugate
@@ -68,24 +70,32 @@ __global__ void k_bake_nodes(Grid G, Hole h, T *__restrict__ dS, T *__restrict__
                        {c20 * idet, c21 * idet, c22 * idet}};
     // S_DD = -Mi ; S_DB = Mi M_ts ; S_BB = M_ss - M_st Mi M_ts
     double SDB[3][3];
+#pragma unroll
     for (int r = 0; r < 3; r++)
+#pragma unroll
         for (int c = 0; c < 3; c++) {
             double s = 0.0;
+#pragma unroll
             for (int q = 0; q < 3; q++) s += Mi[r][q] * M[3 + q][c];
             SDB[r][c] = s;
         }
     double S[6][6];
+#pragma unroll
     for (int r = 0; r < 3; r++)
+#pragma unroll
         for (int c = 0; c < 3; c++) {
             S[r][c] = -Mi[r][c];
             S[r][3 + c] = SDB[r][c];
             S[3 + c][r] = SDB[r][c];
             double s = M[r][c];
+#pragma unroll
             for (int q = 0; q < 3; q++) s -= M[r][3 + q] * SDB[q][c];
             S[3 + r][3 + c] = s;
         }
+#pragma unroll
     for (int r = 0; r < 6; r++)
-        for (int c = r; c < 6; c++) dS[sym6(r, c) * nn + id] = (T)(S[r][c] - (r == c ? 1.0 : 0.0));
+#pragma unroll
+        for (int c = r; c < 6; c++) dS[sym6(r, c)] = S[r][c] - (r == c ? 1.0 : 0.0);
 }
 
 // Update masks: bit c set if E_c at this index is updated, bit 3+c for B_c.
@@ -138,11 +148,14 @@ __device__ __forceinline__ void node_pair(const Grid &G, const T *const D[3], co
 }
 
 template <typename T>
-__device__ __forceinline__ void apply_dS(const T *__restrict__ dS, int64_t nn, int64_t id, const T v[6], T w[6]) {
+__device__ __forceinline__ void apply_dS(const double dS[21], const T v[6], T w[6]) {
+#pragma unroll
     for (int r = 0; r < 6; r++) w[r] = (T)0;
+#pragma unroll
     for (int r = 0; r < 6; r++)
+#pragma unroll
         for (int c = r; c < 6; c++) {
-            T s = dS[sym6(r, c) * nn + id];
+            T s = (T)dS[sym6(r, c)];
             w[r] += s * v[c];
             if (c != r) w[c] += s * v[r];
         }
@@ -161,7 +174,7 @@ __device__ __forceinline__ void node_ijk(const Grid &G, int64_t id, int &i, int 
 
 // w = (S - I) P (D, B) at node id.
 template <typename T>
-__device__ __forceinline__ void node_w_at(const Grid &G, const FieldPtrsT<T> &F, int64_t id) {
+__device__ __forceinline__ void node_w_at(const Grid &G, const Hole &h, const FieldPtrsT<T> &F, int64_t id) {
     const int64_t nn = G.nnodes();
     int i, j, k;
     node_ijk(G, id, i, j, k);
@@ -169,7 +182,9 @@ __device__ __forceinline__ void node_w_at(const Grid &G, const FieldPtrsT<T> &F,
     const T *B[3] = {F.B[0], F.B[1], F.B[2]};
     T v[6], o[6];
     node_pair<T>(G, D, B, i, j, k, v);
-    apply_dS<T>(F.dS, nn, id, v, o);
+    double dS[21], g[10];
+    node_constitutive(h, i, j, k, dS, g);
+    apply_dS<T>(dS, v, o);
     for (int q = 0; q < 6; q++) F.w[q * nn + id] = o[q];
 }
 
@@ -313,15 +328,16 @@ __device__ __forceinline__ void relax_at(const Grid &G, const Hole &h, const Fie
 
 // Node tensor F^a_b = F^{ag} g_{gb} from the node pair completed by S.
 template <typename T>
-__device__ __forceinline__ void node_tensor_at(const Grid &G, const FieldPtrsT<T> &F, int64_t id) {
-    const int64_t nn = G.nnodes();
+__device__ __forceinline__ void node_tensor_at(const Grid &G, const Hole &h, const FieldPtrsT<T> &F, int64_t id) {
     int i, j, k;
     node_ijk(G, id, i, j, k);
     const T *D[3] = {F.D[0], F.D[1], F.D[2]};
     const T *B[3] = {F.B[0], F.B[1], F.B[2]};
     T v[6], w[6];
     node_pair<T>(G, D, B, i, j, k, v);
-    apply_dS<T>(F.dS, nn, id, v, w);
+    double dS[21], gd[10];
+    node_constitutive(h, i, j, k, dS, gd);
+    apply_dS<T>(dS, v, w);
     // contravariant components: F^{c4} = v_D, F^{s} = v_B + w_B
     T Fu[4][4];
     for (int a = 0; a < 4; a++) Fu[a][a] = (T)0;
@@ -334,7 +350,7 @@ __device__ __forceinline__ void node_tensor_at(const Grid &G, const FieldPtrsT<T
         Fu[3][c] = -v[c];
     }
     T g[10];
-    for (int q = 0; q < 10; q++) g[q] = F.gn[q * nn + id];
+    for (int q = 0; q < 10; q++) g[q] = (T)gd[q];
     T *o = F.node + 16 * id;
     for (int a = 0; a < 4; a++)
         for (int b = 0; b < 4; b++) {
@@ -346,9 +362,9 @@ __device__ __forceinline__ void node_tensor_at(const Grid &G, const FieldPtrsT<T
 
 // Single-run kernels: one thread per index.
 template <typename T>
-__global__ void k_node_w(Grid G, FieldPtrsT<T> F) {
+__global__ void k_node_w(Grid G, Hole h, FieldPtrsT<T> F) {
     int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (id < G.nnodes()) node_w_at<T>(G, F, id);
+    if (id < G.nnodes()) node_w_at<T>(G, h, F, id);
 }
 template <typename T>
 __global__ void k_ecov(Grid G, FieldPtrsT<T> F, bool use_ref) {
@@ -382,9 +398,9 @@ __global__ void k_relax(Grid G, Hole h, FieldPtrsT<T> F, double r_damp, double d
     if (id < (int64_t)bx * by * bz) relax_at<T>(G, h, F, r_damp, damp_max, box, id);
 }
 template <typename T>
-__global__ void k_node_tensor(Grid G, FieldPtrsT<T> F) {
+__global__ void k_node_tensor(Grid G, Hole h, FieldPtrsT<T> F) {
     int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (id < G.nnodes()) node_tensor_at<T>(G, F, id);
+    if (id < G.nnodes()) node_tensor_at<T>(G, h, F, id);
 }
 
 // Initial fields: uniform F (contravariant or covariant B0) lowered/raised
@@ -424,7 +440,6 @@ __global__ void k_init_fields(Grid G, Hole h, FieldPtrsT<T> F, double b0, double
 static inline unsigned nblk(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
 
 template <typename T> void launch_bake(const Grid &G, const Hole &h, FieldPtrsT<T> &F, hipStream_t s) {
-    hipLaunchKernelGGL(k_bake_nodes<T>, dim3(nblk(G.nnodes(), 128)), dim3(128), 0, s, G, h, F.dS, F.gn);
     hipLaunchKernelGGL(k_masks, dim3(nblk(G.gsize(), 256)), dim3(256), 0, s, G, h, F.mask);
 }
 
@@ -436,9 +451,10 @@ void launch_init_fields(const Grid &G, const Hole &h, FieldPtrsT<T> &F, const do
 }
 
 template <typename T>
-void launch_derived(const Grid &G, FieldPtrsT<T> &F, bool use_ref, bool do_e, bool do_h, hipStream_t s) {
+void launch_derived(const Grid &G, const Hole &h, FieldPtrsT<T> &F, bool use_ref, bool do_e, bool do_h,
+                    hipStream_t s) {
     unsigned nb = nblk(G.nnodes(), 256);
-    hipLaunchKernelGGL(k_node_w<T>, dim3(nb), dim3(256), 0, s, G, F);
+    hipLaunchKernelGGL(k_node_w<T>, dim3(nb), dim3(256), 0, s, G, h, F);
     if (do_e) hipLaunchKernelGGL(k_ecov<T>, dim3(nb), dim3(256), 0, s, G, F, use_ref);
     if (do_h) hipLaunchKernelGGL(k_hfield<T>, dim3(nb), dim3(256), 0, s, G, F, use_ref);
 }
@@ -454,6 +470,23 @@ void launch_dstep(const Grid &G, FieldPtrsT<T> &F, const T *const Din[3], double
                   hipStream_t s) {
     hipLaunchKernelGGL(k_dstep<T>, dim3(nblk(G.nnodes(), 256)), dim3(256), 0, s, G, F, Din[0], Din[1], Din[2],
                        (T)dx4, (T)fpc, inv_jscale);
+}
+
+// Copy of three field components (one launch instead of three copies).
+template <typename T>
+__global__ void k_save3(FieldPtrsT<T> F, int which, int64_t n) {
+    int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (id >= n) return;
+    for (int q = 0; q < 3; q++) {
+        if (which == 0)
+            F.Bsave[q][id] = F.B[q][id];
+        else
+            F.Dsave[q][id] = F.D[q][id];
+    }
+}
+
+template <typename T> void launch_save(const Grid &G, FieldPtrsT<T> &F, int which, hipStream_t s) {
+    hipLaunchKernelGGL(k_save3<T>, dim3(nblk(G.gsize(), 256)), dim3(256), 0, s, F, which, G.gsize());
 }
 
 // Index box of the relaxation layer: the bounding box of the oblate region
@@ -511,10 +544,10 @@ __global__ __launch_bounds__(kBatchBlock) void k_batch_field(const BatchTable *_
                 relax_at<float>(G, R.h, F, R.r_damp, R.damp_max, R.relax_box, id);
         } else {
             if (id >= G.nnodes()) continue;
-            if (OP == BF_NODE_W) node_w_at<float>(G, F, id);
+            if (OP == BF_NODE_W) node_w_at<float>(G, R.h, F, id);
             if (OP == BF_ECOV) ecov_at<float>(G, F, true, id);
             if (OP == BF_HFIELD) hfield_at<float>(G, F, true, id);
-            if (OP == BF_NODE_TENSOR) node_tensor_at<float>(G, F, id);
+            if (OP == BF_NODE_TENSOR) node_tensor_at<float>(G, R.h, F, id);
             if (OP == BF_BHALF_SAVED || OP == BF_BHALF_CUR) {
                 const float *Bin[3] = {F.Bsave[0], F.Bsave[1], F.Bsave[2]};
                 if (OP == BF_BHALF_CUR) {
@@ -552,20 +585,22 @@ void launch_batch_field(int op, const BatchTable *table, int it, int grid, hipSt
     }
 }
 
-template <typename T> void launch_node_tensor(const Grid &G, FieldPtrsT<T> &F, hipStream_t s) {
-    hipLaunchKernelGGL(k_node_tensor<T>, dim3(nblk(G.nnodes(), 128)), dim3(128), 0, s, G, F);
+template <typename T> void launch_node_tensor(const Grid &G, const Hole &h, FieldPtrsT<T> &F, hipStream_t s) {
+    hipLaunchKernelGGL(k_node_tensor<T>, dim3(nblk(G.nnodes(), 128)), dim3(128), 0, s, G, h, F);
 }
 
 #define GRPIC_FIELD_INSTANTIATE(T)                                                                          \
     template void launch_bake<T>(const Grid &, const Hole &, FieldPtrsT<T> &, hipStream_t);                 \
     template void launch_init_fields<T>(const Grid &, const Hole &, FieldPtrsT<T> &, const double *, int,   \
                                         hipStream_t);                                                       \
-    template void launch_derived<T>(const Grid &, FieldPtrsT<T> &, bool, bool, bool, hipStream_t);          \
+    template void launch_derived<T>(const Grid &, const Hole &, FieldPtrsT<T> &, bool, bool, bool,          \
+                                    hipStream_t);                                                           \
     template void launch_bhalf<T>(const Grid &, FieldPtrsT<T> &, const T *const *, double, hipStream_t);    \
     template void launch_dstep<T>(const Grid &, FieldPtrsT<T> &, const T *const *, double, double, double,  \
                                   hipStream_t);                                                             \
     template void launch_relax<T>(const Grid &, const Hole &, FieldPtrsT<T> &, double, double, hipStream_t); \
-    template void launch_node_tensor<T>(const Grid &, FieldPtrsT<T> &, hipStream_t);
+    template void launch_node_tensor<T>(const Grid &, const Hole &, FieldPtrsT<T> &, hipStream_t);          \
+    template void launch_save<T>(const Grid &, FieldPtrsT<T> &, int, hipStream_t);
 GRPIC_FIELD_INSTANTIATE(double)
 GRPIC_FIELD_INSTANTIATE(float)
 

@@ -118,10 +118,9 @@ struct Sym4 {
     double v[10];
 };
 
-__device__ __forceinline__ int sym4(int a, int b) {
+__host__ __device__ constexpr int sym4(int a, int b) {
     // index of (a,b) in the packed upper triangle
-    int lo = a < b ? a : b, hi = a < b ? b : a;
-    return lo * 4 - (lo * (lo - 1)) / 2 + (hi - lo);
+    return (a < b ? a : b) * 4 - ((a < b ? a : b) * ((a < b ? a : b) - 1)) / 2 + ((a < b ? b : a) - (a < b ? a : b));
 }
 
 // g_{ab} and g^{ab} at a grid point (node coordinates X, Y, Z).

@@ -20,8 +20,6 @@ struct FieldPtrsT {
     unsigned long long *Jint[3];  // int64 fixed-point current on E points
     unsigned long long *rho_abs;  // int64 fixed-point charge removed at the horizon (nodes, ghosted)
     uint8_t *mask;          // update bits per ghosted index
-    T *dS;                  // [21][nnodes] packed S - I
-    T *gn;                  // [10][nnodes] packed g_ab
     T *w;                   // [6][nnodes] scratch (S - I) P v
     T *node;                // [nnodes][16] mixed tensor F^a_b
 };
@@ -92,7 +90,8 @@ template <typename T>
 void launch_init_fields(const Grid &G, const Hole &h, FieldPtrsT<T> &F, const double B0[3], int covariant,
                         hipStream_t s);
 template <typename T>
-void launch_derived(const Grid &G, FieldPtrsT<T> &F, bool use_ref, bool do_e, bool do_h, hipStream_t s);
+void launch_derived(const Grid &G, const Hole &h, FieldPtrsT<T> &F, bool use_ref, bool do_e, bool do_h,
+                    hipStream_t s);
 template <typename T>
 void launch_bhalf(const Grid &G, FieldPtrsT<T> &F, const T *const Bin[3], double hstep, hipStream_t s);
 template <typename T>
@@ -100,7 +99,11 @@ void launch_dstep(const Grid &G, FieldPtrsT<T> &F, const T *const Din[3], double
                   double inv_jscale, hipStream_t s);
 template <typename T>
 void launch_relax(const Grid &G, const Hole &h, FieldPtrsT<T> &F, double r_damp, double damp_max, hipStream_t s);
-template <typename T> void launch_node_tensor(const Grid &G, FieldPtrsT<T> &F, hipStream_t s);
+template <typename T> void launch_node_tensor(const Grid &G, const Hole &h, FieldPtrsT<T> &F, hipStream_t s);
+// Bsave <- B (which = 0) or Dsave <- D (which = 1), all three components.
+template <typename T> void launch_save(const Grid &G, FieldPtrsT<T> &F, int which, hipStream_t s);
+// Clear the three int64 current arrays.
+void launch_zero3_u64(unsigned long long *const p[3], int64_t n, hipStream_t s);
 
 // particle kernels
 void launch_push(const PushParams &P, const Species &S, const double *node, ParticlePtrs in, ParticlePtrs out,

@@ -621,4 +621,18 @@ void launch_zero_u64(unsigned long long *p, int64_t n, hipStream_t s) {
     hipLaunchKernelGGL(k_zero_u64, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, n);
 }
 
+__global__ void k_zero3_u64(unsigned long long *p0, unsigned long long *p1, unsigned long long *p2, int64_t n) {
+    int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (id < n) {
+        p0[id] = 0ull;
+        p1[id] = 0ull;
+        p2[id] = 0ull;
+    }
+}
+
+void launch_zero3_u64(unsigned long long *const p[3], int64_t n, hipStream_t s) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_zero3_u64, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p[0], p[1], p[2], n);
+}
+
 }  // namespace grpic
