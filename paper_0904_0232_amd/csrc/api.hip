@@ -294,6 +294,9 @@ PushParams push_params(grpic_t *h) {
     P.h = h->h;
     P.c = h->cfg.c;
     P.dt = h->cfg.dt;
+    P.inv_c = 1.0 / h->cfg.c;
+    P.dt_2c = h->cfg.dt / (2.0 * h->cfg.c);
+    P.dt_6 = h->cfg.dt / 6.0;
     P.gamma_mode = h->cfg.gamma_mode;
     P.n = h->n_slots;
     return P;

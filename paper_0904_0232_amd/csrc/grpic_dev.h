@@ -237,10 +237,10 @@ __device__ __forceinline__ void gamma_uu(const KSGradT<T> &p, const T u[4], T G[
     G[3] = -Gl[3] + fkG;
 }
 
-// l / d for 0 <= l < 2^20 and d >= 1 through the float reciprocal inv_d = 1/d:
-// (l + 1/2)/d lies at least 1/(2d) from an integer while the float rounding
-// moves it by less than (l + 1/2)/d * 2^-22, so the truncation is the exact
-// quotient.
+// l / d for 0 <= l < 2^20 and d >= 1 through a float reciprocal inv_d of d
+// accurate to one ulp (the hardware estimate): (l + 1/2)/d lies at least
+// 1/(2d) from an integer while the float roundings move it by less than
+// (l + 1/2)/d * 2^-22, so the truncation is the exact quotient.
 __device__ __forceinline__ int small_div(int l, float inv_d) { return (int)(((float)l + 0.5f) * inv_d); }
 
 // Fixed-point conversion of one current or charge contribution.

@@ -80,6 +80,9 @@ struct PushParams {
     Grid G;
     Hole h;
     double c, dt;
+    double inv_c;        // 1 / c
+    double dt_2c;        // dt / (2 c)
+    double dt_6;         // dt / 6
     int gamma_mode;
     int64_t n;  // slots to process
 };

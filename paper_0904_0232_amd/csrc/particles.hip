@@ -96,9 +96,9 @@ __device__ __forceinline__ void accel(const PushParams &P, const double *__restr
 // Stage time-dilation factor: PAPER = 1/2 [u4/c + sqrt((u4/c)^2 + 2 a4 dt / c)]
 // (negative discriminant clamped to 0 and counted), U4 = u4/c.
 __device__ __forceinline__ double stage_gamma(const PushParams &P, double u4, double a4, int &clamps) {
-    double uc = u4 / P.c;
+    double uc = u4 * P.inv_c;
     if (P.gamma_mode == 1) return uc;
-    double disc = uc * uc + 4.0 * a4 * (P.dt / (2.0 * P.c));
+    double disc = uc * uc + 4.0 * a4 * P.dt_2c;
     if (disc < 0.0) {
         disc = 0.0;
         clamps++;
@@ -139,7 +139,7 @@ __device__ __forceinline__ void stage_nodes(const Grid &G, const double *__restr
     if (B.use) {
         const double2 *src = reinterpret_cast<const double2 *>(node);
         const int nb0 = B.n[0], nb01 = B.n[0] * B.n[1];
-        const float inv0 = 1.0f / (float)nb0, inv01 = 1.0f / (float)nb01;
+        const float inv0 = __builtin_amdgcn_rcpf((float)nb0), inv01 = __builtin_amdgcn_rcpf((float)nb01);
         for (int e = tid; e < count * 8; e += kPushBlock) {
             const int l = e >> 3, part = e & 7;
             const int lk = small_div(l, inv01), r = l - lk * nb01, lj = small_div(r, inv0), li = r - lj * nb0;
@@ -204,7 +204,7 @@ __global__ __launch_bounds__(kPushBlock, 4) void k_push(PushParams P, Species cS
         }
     }
     if (live) {
-        double h6 = P.dt / 6.0;
+        double h6 = P.dt_6;
         for (int q = 0; q < 3; q++) out.x[q][id] = X0[q] + h6 * Sx[q];
         for (int q = 0; q < 4; q++) out.u[q][id] = U0[q] + h6 * Su[q];
     }
@@ -517,7 +517,7 @@ __global__ __launch_bounds__(kDepBlock) void k_deposit(DepCtx D, Species cS, dou
     }
     if (use_lds) {
         __syncthreads();
-        const float inv_bx = 1.0f / (float)bx, inv_bxy = 1.0f / (float)(bx * by);
+        const float inv_bx = __builtin_amdgcn_rcpf((float)bx), inv_bxy = __builtin_amdgcn_rcpf((float)(bx * by));
         for (int e = tid; e < 3 * V; e += kDepBlock) {
             unsigned long long v = sm[e];
             if (v == 0ull) continue;

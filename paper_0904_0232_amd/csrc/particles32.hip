@@ -116,10 +116,9 @@ __device__ __forceinline__ void accel32(const PushParams &P, const Mixed &M, con
 }
 
 __device__ __forceinline__ float stage_gamma32(const PushParams &P, float u4, float a4, int &clamps) {
-    const float c = (float)P.c;
-    float uc = u4 / c;
+    float uc = u4 * (float)P.inv_c;
     if (P.gamma_mode == 1) return uc;
-    float disc = uc * uc + 4.0f * a4 * (float)(P.dt / (2.0 * P.c));
+    float disc = uc * uc + 4.0f * a4 * (float)P.dt_2c;
     if (disc < 0.0f) {
         disc = 0.0f;
         clamps++;
@@ -159,7 +158,7 @@ __device__ __forceinline__ void stage_nodes32(const Grid &G, const float *__rest
     if (B.use) {
         const float4 *src = reinterpret_cast<const float4 *>(node);
         const int nb0 = B.n[0], nb01 = B.n[0] * B.n[1];
-        const float inv0 = 1.0f / (float)nb0, inv01 = 1.0f / (float)nb01;
+        const float inv0 = __builtin_amdgcn_rcpf((float)nb0), inv01 = __builtin_amdgcn_rcpf((float)nb01);
         for (int e = tid; e < count * 4; e += kPush32Block) {
             const int l = e >> 2, part = e & 3;
             const int lk = small_div(l, inv01), r = l - lk * nb01, lj = small_div(r, inv0), li = r - lj * nb0;
@@ -226,7 +225,7 @@ __device__ __forceinline__ void push32_block(const PushParams &P, const Mixed &M
         }
     }
     if (alive) {
-        const float h6 = (float)(P.dt / 6.0);
+        const float h6 = (float)P.dt_6;
         int cc[3] = {i, j, k};
         for (int q = 0; q < 3; q++) {
             float xo = X0[q] + h6 * Sx[q];
@@ -559,7 +558,7 @@ __device__ __forceinline__ void deposit32_block(const Dep32 &D, const Species &c
     }
     if (use_lds) {
         __syncthreads();
-        const float inv_bx = 1.0f / (float)bx, inv_bxy = 1.0f / (float)(bx * by);
+        const float inv_bx = __builtin_amdgcn_rcpf((float)bx), inv_bxy = __builtin_amdgcn_rcpf((float)(bx * by));
         for (int e = tid; e < 3 * V; e += kDep32Block) {
             unsigned long long v = sm[e];
             if (v == 0ull) continue;
