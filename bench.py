@@ -78,6 +78,9 @@ def read_traffic(n_per_launch):
 
 
 def cpu_baseline(workload, sample_per_species):
+    """The FP64 oracle (one thread) timed on one cycle of a sample of the
+    workload: the first sample_per_species particles of each species.
+    Returns the figures and the oracle's particle state after the cycle."""
     import oracle as O
     from paper_0904_0232_amd import inputs
     w = inputs.workload_params(workload)
@@ -98,7 +101,44 @@ def cpu_baseline(workload, sample_per_species):
         "kind": "oracle",
         "sample": "one full FP64 oracle cycle (64^3 field solve + push/deposit) of the first %d particles "
                   "per species of the %s workload (%d live), %.1f s" % (sample_per_species, workload, kept, dt),
-    }
+    }, s.particles()
+
+
+def error_vs_oracle(workload, precision, sort_every, sample_per_species, oracle_state):
+    """Largest relative error, after the first cycle, of the GPU state against
+    the oracle's for the oracle's sample (the first sample_per_species inputs
+    of each species).  Positions after one cycle depend only on the initial
+    fields, so the oracle's smaller particle set does not matter."""
+    import numpy as np
+    import oracle as O
+    from paper_0904_0232_amd import capi, inputs
+    from paper_0904_0232_amd import run as R
+    w = inputs.workload_params(workload)
+    parts = inputs.workload_particles(workload, seed=0)
+    ntot = sum(p[1].shape[1] for p in parts)
+    cfg = R.make_config(w["n"], m=w["m"], a=w["a"], dt=w["dt"], B0=(0.0, 0.0, w["B0"]), species=w["species"],
+                        r_rm=w["r_rm"], sort_every=sort_every, capacity=ntot,
+                        precision=capi.FP32_MIXED if precision == "fp32" else capi.FP64)
+    run = R.Run(cfg)
+    slots, off = [], 0
+    for sp, x, uc in parts:
+        run.load(sp, x, uc)
+        slots.append(off + np.arange(min(sample_per_species, x.shape[1])))
+        off += x.shape[1]
+    sp0 = run.particles()[2]
+    run.step(1)
+    x1, u1, sp1 = run.particles()
+    run.close()
+    slots = np.concatenate(slots)
+    slots = slots[sp0[slots] != O.DEAD]  # the oracle keeps the same inputs, in input order
+    xo, uo, spo = oracle_state
+    live_o = spo != O.DEAD
+    same_removal = bool(np.array_equal(sp1[slots] != O.DEAD, live_o))
+    both = (sp1[slots] != O.DEAD) & live_o
+    ex = np.abs(x1[:, slots][:, both] - xo[:, both]) / np.maximum(np.abs(xo[:, both]), 1.0)
+    eu = np.abs(u1[:, slots][:, both] - uo[:, both]) / np.maximum(np.abs(uo[:, both]), 1.0)
+    return {"x_rel": float(ex.max()), "u_rel": float(eu.max()), "particles": int(both.sum()),
+            "same_removals": same_removal}
 
 
 def measure(workload, precision, steps, warmup, sort_every):
@@ -381,8 +421,15 @@ def main():
     if args.precision:
         line["precision_torus128"] = precision_study("torus128", n_override=args.precision_particles or None)
     if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(args.workload, args.cpu_sample)
+        line["cpu_baseline"], ostate = cpu_baseline(args.workload, args.cpu_sample)
         log("cpu baseline: %.4g particle-steps/s" % line["cpu_baseline"]["value"])
+        errs = {"fp64": error_vs_oracle(args.workload, "fp64", args.sort_every, args.cpu_sample, ostate)}
+        if not args.no_fp32:
+            errs["fp32_mixed"] = error_vs_oracle(args.workload, "fp32", args.sort_every, args.cpu_sample, ostate)
+        errs["what"] = ("largest relative error after the first cycle against the FP64 oracle, on the oracle's "
+                        "sample (positions relative to max(|x|, 1 cell), four-velocities to max(|u|, c))")
+        line["error_vs_oracle"] = errs
+        log("error vs oracle: %s" % json.dumps(errs))
     print(json.dumps(line), flush=True)
 
 

@@ -7,10 +7,10 @@ are pinned two ways:
 
 - sampled particles, one test-particle step (the node tensor of the initial
   fields, as grpic_push_only uses): the oracle runs on a 20^3 window of the
-  big grid, placed by giving it the hole centre in window coordinates; the
-  initial fields and their node tensor are local, so the window's interior
-  reproduces the big grid's exactly.  Windows sit near the hole, in the bulk
-  of the plasma and further out;
+  big grid, placed by giving it the hole centre in window coordinates, and
+  loads the sampled inputs itself; the initial fields and their node tensor
+  are local, so the window's interior reproduces the big grid's exactly.
+  Windows sit near the hole, in the bulk of the plasma and further out;
 - one full cycle from the same state: the total current per direction
   equals sum q dx / dt over the particles' own moves (true for any
   transverse weights, at any size).
@@ -85,6 +85,7 @@ def test_full_size(name, precision):
     x1, u1, _ = r.particles()
     tol = 1e-12 if precision == "fp64" else 1e-5
     g = np.random.default_rng(7)
+    offs = np.cumsum([0] + [p[1].shape[1] for p in parts])
     for o in _windows(w):
         inside = live.copy()
         for ax in range(3):
@@ -99,7 +100,12 @@ def test_full_size(name, precision):
         s = O.Sim(p, pick.size)
         s.init_fields([0.0, 0.0, w["B0"]])
         s.compute_nodes()
-        s.set_particles(x0[:, pick] - o[:, None], u0[:, pick], sp0[pick])
+        # the oracle loads the picked inputs itself (window coordinates)
+        kept = 0
+        for (spc, x, uc), a, b in zip(parts, offs[:-1], offs[1:]):
+            k = pick[(pick >= a) & (pick < b)] - a
+            kept += s.load(spc, x[:, k] - o[:, None], uc[:, k])
+        assert kept == pick.size
         s.push_only(1)
         xs, us, _ = s.particles()
         ex = rel_err(x1[:, pick] - o[:, None], xs, 1.0)
