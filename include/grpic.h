@@ -58,7 +58,7 @@ typedef struct {
     int32_t field_iters;    /* constitutive passes per half-cycle, >= 1 (3)         */
     int32_t sort_every;     /* steps between cell sorts; 0 = never                 */
     int32_t tile;           /* sort tile edge in cells (8)                         */
-    int32_t fp_bits;        /* fraction bits of the int64 current accumulator (44) */
+    int32_t fp_bits;        /* fraction bits of the int64 current accumulator, 16..50 (44) */
     int32_t nspecies;       /* 1..GRPIC_MAX_SPECIES                                 */
     int32_t init_covariant; /* 0: uniform contravariant B0 (paper); 1: covariant    */
     double c, dt;           /* speed of light and time step                        */

@@ -169,7 +169,7 @@ int validate(const grpic_config *c) {
     if (c->deposit_mode != GRPIC_DEPOSIT_CURVED && c->deposit_mode != GRPIC_DEPOSIT_FLAT) return GRPIC_EINVAL;
     if (c->field_iters < 1 || c->field_iters > 16) return GRPIC_EINVAL;
     if (c->sort_every < 0 || c->tile < 1 || c->tile > 64) return GRPIC_EINVAL;
-    if (c->fp_bits < 16 || c->fp_bits > 56) return GRPIC_EINVAL;
+    if (c->fp_bits < 16 || c->fp_bits > 50) return GRPIC_EINVAL;
     if (c->nspecies < 1 || c->nspecies > GRPIC_MAX_SPECIES) return GRPIC_EINVAL;
     if (!(c->c > 0.0) || !(c->dt > 0.0) || !isfinite(c->c) || !isfinite(c->dt)) return GRPIC_EINVAL;
     // Courant condition of the 3D Yee scheme with unit cells

@@ -243,9 +243,14 @@ __device__ __forceinline__ void gamma_uu(const KSGradT<T> &p, const T u[4], T G[
 // (l + 1/2)/d * 2^-22, so the truncation is the exact quotient.
 __device__ __forceinline__ int small_div(int l, float inv_d) { return (int)(((float)l + 0.5f) * inv_d); }
 
-// Fixed-point conversion of one current or charge contribution.
-__device__ __forceinline__ unsigned long long to_fixed(double v, double scale) {
-    return (unsigned long long)(long long)__double2ll_rn(v * scale);
+// Round-to-nearest-even int64 of v for |v| < 2^51: v + 1.5 * 2^52 lies in
+// [2^52, 2^53), where the ulp is 1, so the addition rounds v to an integer
+// and the difference of the bit patterns is that integer (3 instructions
+// instead of the general conversion sequence).  Current and charge
+// contributions are below 2^(fp_bits + 1) with fp_bits <= 50.
+__device__ __forceinline__ long long fixed_rn(double v) {
+    const double magic = 6755399441055744.0;  // 1.5 * 2^52
+    return __double_as_longlong(v + magic) - __double_as_longlong(magic);
 }
 
 }  // namespace grpic

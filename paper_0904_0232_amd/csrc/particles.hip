@@ -330,10 +330,10 @@ __device__ __forceinline__ void dep_segment(const DepCtx &D, const double A[3], 
         w10 -= t;
         w01 -= t;
         double sc = flux * D.jscale;
-        v[K][0] += __double2ll_rn(sc * w00);
-        v[K][1] += __double2ll_rn(sc * w10);
-        v[K][2] += __double2ll_rn(sc * w01);
-        v[K][3] += __double2ll_rn(sc * w11);
+        v[K][0] += fixed_rn(sc * w00);
+        v[K][1] += fixed_rn(sc * w10);
+        v[K][2] += fixed_rn(sc * w01);
+        v[K][3] += fixed_rn(sc * w11);
     }
 }
 

@@ -364,10 +364,10 @@ __device__ __forceinline__ void dep_segment32(const Dep32 &D, const int base[3],
         w10 -= t;
         w01 -= t;
         double sc = (double)flux * D.jscale;
-        v[K][0] += __double2ll_rn(sc * (double)w00);
-        v[K][1] += __double2ll_rn(sc * (double)w10);
-        v[K][2] += __double2ll_rn(sc * (double)w01);
-        v[K][3] += __double2ll_rn(sc * (double)w11);
+        v[K][0] += fixed_rn(sc * (double)w00);
+        v[K][1] += fixed_rn(sc * (double)w10);
+        v[K][2] += fixed_rn(sc * (double)w01);
+        v[K][3] += fixed_rn(sc * (double)w11);
     }
 }
 
