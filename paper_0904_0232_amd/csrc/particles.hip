@@ -111,8 +111,10 @@ constexpr int kPushLdsNodes = 256;  // 36 KB of padded node tensor per block
 
 // Stage the nodes of the cells the block's live lanes gather from (cell c of
 // each live lane, nodes c .. c+1) into LDS when the box fits.  Every thread
-// of the block calls this; it synchronises the block twice (before the box
-// is overwritten and after it is filled).
+// of the block calls this; it synchronises the block after the box reduction
+// (every wave is then done with the previous box) and, when it copies, after
+// the copy.  When the box equals the one staged for the previous stage (the
+// half-step stages usually gather from the same cells) nothing is copied.
 __device__ __forceinline__ void stage_nodes(const Grid &G, const double *__restrict__ node, bool live, const int c[3],
                                             double2 *snode, int (*sred)[kPushBlock / 64], NodeBox &B) {
     const int tid = threadIdx.x;
@@ -125,17 +127,21 @@ __device__ __forceinline__ void stage_nodes(const Grid &G, const double *__restr
     }
     __syncthreads();  // also: every wave has finished reading the previous box
     int count = 1;
+    bool same = B.use;  // the box already staged for the previous stage
     for (int ax = 0; ax < 3; ax++) {
         int a = sred[ax][0], b = sred[3 + ax][0];
         for (int w = 1; w < kPushBlock / 64; w++) {
             a = sred[ax][w] < a ? sred[ax][w] : a;
             b = sred[3 + ax][w] > b ? sred[3 + ax][w] : b;
         }
+        const int n = b >= a ? b - a + 2 : 0;  // nodes a .. b+1
+        same = same && B.lo[ax] == a && B.n[ax] == n;
         B.lo[ax] = a;
-        B.n[ax] = b >= a ? b - a + 2 : 0;  // nodes a .. b+1
-        count = (B.n[ax] > 0 && count <= kPushLdsNodes) ? count * B.n[ax] : 0;
+        B.n[ax] = n;
+        count = (n > 0 && count <= kPushLdsNodes) ? count * n : 0;
     }
     B.use = count > 0 && count <= kPushLdsNodes;  // count = 0: no live lane
+    if (same) return;  // the LDS copy is still the right one (block-uniform)
     if (B.use) {
         const double2 *src = reinterpret_cast<const double2 *>(node);
         const int nb0 = B.n[0], nb01 = B.n[0] * B.n[1];
@@ -160,7 +166,10 @@ __global__ __launch_bounds__(kPushBlock, 4) void k_push(PushParams P, Species cS
                                                      ParticlePtrs in, ParticlePtrs out,
                                                      unsigned long long *counters) {
     __shared__ double2 snode[kPushLdsNodes * kNodeStride2];
-    __shared__ int sred[6][kPushBlock / 64];
+    // two reduction buffers, used by alternate stages: a stage whose box is
+    // unchanged passes only one barrier, so the next stage must not
+    // overwrite the buffer a slower wave may still be reading
+    __shared__ int sred[2][6][kPushBlock / 64];
     const int tid = threadIdx.x;
     const int64_t id = (int64_t)blockIdx.x * kPushBlock + tid;
     int clamps = 0;
@@ -181,11 +190,12 @@ __global__ __launch_bounds__(kPushBlock, 4) void k_push(PushParams P, Species cS
     double Sx[3] = {0.0, 0.0, 0.0}, Su[4] = {0.0, 0.0, 0.0, 0.0};
     NodeBox B;
     B.lds = snode;
+    B.use = false;
 #pragma unroll 1
     for (int st = 0; st < 4; st++) {
         int c[3];
         gather_cell(P.G, Xs, c);
-        stage_nodes(P.G, node, live, c, snode, sred, B);
+        stage_nodes(P.G, node, live, c, snode, sred[st & 1], B);
         if (live) {
             double A[4];
             accel(P, node, B, c, qm, Xs, Us, A);

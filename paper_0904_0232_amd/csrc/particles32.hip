@@ -130,8 +130,8 @@ constexpr int kPush32Block = 256;
 constexpr int kPush32LdsNodes = 448;  // 35 KB of padded FP32 node tensor per block
 
 // Stage the FP32 nodes of the cells the block's live lanes gather from into
-// LDS when the box fits (as the FP64 pusher does).  Every thread of the block
-// calls this; it synchronises the block twice.
+// LDS when the box fits (as the FP64 pusher does, including keeping the copy
+// when the box is unchanged).  Every thread of the block calls this.
 __device__ __forceinline__ void stage_nodes32(const Grid &G, const float *__restrict__ node, bool live, const int c[3],
                                               float4 *snode, int (*sred)[kPush32Block / 64], NodeBox32 &B) {
     const int tid = threadIdx.x;
@@ -144,17 +144,21 @@ __device__ __forceinline__ void stage_nodes32(const Grid &G, const float *__rest
     }
     __syncthreads();  // also: every wave has finished reading the previous box
     int count = 1;
+    bool same = B.use;  // the box already staged for the previous stage
     for (int ax = 0; ax < 3; ax++) {
         int a = sred[ax][0], b = sred[3 + ax][0];
         for (int w = 1; w < kPush32Block / 64; w++) {
             a = sred[ax][w] < a ? sred[ax][w] : a;
             b = sred[3 + ax][w] > b ? sred[3 + ax][w] : b;
         }
+        const int n = b >= a ? b - a + 2 : 0;  // nodes a .. b+1
+        same = same && B.lo[ax] == a && B.n[ax] == n;
         B.lo[ax] = a;
-        B.n[ax] = b >= a ? b - a + 2 : 0;  // nodes a .. b+1
-        count = (B.n[ax] > 0 && count <= kPush32LdsNodes) ? count * B.n[ax] : 0;
+        B.n[ax] = n;
+        count = (n > 0 && count <= kPush32LdsNodes) ? count * n : 0;
     }
     B.use = count > 0 && count <= kPush32LdsNodes;  // count = 0: no live lane
+    if (same) return;  // the LDS copy is still the right one (block-uniform)
     if (B.use) {
         const float4 *src = reinterpret_cast<const float4 *>(node);
         const int nb0 = B.n[0], nb01 = B.n[0] * B.n[1];
@@ -172,12 +176,13 @@ __device__ __forceinline__ void stage_nodes32(const Grid &G, const float *__rest
 // to the particle's cell; the cell is re-based after the step.  The nodes of
 // each stage are staged in LDS per block, as in the FP64 pusher.
 // Block `blk` of the push (particles blk * kPush32Block ...); LDS scratch
-// snode and sred come from the calling kernel.  Every thread of the block
-// calls this.
+// snode and sred come from the calling kernel; sred holds two reduction
+// buffers, used by alternate stages, because a stage whose box is unchanged
+// passes only one barrier.  Every thread of the block calls this.
 __device__ __forceinline__ void push32_block(const PushParams &P, const Mixed &M, const Species &cS,
                                              const float *__restrict__ node, const ParticlePtrs32 &in,
                                              const ParticlePtrs32 &out, unsigned long long *counters, int64_t blk,
-                                             float4 *snode, int (*sred)[kPush32Block / 64]) {
+                                             float4 *snode, int (*sred)[6][kPush32Block / 64]) {
     const int tid = threadIdx.x;
     const int64_t id = blk * kPush32Block + tid;
     int clamps = 0;
@@ -202,11 +207,12 @@ __device__ __forceinline__ void push32_block(const PushParams &P, const Mixed &M
     const float dt = (float)P.dt;
     NodeBox32 B;
     B.lds = snode;
+    B.use = false;
 #pragma unroll 1
     for (int st = 0; st < 4; st++) {
         int c[3];
         gather_cell32(P.G, base, Xs, c);
-        stage_nodes32(P.G, node, alive, c, snode, sred, B);
+        stage_nodes32(P.G, node, alive, c, snode, sred[st & 1], B);
         if (alive) {
             float A[4];
             accel32(P, M, node, B, c, qm, i, j, k, Xs, Us, A);
@@ -248,7 +254,7 @@ __global__ __launch_bounds__(kPush32Block, 4) void k_push32(PushParams P, Mixed 
                                                            const float *__restrict__ node, ParticlePtrs32 in,
                                                            ParticlePtrs32 out, unsigned long long *counters) {
     __shared__ float4 snode[kPush32LdsNodes * kNode32Stride4];
-    __shared__ int sred[6][kPush32Block / 64];
+    __shared__ int sred[2][6][kPush32Block / 64];
     push32_block(P, M, cS, node, in, out, counters, blockIdx.x, snode, sred);
 }
 
@@ -593,7 +599,7 @@ Dep32 make_dep32(const Grid &G, const Hole &h, const Mixed &M, double dt, int de
 // active runs (the run table is in device memory).
 __global__ __launch_bounds__(kPush32Block, 4) void k_batch_push32(const BatchTable *__restrict__ T) {
     __shared__ float4 snode[kPush32LdsNodes * kNode32Stride4];
-    __shared__ int sred[6][kPush32Block / 64];
+    __shared__ int sred[2][6][kPush32Block / 64];
     const int64_t total = T->total[BK_PUSH];
     for (int64_t lb = blockIdx.x; lb < total; lb += gridDim.x) {
         __syncthreads();  // the previous logical block is done with the LDS scratch
