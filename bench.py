@@ -11,9 +11,10 @@ timed region starts.
 
 Prints ONE JSON line.  value = particle pushes per second over the timed
 steps (live particles summed over steps / wall time).  The roofline object
-prices the dominant kernel (the pusher) by its algorithmic FP64 operation
-count per particle-step against the MI355X FP64 vector peak, with the
-average kernel time measured by HIP events on the run's stream.  The CPU
+prices the kernel that takes the most time (the pusher or the deposit; both
+are in "rooflines") by its algorithmic FP64 operation count per particle
+against the MI355X FP64 vector peak, with the average kernel time measured by
+HIP events on the run's stream.  The CPU
 baseline times the FP64 oracle (single thread) on a bounded sample of the
 same workload.
 """
@@ -41,6 +42,16 @@ HBM_PEAK_GBS = 8000.0
 # the design notes from the kernel source.
 PUSH_FLOPS_PER_PARTICLE_STEP = 2219
 
+# Algorithmic FP64 operations of the curved-weight deposit of one particle
+# (counted from the kernel source the same way): zigzag split 9; per segment
+# 9 plus, for each of the 3 current directions, 59 for the flux, the
+# segment-average term, the four sub-rectangles and the normalised fixed-point
+# weights and 4 face-area densities (radius quartic, f, k_K, sqrt(1 + f(1 -
+# k_K^2)): 41 for K = 0, 1 and 33 for K = 2); the removal test 19.  That is
+# 9 + 2 (9 + 3 * 59 + 4 * 115) + 19 = 1320 per particle, with two segments
+# per particle.
+DEPOSIT_FLOPS_PER_PARTICLE = 1320
+
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_push_kerr64_traffic.txt")
 PUSH_SOURCES = [os.path.join(ROOT, "paper_0904_0232_amd", "csrc", f) for f in ("particles.hip", "grpic_dev.h")]
 
@@ -57,9 +68,11 @@ def push_source_hash():
     return h.hexdigest()[:16]
 
 
-def read_traffic(n_per_launch):
-    """HBM bytes per push launch from the committed rocprofv3 counter summary,
-    or None when the summary is missing or the kernel source changed since."""
+def read_traffic(n_per_launch, key="hbm_bytes_per_particle"):
+    """HBM bytes per launch of the pusher (or, with key
+    "deposit_hbm_bytes_per_particle", of the deposit) from the committed
+    rocprofv3 counter summary, or None when the summary is missing or the
+    kernel source changed since."""
     if not os.path.exists(TRAFFIC_FILE):
         return None
     kv = {}
@@ -71,7 +84,7 @@ def read_traffic(n_per_launch):
     if kv.get("source_sha") != push_source_hash():
         return None
     try:
-        per_particle = float(kv["hbm_bytes_per_particle"])
+        per_particle = float(kv[key])
     except (KeyError, ValueError):
         return None
     return per_particle * n_per_launch
@@ -183,23 +196,41 @@ def measure(workload, precision, steps, warmup, sort_every):
     }
 
 
-def push_roofline(m, flops_per_ps, peak, traffic=None):
-    push_ms, push_n = m["timers"]["push"]
-    avg_push_s = push_ms / 1e3 / max(push_n, 1)
-    per_launch = m["psteps"] / max(push_n, 1)
-    achieved = flops_per_ps * per_launch / avg_push_s / 1e12
+KERNELS = {
+    "push": ("k_push (gather + RK4 pusher)", PUSH_FLOPS_PER_PARTICLE_STEP, "hbm_bytes_per_particle"),
+    "deposit": ("k_deposit (zigzag, curved face-area weights, int64 current)", DEPOSIT_FLOPS_PER_PARTICLE,
+                "deposit_hbm_bytes_per_particle"),
+}
+
+
+def kernel_roofline(m, name, peak, with_traffic):
+    """Algorithmic FLOP/s of one kernel over its event-timed launches
+    (particles per launch = particle-steps of the timed region / launches)."""
+    label, flops, tkey = KERNELS[name]
+    ms, n = m["timers"][name]
+    avg_s = ms / 1e3 / max(n, 1)
+    per_launch = m["psteps"] / max(n, 1)
+    achieved = flops * per_launch / avg_s / 1e12
     return {
-        "kernel": "k_push (gather + RK4 pusher)",
+        "kernel": label,
         "bound": "alu",
         "achieved": achieved,
         "peak": peak,
         "unit": "TFLOP/s",
         "frac": achieved / peak,
-        "traffic": traffic,
-        "avg_launch_ms": avg_push_s * 1e3,
-        "flops_per_particle_step": flops_per_ps,
+        "traffic": read_traffic(per_launch, tkey) if with_traffic else None,
+        "avg_launch_ms": avg_s * 1e3,
+        "flops_per_particle": flops,
         "particles_per_launch": per_launch,
     }
+
+
+def rooflines(m, peak, with_traffic):
+    """Both particle kernels' rooflines and the one of the kernel that takes
+    the most time (each launches once per cycle)."""
+    both = {k: kernel_roofline(m, k, peak, with_traffic) for k in KERNELS}
+    dominant = max(both, key=lambda k: both[k]["avg_launch_ms"])
+    return both[dominant], both
 
 
 def serving(args):
@@ -371,8 +402,7 @@ def main():
     m64 = measure(args.workload, "fp64", args.steps, args.warmup, args.sort_every)
     log("fp64 %s: %.4g particle-steps/s" % (args.workload, m64["value"]))
     w = m64["w"]
-    per_launch = m64["psteps"] / max(m64["timers"]["push"][1], 1)
-    roofline = push_roofline(m64, PUSH_FLOPS_PER_PARTICLE_STEP, FP64_PEAK_TFLOPS, read_traffic(per_launch))
+    roofline, rooflines64 = rooflines(m64, FP64_PEAK_TFLOPS, True)
     line = {
         "metric": METRIC,
         "value": m64["value"],
@@ -396,6 +426,7 @@ def main():
         },
         "kernel_ms_per_launch": m64["kernel_ms_per_launch"],
         "roofline": roofline,
+        "rooflines": rooflines64,
         "cpu_baseline": None,
     }
     if not args.no_fp32:
@@ -405,8 +436,8 @@ def main():
             "value": m32["value"], "unit": UNIT, "ms_per_step": m32["ms_per_step"], "dtype": "f32 (FP64 quartic, "
             "near-horizon metric and diagnostics)", "kernel_ms_per_launch": m32["kernel_ms_per_launch"],
             "speedup_vs_fp64": m32["value"] / m64["value"], "live_particles_end": m32["live_end"],
-            "roofline": push_roofline(m32, PUSH_FLOPS_PER_PARTICLE_STEP, FP32_PEAK_TFLOPS),
         }
+        line["fp32_mixed"]["roofline"], line["fp32_mixed"]["rooflines"] = rooflines(m32, FP32_PEAK_TFLOPS, False)
     if args.serve_runs > 0:
         line["serving"] = serving(args)
         log("serving: p50 %.3f s p99 %.3f s" % (line["serving"]["p50_latency_s"], line["serving"]["p99_latency_s"]))
