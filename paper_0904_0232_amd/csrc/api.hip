@@ -839,7 +839,9 @@ int grpic_create(const grpic_config *cfg, void *stream, grpic_t **out) {
     h->h.cz = cfg->center[2];
     h->h.r_exc = cfg->r_exc;
     // FP64 metric and Christoffel symbols within 4 m of the horizon
-    h->M.r_fp64 = cfg->m + sqrt(fmax(cfg->m * cfg->m - cfg->a * cfg->a, 0.0)) + 4.0 * cfg->m;
+    // at least 1.25 r_exc, so every excision decision of the FP32-mixed
+    // deposit is taken on the FP64 radius
+    h->M.r_fp64 = fmax(cfg->m + sqrt(fmax(cfg->m * cfg->m - cfg->a * cfg->a, 0.0)) + 4.0 * cfg->m, 1.25 * cfg->r_exc);
     double qmax = 0.0;
     for (int s = 0; s < kMaxSpecies; s++) {
         bool on = s < cfg->nspecies;

@@ -42,22 +42,30 @@ struct Hole {
     double r_exc;
 };
 
-// Square root and quotient from the hardware reciprocal (square-root)
-// estimates refined by two Newton steps, plus a residual correction for the
-// quotient: a few ulps instead of the correctly rounded result, at about
-// half the instructions.  sqrt_nr takes x >= 0 (0 gives 0); div_nr takes a
-// finite non-zero normal d.
+// Square root, reciprocal square root, reciprocal and quotient from the
+// hardware estimates (about 2^-23 relative) refined by one third-order step:
+// with e = 1 - x y^2 the error of y = x^-1/2, y (1 + e/2 + 3 e^2 / 8) has
+// error O(e^3); with e = 1 - d r, r (1 + e + e^2) has error O(e^3); the
+// quotient adds a residual correction.  A few ulps instead of the correctly
+// rounded result, at about a third of the instructions.  sqrt_nr takes
+// x >= 0 (0 gives 0); rsqrt_nr a finite positive normal x; rcp_nr and div_nr
+// a finite non-zero normal d.
 __device__ __forceinline__ double sqrt_nr(double x) {
-    double y = __builtin_amdgcn_rsq(x);
-    const double h = 0.5 * x;
-    y = y * fma(-h * y, y, 1.5);
-    y = y * fma(-h * y, y, 1.5);
-    return x > 0.0 ? x * y : 0.0;
+    const double y = __builtin_amdgcn_rsq(x);
+    const double s = x * y;
+    const double e = fma(-s, y, 1.0);
+    const double r = fma(s * e, fma(e, 0.375, 0.5), s);
+    return x > 0.0 ? r : 0.0;
+}
+__device__ __forceinline__ double rsqrt_nr(double x) {
+    const double y = __builtin_amdgcn_rsq(x);
+    const double e = fma(-x * y, y, 1.0);
+    return fma(y * e, fma(e, 0.375, 0.5), y);
 }
 __device__ __forceinline__ double rcp_nr(double d) {
-    double r = __builtin_amdgcn_rcp(d);
-    r = fma(fma(-d, r, 1.0), r, r);
-    return fma(fma(-d, r, 1.0), r, r);
+    const double r = __builtin_amdgcn_rcp(d);
+    const double e = fma(-d, r, 1.0);
+    return fma(r, fma(e, e, e), r);
 }
 __device__ __forceinline__ double div_nr(double n, double d) {
     const double r = rcp_nr(d);
@@ -85,11 +93,50 @@ __device__ __forceinline__ double ks_radius(double a, double x, double y, double
 }
 
 // The same root with the refined square roots and quotient (the hot paths:
-// every RK4 stage and every deposit face point).
+// every RK4 stage and every deposit face point); r2 receives r^2 as the
+// quartic gives it.  The quotient branch (R < |a|, deep inside the horizon)
+// is a real branch so the common case does not pay for it.
+__device__ __forceinline__ double ks_radius_nr(double a, double x, double y, double z, double &r2) {
+    const double b = x * x + y * y + z * z - a * a, a2z2 = a * a * (z * z);
+    const double s = sqrt_nr(fma(b, b, 4.0 * a2z2));
+    if (b >= 0.0)
+        r2 = 0.5 * (b + s);
+    else
+        r2 = div_nr(2.0 * a2z2, s - b);
+    return sqrt_nr(r2);
+}
 __device__ __forceinline__ double ks_radius_nr(double a, double x, double y, double z) {
-    const double b = x * x + y * y + z * z - a * a, a2z2 = a * a * z * z;
-    const double s = sqrt_nr(b * b + 4.0 * a2z2);
-    return sqrt_nr(b >= 0.0 ? 0.5 * (b + s) : div_nr(2.0 * a2z2, s - b));
+    double r2;
+    return ks_radius_nr(a, x, y, z, r2);
+}
+
+// Area density of a K-face at a hole-relative point (m > 0):
+// sqrt(g_II g_JJ - g_IJ^2) = sqrt(1 + f (1 - k_K^2)) (I, J the other two
+// axes; k null, so k_1^2 + k_2^2 + k_3^2 = 1), 1 inside r < r_exc.  With
+// f = 2 m r^3 / S4, S4 = r^4 + a^2 z^2, and
+//   K = 2:    1 - k_K^2 = (r - z)(r + z) / r^2,
+//   K = 0, 1: 1 - k_K^2 = (Dn - n)(Dn + n) / Dn^2, Dn = r^2 + a^2,
+//             n = r x - a y (K = 0) or r y + a x (K = 1),
+// the density is sqrt(N / den) = N / sqrt(N den) with f (1 - k_K^2) =
+// num / den and N = den + num: one reciprocal square root, no quotient.
+__device__ __forceinline__ double ks_area_density(double m, double a, double r_exc, int K, double x, double y,
+                                                  double z) {
+    double r2;
+    const double r = ks_radius_nr(a, x, y, z, r2);
+    if (r < r_exc) return 1.0;
+    const double S4 = fma(r2, r2, a * a * (z * z)), m2r = 2.0 * m * r;
+    double num, den;
+    if (K == 2) {
+        num = m2r * ((r - z) * (r + z));
+        den = S4;
+    } else {
+        const double Dn = r2 + a * a;
+        const double nK = K == 0 ? r * x - a * y : r * y + a * x;
+        num = m2r * r2 * ((Dn - nK) * (Dn + nK));
+        den = S4 * (Dn * Dn);
+    }
+    const double N = den + num;
+    return N * rsqrt_nr(N * den);
 }
 
 // f and the spatial part of k at a hole-relative point (m > 0, r > 0).

@@ -132,6 +132,8 @@ struct Dep32 {
     Grid G;
     Hole h;
     double r_fp64;
+    float r_fp64_sq;  // r_fp64^2: FP32 densities only beyond it
+    float af, m2;     // a and 2 m in FP32
     float inv_dt;
     double jscale;
     int curved;

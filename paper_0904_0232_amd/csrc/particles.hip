@@ -248,32 +248,11 @@ struct DepCtx {
     int curved;
 };
 
-// sqrt(1 + f (1 - k_K^2)) with f = 2 m r^3 / (r^4 + a^2 z^2), folded into
-// one division:  for K = 0, 1, 1 - k_K^2 = (D - n)(D + n) / D^2 with
-// D = r^2 + a^2 and n = r x - a y (K = 0) or r y + a x (K = 1); for K = 2,
-// 1 - k_K^2 = (r^2 - z^2) / r^2.
-// The radius quartic, square root and quotient here use the refined hardware
-// estimates (a few ulps): 24 of these per particle dominate the deposit's
-// arithmetic.
+// Area density at a grid-coordinate point (24 of these per particle are
+// most of the deposit's arithmetic).
 __device__ __forceinline__ double area_density(const DepCtx &D, int K, double X, double Y, double Z) {
     if (D.h.m == 0.0) return 1.0;
-    const double x = X - D.h.cx, y = Y - D.h.cy, z = Z - D.h.cz;
-    const double a = D.h.a;
-    const double r = ks_radius_nr(a, x, y, z);
-    if (r < D.h.r_exc) return 1.0;
-    const double rr = r * r;
-    const double S4 = rr * rr + a * a * z * z;
-    double num, den;
-    if (K == 2) {
-        num = 2.0 * D.h.m * r * ((r - z) * (r + z));
-        den = S4;
-    } else {
-        const double Dn = rr + a * a;
-        const double nK = K == 0 ? r * x - a * y : r * y + a * x;
-        num = 2.0 * D.h.m * r * rr * ((Dn - nK) * (Dn + nK));
-        den = S4 * (Dn * Dn);
-    }
-    return sqrt_nr(1.0 + div_nr(num, den));
+    return ks_area_density(D.h.m, D.h.a, D.h.r_exc, K, X - D.h.cx, Y - D.h.cy, Z - D.h.cz);
 }
 
 // Destinations of the fixed-point current: straight to the global int64
@@ -329,7 +308,7 @@ __device__ __forceinline__ void dep_segment(const DepCtx &D, const double A[3], 
                     P3[J] = 0.5 * (j0 + j1);
                     area[bi][bj] = area_density(D, K, P3[0], P3[1], P3[2]) * ((i1 - i0) * (j1 - j0));
                 }
-            double inv = 1.0 / (area[0][0] + area[1][0] + area[0][1] + area[1][1]);
+            const double inv = rcp_nr(area[0][0] + area[1][0] + area[0][1] + area[1][1]);
             w00 = area[0][0] * inv;
             w10 = area[1][0] * inv;
             w01 = area[0][1] * inv;

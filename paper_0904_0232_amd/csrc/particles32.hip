@@ -3,9 +3,11 @@
 // FP32 contravariant four-velocity: 32 bytes plus the species byte.
 // Gather, Lorentz term, RK4 stages and deposition weights run in FP32 on
 // offsets relative to the particle's cell (so the position error does not
-// grow with the grid size); the radius quartic is always solved in FP64 from
-// the exact cell + offset, and within r_fp64 (r_+ + 4 m) of the hole the
-// metric gradients and the Christoffel contraction are evaluated in FP64.
+// grow with the grid size).  In the pusher the radius quartic is always
+// solved in FP64 from the exact cell + offset, and within r_fp64
+// (max(r_+ + 4 m, 1.25 r_exc)) of the hole the metric gradients and the
+// Christoffel contraction are evaluated in FP64; the deposition's area
+// densities are FP32 beyond r_fp64 and FP64 within it.
 #include "grpic_dev.h"
 #include "grpic_impl.h"
 
@@ -271,40 +273,36 @@ void launch_push32(const PushParams &P, const Mixed &M, const Species &S, const 
 
 
 // Area density sqrt(1 + f (1 - k_K^2)) at a point given as cell + local
-// offset, folded into one division as in the FP64 kernel; FP64 within r_fp64.
-__device__ __forceinline__ float area_density32(const Dep32 &D, int K, const int base[3], const float P3[3]) {
+// offset (O: the cell corner relative to the hole in FP32, P3: the offset).
+// Beyond r_fp64 in FP32 with the hardware square root and reciprocals:
+//   f (1 - k_K^2) = t g,  t = 2 m r / S4,  S4 = r^4 + a^2 z^2,
+//   g = (r - z)(r + z) (K = 2)  or  r^2 (1 - q)(1 + q), q = n / Dn (K = 0, 1)
+// (n, Dn as in the FP64 density).  Within r_fp64, and wherever R < |a|, in
+// FP64 from the exact cell coordinates; every excision decision (r_exc <
+// r_fp64) is taken there.
+__device__ __forceinline__ float area_density32(const Dep32 &D, int K, const int base[3], const float O[3],
+                                                const float P3[3]) {
     if (D.h.m == 0.0) return 1.0f;
-    const double x = ((double)base[0] - D.h.cx) + (double)P3[0];
-    const double y = ((double)base[1] - D.h.cy) + (double)P3[1];
-    const double z = ((double)base[2] - D.h.cz) + (double)P3[2];
-    const double a = D.h.a;
-    const double r = ks_radius_nr(a, x, y, z);
-    if (r < D.h.r_exc) return 1.0f;
-    if (r < D.r_fp64) {
-        const double rr = r * r, S4 = rr * rr + a * a * z * z;
-        double num, den;
-        if (K == 2) {
-            num = 2.0 * D.h.m * r * ((r - z) * (r + z));
-            den = S4;
-        } else {
-            const double Dn = rr + a * a, nK = K == 0 ? r * x - a * y : r * y + a * x;
-            num = 2.0 * D.h.m * r * rr * ((Dn - nK) * (Dn + nK));
-            den = S4 * (Dn * Dn);
-        }
-        return (float)sqrt_nr(1.0 + div_nr(num, den));
+    const float x = O[0] + P3[0], y = O[1] + P3[1], z = O[2] + P3[2];
+    const float a = D.af, a2 = a * a, a2z2 = a2 * (z * z);
+    const float b = fmaf(x, x, fmaf(y, y, z * z)) - a2;
+    const float r2 = 0.5f * (b + __builtin_amdgcn_sqrtf(fmaf(b, b, 4.0f * a2z2)));
+    if (b < 0.0f || r2 < D.r_fp64_sq) {
+        const double xd = ((double)base[0] - D.h.cx) + (double)P3[0];
+        const double yd = ((double)base[1] - D.h.cy) + (double)P3[1];
+        const double zd = ((double)base[2] - D.h.cz) + (double)P3[2];
+        return (float)ks_area_density(D.h.m, D.h.a, D.h.r_exc, K, xd, yd, zd);
     }
-    const float rf = (float)r, af = (float)a, xf = (float)x, yf = (float)y, zf = (float)z, mf = (float)D.h.m;
-    const float rr = rf * rf, S4 = rr * rr + af * af * zf * zf;
-    float num, den;
+    const float r = __builtin_amdgcn_sqrtf(r2);
+    const float t = D.m2 * r * __builtin_amdgcn_rcpf(fmaf(r2, r2, a2z2));
+    float g;
     if (K == 2) {
-        num = 2.0f * mf * rf * ((rf - zf) * (rf + zf));
-        den = S4;
+        g = (r - z) * (r + z);
     } else {
-        const float Dn = rr + af * af, nK = K == 0 ? rf * xf - af * yf : rf * yf + af * xf;
-        num = 2.0f * mf * rf * rr * ((Dn - nK) * (Dn + nK));
-        den = S4 * (Dn * Dn);
+        const float q = (K == 0 ? r * x - a * y : r * y + a * x) * __builtin_amdgcn_rcpf(r2 + a2);
+        g = r2 * ((1.0f - q) * (1.0f + q));
     }
-    return sqrtf(1.0f + num / den);
+    return __builtin_amdgcn_sqrtf(fmaf(t, g, 1.0f));
 }
 
 struct GlobalAcc32 {
@@ -326,8 +324,8 @@ struct LdsAcc32 {
 // One segment A -> B, local to cell `base` + `cell` (cell relative to base).
 // Its fixed-point contributions are added to v[K][bi + 2 bj] (the K-edge at
 // base + cell + bi e_I + bj e_J).
-__device__ __forceinline__ void dep_segment32(const Dep32 &D, const int base[3], const float A[3], const float B[3],
-                                              const int cell[3], float Q, long long v[3][4]) {
+__device__ __forceinline__ void dep_segment32(const Dep32 &D, const int base[3], const float O[3], const float A[3],
+                                              const float B[3], const int cell[3], float Q, long long v[3][4]) {
     float d[3], mid[3];
     for (int ax = 0; ax < 3; ax++) {
         d[ax] = B[ax] - A[ax];
@@ -357,9 +355,9 @@ __device__ __forceinline__ void dep_segment32(const Dep32 &D, const int base[3],
                     P3[K] = mid[K];
                     P3[I] = 0.5f * (i0 + i1);
                     P3[J] = 0.5f * (j0 + j1);
-                    area[bi][bj] = area_density32(D, K, base, P3) * ((i1 - i0) * (j1 - j0));
+                    area[bi][bj] = area_density32(D, K, base, O, P3) * ((i1 - i0) * (j1 - j0));
                 }
-            float inv = 1.0f / (area[0][0] + area[1][0] + area[0][1] + area[1][1]);
+            const float inv = __builtin_amdgcn_rcpf(area[0][0] + area[1][0] + area[0][1] + area[1][1]);
             w00 = area[0][0] * inv;
             w10 = area[1][0] * inv;
             w01 = area[0][1] * inv;
@@ -407,9 +405,12 @@ __device__ __forceinline__ void dep_chord32(const Dep32 &D, const Acc &acc, cons
 #pragma unroll
     for (int K = 0; K < 3; K++)
         for (int c = 0; c < 4; c++) v[K][c] = 0;
-    dep_segment32(D, base, X1, xr, l1, Q, v);
+    // the cell corner relative to the hole, exact in FP64, rounded once
+    const float O[3] = {(float)((double)base[0] - D.h.cx), (float)((double)base[1] - D.h.cy),
+                        (float)((double)base[2] - D.h.cz)};
+    dep_segment32(D, base, O, X1, xr, l1, Q, v);
     if (l1[0] != l2[0] || l1[1] != l2[1] || l1[2] != l2[2]) dep_flush32(acc, base, l1, v);
-    dep_segment32(D, base, xr, X2, l2, Q, v);
+    dep_segment32(D, base, O, xr, X2, l2, Q, v);
     dep_flush32(acc, base, l2, v);
 }
 
@@ -588,6 +589,9 @@ Dep32 make_dep32(const Grid &G, const Hole &h, const Mixed &M, double dt, int de
     D.G = G;
     D.h = h;
     D.r_fp64 = M.r_fp64;
+    D.r_fp64_sq = (float)(M.r_fp64 * M.r_fp64);
+    D.af = (float)h.a;
+    D.m2 = (float)(2.0 * h.m);
     D.inv_dt = (float)(1.0 / dt);
     D.jscale = jscale;
     D.curved = deposit_mode == 0;
