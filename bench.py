@@ -52,7 +52,7 @@ PUSH_FLOPS_PER_PARTICLE_STEP = 2219
 # per particle.
 DEPOSIT_FLOPS_PER_PARTICLE = 1320
 
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_push_kerr64_traffic.txt")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "fp64_particle_kernels_kerr64_traffic.txt")
 PUSH_SOURCES = [os.path.join(ROOT, "paper_0904_0232_amd", "csrc", f) for f in ("particles.hip", "grpic_dev.h")]
 
 
