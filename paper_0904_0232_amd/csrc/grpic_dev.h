@@ -48,14 +48,15 @@ struct Hole {
 // error O(e^3); with e = 1 - d r, r (1 + e + e^2) has error O(e^3); the
 // quotient adds a residual correction.  A few ulps instead of the correctly
 // rounded result, at about a third of the instructions.  sqrt_nr takes
-// x >= 0 (0 gives 0); rsqrt_nr a finite positive normal x; rcp_nr and div_nr
-// a finite non-zero normal d.
+// x >= 0 and raises it to the smallest normal first (so 0 gives about
+// 1.5e-154, which vanishes against anything it is added to); rsqrt_nr takes
+// a finite positive normal x; rcp_nr and div_nr a finite non-zero normal d.
 __device__ __forceinline__ double sqrt_nr(double x) {
+    x = fmax(x, 2.2250738585072014e-308);
     const double y = __builtin_amdgcn_rsq(x);
     const double s = x * y;
     const double e = fma(-s, y, 1.0);
-    const double r = fma(s * e, fma(e, 0.375, 0.5), s);
-    return x > 0.0 ? r : 0.0;
+    return fma(s * e, fma(e, 0.375, 0.5), s);
 }
 __device__ __forceinline__ double rsqrt_nr(double x) {
     const double y = __builtin_amdgcn_rsq(x);

@@ -273,10 +273,11 @@ struct LdsAcc {
     }
 };
 
-// Fixed-point contributions of one segment A -> B inside `cell`, added to
-// v[K][bi + 2 bj] (the K-edge at cell + bi e_I + bj e_J, I = K+1, J = K+2).
+// Contributions of one segment A -> B inside `cell`, in units of the
+// fixed-point current (FP64), added to v[K][bi + 2 bj] (the K-edge at
+// cell + bi e_I + bj e_J, I = K+1, J = K+2).
 __device__ __forceinline__ void dep_segment(const DepCtx &D, const double A[3], const double B[3], const int cell[3],
-                                            double Q, long long v[3][4]) {
+                                            double Q, double v[3][4]) {
     double d[3], mid[3];
     for (int ax = 0; ax < 3; ax++) {
         d[ax] = B[ax] - A[ax];
@@ -319,41 +320,44 @@ __device__ __forceinline__ void dep_segment(const DepCtx &D, const double A[3], 
         w10 -= t;
         w01 -= t;
         double sc = flux * D.jscale;
-        v[K][0] += fixed_rn(sc * w00);
-        v[K][1] += fixed_rn(sc * w10);
-        v[K][2] += fixed_rn(sc * w01);
-        v[K][3] += fixed_rn(sc * w11);
+        v[K][0] += sc * w00;
+        v[K][1] += sc * w10;
+        v[K][2] += sc * w01;
+        v[K][3] += sc * w11;
     }
 }
 
-// Add the twelve edge sums of one cell to the accumulator (zeros skipped).
+// Round the twelve edge sums of one cell to fixed point, add them to the
+// accumulator and clear them.
 template <typename Acc>
-__device__ __forceinline__ void dep_flush(const Acc &acc, const int cell[3], long long v[3][4]) {
+__device__ __forceinline__ void dep_flush(const Acc &acc, const int cell[3], double v[3][4]) {
 #pragma unroll
     for (int K = 0; K < 3; K++) {
         const int I = (K + 1) % 3, J = (K + 2) % 3;
 #pragma unroll
         for (int c = 0; c < 4; c++) {
-            if (v[K][c] != 0) {
+            {
                 int id[3] = {cell[0], cell[1], cell[2]};
                 id[I] += c & 1;
                 id[J] += c >> 1;
-                acc.add(K, id[0], id[1], id[2], v[K][c]);
+                acc.add(K, id[0], id[1], id[2], fixed_rn(v[K][c]));
             }
-            v[K][c] = 0;
+            v[K][c] = 0.0;
         }
     }
 }
 
-// Both segments of one chord: summed in registers first when they lie in
-// the same cell (integer sums, so the totals are unchanged).
+// Both segments of one chord: summed in FP64 registers first when they lie
+// in the same cell (two terms in a fixed order), so each particle's share of
+// an edge is rounded to fixed point once and the atomic sums stay
+// independent of order.
 template <typename Acc>
 __device__ __forceinline__ void dep_chord(const DepCtx &D, const Acc &acc, const double X1[3], const double xr[3],
                                           const double X2[3], const int c1[3], const int c2[3], double Q) {
-    long long v[3][4];
+    double v[3][4];
 #pragma unroll
     for (int K = 0; K < 3; K++)
-        for (int c = 0; c < 4; c++) v[K][c] = 0;
+        for (int c = 0; c < 4; c++) v[K][c] = 0.0;
     dep_segment(D, X1, xr, c1, Q, v);
     if (c1[0] != c2[0] || c1[1] != c2[1] || c1[2] != c2[2]) dep_flush(acc, c1, v);
     dep_segment(D, xr, X2, c2, Q, v);

@@ -322,10 +322,10 @@ struct LdsAcc32 {
 };
 
 // One segment A -> B, local to cell `base` + `cell` (cell relative to base).
-// Its fixed-point contributions are added to v[K][bi + 2 bj] (the K-edge at
-// base + cell + bi e_I + bj e_J).
+// Its contributions, in units of the fixed-point current (FP64), are added
+// to v[K][bi + 2 bj] (the K-edge at base + cell + bi e_I + bj e_J).
 __device__ __forceinline__ void dep_segment32(const Dep32 &D, const int base[3], const float O[3], const float A[3],
-                                              const float B[3], const int cell[3], float Q, long long v[3][4]) {
+                                              const float B[3], const int cell[3], float Q, double v[3][4]) {
     float d[3], mid[3];
     for (int ax = 0; ax < 3; ax++) {
         d[ax] = B[ax] - A[ax];
@@ -368,43 +368,43 @@ __device__ __forceinline__ void dep_segment32(const Dep32 &D, const int base[3],
         w10 -= t;
         w01 -= t;
         double sc = (double)flux * D.jscale;
-        v[K][0] += fixed_rn(sc * (double)w00);
-        v[K][1] += fixed_rn(sc * (double)w10);
-        v[K][2] += fixed_rn(sc * (double)w01);
-        v[K][3] += fixed_rn(sc * (double)w11);
+        v[K][0] += sc * (double)w00;
+        v[K][1] += sc * (double)w10;
+        v[K][2] += sc * (double)w01;
+        v[K][3] += sc * (double)w11;
     }
 }
 
-// Add the twelve edge sums of cell base + cell to the accumulator (zeros
-// skipped) and clear them.
+// Round the twelve edge sums of cell base + cell to fixed point, add them to
+// the accumulator and clear them.
 template <typename Acc>
-__device__ __forceinline__ void dep_flush32(const Acc &acc, const int base[3], const int cell[3], long long v[3][4]) {
+__device__ __forceinline__ void dep_flush32(const Acc &acc, const int base[3], const int cell[3], double v[3][4]) {
 #pragma unroll
     for (int K = 0; K < 3; K++) {
         const int I = (K + 1) % 3, J = (K + 2) % 3;
 #pragma unroll
         for (int c = 0; c < 4; c++) {
-            if (v[K][c] != 0) {
+            {
                 int id[3] = {base[0] + cell[0], base[1] + cell[1], base[2] + cell[2]};
                 id[I] += c & 1;
                 id[J] += c >> 1;
-                acc.add(K, id[0], id[1], id[2], v[K][c]);
+                acc.add(K, id[0], id[1], id[2], fixed_rn(v[K][c]));
             }
-            v[K][c] = 0;
+            v[K][c] = 0.0;
         }
     }
 }
 
-// Both segments of one chord, summed in registers first when they lie in the
-// same cell.
+// Both segments of one chord, summed in FP64 registers first when they lie in
+// the same cell (each particle's share of an edge is rounded once).
 template <typename Acc>
 __device__ __forceinline__ void dep_chord32(const Dep32 &D, const Acc &acc, const int base[3], const float X1[3],
                                             const float xr[3], const float X2[3], const int l1[3], const int l2[3],
                                             float Q) {
-    long long v[3][4];
+    double v[3][4];
 #pragma unroll
     for (int K = 0; K < 3; K++)
-        for (int c = 0; c < 4; c++) v[K][c] = 0;
+        for (int c = 0; c < 4; c++) v[K][c] = 0.0;
     // the cell corner relative to the hole, exact in FP64, rounded once
     const float O[3] = {(float)((double)base[0] - D.h.cx), (float)((double)base[1] - D.h.cy),
                         (float)((double)base[2] - D.h.cz)};
