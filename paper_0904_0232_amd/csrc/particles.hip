@@ -60,14 +60,16 @@ __device__ __forceinline__ void gather_cell(const Grid &G, const double X[3], in
 
 // Lorentz term (q/m-free) L^a = F^a_b(X) u^b with F^a_b gathered trilinearly
 // from the nodes of cell c (cloud-in-cell with sqrt(-det g) = 1, Sec. 3.3),
-// from the block's LDS box when it holds one, else from global memory; the
-// arithmetic is the same.
+// from the block's LDS box when it holds the cell's nodes, else from global
+// memory; the arithmetic is the same.
 __device__ __forceinline__ void gather_lorentz(const Grid &G, const double *__restrict__ node, const NodeBox &B,
                                                const int c[3], const double X[3], const double U[4], double L[4]) {
     double w[3];
     for (int ax = 0; ax < 3; ax++) w[ax] = X[ax] - (double)c[ax];
     L[0] = L[1] = L[2] = L[3] = 0.0;
-    if (B.use) {
+    bool inside = B.use;
+    for (int ax = 0; ax < 3; ax++) inside = inside && c[ax] >= B.lo[ax] && c[ax] + 1 < B.lo[ax] + B.n[ax];
+    if (inside) {
         const int64_t l = ((int64_t)(c[2] - B.lo[2]) * B.n[1] + (c[1] - B.lo[1])) * B.n[0] + (c[0] - B.lo[0]);
         gather_rows(B.lds + kNodeStride2 * l, kNodeStride2, kNodeStride2 * B.n[0],
                     (int64_t)kNodeStride2 * B.n[0] * B.n[1], w, U, L);
@@ -109,14 +111,13 @@ __device__ __forceinline__ double stage_gamma(const PushParams &P, double u4, do
 constexpr int kPushBlock = 256;
 constexpr int kPushLdsNodes = 256;  // 36 KB of padded node tensor per block
 
-// Stage the nodes of the cells the block's live lanes gather from (cell c of
-// each live lane, nodes c .. c+1) into LDS when the box fits.  Every thread
-// of the block calls this; it synchronises the block after the box reduction
-// (every wave is then done with the previous box) and, when it copies, after
-// the copy.  When the box equals the one staged for the previous stage (the
-// half-step stages usually gather from the same cells) nothing is copied.
-__device__ __forceinline__ void stage_nodes(const Grid &G, const double *__restrict__ node, bool live, const int c[3],
-                                            double2 *snode, int (*sred)[kPushBlock / 64], NodeBox &B) {
+// Stage, once per push, the node box of the cells the block's live lanes
+// start in (cell c, nodes c .. c+1), widened by one cell on every side when
+// that still fits, so the later RK4 stages (moves below a cell) usually
+// gather from the same copy.  Every thread of the block calls this; it
+// synchronises the block after the box reduction and after the copy.
+__device__ __forceinline__ void stage_box(const Grid &G, const double *__restrict__ node, bool live, const int c[3],
+                                          double2 *snode, int (*sred)[kPushBlock / 64], NodeBox &B) {
     const int tid = threadIdx.x;
     for (int ax = 0; ax < 3; ax++) {
         int a = wave_min(live ? c[ax] : (1 << 30)), b = wave_max(live ? c[ax] : -(1 << 30));
@@ -125,29 +126,35 @@ __device__ __forceinline__ void stage_nodes(const Grid &G, const double *__restr
             sred[3 + ax][tid >> 6] = b;
         }
     }
-    __syncthreads();  // also: every wave has finished reading the previous box
-    int count = 1;
-    bool same = B.use;  // the box already staged for the previous stage
+    __syncthreads();
+    int lo[2][3], n[2][3], count[2] = {1, 1};
     for (int ax = 0; ax < 3; ax++) {
         int a = sred[ax][0], b = sred[3 + ax][0];
         for (int w = 1; w < kPushBlock / 64; w++) {
             a = sred[ax][w] < a ? sred[ax][w] : a;
             b = sred[3 + ax][w] > b ? sred[3 + ax][w] : b;
         }
-        const int n = b >= a ? b - a + 2 : 0;  // nodes a .. b+1
-        same = same && B.lo[ax] == a && B.n[ax] == n;
-        B.lo[ax] = a;
-        B.n[ax] = n;
-        count = (n > 0 && count <= kPushLdsNodes) ? count * n : 0;
+        for (int e = 0; e < 2; e++) {  // e = 1: widened by one cell, within the nodes 0 .. dim
+            const int l = a - e < 0 ? 0 : a - e;
+            const int h = b + 1 + e > G.dim(ax) ? G.dim(ax) : b + 1 + e;
+            lo[e][ax] = l;
+            n[e][ax] = b >= a ? h - l + 1 : 0;
+            count[e] = (n[e][ax] > 0 && count[e] <= kPushLdsNodes) ? count[e] * n[e][ax] : 0;
+        }
     }
-    B.use = count > 0 && count <= kPushLdsNodes;  // count = 0: no live lane
-    if (same) return;  // the LDS copy is still the right one (block-uniform)
+    // count = 0: no live lane
+    const int e = (count[1] > 0 && count[1] <= kPushLdsNodes) ? 1 : 0;
+    for (int ax = 0; ax < 3; ax++) {
+        B.lo[ax] = lo[e][ax];
+        B.n[ax] = n[e][ax];
+    }
+    B.use = count[e] > 0 && count[e] <= kPushLdsNodes;
     if (B.use) {
         const double2 *src = reinterpret_cast<const double2 *>(node);
         const int nb0 = B.n[0], nb01 = B.n[0] * B.n[1];
         const float inv0 = __builtin_amdgcn_rcpf((float)nb0), inv01 = __builtin_amdgcn_rcpf((float)nb01);
-        for (int e = tid; e < count * 8; e += kPushBlock) {
-            const int l = e >> 3, part = e & 7;
+        for (int q = tid; q < count[e] * 8; q += kPushBlock) {
+            const int l = q >> 3, part = q & 7;
             const int lk = small_div(l, inv01), r = l - lk * nb01, lj = small_div(r, inv0), li = r - lj * nb0;
             snode[kNodeStride2 * l + part] = src[8 * G.node(B.lo[0] + li, B.lo[1] + lj, B.lo[2] + lk) + part];
         }
@@ -158,18 +165,16 @@ __device__ __forceinline__ void stage_nodes(const Grid &G, const double *__restr
 // Classic RK4 in coordinate time on Y = (x, u): K_k = (u_k, A_k)/gamma_k,
 // stages at dt/2, dt/2, dt, combination 1:2:2:1 over 6.
 //
-// Before each stage the block copies the node tensor of the box of cells its
-// particles gather from into LDS: cell-sorted particles of one block cover a
-// few cells, so each node is read from L2/HBM once per block and stage
-// instead of once per particle.
+// The block first copies the node tensor of the (widened) box of cells its
+// particles start in into LDS: cell-sorted particles of one block cover a
+// few cells, so each node is read from L2/HBM once per block instead of once
+// per particle and stage.  A lane whose stage cell lies outside the box reads
+// global memory; no stage waits for the others.
 __global__ __launch_bounds__(kPushBlock, 4) void k_push(PushParams P, Species cS, const double *__restrict__ node,
                                                      ParticlePtrs in, ParticlePtrs out,
                                                      unsigned long long *counters) {
     __shared__ double2 snode[kPushLdsNodes * kNodeStride2];
-    // two reduction buffers, used by alternate stages: a stage whose box is
-    // unchanged passes only one barrier, so the next stage must not
-    // overwrite the buffer a slower wave may still be reading
-    __shared__ int sred[2][6][kPushBlock / 64];
+    __shared__ int sred[6][kPushBlock / 64];
     const int tid = threadIdx.x;
     const int64_t id = (int64_t)blockIdx.x * kPushBlock + tid;
     int clamps = 0;
@@ -190,12 +195,15 @@ __global__ __launch_bounds__(kPushBlock, 4) void k_push(PushParams P, Species cS
     double Sx[3] = {0.0, 0.0, 0.0}, Su[4] = {0.0, 0.0, 0.0, 0.0};
     NodeBox B;
     B.lds = snode;
-    B.use = false;
+    {
+        int c0[3];
+        gather_cell(P.G, X0, c0);
+        stage_box(P.G, node, live, c0, snode, sred, B);
+    }
 #pragma unroll 1
     for (int st = 0; st < 4; st++) {
         int c[3];
         gather_cell(P.G, Xs, c);
-        stage_nodes(P.G, node, live, c, snode, sred[st & 1], B);
         if (live) {
             double A[4];
             accel(P, node, B, c, qm, Xs, Us, A);

@@ -72,14 +72,16 @@ __device__ __forceinline__ void gather_cell32(const Grid &G, const int base[3], 
 
 // L^a = F^a_b u^b gathered from the FP32 node tensor at offset X relative to
 // cell `base` (X may leave [0,1) by up to a cell), from the nodes of the
-// gather cell c, read from the block's LDS box when it holds one.
+// gather cell c, read from the block's LDS box when it holds the cell's nodes.
 __device__ __forceinline__ void gather_lorentz32(const Grid &G, const float *__restrict__ node, const NodeBox32 &B,
                                                  const int base[3], const int c[3], const float X[3],
                                                  const float U[4], float L[4]) {
     float w[3];
     for (int ax = 0; ax < 3; ax++) w[ax] = (float)(base[ax] - c[ax]) + X[ax];
     L[0] = L[1] = L[2] = L[3] = 0.0f;
-    if (B.use) {
+    bool inside = B.use;
+    for (int ax = 0; ax < 3; ax++) inside = inside && c[ax] >= B.lo[ax] && c[ax] + 1 < B.lo[ax] + B.n[ax];
+    if (inside) {
         const int64_t l = ((int64_t)(c[2] - B.lo[2]) * B.n[1] + (c[1] - B.lo[1])) * B.n[0] + (c[0] - B.lo[0]);
         gather_rows32(B.lds + kNode32Stride4 * l, kNode32Stride4, kNode32Stride4 * B.n[0],
                       (int64_t)kNode32Stride4 * B.n[0] * B.n[1], w, U, L);
@@ -131,11 +133,12 @@ __device__ __forceinline__ float stage_gamma32(const PushParams &P, float u4, fl
 constexpr int kPush32Block = 256;
 constexpr int kPush32LdsNodes = 448;  // 35 KB of padded FP32 node tensor per block
 
-// Stage the FP32 nodes of the cells the block's live lanes gather from into
-// LDS when the box fits (as the FP64 pusher does, including keeping the copy
-// when the box is unchanged).  Every thread of the block calls this.
-__device__ __forceinline__ void stage_nodes32(const Grid &G, const float *__restrict__ node, bool live, const int c[3],
-                                              float4 *snode, int (*sred)[kPush32Block / 64], NodeBox32 &B) {
+// Stage, once per push, the FP32 node box of the cells the block's live
+// lanes start in, widened by one cell on every side when that still fits (as
+// the FP64 pusher does).  Every thread of the block calls this; it
+// synchronises the block after the box reduction and after the copy.
+__device__ __forceinline__ void stage_box32(const Grid &G, const float *__restrict__ node, bool live, const int c[3],
+                                            float4 *snode, int (*sred)[kPush32Block / 64], NodeBox32 &B) {
     const int tid = threadIdx.x;
     for (int ax = 0; ax < 3; ax++) {
         int a = wave_min32(live ? c[ax] : (1 << 30)), b = wave_max32(live ? c[ax] : -(1 << 30));
@@ -144,29 +147,35 @@ __device__ __forceinline__ void stage_nodes32(const Grid &G, const float *__rest
             sred[3 + ax][tid >> 6] = b;
         }
     }
-    __syncthreads();  // also: every wave has finished reading the previous box
-    int count = 1;
-    bool same = B.use;  // the box already staged for the previous stage
+    __syncthreads();
+    int lo[2][3], n[2][3], count[2] = {1, 1};
     for (int ax = 0; ax < 3; ax++) {
         int a = sred[ax][0], b = sred[3 + ax][0];
         for (int w = 1; w < kPush32Block / 64; w++) {
             a = sred[ax][w] < a ? sred[ax][w] : a;
             b = sred[3 + ax][w] > b ? sred[3 + ax][w] : b;
         }
-        const int n = b >= a ? b - a + 2 : 0;  // nodes a .. b+1
-        same = same && B.lo[ax] == a && B.n[ax] == n;
-        B.lo[ax] = a;
-        B.n[ax] = n;
-        count = (n > 0 && count <= kPush32LdsNodes) ? count * n : 0;
+        for (int e = 0; e < 2; e++) {  // e = 1: widened by one cell, within the nodes 0 .. dim
+            const int l = a - e < 0 ? 0 : a - e;
+            const int h = b + 1 + e > G.dim(ax) ? G.dim(ax) : b + 1 + e;
+            lo[e][ax] = l;
+            n[e][ax] = b >= a ? h - l + 1 : 0;
+            count[e] = (n[e][ax] > 0 && count[e] <= kPush32LdsNodes) ? count[e] * n[e][ax] : 0;
+        }
     }
-    B.use = count > 0 && count <= kPush32LdsNodes;  // count = 0: no live lane
-    if (same) return;  // the LDS copy is still the right one (block-uniform)
+    // count = 0: no live lane
+    const int e = (count[1] > 0 && count[1] <= kPush32LdsNodes) ? 1 : 0;
+    for (int ax = 0; ax < 3; ax++) {
+        B.lo[ax] = lo[e][ax];
+        B.n[ax] = n[e][ax];
+    }
+    B.use = count[e] > 0 && count[e] <= kPush32LdsNodes;
     if (B.use) {
         const float4 *src = reinterpret_cast<const float4 *>(node);
         const int nb0 = B.n[0], nb01 = B.n[0] * B.n[1];
         const float inv0 = __builtin_amdgcn_rcpf((float)nb0), inv01 = __builtin_amdgcn_rcpf((float)nb01);
-        for (int e = tid; e < count * 4; e += kPush32Block) {
-            const int l = e >> 2, part = e & 3;
+        for (int q = tid; q < count[e] * 4; q += kPush32Block) {
+            const int l = q >> 2, part = q & 3;
             const int lk = small_div(l, inv01), r = l - lk * nb01, lj = small_div(r, inv0), li = r - lj * nb0;
             snode[kNode32Stride4 * l + part] = src[4 * G.node(B.lo[0] + li, B.lo[1] + lj, B.lo[2] + lk) + part];
         }
@@ -175,16 +184,15 @@ __device__ __forceinline__ void stage_nodes32(const Grid &G, const float *__rest
 }
 
 // The same RK4 in coordinate time as the FP64 pusher, on offsets relative
-// to the particle's cell; the cell is re-based after the step.  The nodes of
-// each stage are staged in LDS per block, as in the FP64 pusher.
+// to the particle's cell; the cell is re-based after the step.  The nodes are
+// staged in LDS once per block and push, as in the FP64 pusher.
 // Block `blk` of the push (particles blk * kPush32Block ...); LDS scratch
-// snode and sred come from the calling kernel; sred holds two reduction
-// buffers, used by alternate stages, because a stage whose box is unchanged
-// passes only one barrier.  Every thread of the block calls this.
+// snode and sred come from the calling kernel.  Every thread of the block
+// calls this.
 __device__ __forceinline__ void push32_block(const PushParams &P, const Mixed &M, const Species &cS,
                                              const float *__restrict__ node, const ParticlePtrs32 &in,
                                              const ParticlePtrs32 &out, unsigned long long *counters, int64_t blk,
-                                             float4 *snode, int (*sred)[6][kPush32Block / 64]) {
+                                             float4 *snode, int (*sred)[kPush32Block / 64]) {
     const int tid = threadIdx.x;
     const int64_t id = blk * kPush32Block + tid;
     int clamps = 0;
@@ -209,12 +217,15 @@ __device__ __forceinline__ void push32_block(const PushParams &P, const Mixed &M
     const float dt = (float)P.dt;
     NodeBox32 B;
     B.lds = snode;
-    B.use = false;
+    {
+        int c0[3];
+        gather_cell32(P.G, base, X0, c0);
+        stage_box32(P.G, node, alive, c0, snode, sred, B);
+    }
 #pragma unroll 1
     for (int st = 0; st < 4; st++) {
         int c[3];
         gather_cell32(P.G, base, Xs, c);
-        stage_nodes32(P.G, node, alive, c, snode, sred[st & 1], B);
         if (alive) {
             float A[4];
             accel32(P, M, node, B, c, qm, i, j, k, Xs, Us, A);
@@ -256,7 +267,7 @@ __global__ __launch_bounds__(kPush32Block, 4) void k_push32(PushParams P, Mixed 
                                                            const float *__restrict__ node, ParticlePtrs32 in,
                                                            ParticlePtrs32 out, unsigned long long *counters) {
     __shared__ float4 snode[kPush32LdsNodes * kNode32Stride4];
-    __shared__ int sred[2][6][kPush32Block / 64];
+    __shared__ int sred[6][kPush32Block / 64];
     push32_block(P, M, cS, node, in, out, counters, blockIdx.x, snode, sred);
 }
 
@@ -603,7 +614,7 @@ Dep32 make_dep32(const Grid &G, const Hole &h, const Mixed &M, double dt, int de
 // active runs (the run table is in device memory).
 __global__ __launch_bounds__(kPush32Block, 4) void k_batch_push32(const BatchTable *__restrict__ T) {
     __shared__ float4 snode[kPush32LdsNodes * kNode32Stride4];
-    __shared__ int sred[2][6][kPush32Block / 64];
+    __shared__ int sred[6][kPush32Block / 64];
     const int64_t total = T->total[BK_PUSH];
     for (int64_t lb = blockIdx.x; lb < total; lb += gridDim.x) {
         __syncthreads();  // the previous logical block is done with the LDS scratch
