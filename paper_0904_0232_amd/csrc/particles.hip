@@ -27,10 +27,11 @@ struct NodeBox {
 
 // L^a += sum over the 8 nodes of W_n (F_n u)^a, nodes addressed from the
 // (0,0,0) node `p` with strides (in double2) si, sj, sk; the contraction with
-// u is taken node by node, so only four accumulators stay live.
+// u is taken node by node, so only four accumulators stay live; two (j, k)
+// pairs per loop pass give the scheduler more loads to overlap.
 __device__ __forceinline__ void gather_rows(const double2 *p, int64_t si, int64_t sj, int64_t sk, const double w[3],
                                             const double U[4], double L[4]) {
-#pragma unroll 1
+#pragma unroll 2
     for (int q = 0; q < 4; q++) {
         const int dj = q & 1, dk = q >> 1;
         const double wyz = (dj ? w[1] : 1.0 - w[1]) * (dk ? w[2] : 1.0 - w[2]);
