@@ -444,10 +444,13 @@ def main():
     if args.scale:
         scale = {}
         for prec in ("fp32", "fp64"):
-            ms = measure("shell256", prec, 20, 2, args.sort_every)
+            # warm up past the first cell sort (loaded particles are in
+            # generation order), as the main measurement does
+            ms = measure("shell256", prec, 20, max(2, args.sort_every), args.sort_every)
             log("shell256 %s: %.4g particle-steps/s" % (prec, ms["value"]))
             scale[prec] = {"value": ms["value"], "ms_per_step": ms["ms_per_step"], "particles": ms["ntot"],
-                           "kernel_ms_per_launch": ms["kernel_ms_per_launch"], "steps": 20}
+                           "kernel_ms_per_launch": ms["kernel_ms_per_launch"], "steps": 20,
+                           "warmup": max(2, args.sort_every)}
         line["throughput_scale_shell256"] = scale
     if args.precision:
         line["precision_torus128"] = precision_study("torus128", n_override=args.precision_particles or None)
