@@ -33,7 +33,8 @@ class Params(ctypes.Structure):
         ("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
         ("gamma_mode", ctypes.c_int32), ("deposit_mode", ctypes.c_int32),
         ("nspecies", ctypes.c_int32),
-        ("field_iters", ctypes.c_int32), ("pad_", ctypes.c_int32),
+        ("field_iters", ctypes.c_int32), ("rk_mode", ctypes.c_int32),
+        ("gather_mode", ctypes.c_int32), ("pad_", ctypes.c_int32),
         ("c", ctypes.c_double), ("dt", ctypes.c_double),
         ("m", ctypes.c_double), ("a", ctypes.c_double),
         ("center", ctypes.c_double * 3),
@@ -126,14 +127,18 @@ def _f64(a):
 
 def make_params(nx, ny=None, nz=None, *, c=1.0, dt=0.5, m=0.0, a=0.0, center=None,
                 r_rm=None, r_exc=None, gamma_mode=0, deposit_mode=0,
-                field_iters=3, r_damp=None, damp_max=0.1, species=((-1.0, 1.0),)):
-    """species: sequence of (macro charge, macro mass)."""
+                field_iters=3, r_damp=None, damp_max=0.1, species=((-1.0, 1.0),),
+                rk_mode=0, gather_mode=0):
+    """species: sequence of (macro charge, macro mass).  rk_mode 1 takes the
+    printed RK steps literally, gather_mode 1 gathers the fields once at x_n
+    (both ablations of the default readings)."""
     ny = nx if ny is None else ny
     nz = nx if nz is None else nz
     p = Params()
     p.nx, p.ny, p.nz = nx, ny, nz
     p.gamma_mode, p.deposit_mode = gamma_mode, deposit_mode
     p.field_iters = field_iters
+    p.rk_mode, p.gather_mode = rk_mode, gather_mode
     p.c, p.dt, p.m, p.a = c, dt, m, a
     cen = (nx / 2.0, ny / 2.0, nz / 2.0) if center is None else center
     for i in range(3):

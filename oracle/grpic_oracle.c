@@ -46,6 +46,8 @@ typedef struct {
     int32_t deposit_mode; /* 0: curved face-area weights; 1: flat weights       */
     int32_t nspecies;
     int32_t field_iters;  /* evaluations of the constitutive map per half-cycle  */
+    int32_t rk_mode;      /* 0: classic RK4 reading; 1: the printed steps        */
+    int32_t gather_mode;  /* 0: fields at every stage; 1: at x_n for all stages  */
     int32_t pad_;
     double c, dt;
     double m, a;          /* hole mass and spin parameter, in cells              */
@@ -792,14 +794,19 @@ void or_gather(const or_params *p, const double *node, const double X[3], double
 /* ------------------------------------------------------------------ */
 /* Equation of motion (Sec. 3.3):
  *   du^a/dtau = (q/m) F^a_b u^b - Gamma^a_{mn} u^m u^n.
- * reading: as printed, with no 1/c on the Lorentz term. */
-static void accel(const or_params *p, const double *node, double qm,
+ * reading: as printed, with no 1/c on the Lorentz term.  Fpre, when not
+ * NULL, is the field tensor to use instead of the gather at X (the
+ * per-step gather ablation); the Christoffel symbols are always taken at X,
+ * as the paper states for the push. */
+static void accel(const or_params *p, const double *node, const double *Fpre, double qm,
                   const double X[3], const double u[4], double A[4])
 {
     double G[64];
     or_christoffel(p, X[0] - p->center[0], X[1] - p->center[1], X[2] - p->center[2], G);
     double F[16];
-    if (node && qm != 0.0)
+    if (Fpre)
+        for (int q = 0; q < 16; q++) F[q] = Fpre[q];
+    else if (node && qm != 0.0)
         or_gather(p, node, X, F);
     else
         for (int q = 0; q < 16; q++) F[q] = 0.0;
@@ -829,6 +836,18 @@ static double stage_gamma(const or_params *p, double u4, double a4, int64_t *cla
     return 0.5 * (u4 / c + sqrt(disc));
 }
 
+/* Field tensor for the per-step gather ablation (gather_mode 1): the
+ * gather at the step's start position, used unchanged by all four stages.
+ * Returns NULL (gather at every stage) in the default mode or when the
+ * particle feels no field. */
+static const double *step_fields(const or_params *p, const double *node, double qm, const double X[3],
+                                 double F[16])
+{
+    if (p->gather_mode != 1 || !node || qm == 0.0) return NULL;
+    or_gather(p, node, X, F);
+    return F;
+}
+
 /* One RK4 step in coordinate time of Y = (x^1..3, u^1..4).
  * reading of the printed steps (whose final weights sum to 5/6 and whose
  * half-velocity averaging fails constant-acceleration kinematics): stage k
@@ -836,9 +855,11 @@ static double stage_gamma(const or_params *p, double u4, double a4, int64_t *cla
  * so dt*K_k = (u_k, A_k) dtau_k with dtau_k = dt/gamma_k; then
  * Y_2 = Y_n + dt/2 K_1, Y_3 = Y_n + dt/2 K_2, Y_4 = Y_n + dt K_3,
  * Y_{n+1} = Y_n + dt/6 (K_1 + 2 K_2 + 2 K_3 + K_4).  Fields and
- * Christoffel symbols are evaluated at every stage position.
+ * Christoffel symbols are evaluated at every stage position (fields at
+ * x_n only with gather_mode 1).
  * Pinned: m=0 gyration equals the RK4 stability polynomial, E x B drift,
- * circular and inclined Kerr orbits, convergence order. */
+ * circular and inclined Kerr orbits, convergence order; with gather_mode 1,
+ * the RK4 polynomial of the field frozen at x_n in a linear field. */
 static void rk4_step(const or_params *p, const double *node, double qm,
                      double X[3], double u[4], int64_t *clamps)
 {
@@ -847,10 +868,12 @@ static void rk4_step(const or_params *p, const double *node, double qm,
     for (int i = 0; i < 3; i++) Y0[i] = X[i];
     for (int i = 0; i < 4; i++) Y0[3 + i] = u[i];
     for (int i = 0; i < 7; i++) Yk[i] = Y0[i];
+    double F0[16];
+    const double *Fpre = step_fields(p, node, qm, X, F0);
     static const double fac[3] = {0.5, 0.5, 1.0};
     for (int st = 0; st < 4; st++) {
         double A[4];
-        accel(p, node, qm, &Yk[0], &Yk[3], A);
+        accel(p, node, Fpre, qm, &Yk[0], &Yk[3], A);
         double gam = stage_gamma(p, Yk[6], A[3], clamps);
         for (int i = 0; i < 3; i++) K[st][i] = Yk[3 + i] / gam;
         for (int i = 0; i < 4; i++) K[st][3 + i] = A[i] / gam;
@@ -861,6 +884,59 @@ static void rk4_step(const or_params *p, const double *node, double qm,
         Yk[i] = Y0[i] + (dt / 6.0) * (K[0][i] + 2.0 * K[1][i] + 2.0 * K[2][i] + K[3][i]);
     for (int i = 0; i < 3; i++) X[i] = Yk[i];
     for (int i = 0; i < 4; i++) u[i] = Yk[3 + i];
+}
+
+/* The four steps exactly as printed in Sec. 3.3 (rk_mode 1, an ablation of
+ * the reading above), with the two final sums read as increments added to
+ * x_n and u_n.  Step k (k = 1..4) takes the averaged velocity
+ * ut_k = (u_n + u_k)/2 (ut_1 = u_n) and the position
+ * x_k = x_n + ut_k dtau_{k-1} (x_1 = x_n), evaluates a_k = a(x_k, ut_k) and
+ * gamma_k = f(ut_k^4, a_k^4), with dtau_1 = dt/(2 gamma_1),
+ * dtau_2,3 = dt/gamma_2,3, dtau_4 = dt/(2 gamma_4), and
+ * u_{k+1} = u_n + a_k dtau_k; then
+ *   x_{n+1} = x_n + (ut_1 dtau_1 + 2 (ut_2 dtau_2 + ut_3 dtau_3) + ut_4 dtau_4)/6,
+ *   u_{n+1} = u_n + (a_1 dtau_1 + 2 (a_2 dtau_2 + a_3 dtau_3) + a_4 dtau_4)/6.
+ * Pinned: for du/dtau = Omega u with constant gamma (m = 0, uniform B) the
+ * step is the polynomial I + 5M/6 + 7M^2/24 + M^3/16 + M^4/192 of
+ * M = Omega dt/gamma, and a free particle moves 5/6 of v dt. */
+static void rk4_literal_step(const or_params *p, const double *node, double qm,
+                             double X[3], double u[4], int64_t *clamps)
+{
+    double dt = p->dt;
+    double x0[3], u0[4], xk[3], ut[4], uk[4];
+    double sx[3] = {0.0, 0.0, 0.0}, su[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int i = 0; i < 3; i++) x0[i] = xk[i] = X[i];
+    for (int i = 0; i < 4; i++) u0[i] = ut[i] = uk[i] = u[i];
+    double F0[16];
+    const double *Fpre = step_fields(p, node, qm, X, F0);
+    double dtau_prev = 0.0;
+    for (int st = 0; st < 4; st++) {
+        if (st > 0) {
+            for (int i = 0; i < 4; i++) ut[i] = 0.5 * (u0[i] + uk[i]);
+            for (int i = 0; i < 3; i++) xk[i] = x0[i] + ut[i] * dtau_prev;
+        }
+        double A[4];
+        accel(p, node, Fpre, qm, xk, ut, A);
+        double gam = stage_gamma(p, ut[3], A[3], clamps);
+        double dtau = (st == 0 || st == 3) ? dt / (2.0 * gam) : dt / gam;
+        double w = (st == 0 || st == 3) ? 1.0 : 2.0;
+        for (int i = 0; i < 3; i++) sx[i] += w * ut[i] * dtau;
+        for (int i = 0; i < 4; i++) su[i] += w * A[i] * dtau;
+        for (int i = 0; i < 4; i++) uk[i] = u0[i] + A[i] * dtau;
+        dtau_prev = dtau;
+    }
+    for (int i = 0; i < 3; i++) X[i] = x0[i] + sx[i] / 6.0;
+    for (int i = 0; i < 4; i++) u[i] = u0[i] + su[i] / 6.0;
+}
+
+/* The push of one particle in the configured reading. */
+static void push_step(const or_params *p, const double *node, double qm, double X[3], double u[4],
+                      int64_t *clamps)
+{
+    if (p->rk_mode == 1)
+        rk4_literal_step(p, node, qm, X, u, clamps);
+    else
+        rk4_step(p, node, qm, X, u, clamps);
 }
 
 /* ------------------------------------------------------------------ */
@@ -1269,7 +1345,7 @@ void or_sim_push_only(or_sim *s, int nsteps, int use_nodes)
             double X[3], U[4];
             for (int ax = 0; ax < 3; ax++) X[ax] = s->x[ax * s->ncap + i];
             for (int c = 0; c < 4; c++) U[c] = s->u[c * s->ncap + i];
-            rk4_step(p, use_nodes ? s->node : NULL, qm, X, U, &s->gamma_clamps);
+            push_step(p, use_nodes ? s->node : NULL, qm, X, U, &s->gamma_clamps);
             for (int ax = 0; ax < 3; ax++) s->x[ax * s->ncap + i] = X[ax];
             for (int c = 0; c < 4; c++) s->u[c * s->ncap + i] = U[c];
         }
@@ -1329,7 +1405,7 @@ void or_sim_step(or_sim *s, int nsteps)
             double X[3], U[4];
             for (int ax = 0; ax < 3; ax++) X[ax] = s->x[ax * s->ncap + i];
             for (int c = 0; c < 4; c++) U[c] = s->u[c * s->ncap + i];
-            rk4_step(p, s->node, qm, X, U, &s->gamma_clamps);
+            push_step(p, s->node, qm, X, U, &s->gamma_clamps);
             for (int ax = 0; ax < 3; ax++) s->x[ax * s->ncap + i] = X[ax];
             for (int c = 0; c < 4; c++) s->u[c * s->ncap + i] = U[c];
         }

@@ -190,3 +190,101 @@ def test_gather_partition_of_unity_and_linear_exactness():
         O.lib().or_gather(ctypes.byref(p), O._dp(nodes), O._dp(np.ascontiguousarray(X)), O._dp(out))
         ref = c0 + cx * X[0] + cy * X[1] + cz * X[2]
         assert np.abs(out - ref).max() < 1e-12
+
+
+# --- ablations of the push readings (rk_mode 1: the printed RK steps taken
+# literally; gather_mode 1: the field tensor gathered once at x_n) ---------
+
+def _lit_poly(z):
+    # u_{n+1} = P(z) u_n for du/dtau = Omega u at constant gamma, z = Omega dt/gamma
+    return 1 + 5 * z / 6 + 7 * z * z / 24 + z ** 3 / 16 + z ** 4 / 192
+
+
+def _lit_xpoly(z):
+    # x_{n+1} - x_n = (dt/gamma) Q(z) u_n for the same equation
+    return (5 + 7 * z / 4 + 3 * z * z / 8 + z ** 3 / 32) / 6
+
+
+def _gyro_setup(gamma_mode, qm, B, rk_mode=0, gather_mode=0, nodes=None):
+    N = 32
+    p = O.make_params(N, m=0.0, a=0.0, dt=0.5, gamma_mode=gamma_mode, species=((qm, 1.0),),
+                      rk_mode=rk_mode, gather_mode=gather_mode)
+    s = O.Sim(p, 1)
+    if nodes is None:
+        F = np.zeros((4, 4))
+        F[0, 1], F[1, 0] = B, -B   # F^1_2 = F^{12} = B^z in flat space
+        nodes = _uniform_nodes(p, F)
+    s.set_nodes(nodes)
+    return p, s
+
+
+@pytest.mark.parametrize("gamma_mode", [0, 1])
+def test_literal_rk_gyration_matches_its_polynomial(gamma_mode):
+    qm, B = -1.0, 0.05
+    p, s = _gyro_setup(gamma_mode, qm, B, rk_mode=1)
+    u3 = np.array([0.3, 0.1, 0.2])
+    u4 = np.sqrt(1.0 + u3 @ u3)
+    x0 = np.array([16.2, 15.7, 16.1])
+    s.set_particles(x0[:, None].copy(), np.array([[u3[0]], [u3[1]], [u3[2]], [u4]]), np.zeros(1, np.uint8))
+    nsteps = 200
+    s.push_only(nsteps)
+    xN, uN, _ = s.particles()
+    # closed form: a magnetic field leaves u^4 (so gamma = u^4/c) unchanged
+    h = p.dt / u4
+    z = -1j * qm * B * h
+    w, pos = u3[0] + 1j * u3[1], x0[0] + 1j * x0[1]
+    for _ in range(nsteps):
+        pos += h * _lit_xpoly(z) * w
+        w *= _lit_poly(z)
+    assert abs(uN[0, 0] + 1j * uN[1, 0] - w) < 1e-13 * nsteps * abs(w)
+    assert abs(xN[0, 0] + 1j * xN[1, 0] - pos) < 1e-13 * nsteps * abs(pos)
+    # along B the particle drifts 5/6 of v dt per step (weights summing to 5/6)
+    assert abs(xN[2, 0] - (x0[2] + nsteps * (5.0 / 6.0) * u3[2] / u4 * p.dt)) < 1e-12
+    assert abs(uN[3, 0] - u4) < 1e-14
+
+
+def test_literal_rk_free_particle_moves_five_sixths():
+    p = O.make_params(16, m=0.0, a=0.0, dt=0.5, rk_mode=1)
+    s = O.Sim(p, 1)
+    s.set_nodes(np.zeros(((p.nz + 1) * (p.ny + 1) * (p.nx + 1), 16)))
+    u3 = np.array([0.4, -0.2, 0.1])
+    u4 = np.sqrt(1.0 + u3 @ u3)
+    x0 = np.array([8.0, 8.0, 8.0])
+    s.set_particles(x0[:, None].copy(), np.r_[u3, u4][:, None].copy(), np.zeros(1, np.uint8))
+    s.push_only(3)
+    xN, uN, _ = s.particles()
+    assert np.abs(xN[:, 0] - (x0 + 3 * (5.0 / 6.0) * u3 / u4 * p.dt)).max() < 1e-13
+    assert np.abs(uN[:3, 0] - u3).max() == 0.0
+
+
+def test_per_step_gather_is_rk4_of_the_field_frozen_at_x_n():
+    # B^z linear in x, so the trilinear gather is exact: B(x) = B0 + G x
+    qm, B0, G = -1.0, 0.04, 0.004
+    N = 32
+    nn = (N + 1) ** 3
+    kk, jj, ii = np.meshgrid(np.arange(N + 1), np.arange(N + 1), np.arange(N + 1), indexing="ij")
+    Bn = (B0 + G * ii).reshape(-1)
+    nodes = np.zeros((nn, 16))
+    nodes[:, 1], nodes[:, 4] = Bn, -Bn
+    u3 = np.array([0.3, 0.1, 0.0])
+    u4 = np.sqrt(1.0 + u3 @ u3)
+    x0 = np.array([15.2, 15.7, 16.1])
+    out = {}
+    for gm in (0, 1):
+        p, s = _gyro_setup(1, qm, None, gather_mode=gm, nodes=nodes)
+        s.set_particles(x0[:, None].copy(), np.r_[u3, u4][:, None].copy(), np.zeros(1, np.uint8))
+        s.push_only(100)
+        out[gm] = s.particles()
+    # closed form, step by step: classic RK4 of dw/dtau = -i qm B(x_n) w
+    h = p.dt / u4
+    w, pos = u3[0] + 1j * u3[1], x0[0] + 1j * x0[1]
+    for _ in range(100):
+        z = -1j * qm * (B0 + G * pos.real) * h
+        pos += h * (1 + z / 2 + z * z / 6 + z ** 3 / 24) * w
+        w *= _rk4_poly(z)
+    xN, uN, _ = out[1]
+    assert abs(uN[0, 0] + 1j * uN[1, 0] - w) < 1e-12 * abs(w)
+    assert abs(xN[0, 0] + 1j * xN[1, 0] - pos) < 1e-11 * abs(pos)
+    # the per-stage gather sees B change within the step: a different orbit
+    x0N, u0N, _ = out[0]
+    assert abs(u0N[0, 0] + 1j * u0N[1, 0] - w) > 1e-9
