@@ -46,6 +46,18 @@ enum { GRPIC_GAMMA_PAPER = 0, GRPIC_GAMMA_U4 = 1 };
 /* Transverse current weights (Sec. 4): CURVED = face-area fractions with the
  * metric area density; FLAT = bilinear (exactly charge conserving). */
 enum { GRPIC_DEPOSIT_CURVED = 0, GRPIC_DEPOSIT_FLAT = 1 };
+/* RK4 structure of the pusher (Sec. 3.3).  CLASSIC = the default reading of
+ * the printed steps: stages at dt/2, dt/2, dt of the slopes
+ * (u_k, a_k)/gamma_k in coordinate time, combined 1:2:2:1 over 6 (fourth
+ * order).  PRINTED = the four steps exactly as printed (averaged stage
+ * velocities, dtau = dt/2gamma, dt/gamma, dt/gamma, dt/2gamma, final sums
+ * added to x_n and u_n; their weights sum to 5/6), an ablation that
+ * quantifies the printed form.  FP64 only. */
+enum { GRPIC_RK_CLASSIC = 0, GRPIC_RK_PRINTED = 1 };
+/* Where the pusher gathers the field tensor (Sec. 3.3): STAGE = at every RK
+ * stage position (default); STEP = once at x_n for all four stages (an
+ * ablation; the Christoffel symbols stay at the stage positions).  FP64 only. */
+enum { GRPIC_GATHER_STAGE = 0, GRPIC_GATHER_STEP = 1 };
 
 typedef void *(*grpic_alloc_fn)(size_t bytes, void *ctx);
 typedef void (*grpic_free_fn)(void *ptr, void *ctx);
@@ -61,6 +73,8 @@ typedef struct {
     int32_t fp_bits;        /* fraction bits of the int64 current accumulator, 16..50 (44) */
     int32_t nspecies;       /* 1..GRPIC_MAX_SPECIES                                 */
     int32_t init_covariant; /* 0: uniform contravariant B0 (paper); 1: covariant    */
+    int32_t rk_mode;        /* GRPIC_RK_* (FP64 only; CLASSIC otherwise)            */
+    int32_t gather_mode;    /* GRPIC_GATHER_* (FP64 only; STAGE otherwise)          */
     double c, dt;           /* speed of light and time step                        */
     double m, a;            /* hole mass and spin parameter, |a| <= m               */
     double center[3];       /* hole position in node coordinates                   */
@@ -96,12 +110,17 @@ typedef struct grpic_s grpic_t;
 /* Fill *cfg with the defaults for an nx x ny x nz grid: c = 1, dt = 0.5,
  * m = a = 0, centre at the grid centre, r_rm = 1.1 r_+, r_exc = 0.5 r_+,
  * r_damp = r_+, damp_max = 0.1, field_iters = 3, sort_every = 10, tile = 8,
- * fp_bits = 44, FP64, PAPER gamma, CURVED deposit, one species (-1, 1). */
+ * fp_bits = 44, FP64, PAPER gamma, CURVED deposit, CLASSIC RK, STAGE gather,
+ * one species (-1, 1). */
 void grpic_config_default(grpic_config *cfg, int32_t nx, int32_t ny, int32_t nz);
+
+/* sizeof(grpic_config) as this library was built, so bindings can check
+ * their copy of the layout. */
+size_t grpic_config_size(void);
 
 /* Create a run.  Validates the configuration (grid >= 4 cells per axis,
  * 0 <= |a| <= m, c > 0, dt > 0, Courant c dt < 1/sqrt(3), r_exc < r_rm,
- * masses > 0) and initialises the fields (Sec. 6: uniform contravariant
+ * masses > 0, rk_mode and gather_mode at their defaults unless FP64) and initialises the fields (Sec. 6: uniform contravariant
  * field).  stream is a hipStream_t (NULL: the null stream).
  * Returns GRPIC_EINVAL, GRPIC_ENOMEM or GRPIC_EDEVICE on failure. */
 int grpic_create(const grpic_config *cfg, void *stream, grpic_t **out);

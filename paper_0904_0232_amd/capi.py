@@ -19,6 +19,8 @@ DEAD = 0xFF
 FP64, FP32_MIXED = 0, 1
 GAMMA_PAPER, GAMMA_U4 = 0, 1
 DEPOSIT_CURVED, DEPOSIT_FLAT = 0, 1
+RK_CLASSIC, RK_PRINTED = 0, 1
+GATHER_STAGE, GATHER_STEP = 0, 1
 
 ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
 FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
@@ -31,6 +33,7 @@ class Config(ctypes.Structure):
         ("deposit_mode", ctypes.c_int32), ("field_iters", ctypes.c_int32),
         ("sort_every", ctypes.c_int32), ("tile", ctypes.c_int32), ("fp_bits", ctypes.c_int32),
         ("nspecies", ctypes.c_int32), ("init_covariant", ctypes.c_int32),
+        ("rk_mode", ctypes.c_int32), ("gather_mode", ctypes.c_int32),
         ("c", ctypes.c_double), ("dt", ctypes.c_double),
         ("m", ctypes.c_double), ("a", ctypes.c_double),
         ("center", ctypes.c_double * 3),
@@ -68,6 +71,7 @@ class GrpicError(RuntimeError):
         self.code = code
 
 
+EINVAL = -1
 EAGAIN = -6
 RUN_UNKNOWN, RUN_ACTIVE, RUN_DONE = 0, 1, 2
 
@@ -91,6 +95,11 @@ def lib():
         L = ctypes.CDLL(LIB_PATH)
         L.grpic_config_default.argtypes = [ctypes.POINTER(Config), ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]
         L.grpic_config_default.restype = None
+        L.grpic_config_size.argtypes = []
+        L.grpic_config_size.restype = ctypes.c_size_t
+        if L.grpic_config_size() != ctypes.sizeof(Config):
+            raise GrpicError("grpic_config layout mismatch: library %d bytes, binding %d"
+                             % (L.grpic_config_size(), ctypes.sizeof(Config)))
         L.grpic_create.argtypes = [ctypes.POINTER(Config), ctypes.c_void_p, ctypes.POINTER(_H)]
         L.grpic_load_particles.argtypes = [_H, ctypes.c_int32, ctypes.c_int64, _D, _D, _I64]
         L.grpic_step.argtypes = [_H, ctypes.c_int32]

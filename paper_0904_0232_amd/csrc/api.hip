@@ -167,6 +167,11 @@ int validate(const grpic_config *c) {
     if (c->precision != GRPIC_FP64 && c->precision != GRPIC_FP32_MIXED) return GRPIC_EINVAL;
     if (c->gamma_mode != GRPIC_GAMMA_PAPER && c->gamma_mode != GRPIC_GAMMA_U4) return GRPIC_EINVAL;
     if (c->deposit_mode != GRPIC_DEPOSIT_CURVED && c->deposit_mode != GRPIC_DEPOSIT_FLAT) return GRPIC_EINVAL;
+    if (c->rk_mode != GRPIC_RK_CLASSIC && c->rk_mode != GRPIC_RK_PRINTED) return GRPIC_EINVAL;
+    if (c->gather_mode != GRPIC_GATHER_STAGE && c->gather_mode != GRPIC_GATHER_STEP) return GRPIC_EINVAL;
+    // the push ablations exist in the FP64 pusher only
+    if (c->precision != GRPIC_FP64 && (c->rk_mode != GRPIC_RK_CLASSIC || c->gather_mode != GRPIC_GATHER_STAGE))
+        return GRPIC_EINVAL;
     if (c->field_iters < 1 || c->field_iters > 16) return GRPIC_EINVAL;
     if (c->sort_every < 0 || c->tile < 1 || c->tile > 64) return GRPIC_EINVAL;
     if (c->fp_bits < 16 || c->fp_bits > 50) return GRPIC_EINVAL;
@@ -298,6 +303,8 @@ PushParams push_params(grpic_t *h) {
     P.dt_2c = h->cfg.dt / (2.0 * h->cfg.c);
     P.dt_6 = h->cfg.dt / 6.0;
     P.gamma_mode = h->cfg.gamma_mode;
+    P.rk_mode = h->cfg.rk_mode;
+    P.gather_mode = h->cfg.gather_mode;
     P.n = h->n_slots;
     return P;
 }
@@ -789,6 +796,8 @@ void grpic_config_default(grpic_config *cfg, int32_t nx, int32_t ny, int32_t nz)
     cfg->charge[0] = -1.0;
     cfg->mass[0] = 1.0;
 }
+
+size_t grpic_config_size(void) { return sizeof(grpic_config); }
 
 const char *grpic_strerror(int code) {
     switch (code) {

@@ -84,6 +84,8 @@ struct PushParams {
     double dt_2c;        // dt / (2 c)
     double dt_6;         // dt / 6
     int gamma_mode;
+    int rk_mode;      // GRPIC_RK_* (FP64 pusher only)
+    int gather_mode;  // GRPIC_GATHER_* (FP64 pusher only)
     int64_t n;  // slots to process
 };
 

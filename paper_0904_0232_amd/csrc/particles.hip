@@ -230,11 +230,133 @@ __global__ __launch_bounds__(kPushBlock, 4) void k_push(PushParams P, Species cS
     if (clamps) atomicAdd(&counters[C_GAMMA_CLAMPS], (unsigned long long)clamps);
 }
 
+// ---------------------------------------------------------------------------
+// Push ablations (FP64, Sec. 3.3 readings): the printed RK steps taken
+// literally (RK = 1) and the field tensor gathered once at x_n for all four
+// stages (GATHER = 1).  They exist to measure the readings, so they gather
+// from global memory without the LDS box.
+
+// F^a_b at X, trilinear from the nodes of cell c (row a at 4a .. 4a+3).
+__device__ __forceinline__ void gather_tensor(const Grid &G, const double *__restrict__ node, const int c[3],
+                                              const double X[3], double F[16]) {
+    double w[3];
+    for (int ax = 0; ax < 3; ax++) w[ax] = X[ax] - (double)c[ax];
+    for (int q = 0; q < 16; q++) F[q] = 0.0;
+    for (int dk = 0; dk < 2; dk++)
+        for (int dj = 0; dj < 2; dj++)
+            for (int di = 0; di < 2; di++) {
+                const double W = (di ? w[0] : 1.0 - w[0]) * (dj ? w[1] : 1.0 - w[1]) * (dk ? w[2] : 1.0 - w[2]);
+                const double *src = node + 16 * G.node(c[0] + di, c[1] + dj, c[2] + dk);
+                for (int q = 0; q < 16; q++) F[q] += W * src[q];
+            }
+}
+
+// du^a/dtau at (X, U) with the field tensor gathered at X (GATHER = 0) or
+// the one gathered at x_n (F0, GATHER = 1); Christoffel symbols at X.
+template <int GATHER>
+__device__ __forceinline__ void accel_ablation(const PushParams &P, const double *__restrict__ node,
+                                               const double F0[16], double qm, const double X[3], const double U[4],
+                                               double A[4]) {
+    double F[16];
+    if (GATHER == 1) {
+        for (int q = 0; q < 16; q++) F[q] = F0[q];
+    } else {
+        int c[3];
+        gather_cell(P.G, X, c);
+        gather_tensor(P.G, node, c, X, F);
+    }
+    double Gm[4] = {0.0, 0.0, 0.0, 0.0};
+    if (P.h.m != 0.0) {
+        KSGrad kp;
+        ks_grad(P.h.m, P.h.a, X[0] - P.h.cx, X[1] - P.h.cy, X[2] - P.h.cz, kp);
+        gamma_uu(kp, U, Gm);
+    }
+    for (int a = 0; a < 4; a++)
+        A[a] = qm * (F[4 * a] * U[0] + F[4 * a + 1] * U[1] + F[4 * a + 2] * U[2] + F[4 * a + 3] * U[3]) - Gm[a];
+}
+
+template <int RK, int GATHER>
+__global__ __launch_bounds__(kPushBlock) void k_push_ablation(PushParams P, Species cS,
+                                                              const double *__restrict__ node, ParticlePtrs in,
+                                                              ParticlePtrs out, unsigned long long *counters) {
+    const int tid = threadIdx.x;
+    const int64_t id = (int64_t)blockIdx.x * kPushBlock + tid;
+    const uint8_t sp = id < P.n ? in.sp[id] : kDead;
+    const bool live = sp != kDead;
+    const unsigned long long ballot = __ballot(live);
+    if ((tid & 63) == 0 && ballot)
+        atomicAdd(&counters[pushed_index(blockIdx.x)], (unsigned long long)__popcll(ballot));
+    if (!live) return;
+    int clamps = 0;
+    const double qm = cS.qm[sp];
+    double X0[3], U0[4];
+    for (int q = 0; q < 3; q++) X0[q] = in.x[q][id];
+    for (int q = 0; q < 4; q++) U0[q] = in.u[q][id];
+    double F0[16];
+    if (GATHER == 1) {
+        int c0[3];
+        gather_cell(P.G, X0, c0);
+        gather_tensor(P.G, node, c0, X0, F0);
+    }
+    double Sx[3] = {0.0, 0.0, 0.0}, Su[4] = {0.0, 0.0, 0.0, 0.0};
+    if (RK == 0) {
+        // the default reading (as k_push): slopes (u_k, A_k)/gamma_k
+        double Xs[3] = {X0[0], X0[1], X0[2]}, Us[4] = {U0[0], U0[1], U0[2], U0[3]};
+        for (int st = 0; st < 4; st++) {
+            double A[4];
+            accel_ablation<GATHER>(P, node, F0, qm, Xs, Us, A);
+            const double ig = 1.0 / stage_gamma(P, Us[3], A[3], clamps);
+            const double wgt = (st == 0 || st == 3) ? 1.0 : 2.0;
+            for (int q = 0; q < 3; q++) Sx[q] += wgt * (Us[q] * ig);
+            for (int q = 0; q < 4; q++) Su[q] += wgt * (A[q] * ig);
+            if (st < 3) {
+                const double fac = (st < 2 ? 0.5 : 1.0) * P.dt;
+                for (int q = 0; q < 3; q++) Xs[q] = X0[q] + fac * (Us[q] * ig);
+                for (int q = 0; q < 4; q++) Us[q] = U0[q] + fac * (A[q] * ig);
+            }
+        }
+        for (int q = 0; q < 3; q++) out.x[q][id] = X0[q] + P.dt_6 * Sx[q];
+        for (int q = 0; q < 4; q++) out.u[q][id] = U0[q] + P.dt_6 * Su[q];
+    } else {
+        // the printed steps: averaged stage velocities ut_k = (u_n + u_k)/2,
+        // x_k = x_n + ut_k dtau_{k-1}, dtau = dt/2g, dt/g, dt/g, dt/2g,
+        // u_{k+1} = u_n + a_k dtau_k; sums 1:2:2:1 over 6 added to x_n, u_n
+        double ut[4] = {U0[0], U0[1], U0[2], U0[3]}, uk[4] = {U0[0], U0[1], U0[2], U0[3]};
+        double xk[3] = {X0[0], X0[1], X0[2]};
+        double dtau_prev = 0.0;
+        for (int st = 0; st < 4; st++) {
+            if (st > 0) {
+                for (int q = 0; q < 4; q++) ut[q] = 0.5 * (U0[q] + uk[q]);
+                for (int q = 0; q < 3; q++) xk[q] = X0[q] + ut[q] * dtau_prev;
+            }
+            double A[4];
+            accel_ablation<GATHER>(P, node, F0, qm, xk, ut, A);
+            const double gam = stage_gamma(P, ut[3], A[3], clamps);
+            const double dtau = (st == 0 || st == 3) ? P.dt / (2.0 * gam) : P.dt / gam;
+            const double wgt = (st == 0 || st == 3) ? 1.0 : 2.0;
+            for (int q = 0; q < 3; q++) Sx[q] += wgt * (ut[q] * dtau);
+            for (int q = 0; q < 4; q++) Su[q] += wgt * (A[q] * dtau);
+            for (int q = 0; q < 4; q++) uk[q] = U0[q] + A[q] * dtau;
+            dtau_prev = dtau;
+        }
+        for (int q = 0; q < 3; q++) out.x[q][id] = X0[q] + Sx[q] / 6.0;
+        for (int q = 0; q < 4; q++) out.u[q][id] = U0[q] + Su[q] / 6.0;
+    }
+    if (clamps) atomicAdd(&counters[C_GAMMA_CLAMPS], (unsigned long long)clamps);
+}
+
 void launch_push(const PushParams &P, const Species &S, const double *node, ParticlePtrs in, ParticlePtrs out,
                  unsigned long long *counters, hipStream_t s) {
     if (P.n <= 0) return;
     unsigned nb = (unsigned)((P.n + kPushBlock - 1) / kPushBlock);
-    hipLaunchKernelGGL(k_push, dim3(nb), dim3(kPushBlock), 0, s, P, S, node, in, out, counters);
+    if (P.rk_mode == 0 && P.gather_mode == 0)
+        hipLaunchKernelGGL(k_push, dim3(nb), dim3(kPushBlock), 0, s, P, S, node, in, out, counters);
+    else if (P.rk_mode == 0)
+        hipLaunchKernelGGL((k_push_ablation<0, 1>), dim3(nb), dim3(kPushBlock), 0, s, P, S, node, in, out, counters);
+    else if (P.gather_mode == 0)
+        hipLaunchKernelGGL((k_push_ablation<1, 0>), dim3(nb), dim3(kPushBlock), 0, s, P, S, node, in, out, counters);
+    else
+        hipLaunchKernelGGL((k_push_ablation<1, 1>), dim3(nb), dim3(kPushBlock), 0, s, P, S, node, in, out, counters);
 }
 
 // ---------------------------------------------------------------------------

@@ -59,6 +59,9 @@ def test_binding_struct_layouts_follow_header():
     assert (cfg.nx, cfg.ny, cfg.nz) == (16, 20, 24)
     assert cfg.field_iters == 3 and cfg.fp_bits == 44 and cfg.c == 1.0
     assert list(cfg.center) == [8.0, 10.0, 12.0]
+    assert cfg.rk_mode == capi.RK_CLASSIC and cfg.gather_mode == capi.GATHER_STAGE
+    L.grpic_config_size.restype = ctypes.c_size_t
+    assert L.grpic_config_size() == ctypes.sizeof(capi.Config)
 
 
 def test_strerror_codes():
