@@ -34,7 +34,7 @@ class Params(ctypes.Structure):
         ("gamma_mode", ctypes.c_int32), ("deposit_mode", ctypes.c_int32),
         ("nspecies", ctypes.c_int32),
         ("field_iters", ctypes.c_int32), ("rk_mode", ctypes.c_int32),
-        ("gather_mode", ctypes.c_int32), ("pad_", ctypes.c_int32),
+        ("gather_mode", ctypes.c_int32), ("gather_weights", ctypes.c_int32),
         ("c", ctypes.c_double), ("dt", ctypes.c_double),
         ("m", ctypes.c_double), ("a", ctypes.c_double),
         ("center", ctypes.c_double * 3),
@@ -82,6 +82,9 @@ def lib():
         L.or_metric_deriv.argtypes = [_P, ctypes.c_double, ctypes.c_double, ctypes.c_double, _D]
         L.or_christoffel.argtypes = [_P, ctypes.c_double, ctypes.c_double, ctypes.c_double, _D]
         L.or_gather.argtypes = [_P, _D, _D, _D]
+        L.or_gather_weights.argtypes = [_P, ctypes.POINTER(ctypes.c_int), _D, _D]
+        L.or_spatial_density.restype = ctypes.c_double
+        L.or_spatial_density.argtypes = [_P, ctypes.c_double, ctypes.c_double, ctypes.c_double]
         L.or_mass_shell.argtypes = [_P, _D, _D, _D]
         L.or_sim_new.restype = ctypes.c_void_p
         L.or_sim_new.argtypes = [_P, ctypes.c_int64]
@@ -128,17 +131,18 @@ def _f64(a):
 def make_params(nx, ny=None, nz=None, *, c=1.0, dt=0.5, m=0.0, a=0.0, center=None,
                 r_rm=None, r_exc=None, gamma_mode=0, deposit_mode=0,
                 field_iters=3, r_damp=None, damp_max=0.1, species=((-1.0, 1.0),),
-                rk_mode=0, gather_mode=0):
+                rk_mode=0, gather_mode=0, gather_weights=0):
     """species: sequence of (macro charge, macro mass).  rk_mode 1 takes the
-    printed RK steps literally, gather_mode 1 gathers the fields once at x_n
-    (both ablations of the default readings)."""
+    printed RK steps literally, gather_mode 1 gathers the fields once at x_n,
+    gather_weights 1 weights the gather by the spatial volume (all ablations
+    of the default readings)."""
     ny = nx if ny is None else ny
     nz = nx if nz is None else nz
     p = Params()
     p.nx, p.ny, p.nz = nx, ny, nz
     p.gamma_mode, p.deposit_mode = gamma_mode, deposit_mode
     p.field_iters = field_iters
-    p.rk_mode, p.gather_mode = rk_mode, gather_mode
+    p.rk_mode, p.gather_mode, p.gather_weights = rk_mode, gather_mode, gather_weights
     p.c, p.dt, p.m, p.a = c, dt, m, a
     cen = (nx / 2.0, ny / 2.0, nz / 2.0) if center is None else center
     for i in range(3):
@@ -153,6 +157,18 @@ def make_params(nx, ny=None, nz=None, *, c=1.0, dt=0.5, m=0.0, a=0.0, center=Non
         p.charge[i] = q
         p.mass[i] = mass
     return p
+
+
+def gather_weights(p, c, X):
+    """The 8 cloud-in-cell weights (index di + 2 dj + 4 dk) of cell c at X."""
+    ci = (ctypes.c_int * 3)(*[int(v) for v in c])
+    W = np.zeros(8)
+    lib().or_gather_weights(ctypes.byref(p), ci, _dp(np.ascontiguousarray(X, dtype=float)), _dp(W))
+    return W
+
+
+def spatial_density(p, x, y, z):
+    return lib().or_spatial_density(ctypes.byref(p), x, y, z)
 
 
 def radius(a, x, y, z):

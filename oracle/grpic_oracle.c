@@ -48,7 +48,7 @@ typedef struct {
     int32_t field_iters;  /* evaluations of the constitutive map per half-cycle  */
     int32_t rk_mode;      /* 0: classic RK4 reading; 1: the printed steps        */
     int32_t gather_mode;  /* 0: fields at every stage; 1: at x_n for all stages  */
-    int32_t pad_;
+    int32_t gather_weights; /* 0: trilinear (4-volume, det g = -1); 1: spatial volume */
     double c, dt;
     double m, a;          /* hole mass and spin parameter, in cells              */
     double center[3];     /* hole position in node coordinates                   */
@@ -768,26 +768,72 @@ static void compute_nodes(or_sim *s)
  * and the fractional offset is not clamped, so a stage position just
  * outside the grid extrapolates linearly.  Pinned: weights sum to one and
  * a linear field is reproduced exactly. */
+/* Spatial volume density sqrt(det g_ij), i, j = 1..3, at a hole-relative
+ * point: the determinant of the spatial block of the metric, written out;
+ * 1 inside the excision radius (those points are flat, as in the field
+ * solve).  Used by gather reading B only. */
+double or_spatial_density(const or_params *p, double x, double y, double z)
+{
+    if (p->m == 0.0) return 1.0;
+    double g[16], r;
+    or_metric(p, x, y, z, g, NULL, &r);
+    if (r < p->r_exc) return 1.0;
+    double det = g[0] * (g[5] * g[10] - g[6] * g[9]) - g[1] * (g[4] * g[10] - g[6] * g[8]) +
+                 g[2] * (g[4] * g[9] - g[5] * g[8]);
+    return sqrt(det);
+}
+
+/* Cloud-in-cell weights of the 8 nodes of cell c for a particle at X.
+ * gather_weights 0: the sub-volume opposite each node with the 4-metric
+ * density sqrt(-det g) = 1, i.e. the trilinear weights.  gather_weights 1
+ * (reading B, an ablation): the sub-volume weighted by the spatial density
+ * sqrt(det g_ij) at its centre (midpoint rule), normalised by the sum.
+ * Pinned: reading B equals trilinear at m = 0, sums to one, keeps a
+ * constant field, is mirror symmetric where the density is, and its
+ * sub-volumes approach a high-order quadrature at second order. */
+void or_gather_weights(const or_params *p, const int c[3], const double X[3], double W[8])
+{
+    double sum = 0.0;
+    for (int dk = 0; dk < 2; dk++)
+        for (int dj = 0; dj < 2; dj++)
+            for (int di = 0; di < 2; di++) {
+                /* the sub-volume opposite the node spans [X, c+1] on axes
+                 * where the node is at c and [c, X] where it is at c+1 */
+                int d[3] = {di, dj, dk};
+                double w[3], mid[3];
+                for (int ax = 0; ax < 3; ax++) {
+                    w[ax] = X[ax] - (double)c[ax];
+                    mid[ax] = d[ax] ? 0.5 * ((double)c[ax] + X[ax]) : 0.5 * (X[ax] + (double)c[ax] + 1.0);
+                }
+                double V = (di ? w[0] : 1.0 - w[0]) * (dj ? w[1] : 1.0 - w[1]) * (dk ? w[2] : 1.0 - w[2]);
+                if (p->gather_weights == 1)
+                    V *= or_spatial_density(p, mid[0] - p->center[0], mid[1] - p->center[1],
+                                            mid[2] - p->center[2]);
+                W[di + 2 * dj + 4 * dk] = V;
+                sum += V;
+            }
+    if (p->gather_weights == 1)
+        for (int n = 0; n < 8; n++) W[n] /= sum;
+}
+
 void or_gather(const or_params *p, const double *node, const double X[3], double Fo[16])
 {
     int c[3];
-    double w[3];
     for (int ax = 0; ax < 3; ax++) {
         int n = ndim(p, ax);
         int ci = (int)floor(X[ax]);
         if (ci < 0) ci = 0;
         if (ci > n - 1) ci = n - 1;
         c[ax] = ci;
-        w[ax] = X[ax] - (double)ci;
     }
+    double W[8];
+    or_gather_weights(p, c, X, W);
     for (int q = 0; q < 16; q++) Fo[q] = 0.0;
     for (int dk = 0; dk < 2; dk++)
         for (int dj = 0; dj < 2; dj++)
             for (int di = 0; di < 2; di++) {
-                double W = (di ? w[0] : 1.0 - w[0]) * (dj ? w[1] : 1.0 - w[1]) *
-                           (dk ? w[2] : 1.0 - w[2]);
                 const double *src = node + 16 * nidx(p, c[0] + di, c[1] + dj, c[2] + dk);
-                for (int q = 0; q < 16; q++) Fo[q] += W * src[q];
+                for (int q = 0; q < 16; q++) Fo[q] += W[di + 2 * dj + 4 * dk] * src[q];
             }
 }
 

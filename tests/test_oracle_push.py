@@ -288,3 +288,101 @@ def test_per_step_gather_is_rk4_of_the_field_frozen_at_x_n():
     # the per-stage gather sees B change within the step: a different orbit
     x0N, u0N, _ = out[0]
     assert abs(u0N[0, 0] + 1j * u0N[1, 0] - w) > 1e-9
+
+
+# --- gather reading B (gather_weights 1): CIC sub-volumes weighted by the
+# spatial volume density sqrt(det g_ij) by the midpoint rule ----------------
+
+def _ks_f(m, a, x, y, z):
+    # textbook Kerr-Schild f = 2 m r^3 / (r^4 + a^2 z^2), r from the quartic
+    b = x * x + y * y + z * z - a * a
+    r2 = 0.5 * (b + np.sqrt(b * b + 4 * a * a * z * z))
+    r = np.sqrt(r2)
+    return 2 * m * r * r2 / (r2 * r2 + a * a * z * z)
+
+
+def test_spatial_density_is_sqrt_one_plus_f():
+    # det(delta_ij + f k_i k_j) = 1 + f |k|^2 and |k|^2 = 1 for the null k
+    p = O.make_params(16, m=1.5, a=1.2, r_exc=0.0)
+    rng = np.random.default_rng(11)
+    for _ in range(200):
+        x, y, z = rng.uniform(-7, 7, 3)
+        if x * x + y * y + z * z < 4.0:
+            continue
+        assert abs(O.spatial_density(p, x, y, z) - np.sqrt(1 + _ks_f(1.5, 1.2, x, y, z))) < 1e-14
+
+
+def test_gather_reading_b_reduces_to_trilinear_at_m0():
+    pa = O.make_params(16, m=0.0, gather_weights=1)
+    pb = O.make_params(16, m=0.0, gather_weights=0)
+    rng = np.random.default_rng(12)
+    for _ in range(100):
+        X = rng.uniform(0, 15.999, 3)
+        c = np.floor(X)
+        Wa, Wb = O.gather_weights(pa, c, X), O.gather_weights(pb, c, X)
+        w = X - c
+        tri = np.array([(1 - w[0] if (n & 1) == 0 else w[0]) * (1 - w[1] if (n & 2) == 0 else w[1])
+                        * (1 - w[2] if (n & 4) == 0 else w[2]) for n in range(8)])
+        assert np.abs(Wb - tri).max() == 0.0
+        assert np.abs(Wa - tri).max() < 1e-15
+
+
+def test_gather_reading_b_unity_constant_field_and_mirror_symmetry():
+    N = 16
+    p = O.make_params(N, m=1.5, a=1.2, gather_weights=1)
+    rng = np.random.default_rng(13)
+    nodes = np.broadcast_to(rng.normal(size=16), ((N + 1) ** 3, 16)).copy()
+    import ctypes
+    flat = np.ascontiguousarray(nodes.reshape(-1))
+    for _ in range(100):
+        X = rng.uniform(2, 13.999, 3)
+        W = O.gather_weights(p, np.floor(X), X)
+        assert abs(W.sum() - 1.0) < 1e-15
+        out = np.zeros(16)
+        O.lib().or_gather(ctypes.byref(p), O._dp(flat), O._dp(np.ascontiguousarray(X)), O._dp(out))
+        assert np.abs(out - nodes[0]).max() < 1e-14 * np.abs(nodes[0]).max()
+    # Schwarzschild: the density is symmetric under y -> 2 c_y - y, so the
+    # mirrored particle's weights are the mirrored nodes' weights
+    ps = O.make_params(N, m=1.5, a=0.0, gather_weights=1)
+    for _ in range(50):
+        X = rng.uniform(3, 12.999, 3)
+        Xm = X.copy()
+        Xm[1] = N - X[1]
+        W, Wm = O.gather_weights(ps, np.floor(X), X), O.gather_weights(ps, np.floor(Xm), Xm)
+        perm = [n ^ 2 for n in range(8)]  # dj -> 1 - dj
+        assert np.abs(Wm - W[perm]).max() < 1e-14
+
+
+def test_gather_reading_b_sub_volumes_match_quadrature():
+    # near the hole (R 4..8 cells) the midpoint rule differs from a 5-point
+    # Gauss-Legendre integral of sqrt(1 + f) over each sub-volume by its own
+    # O(h^2) error (< 2e-3 of the weights); a density taken half a cell
+    # away would be off by ~1e-2
+    m, a, N = 1.5, 1.2, 16
+    p = O.make_params(N, m=m, a=a, gather_weights=1, r_exc=0.0)
+    cen = np.array([N / 2.0] * 3)
+    gx, gw = np.polynomial.legendre.leggauss(5)
+    rng = np.random.default_rng(14)
+    worst = 0.0
+    done = 0
+    while done < 60:
+        X = cen + rng.uniform(-8, 8, 3)
+        R = np.linalg.norm(X - cen)
+        if not (4.0 < R < 8.0):
+            continue
+        c = np.floor(X)
+        W = O.gather_weights(p, c, X)
+        V = np.zeros(8)
+        for n in range(8):
+            d = [(n >> ax) & 1 for ax in range(3)]
+            lo = np.array([c[ax] if d[ax] else X[ax] for ax in range(3)])
+            hi = np.array([X[ax] if d[ax] else c[ax] + 1 for ax in range(3)])
+            pts = [0.5 * (lo[ax] + hi[ax]) + 0.5 * (hi[ax] - lo[ax]) * gx for ax in range(3)]
+            wts = [0.5 * (hi[ax] - lo[ax]) * gw for ax in range(3)]
+            PX, PY, PZ = np.meshgrid(*pts, indexing="ij")
+            WW = wts[0][:, None, None] * wts[1][None, :, None] * wts[2][None, None, :]
+            V[n] = (WW * np.sqrt(1 + _ks_f(m, a, PX - cen[0], PY - cen[1], PZ - cen[2]))).sum()
+        ref = V / V.sum()
+        worst = max(worst, np.abs(W - ref).max())
+        done += 1
+    assert worst < 2e-3, worst
