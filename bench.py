@@ -271,15 +271,16 @@ def serving(args):
 
 def ablation_study(workload="kerr64", per_species=131072, T=8.0, dts=(0.4, 0.2, 0.1, 0.05), timing_steps=10):
     """The push readings side by side (FP64): the stage gamma (PAPER estimate
-    or u^4/c), the RK structure (CLASSIC reading or the steps as PRINTED)
-    and where the field tensor is gathered (every STAGE or once per STEP).
+    or u^4/c), the RK structure (CLASSIC reading or the steps as PRINTED),
+    where the field tensor is gathered (every STAGE or once per STEP) and
+    the gather weights (TRILINEAR, or SPATIAL: reading B).
     For each: the observed order in coordinate time of test particles in the
     workload's frozen initial fields (positions at time T for the step sizes
     dts; order = log2 of the median ratio of successive differences, over
     particles that stay finite, inside the grid and outside R = 3m in every
-    run), the distance of the finest solution from the U4 / CLASSIC / STAGE
-    one (consistency: a scheme can converge to the wrong path) and the push
-    kernel time per launch on the whole workload.  Also
+    run), the distance of the finest solution from the U4 / CLASSIC /
+    STAGE / TRILINEAR one (consistency: a scheme can converge to the wrong
+    path) and the push kernel time per launch on the whole workload.  Also
     the Gauss-law residual after 20 cycles with CURVED and FLAT deposition
     (only FLAT conserves charge exactly)."""
     import numpy as np
@@ -294,59 +295,66 @@ def ablation_study(workload="kerr64", per_species=131072, T=8.0, dts=(0.4, 0.2, 
     ntot = sum(x.shape[1] for _, x, _ in parts)
     cen = np.full(3, w["n"] / 2.0)
 
-    def cfg(dt, gm, rk, ga, cap, sort_every=0, deposit_mode=capi.DEPOSIT_CURVED):
+    def cfg(dt, gm, rk, ga, wt, cap, sort_every=0, deposit_mode=capi.DEPOSIT_CURVED):
         return R.make_config(w["n"], m=w["m"], a=w["a"], dt=dt, B0=(0.0, 0.0, w["B0"]), species=w["species"],
                              r_rm=w["r_rm"], sort_every=sort_every, capacity=cap, gamma_mode=gm, rk_mode=rk,
-                             gather_mode=ga, deposit_mode=deposit_mode)
+                             gather_mode=ga, gather_weights=wt, deposit_mode=deposit_mode)
 
+    G = {"PAPER": capi.GAMMA_PAPER, "U4": capi.GAMMA_U4}
+    K = {"CLASSIC": capi.RK_CLASSIC, "PRINTED": capi.RK_PRINTED}
+    A = {"STAGE": capi.GATHER_STAGE, "STEP": capi.GATHER_STEP}
+    Wt = {"TRILINEAR": capi.WEIGHTS_TRILINEAR, "SPATIAL": capi.WEIGHTS_SPATIAL}
+    ref = ("U4", "CLASSIC", "STAGE", "TRILINEAR")  # first: the others are compared with it
+    combos = [ref, ("U4", "CLASSIC", "STEP", "TRILINEAR"), ("U4", "PRINTED", "STAGE", "TRILINEAR"),
+              ("U4", "CLASSIC", "STAGE", "SPATIAL"), ("PAPER", "CLASSIC", "STAGE", "TRILINEAR"),
+              ("PAPER", "CLASSIC", "STEP", "TRILINEAR"), ("PAPER", "PRINTED", "STAGE", "TRILINEAR"),
+              ("PAPER", "PRINTED", "STEP", "TRILINEAR"), ("PAPER", "CLASSIC", "STAGE", "SPATIAL")]
     out = {"workload": workload, "test_particles": nsub, "T": T, "dts": list(dts), "readings": {}}
     finest = {}
-    for gm, gname in ((capi.GAMMA_U4, "U4"), (capi.GAMMA_PAPER, "PAPER")):
-        for rk, rname in ((capi.RK_CLASSIC, "CLASSIC"), (capi.RK_PRINTED, "PRINTED")):
-            for ga, aname in ((capi.GATHER_STAGE, "STAGE"), (capi.GATHER_STEP, "STEP")):
-                xs = []
-                for dt in dts:
-                    r = R.Run(cfg(dt, gm, rk, ga, nsub))
-                    for sp, x, uc in sub:
-                        r.load(sp, x, uc)
-                    r.push_only(int(round(T / dt)))
-                    xs.append(r.particles()[0])
-                    r.close()
-                ok = np.ones(xs[0].shape[1], bool)
-                for x in xs:
-                    ok &= np.isfinite(x).all(axis=0) & (x >= 0).all(axis=0) & (x <= w["n"]).all(axis=0)
-                    ok &= np.linalg.norm(x - cen[:, None], axis=0) > 3.0 * w["m"]
-                d = [np.abs(xs[i] - xs[i + 1]).max(axis=0)[ok] for i in range(len(xs) - 1)]
-                keep = d[-1] > 1e-13
-                ratio = np.median(d[-2][keep] / d[-1][keep]) if keep.any() else float("nan")
-                name = "gamma_%s/rk_%s/gather_%s" % (gname, rname, aname)
-                entry = {"order": float(np.log2(ratio)), "particles": int(ok.sum()),
-                         "median_diff_dt%g_vs_dt%g" % (dts[0], dts[1]): float(np.median(d[0])),
-                         "median_diff_dt%g_vs_dt%g" % (dts[-2], dts[-1]): float(np.median(d[-1]))}
-                # consistency: the finest solution against the U4 / CLASSIC /
-                # STAGE one (fourth order in smooth fields), which runs first
-                finest[name] = (xs[-1], ok)
-                xr, okr = finest["gamma_U4/rk_CLASSIC/gather_STAGE"]
-                both = ok & okr
-                entry["median_diff_vs_U4_CLASSIC_STAGE_at_dt%g" % dts[-1]] = float(
-                    np.median(np.abs(xs[-1] - xr).max(axis=0)[both]))
-                if gm == capi.GAMMA_PAPER:
-                    r = R.Run(cfg(w["dt"], gm, rk, ga, ntot, sort_every=5))
-                    for sp, x, uc in parts:
-                        r.load(sp, x, uc)
-                    capi.grpic_step(r.h, 10)
-                    capi.grpic_set_timing(r.h, True)
-                    capi.grpic_read_timing(r.h)
-                    capi.grpic_step(r.h, timing_steps)
-                    torch.cuda.synchronize()
-                    t = capi.grpic_read_timing(r.h)
-                    r.close()
-                    entry["push_ms_per_launch"] = t["push"][0] / max(t["push"][1], 1)
-                out["readings"][name] = entry
-                log("ablation %s: %s" % (name, json.dumps(entry)))
+    for combo in combos:
+        gm, rk, ga, wt = G[combo[0]], K[combo[1]], A[combo[2]], Wt[combo[3]]
+        xs = []
+        for dt in dts:
+            r = R.Run(cfg(dt, gm, rk, ga, wt, nsub))
+            for sp, x, uc in sub:
+                r.load(sp, x, uc)
+            r.push_only(int(round(T / dt)))
+            xs.append(r.particles()[0])
+            r.close()
+        ok = np.ones(xs[0].shape[1], bool)
+        for x in xs:
+            ok &= np.isfinite(x).all(axis=0) & (x >= 0).all(axis=0) & (x <= w["n"]).all(axis=0)
+            ok &= np.linalg.norm(x - cen[:, None], axis=0) > 3.0 * w["m"]
+        d = [np.abs(xs[i] - xs[i + 1]).max(axis=0)[ok] for i in range(len(xs) - 1)]
+        keep = d[-1] > 1e-13
+        ratio = np.median(d[-2][keep] / d[-1][keep]) if keep.any() else float("nan")
+        name = "gamma_%s/rk_%s/gather_%s/weights_%s" % combo
+        entry = {"order": float(np.log2(ratio)), "particles": int(ok.sum()),
+                 "median_diff_dt%g_vs_dt%g" % (dts[0], dts[1]): float(np.median(d[0])),
+                 "median_diff_dt%g_vs_dt%g" % (dts[-2], dts[-1]): float(np.median(d[-1]))}
+        # consistency: the finest solution against the reference one (fourth
+        # order in smooth fields); a scheme can converge to the wrong path
+        finest[combo] = (xs[-1], ok)
+        xr, okr = finest[ref]
+        both = ok & okr
+        entry["median_diff_vs_reference_at_dt%g" % dts[-1]] = float(np.median(np.abs(xs[-1] - xr).max(axis=0)[both]))
+        if combo[0] == "PAPER":
+            r = R.Run(cfg(w["dt"], gm, rk, ga, wt, ntot, sort_every=5))
+            for sp, x, uc in parts:
+                r.load(sp, x, uc)
+            capi.grpic_step(r.h, 10)
+            capi.grpic_set_timing(r.h, True)
+            capi.grpic_read_timing(r.h)
+            capi.grpic_step(r.h, timing_steps)
+            torch.cuda.synchronize()
+            t = capi.grpic_read_timing(r.h)
+            r.close()
+            entry["push_ms_per_launch"] = t["push"][0] / max(t["push"][1], 1)
+        out["readings"][name] = entry
+        log("ablation %s: %s" % (name, json.dumps(entry)))
     for dm, dname in ((capi.DEPOSIT_CURVED, "CURVED"), (capi.DEPOSIT_FLAT, "FLAT")):
-        r = R.Run(cfg(w["dt"], capi.GAMMA_PAPER, capi.RK_CLASSIC, capi.GATHER_STAGE, ntot, sort_every=5,
-                      deposit_mode=dm))
+        r = R.Run(cfg(w["dt"], capi.GAMMA_PAPER, capi.RK_CLASSIC, capi.GATHER_STAGE, capi.WEIGHTS_TRILINEAR, ntot,
+                      sort_every=5, deposit_mode=dm))
         for sp, x, uc in parts:
             r.load(sp, x, uc)
         capi.grpic_step(r.h, 20)

@@ -58,6 +58,12 @@ enum { GRPIC_RK_CLASSIC = 0, GRPIC_RK_PRINTED = 1 };
  * stage position (default); STEP = once at x_n for all four stages (an
  * ablation; the Christoffel symbols stay at the stage positions).  FP64 only. */
 enum { GRPIC_GATHER_STAGE = 0, GRPIC_GATHER_STEP = 1 };
+/* Cloud-in-cell weights of the gather (Sec. 3.3).  TRILINEAR = sub-volumes
+ * with the 4-metric density sqrt(-det g), which is exactly 1 here (the
+ * default reading); SPATIAL = sub-volumes weighted by the spatial density
+ * sqrt(det g_ij) = sqrt(1 + f) at their centres, normalised (reading B, an
+ * ablation).  FP64 only. */
+enum { GRPIC_WEIGHTS_TRILINEAR = 0, GRPIC_WEIGHTS_SPATIAL = 1 };
 
 typedef void *(*grpic_alloc_fn)(size_t bytes, void *ctx);
 typedef void (*grpic_free_fn)(void *ptr, void *ctx);
@@ -75,6 +81,7 @@ typedef struct {
     int32_t init_covariant; /* 0: uniform contravariant B0 (paper); 1: covariant    */
     int32_t rk_mode;        /* GRPIC_RK_* (FP64 only; CLASSIC otherwise)            */
     int32_t gather_mode;    /* GRPIC_GATHER_* (FP64 only; STAGE otherwise)          */
+    int32_t gather_weights; /* GRPIC_WEIGHTS_* (FP64 only; TRILINEAR otherwise)     */
     double c, dt;           /* speed of light and time step                        */
     double m, a;            /* hole mass and spin parameter, |a| <= m               */
     double center[3];       /* hole position in node coordinates                   */
@@ -111,7 +118,7 @@ typedef struct grpic_s grpic_t;
  * m = a = 0, centre at the grid centre, r_rm = 1.1 r_+, r_exc = 0.5 r_+,
  * r_damp = r_+, damp_max = 0.1, field_iters = 3, sort_every = 10, tile = 8,
  * fp_bits = 44, FP64, PAPER gamma, CURVED deposit, CLASSIC RK, STAGE gather,
- * one species (-1, 1). */
+ * TRILINEAR weights, one species (-1, 1). */
 void grpic_config_default(grpic_config *cfg, int32_t nx, int32_t ny, int32_t nz);
 
 /* sizeof(grpic_config) as this library was built, so bindings can check
@@ -120,7 +127,8 @@ size_t grpic_config_size(void);
 
 /* Create a run.  Validates the configuration (grid >= 4 cells per axis,
  * 0 <= |a| <= m, c > 0, dt > 0, Courant c dt < 1/sqrt(3), r_exc < r_rm,
- * masses > 0, rk_mode and gather_mode at their defaults unless FP64) and initialises the fields (Sec. 6: uniform contravariant
+ * masses > 0, rk_mode, gather_mode and gather_weights at their defaults
+ * unless FP64) and initialises the fields (Sec. 6: uniform contravariant
  * field).  stream is a hipStream_t (NULL: the null stream).
  * Returns GRPIC_EINVAL, GRPIC_ENOMEM or GRPIC_EDEVICE on failure. */
 int grpic_create(const grpic_config *cfg, void *stream, grpic_t **out);

@@ -21,6 +21,7 @@ GAMMA_PAPER, GAMMA_U4 = 0, 1
 DEPOSIT_CURVED, DEPOSIT_FLAT = 0, 1
 RK_CLASSIC, RK_PRINTED = 0, 1
 GATHER_STAGE, GATHER_STEP = 0, 1
+WEIGHTS_TRILINEAR, WEIGHTS_SPATIAL = 0, 1
 
 ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
 FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
@@ -33,7 +34,7 @@ class Config(ctypes.Structure):
         ("deposit_mode", ctypes.c_int32), ("field_iters", ctypes.c_int32),
         ("sort_every", ctypes.c_int32), ("tile", ctypes.c_int32), ("fp_bits", ctypes.c_int32),
         ("nspecies", ctypes.c_int32), ("init_covariant", ctypes.c_int32),
-        ("rk_mode", ctypes.c_int32), ("gather_mode", ctypes.c_int32),
+        ("rk_mode", ctypes.c_int32), ("gather_mode", ctypes.c_int32), ("gather_weights", ctypes.c_int32),
         ("c", ctypes.c_double), ("dt", ctypes.c_double),
         ("m", ctypes.c_double), ("a", ctypes.c_double),
         ("center", ctypes.c_double * 3),

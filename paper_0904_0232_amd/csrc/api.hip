@@ -169,8 +169,11 @@ int validate(const grpic_config *c) {
     if (c->deposit_mode != GRPIC_DEPOSIT_CURVED && c->deposit_mode != GRPIC_DEPOSIT_FLAT) return GRPIC_EINVAL;
     if (c->rk_mode != GRPIC_RK_CLASSIC && c->rk_mode != GRPIC_RK_PRINTED) return GRPIC_EINVAL;
     if (c->gather_mode != GRPIC_GATHER_STAGE && c->gather_mode != GRPIC_GATHER_STEP) return GRPIC_EINVAL;
+    if (c->gather_weights != GRPIC_WEIGHTS_TRILINEAR && c->gather_weights != GRPIC_WEIGHTS_SPATIAL)
+        return GRPIC_EINVAL;
     // the push ablations exist in the FP64 pusher only
-    if (c->precision != GRPIC_FP64 && (c->rk_mode != GRPIC_RK_CLASSIC || c->gather_mode != GRPIC_GATHER_STAGE))
+    if (c->precision != GRPIC_FP64 && (c->rk_mode != GRPIC_RK_CLASSIC || c->gather_mode != GRPIC_GATHER_STAGE ||
+                                       c->gather_weights != GRPIC_WEIGHTS_TRILINEAR))
         return GRPIC_EINVAL;
     if (c->field_iters < 1 || c->field_iters > 16) return GRPIC_EINVAL;
     if (c->sort_every < 0 || c->tile < 1 || c->tile > 64) return GRPIC_EINVAL;
@@ -305,6 +308,7 @@ PushParams push_params(grpic_t *h) {
     P.gamma_mode = h->cfg.gamma_mode;
     P.rk_mode = h->cfg.rk_mode;
     P.gather_mode = h->cfg.gather_mode;
+    P.gather_weights = h->cfg.gather_weights;
     P.n = h->n_slots;
     return P;
 }

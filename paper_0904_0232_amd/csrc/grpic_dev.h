@@ -140,6 +140,19 @@ __device__ __forceinline__ double ks_area_density(double m, double a, double r_e
     return N * rsqrt_nr(N * den);
 }
 
+// Spatial volume density sqrt(det g_ij) = sqrt(1 + f) (|k| = 1 for the
+// spatial part of the null k) at a hole-relative point (m > 0), 1 inside
+// r < r_exc: with S4 = r^4 + a^2 z^2 and N = S4 + 2 m r^3 it is
+// sqrt(N / S4) = N / sqrt(N S4).
+__device__ __forceinline__ double ks_volume_density(double m, double a, double r_exc, double x, double y, double z) {
+    double r2;
+    const double r = ks_radius_nr(a, x, y, z, r2);
+    if (r < r_exc) return 1.0;
+    const double S4 = fma(r2, r2, a * a * (z * z));
+    const double N = fma(2.0 * m * r, r2, S4);
+    return N * rsqrt_nr(N * S4);
+}
+
 // f and the spatial part of k at a hole-relative point (m > 0, r > 0).
 template <typename T>
 struct KSPoint {

@@ -86,6 +86,7 @@ struct PushParams {
     int gamma_mode;
     int rk_mode;      // GRPIC_RK_* (FP64 pusher only)
     int gather_mode;  // GRPIC_GATHER_* (FP64 pusher only)
+    int gather_weights;  // GRPIC_WEIGHTS_* (FP64 pusher only)
     int64_t n;  // slots to process
 };
 

@@ -232,28 +232,45 @@ __global__ __launch_bounds__(kPushBlock, 4) void k_push(PushParams P, Species cS
 
 // ---------------------------------------------------------------------------
 // Push ablations (FP64, Sec. 3.3 readings): the printed RK steps taken
-// literally (RK = 1) and the field tensor gathered once at x_n for all four
-// stages (GATHER = 1).  They exist to measure the readings, so they gather
+// literally (RK = 1), the field tensor gathered once at x_n for all four
+// stages (GATHER = 1) and the spatial-volume gather weights (WTS = 1).  They exist to measure the readings, so they gather
 // from global memory without the LDS box.
 
-// F^a_b at X, trilinear from the nodes of cell c (row a at 4a .. 4a+3).
-__device__ __forceinline__ void gather_tensor(const Grid &G, const double *__restrict__ node, const int c[3],
+// F^a_b at X from the nodes of cell c (row a at 4a .. 4a+3): trilinear
+// weights (WTS = 0), or (WTS = 1, reading B) the sub-volume opposite each
+// node, [X, c+1] or [c, X] per axis, times the spatial density at its
+// centre, normalised by their sum.
+template <int WTS>
+__device__ __forceinline__ void gather_tensor(const PushParams &P, const double *__restrict__ node, const int c[3],
                                               const double X[3], double F[16]) {
     double w[3];
     for (int ax = 0; ax < 3; ax++) w[ax] = X[ax] - (double)c[ax];
+    double W[8], sum = 0.0;
+    for (int n = 0; n < 8; n++) {
+        const int di = n & 1, dj = (n >> 1) & 1, dk = n >> 2;
+        W[n] = (di ? w[0] : 1.0 - w[0]) * (dj ? w[1] : 1.0 - w[1]) * (dk ? w[2] : 1.0 - w[2]);
+        if (WTS == 1 && P.h.m != 0.0) {
+            const double mx = di ? 0.5 * ((double)c[0] + X[0]) : 0.5 * (X[0] + (double)c[0] + 1.0);
+            const double my = dj ? 0.5 * ((double)c[1] + X[1]) : 0.5 * (X[1] + (double)c[1] + 1.0);
+            const double mz = dk ? 0.5 * ((double)c[2] + X[2]) : 0.5 * (X[2] + (double)c[2] + 1.0);
+            W[n] *= ks_volume_density(P.h.m, P.h.a, P.h.r_exc, mx - P.h.cx, my - P.h.cy, mz - P.h.cz);
+        }
+        sum += W[n];
+    }
+    if (WTS == 1) {
+        const double inv = 1.0 / sum;
+        for (int n = 0; n < 8; n++) W[n] *= inv;
+    }
     for (int q = 0; q < 16; q++) F[q] = 0.0;
-    for (int dk = 0; dk < 2; dk++)
-        for (int dj = 0; dj < 2; dj++)
-            for (int di = 0; di < 2; di++) {
-                const double W = (di ? w[0] : 1.0 - w[0]) * (dj ? w[1] : 1.0 - w[1]) * (dk ? w[2] : 1.0 - w[2]);
-                const double *src = node + 16 * G.node(c[0] + di, c[1] + dj, c[2] + dk);
-                for (int q = 0; q < 16; q++) F[q] += W * src[q];
-            }
+    for (int n = 0; n < 8; n++) {
+        const double *src = node + 16 * P.G.node(c[0] + (n & 1), c[1] + ((n >> 1) & 1), c[2] + (n >> 2));
+        for (int q = 0; q < 16; q++) F[q] += W[n] * src[q];
+    }
 }
 
 // du^a/dtau at (X, U) with the field tensor gathered at X (GATHER = 0) or
 // the one gathered at x_n (F0, GATHER = 1); Christoffel symbols at X.
-template <int GATHER>
+template <int GATHER, int WTS>
 __device__ __forceinline__ void accel_ablation(const PushParams &P, const double *__restrict__ node,
                                                const double F0[16], double qm, const double X[3], const double U[4],
                                                double A[4]) {
@@ -263,7 +280,7 @@ __device__ __forceinline__ void accel_ablation(const PushParams &P, const double
     } else {
         int c[3];
         gather_cell(P.G, X, c);
-        gather_tensor(P.G, node, c, X, F);
+        gather_tensor<WTS>(P, node, c, X, F);
     }
     double Gm[4] = {0.0, 0.0, 0.0, 0.0};
     if (P.h.m != 0.0) {
@@ -275,7 +292,7 @@ __device__ __forceinline__ void accel_ablation(const PushParams &P, const double
         A[a] = qm * (F[4 * a] * U[0] + F[4 * a + 1] * U[1] + F[4 * a + 2] * U[2] + F[4 * a + 3] * U[3]) - Gm[a];
 }
 
-template <int RK, int GATHER>
+template <int RK, int GATHER, int WTS>
 __global__ __launch_bounds__(kPushBlock) void k_push_ablation(PushParams P, Species cS,
                                                               const double *__restrict__ node, ParticlePtrs in,
                                                               ParticlePtrs out, unsigned long long *counters) {
@@ -296,7 +313,7 @@ __global__ __launch_bounds__(kPushBlock) void k_push_ablation(PushParams P, Spec
     if (GATHER == 1) {
         int c0[3];
         gather_cell(P.G, X0, c0);
-        gather_tensor(P.G, node, c0, X0, F0);
+        gather_tensor<WTS>(P, node, c0, X0, F0);
     }
     double Sx[3] = {0.0, 0.0, 0.0}, Su[4] = {0.0, 0.0, 0.0, 0.0};
     if (RK == 0) {
@@ -304,7 +321,7 @@ __global__ __launch_bounds__(kPushBlock) void k_push_ablation(PushParams P, Spec
         double Xs[3] = {X0[0], X0[1], X0[2]}, Us[4] = {U0[0], U0[1], U0[2], U0[3]};
         for (int st = 0; st < 4; st++) {
             double A[4];
-            accel_ablation<GATHER>(P, node, F0, qm, Xs, Us, A);
+            accel_ablation<GATHER, WTS>(P, node, F0, qm, Xs, Us, A);
             const double ig = 1.0 / stage_gamma(P, Us[3], A[3], clamps);
             const double wgt = (st == 0 || st == 3) ? 1.0 : 2.0;
             for (int q = 0; q < 3; q++) Sx[q] += wgt * (Us[q] * ig);
@@ -330,7 +347,7 @@ __global__ __launch_bounds__(kPushBlock) void k_push_ablation(PushParams P, Spec
                 for (int q = 0; q < 3; q++) xk[q] = X0[q] + ut[q] * dtau_prev;
             }
             double A[4];
-            accel_ablation<GATHER>(P, node, F0, qm, xk, ut, A);
+            accel_ablation<GATHER, WTS>(P, node, F0, qm, xk, ut, A);
             const double gam = stage_gamma(P, ut[3], A[3], clamps);
             const double dtau = (st == 0 || st == 3) ? P.dt / (2.0 * gam) : P.dt / gam;
             const double wgt = (st == 0 || st == 3) ? 1.0 : 2.0;
@@ -345,18 +362,28 @@ __global__ __launch_bounds__(kPushBlock) void k_push_ablation(PushParams P, Spec
     if (clamps) atomicAdd(&counters[C_GAMMA_CLAMPS], (unsigned long long)clamps);
 }
 
+template <int RK, int GA, int WT>
+void launch_push_ablation(unsigned nb, const PushParams &P, const Species &S, const double *node, ParticlePtrs in,
+                          ParticlePtrs out, unsigned long long *counters, hipStream_t s) {
+    hipLaunchKernelGGL((k_push_ablation<RK, GA, WT>), dim3(nb), dim3(kPushBlock), 0, s, P, S, node, in, out,
+                       counters);
+}
+
 void launch_push(const PushParams &P, const Species &S, const double *node, ParticlePtrs in, ParticlePtrs out,
                  unsigned long long *counters, hipStream_t s) {
     if (P.n <= 0) return;
     unsigned nb = (unsigned)((P.n + kPushBlock - 1) / kPushBlock);
-    if (P.rk_mode == 0 && P.gather_mode == 0)
-        hipLaunchKernelGGL(k_push, dim3(nb), dim3(kPushBlock), 0, s, P, S, node, in, out, counters);
-    else if (P.rk_mode == 0)
-        hipLaunchKernelGGL((k_push_ablation<0, 1>), dim3(nb), dim3(kPushBlock), 0, s, P, S, node, in, out, counters);
-    else if (P.gather_mode == 0)
-        hipLaunchKernelGGL((k_push_ablation<1, 0>), dim3(nb), dim3(kPushBlock), 0, s, P, S, node, in, out, counters);
-    else
-        hipLaunchKernelGGL((k_push_ablation<1, 1>), dim3(nb), dim3(kPushBlock), 0, s, P, S, node, in, out, counters);
+    // modes are validated at creation: rk_mode, gather_mode, gather_weights in {0, 1}
+    switch (P.rk_mode * 4 + P.gather_mode * 2 + P.gather_weights) {
+    case 0: hipLaunchKernelGGL(k_push, dim3(nb), dim3(kPushBlock), 0, s, P, S, node, in, out, counters); break;
+    case 1: launch_push_ablation<0, 0, 1>(nb, P, S, node, in, out, counters, s); break;
+    case 2: launch_push_ablation<0, 1, 0>(nb, P, S, node, in, out, counters, s); break;
+    case 3: launch_push_ablation<0, 1, 1>(nb, P, S, node, in, out, counters, s); break;
+    case 4: launch_push_ablation<1, 0, 0>(nb, P, S, node, in, out, counters, s); break;
+    case 5: launch_push_ablation<1, 0, 1>(nb, P, S, node, in, out, counters, s); break;
+    case 6: launch_push_ablation<1, 1, 0>(nb, P, S, node, in, out, counters, s); break;
+    default: launch_push_ablation<1, 1, 1>(nb, P, S, node, in, out, counters, s); break;
+    }
 }
 
 // ---------------------------------------------------------------------------

@@ -9,7 +9,8 @@ def make_config(n, *, m, a, dt, B0=(0.0, 0.0, 0.0), species=((-1.0, 1.0),), c=1.
                 r_exc=None, r_damp=None, damp_max=0.1, gamma_mode=capi.GAMMA_PAPER,
                 deposit_mode=capi.DEPOSIT_CURVED, field_iters=3, sort_every=0, tile=8, fp_bits=44,
                 capacity=0, precision=capi.FP64, init_covariant=False, ny=None, nz=None, center=None,
-                rk_mode=capi.RK_CLASSIC, gather_mode=capi.GATHER_STAGE):
+                rk_mode=capi.RK_CLASSIC, gather_mode=capi.GATHER_STAGE,
+                gather_weights=capi.WEIGHTS_TRILINEAR):
     ny = n if ny is None else ny
     nz = n if nz is None else nz
     cfg = capi.grpic_config_default(n, ny, nz)
@@ -18,6 +19,7 @@ def make_config(n, *, m, a, dt, B0=(0.0, 0.0, 0.0), species=((-1.0, 1.0),), c=1.
     cfg.deposit_mode = deposit_mode
     cfg.rk_mode = rk_mode
     cfg.gather_mode = gather_mode
+    cfg.gather_weights = gather_weights
     cfg.field_iters = field_iters
     cfg.sort_every = sort_every
     cfg.tile = tile

@@ -5,7 +5,8 @@ FP64 oracle run in the same reading:
   weights summing to 5/6), also against its closed form on uniform-B
   gyration (the polynomial I + 5M/6 + 7M^2/24 + M^3/16 + M^4/192);
 - gather_mode STEP: the field tensor gathered once at x_n for all stages;
-- both together.
+- gather_weights SPATIAL: reading B, sub-volumes weighted by sqrt(1 + f);
+- their combinations.
 
 Tolerances as the other FP64 parity tests: 1e-12 relative per step for the
 particle state, 1e-12 of scale plus the fixed-point rounding for the fields.
@@ -47,13 +48,14 @@ def _cmp_field(a, b, name, abs_floor=0.0):
     assert err <= TOL * scale + abs_floor, (name, err, scale)
 
 
-@pytest.mark.parametrize("rk_mode,gather_mode", [(1, 0), (0, 1), (1, 1)])
+@pytest.mark.parametrize("rk_mode,gather_mode,weights", [(1, 0, 0), (0, 1, 0), (1, 1, 0), (0, 0, 1), (0, 1, 1),
+                                                         (1, 0, 1), (1, 1, 1)])
 @pytest.mark.parametrize("gamma_mode", [0, 1])
-def test_ablation_cycle_parity(rk_mode, gather_mode, gamma_mode):
+def test_ablation_cycle_parity(rk_mode, gather_mode, weights, gamma_mode):
     N = 16
     P = params(N, m=1.5, a=1.2, dt=0.5, B0=(0.0, 0.0, 0.08), species=((-0.02, 0.02), (0.02, 0.4)),
-               gamma_mode=gamma_mode, rk_mode=rk_mode, gather_mode=gather_mode)
-    say("case ablation rk %d gather %d gamma %d" % (rk_mode, gather_mode, gamma_mode))
+               gamma_mode=gamma_mode, rk_mode=rk_mode, gather_mode=gather_mode, gather_weights=weights)
+    say("case ablation rk %d gather %d weights %d gamma %d" % (rk_mode, gather_mode, weights, gamma_mode))
     p, s = oracle_sim(P, 4000)
     r = gpu_run(P, 4000, fp_bits=FPB)
     ko = kg = 0
@@ -105,12 +107,12 @@ def test_printed_rk_gyration_closed_form():
     r.close()
 
 
-@pytest.mark.parametrize("rk_mode,gather_mode", [(1, 0), (0, 1)])
-def test_fp32_mixed_rejects_ablations(rk_mode, gather_mode):
+@pytest.mark.parametrize("rk_mode,gather_mode,weights", [(1, 0, 0), (0, 1, 0), (0, 0, 1)])
+def test_fp32_mixed_rejects_ablations(rk_mode, gather_mode, weights):
     from paper_0904_0232_amd import capi
     from paper_0904_0232_amd import run as R
     cfg = R.make_config(16, m=1.5, a=1.2, dt=0.5, capacity=64, precision=capi.FP32_MIXED,
-                        rk_mode=rk_mode, gather_mode=gather_mode)
+                        rk_mode=rk_mode, gather_mode=gather_mode, gather_weights=weights)
     with pytest.raises(capi.GrpicError) as e:
         R.Run(cfg)
     assert e.value.code == capi.EINVAL
