@@ -176,6 +176,26 @@ int grpic_dump_fields(grpic_t *h, int32_t which, double *out);
 /* Replace the evolved fields D and B_cov (each [3][field_size]). */
 int grpic_restore_fields(grpic_t *h, const double *D, const double *B);
 
+/* Checkpoint and resume.  A state holds everything a run carries from one
+ * cycle to the next: the evolved fields D and B_cov, the particle slots
+ * (order, species, x, u), the absorbed charge of the removal, the device
+ * counters and the cycle count (which schedules the cell sort), plus a
+ * header with the configuration it was saved under.  A run created with the
+ * same configuration (capacity may differ, allocator ignored) that loads the
+ * state continues bit-identically to the run that saved it.
+ *
+ * grpic_state_bytes: the size of the run's current state in bytes (< 0: an
+ * error code).
+ * grpic_save_state: write it into buf (host memory, 8-byte aligned, bytes >=
+ * the state size; the caller owns buf).  Synchronous.
+ * grpic_load_state: replace the run's state by one saved earlier.  Returns
+ * GRPIC_EINVAL for a misaligned or short buffer, a buffer that is not a state
+ * of this format, a different configuration, or more slots than the capacity;
+ * the run is unchanged then.  Synchronous. */
+int64_t grpic_state_bytes(grpic_t *h);
+int grpic_save_state(grpic_t *h, void *buf, int64_t bytes);
+int grpic_load_state(grpic_t *h, const void *buf, int64_t bytes);
+
 /* Copy the node tensor F^a_b of the last step, [(nx+1)(ny+1)(nz+1)][4][4]. */
 int grpic_dump_nodes(grpic_t *h, double *out);
 

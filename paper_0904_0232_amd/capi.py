@@ -114,6 +114,10 @@ def lib():
         L.grpic_dump_fields.argtypes = [_H, ctypes.c_int32, _D]
         L.grpic_restore_fields.argtypes = [_H, _D, _D]
         L.grpic_dump_nodes.argtypes = [_H, _D]
+        L.grpic_state_bytes.argtypes = [_H]
+        L.grpic_state_bytes.restype = ctypes.c_int64
+        L.grpic_save_state.argtypes = [_H, ctypes.c_void_p, ctypes.c_int64]
+        L.grpic_load_state.argtypes = [_H, ctypes.c_void_p, ctypes.c_int64]
         L.grpic_sort.argtypes = [_H, _U32, _I64]
         L.grpic_set_timing.argtypes = [_H, ctypes.c_int32]
         L.grpic_read_timing.argtypes = [_H, _D, _I64]
@@ -249,6 +253,23 @@ def grpic_restore_particles(h, x, u, sp):
     u = _f64(u)
     sp = np.ascontiguousarray(sp, dtype=np.uint8)
     _check(lib().grpic_restore_particles(h, sp.shape[0], _dp(x), _dp(u), sp.ctypes.data_as(_U8)))
+
+
+def grpic_save_state(h):
+    """The run's full state as a uint8 array (see grpic_save_state)."""
+    nb = lib().grpic_state_bytes(h)
+    _check(int(nb) if nb < 0 else 0)
+    buf = np.zeros((nb + 7) // 8, dtype=np.uint64)  # 8-byte aligned
+    _check(lib().grpic_save_state(h, buf.ctypes.data, nb))
+    return buf.view(np.uint8)[:nb]
+
+
+def grpic_load_state(h, state):
+    """Replace the run's state by one from grpic_save_state."""
+    state = np.asarray(state, dtype=np.uint8)
+    buf = np.zeros((state.size + 7) // 8, dtype=np.uint64)
+    buf.view(np.uint8)[:state.size] = state
+    _check(lib().grpic_load_state(h, buf.ctypes.data, state.size))
 
 
 def grpic_field_size(h):

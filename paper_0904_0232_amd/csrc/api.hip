@@ -1047,6 +1047,129 @@ int grpic_restore_fields(grpic_t *h, const double *D, const double *B) {
     return h->mixed ? restore_fields_t<float>(h, D, B) : restore_fields_t<double>(h, D, B);
 }
 
+namespace {
+// Checkpoint layout (host, 8-byte aligned): StateHeader, then D [3][gs] and
+// B [3][gs] as doubles, rho_abs [gs] and the counters [kCounterWords] as
+// uint64, x [3][n] and u [4][n] as doubles, sp [n] bytes.
+const char kStateMagic[8] = {'G', 'R', 'P', 'I', 'C', 'S', 'T', '1'};
+struct StateHeader {
+    char magic[8];
+    int64_t total_bytes;
+    grpic_config key;  // configuration, normalised by state_key
+    int64_t n_slots, step_count, field_size, counter_words;
+};
+
+// The configuration fields that determine the evolution, in a zeroed struct
+// (no padding garbage, no capacity or allocator).
+void state_key(const grpic_config *c, grpic_config *k) {
+    memset(k, 0, sizeof(*k));
+    k->nx = c->nx;
+    k->ny = c->ny;
+    k->nz = c->nz;
+    k->precision = c->precision;
+    k->gamma_mode = c->gamma_mode;
+    k->deposit_mode = c->deposit_mode;
+    k->field_iters = c->field_iters;
+    k->sort_every = c->sort_every;
+    k->tile = c->tile;
+    k->fp_bits = c->fp_bits;
+    k->nspecies = c->nspecies;
+    k->init_covariant = c->init_covariant;
+    k->rk_mode = c->rk_mode;
+    k->gather_mode = c->gather_mode;
+    k->gather_weights = c->gather_weights;
+    k->c = c->c;
+    k->dt = c->dt;
+    k->m = c->m;
+    k->a = c->a;
+    for (int i = 0; i < 3; i++) {
+        k->center[i] = c->center[i];
+        k->B0[i] = c->B0[i];
+    }
+    k->r_rm = c->r_rm;
+    k->r_exc = c->r_exc;
+    k->r_damp = c->r_damp;
+    k->damp_max = c->damp_max;
+    for (int i = 0; i < GRPIC_MAX_SPECIES; i++) {
+        k->charge[i] = c->charge[i];
+        k->mass[i] = c->mass[i];
+    }
+}
+
+int64_t state_bytes_for(int64_t gs, int64_t n) {
+    int64_t b = (int64_t)sizeof(StateHeader) + 8 * (6 * gs + gs + kCounterWords + 7 * n) + n;
+    return (b + 7) & ~(int64_t)7;
+}
+}  // namespace
+
+int64_t grpic_state_bytes(grpic_t *h) {
+    if (!h) return GRPIC_EINVAL;
+    return state_bytes_for(h->G.gsize(), h->n_slots);
+}
+
+int grpic_save_state(grpic_t *h, void *buf, int64_t bytes) {
+    clear_foreign_error();
+    if (!h || !buf || ((uintptr_t)buf & 7)) return GRPIC_EINVAL;
+    const int64_t gs = h->G.gsize(), n = h->n_slots, total = state_bytes_for(gs, n);
+    if (bytes < total) return GRPIC_EINVAL;
+    char *b = (char *)buf;
+    StateHeader *hd = (StateHeader *)b;
+    memcpy(hd->magic, kStateMagic, 8);
+    hd->total_bytes = total;
+    state_key(&h->cfg, &hd->key);
+    hd->n_slots = n;
+    hd->step_count = h->step_count;
+    hd->field_size = gs;
+    hd->counter_words = kCounterWords;
+    double *D = (double *)(b + sizeof(StateHeader));
+    double *B = D + 3 * gs;
+    unsigned long long *rho = (unsigned long long *)(B + 3 * gs);
+    unsigned long long *cnt = rho + gs;
+    double *x = (double *)(cnt + kCounterWords);
+    double *u = x + 3 * n;
+    uint8_t *sp = (uint8_t *)(u + 4 * n);
+    int rc = grpic_dump_fields(h, 0, D);
+    if (!rc) rc = grpic_dump_fields(h, 1, B);
+    hipStream_t s = h->stream;
+    unsigned long long *rho_dev = h->mixed ? h->F32.rho_abs : h->F64.rho_abs;
+    if (!rc) rc = check(hipMemcpyAsync(rho, rho_dev, gs * 8, hipMemcpyDeviceToHost, s));
+    if (!rc) rc = check(hipMemcpyAsync(cnt, h->counters, kCounterWords * 8, hipMemcpyDeviceToHost, s));
+    if (!rc) rc = check(hipStreamSynchronize(s));
+    if (!rc && n > 0) rc = grpic_dump_particles(h, x, u, sp);
+    return rc;
+}
+
+int grpic_load_state(grpic_t *h, const void *buf, int64_t bytes) {
+    clear_foreign_error();
+    if (!h || !buf || ((uintptr_t)buf & 7) || bytes < (int64_t)sizeof(StateHeader)) return GRPIC_EINVAL;
+    const char *b = (const char *)buf;
+    const StateHeader *hd = (const StateHeader *)b;
+    grpic_config key;
+    state_key(&h->cfg, &key);
+    const int64_t gs = h->G.gsize();
+    if (memcmp(hd->magic, kStateMagic, 8) || memcmp(&hd->key, &key, sizeof(key)) || hd->field_size != gs ||
+        hd->counter_words != kCounterWords || hd->n_slots < 0 || hd->n_slots > h->cap || hd->step_count < 0 ||
+        hd->total_bytes != state_bytes_for(gs, hd->n_slots) || bytes < hd->total_bytes)
+        return GRPIC_EINVAL;
+    const int64_t n = hd->n_slots;
+    const double *D = (const double *)(b + sizeof(StateHeader));
+    const double *B = D + 3 * gs;
+    const unsigned long long *rho = (const unsigned long long *)(B + 3 * gs);
+    const unsigned long long *cnt = rho + gs;
+    const double *x = (const double *)(cnt + kCounterWords);
+    const double *u = x + 3 * n;
+    const uint8_t *sp = (const uint8_t *)(u + 4 * n);
+    int rc = grpic_restore_fields(h, D, B);
+    hipStream_t s = h->stream;
+    unsigned long long *rho_dev = h->mixed ? h->F32.rho_abs : h->F64.rho_abs;
+    if (!rc) rc = check(hipMemcpyAsync(rho_dev, rho, gs * 8, hipMemcpyHostToDevice, s));
+    if (!rc) rc = check(hipMemcpyAsync(h->counters, cnt, kCounterWords * 8, hipMemcpyHostToDevice, s));
+    if (!rc) rc = check(hipStreamSynchronize(s));
+    if (!rc) rc = grpic_restore_particles(h, n, x, u, sp);
+    if (!rc) h->step_count = hd->step_count;
+    return rc;
+}
+
 int grpic_dump_nodes(grpic_t *h, double *out) {
     if (!h || !out) return GRPIC_EINVAL;
     int64_t cnt = h->G.nnodes() * 16;

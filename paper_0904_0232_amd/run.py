@@ -71,6 +71,14 @@ class Run:
     def particles(self):
         return capi.grpic_dump_particles(self.h)
 
+    def save_state(self):
+        """Checkpoint: the run's full state as bytes (numpy uint8)."""
+        return capi.grpic_save_state(self.h)
+
+    def load_state(self, state):
+        """Resume from a checkpoint of a run with the same configuration."""
+        capi.grpic_load_state(self.h, state)
+
     def restore_particles(self, x, u, sp):
         capi.grpic_restore_particles(self.h, x, u, sp)
 
