@@ -7,15 +7,15 @@ import oracle as O
 
 def params(n, *, m, a, dt, B0=(0.0, 0.0, 0.05), species=((-1.0, 1.0),), r_rm=None, gamma_mode=0,
            deposit_mode=0, field_iters=3, damp_max=0.1, init_covariant=False, rk_mode=0, gather_mode=0,
-           gather_weights=0):
-    return dict(n=n, m=m, a=a, dt=dt, B0=tuple(B0), species=tuple(species), r_rm=r_rm,
+           gather_weights=0, c=1.0):
+    return dict(n=n, m=m, a=a, dt=dt, c=c, B0=tuple(B0), species=tuple(species), r_rm=r_rm,
                 gamma_mode=gamma_mode, deposit_mode=deposit_mode, field_iters=field_iters,
                 damp_max=damp_max, init_covariant=init_covariant, rk_mode=rk_mode, gather_mode=gather_mode,
                 gather_weights=gather_weights)
 
 
 def oracle_sim(P, ncap):
-    p = O.make_params(P["n"], m=P["m"], a=P["a"], dt=P["dt"], r_rm=P["r_rm"],
+    p = O.make_params(P["n"], m=P["m"], a=P["a"], dt=P["dt"], c=P.get("c", 1.0), r_rm=P["r_rm"],
                       gamma_mode=P["gamma_mode"], deposit_mode=P["deposit_mode"],
                       field_iters=P["field_iters"], damp_max=P["damp_max"], species=P["species"],
                       rk_mode=P.get("rk_mode", 0), gather_mode=P.get("gather_mode", 0),
@@ -27,7 +27,7 @@ def oracle_sim(P, ncap):
 
 def gpu_run(P, capacity, sort_every=0, fp_bits=44):
     from paper_0904_0232_amd import run as R
-    cfg = R.make_config(P["n"], m=P["m"], a=P["a"], dt=P["dt"], B0=P["B0"], species=P["species"],
+    cfg = R.make_config(P["n"], m=P["m"], a=P["a"], dt=P["dt"], c=P.get("c", 1.0), B0=P["B0"], species=P["species"],
                         r_rm=P["r_rm"], gamma_mode=P["gamma_mode"], deposit_mode=P["deposit_mode"],
                         field_iters=P["field_iters"], damp_max=P["damp_max"], sort_every=sort_every,
                         capacity=capacity, fp_bits=fp_bits, init_covariant=P["init_covariant"],

@@ -93,13 +93,18 @@ CASES = [
     dict(m=1.5, a=0.0, gamma_mode=0, deposit_mode=0),
     dict(m=1.5, a=1.2, gamma_mode=0, deposit_mode=0),
     dict(m=1.5, a=1.2, gamma_mode=1, deposit_mode=1),
+    # the units of the paper's application: c = 0.05, dt = 1
+    dict(m=1.5, a=1.2, gamma_mode=0, deposit_mode=0, c=0.05, dt=1.0),
 ]
 
 
-@pytest.mark.parametrize("case", CASES, ids=lambda c: "m%.1f_a%.1f_g%d_d%d" % (c["m"], c["a"], c["gamma_mode"], c["deposit_mode"]))
+@pytest.mark.parametrize("case", CASES, ids=lambda c: "m%.1f_a%.1f_g%d_d%d_c%g" % (c["m"], c["a"], c["gamma_mode"],
+                                                                                  c["deposit_mode"], c.get("c", 1.0)))
 def test_cycle_parity_small(case):
     N = 16
-    P = params(N, dt=0.5, B0=(0.0, 0.0, 0.08), species=((-0.02, 0.02), (0.02, 0.4)), **case)
+    case = dict(case)
+    dt = case.pop("dt", 0.5)
+    P = params(N, dt=dt, B0=(0.0, 0.0, 0.08), species=((-0.02, 0.02), (0.02, 0.4)), **case)
     say("case cycle", case)
     parts = _small_parts(7, 1500, N)
     p, s = oracle_sim(P, 4000)
@@ -113,7 +118,8 @@ def test_cycle_parity_small(case):
         _cmp_particles(s, r, tag="step %d" % it)
         _cmp_field(r.fields("J"), s.get("J"), "J", abs_floor=_j_floor(P))
         _cmp_field(r.fields("B"), s.get("B"), "B")
-        _cmp_field(r.fields("D"), s.get("D"), "D", abs_floor=4 * np.pi * P["dt"] * _j_floor(P))
+        # the current enters D through (4 pi / c) dt
+        _cmp_field(r.fields("D"), s.get("D"), "D", abs_floor=4 * np.pi * P["dt"] / P["c"] * _j_floor(P))
     do, dg = s.diag(), r.diag()
     for k in ("n_alive", "n_removed_horizon", "n_removed_outer", "gamma_clamps", "flags"):
         assert do[k] == dg[k], (k, do[k], dg[k])

@@ -24,30 +24,31 @@ def _rk4_poly(z):
     return 1 + z + z * z / 2 + z ** 3 / 6 + z ** 4 / 24
 
 
-@pytest.mark.parametrize("qm", [-1.0, 0.05])
+@pytest.mark.parametrize("qm,c,dt", [(-1.0, 1.0, 0.5), (0.05, 1.0, 0.5), (-1e-3, 0.05, 1.0)])
 @pytest.mark.parametrize("gamma_mode", [0, 1])
-def test_gyration_matches_rk4_stability_polynomial(qm, gamma_mode):
+def test_gyration_matches_rk4_stability_polynomial(qm, c, dt, gamma_mode):
+    # in coordinate time dw/dt = -i (q/m) B (c / u^4) w (u^4 = dx^4/dtau = c dt/dtau)
     N = 32
-    B = 0.05 if qm == -1.0 else 1.0
-    p = O.make_params(N, m=0.0, a=0.0, dt=0.5, gamma_mode=gamma_mode, species=((qm, 1.0),))
+    B = {-1.0: 0.05, 0.05: 1.0, -1e-3: 30.0}[qm]
+    p = O.make_params(N, m=0.0, a=0.0, c=c, dt=dt, gamma_mode=gamma_mode, species=((qm, 1.0),))
     s = O.Sim(p, 1)
     F = np.zeros((4, 4))
     F[0, 1] = B   # F^1_2 = F^{12} = B^z in flat space
     F[1, 0] = -B
     s.set_nodes(_uniform_nodes(p, F))
-    u3 = np.array([0.3, 0.1, 0.0])
-    u4 = np.sqrt(1.0 + u3 @ u3)
+    u3 = np.array([0.3, 0.1, 0.0]) * c
+    u4 = np.sqrt(c * c + u3 @ u3)
     x = np.array([[16.2], [15.7], [16.1]])
     u = np.array([[u3[0]], [u3[1]], [u3[2]], [u4]])
     s.set_particles(x, u, np.zeros(1, np.uint8))
     nsteps = 1000
     s.push_only(nsteps)
     _, uN, _ = s.particles()
-    lam = -1j * qm * B / u4
+    lam = -1j * qm * B * c / u4
     w_ref = (u3[0] + 1j * u3[1]) * _rk4_poly(lam * p.dt) ** nsteps
     w = uN[0, 0] + 1j * uN[1, 0]
     assert abs(w - w_ref) < 1e-13 * nsteps * abs(w_ref)
-    assert abs(uN[3, 0] - u4) < 1e-15 * 10
+    assert abs(uN[3, 0] - u4) < 1e-14 * u4
 
 
 @pytest.mark.parametrize("qm", [1.0, -1.0])
