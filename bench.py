@@ -269,6 +269,69 @@ def serving(args):
     }
 
 
+def jet_study(snapshots=(0, 50, 100, 150, 200, 250, 300, 350, 400, 450, 500)):
+    """The paper's application (Sec. 6, inputs.jet_params for the readings):
+    500 steps of the disk + corona workload on 64 x 64 x 128 with B^z = 30,
+    in FP64 and FP32-mixed, and an FP64 control with B = 0.  The paper shows
+    only pictures (a bipolar jet spiralling about z), so the check is
+    qualitative: at each snapshot, the particles within 16 cells of the axis,
+    more than 8 cells from the mid-plane and moving away from it faster than
+    0.05 c, above and below the plane, their speeds, mean azimuthal velocity
+    and median distance from the axis, and the same with no field.
+    Throughput is particle-steps per second of the timed steps."""
+    import numpy as np
+    import torch
+    from paper_0904_0232_amd import capi, inputs
+    from paper_0904_0232_amd import run as R
+
+    w = inputs.jet_params()
+    parts = inputs.jet_particles(0)
+    ntot = sum(x.shape[1] for _, x, _ in parts)
+    cen = np.array(w["center"])
+    out = {"workload": "jet64x64x128", "particles": ntot, "m": w["m"], "a": w["a"], "c": w["c"], "dt": w["dt"],
+           "runs": {}}
+    for name, prec, b0 in (("B30_fp64", capi.FP64, w["B0"]), ("B30_fp32", capi.FP32_MIXED, w["B0"]),
+                           ("B0_fp64", capi.FP64, 0.0)):
+        cfg = R.make_config(w["nx"], ny=w["ny"], nz=w["nz"], m=w["m"], a=w["a"], c=w["c"], dt=w["dt"],
+                            B0=(0.0, 0.0, b0), species=w["species"], r_rm=w["r_rm"], sort_every=5, capacity=ntot,
+                            precision=prec, center=w["center"])
+        r = R.Run(cfg)
+        for sp, x, uc in parts:
+            r.load(sp, x, uc)
+        snaps, wall, psteps, done = {}, 0.0, 0, 0
+        for t in snapshots:
+            if t > done:
+                torch.cuda.synchronize()
+                ps0 = capi.grpic_particle_steps(r.h)
+                t0 = time.perf_counter()
+                capi.grpic_step(r.h, t - done)
+                torch.cuda.synchronize()
+                wall += time.perf_counter() - t0
+                psteps += capi.grpic_particle_steps(r.h) - ps0
+                done = t
+            x, u, sp = r.particles()
+            live = sp != 0xFF
+            d = x[:, live] - cen[:, None]
+            v = w["c"] * u[:3, live] / u[3, live]
+            rho = np.hypot(d[0], d[1])
+            vout = v[2] * np.sign(d[2])
+            jet = (rho < 16.0) & (np.abs(d[2]) > 8.0) & (vout > 0.05 * w["c"])
+            speed = np.linalg.norm(v[:, jet], axis=0) / w["c"]
+            # azimuthal velocity about +z (negative: clockwise, with the hole's frame dragging)
+            vphi = (d[0, jet] * v[1, jet] - d[1, jet] * v[0, jet]) / np.maximum(rho[jet], 1e-12) / w["c"]
+            snaps[str(t)] = {"live": int(live.sum()), "outflow_above": int((jet & (d[2] > 0)).sum()),
+                             "outflow_below": int((jet & (d[2] < 0)).sum()),
+                             "outflow_median_speed_c": float(np.median(speed)) if speed.size else None,
+                             "outflow_frac_above_0.5c": float((speed > 0.5).mean()) if speed.size else None,
+                             "outflow_mean_vphi_c": float(vphi.mean()) if speed.size else None,
+                             "outflow_median_rho": float(np.median(rho[jet])) if speed.size else None}
+        r.close()
+        out["runs"][name] = {"particle_steps_per_s": psteps / wall, "ms_per_step": wall * 1e3 / done,
+                             "snapshots": snaps}
+        log("jet %s: %.4g particle-steps/s, %s" % (name, psteps / wall, json.dumps(snaps)))
+    return out
+
+
 def ablation_study(workload="kerr64", per_species=131072, T=8.0, dts=(0.4, 0.2, 0.1, 0.05), timing_steps=10):
     """The push readings side by side (FP64): the stage gamma (PAPER estimate
     or u^4/c), the RK structure (CLASSIC reading or the steps as PRINTED),
@@ -479,6 +542,8 @@ def main():
                     help="also time the 256^3 throughput workload (268M particles) in both precisions")
     ap.add_argument("--precision", action="store_true",
                     help="also run the FP32-mixed vs FP64 precision study on the torus workload (1000 steps)")
+    ap.add_argument("--jet", action="store_true",
+                    help="add the paper's application (disk + corona, 64x64x128, c = 0.05): throughput and outflow")
     ap.add_argument("--ablations", action="store_true",
                     help="add the push-reading ablation study (orders, push time, CURVED/FLAT Gauss residual)")
     ap.add_argument("--precision-particles", type=int, default=0,
@@ -554,6 +619,8 @@ def main():
         line["precision_torus128"] = precision_study("torus128", n_override=args.precision_particles or None)
     if args.ablations:
         line["ablations_kerr64"] = ablation_study()
+    if args.jet:
+        line["jet"] = jet_study()
     if not args.no_cpu_baseline:
         line["cpu_baseline"], ostate = cpu_baseline(args.workload, args.cpu_sample)
         log("cpu baseline: %.4g particle-steps/s" % line["cpu_baseline"]["value"])

@@ -14,7 +14,9 @@ table from the plasma-frequency choice.  Shapes follow the workloads:
   the frame dragging of the metric, clockwise about +z for a > 0), given as
   the covariant velocity of the non-rotating hole's circular geodesic in
   Kerr-Schild form (closed-form initial data), plus thermal spread;
-- uniform plasma with an infalling shell (|R - edge/4| <= 2 gets v_r = -0.3c).
+- uniform plasma with an infalling shell (|R - edge/4| <= 2 gets v_r = -0.3c);
+- the paper's application (a Keplerian disk and an infalling corona, c =
+  0.05; its readings are listed at jet_params).
 
 Velocities are covariant spatial components u_i (the load call completes
 them on the mass shell).  Charges: |Q| = (wpe dt)^2 / (dt^2 4 pi n |q/m|_e)
@@ -129,6 +131,99 @@ def shell_plasma(seed, nx, ny, nz, ppc, u_th, v_r=-0.3, width=2.0, center=None, 
     for _, _, u in species:
         u[:, shell] += rhat * (gam * v_r)
     return species
+
+
+# The paper's application (Sec. 6): a Keplerian disk and an infalling
+# corona around a spinning hole on a 64 x 64 x 128 grid with c = 0.05,
+# dt = 1, contravariant B^z = 30 and q/m = 1e-3 (electrons and positrons),
+# 500 steps.  Readings where the text is silent or garbled:
+#  - the unit charge is unspecified; q = 1 makes the hole's mass length
+#    m = G M_c / c^2 = (dx c^2)^2 M_c / c^2 = 0.75 cells for M_c = 300;
+#  - r_S is the Schwarzschild radius 2m, so the disk's inner edge is
+#    r_d = 3 r_S = 6m and v_K = c sqrt(r_S / 2r) = c sqrt(m/r) is Keplerian;
+#  - the disk (|cos theta| < 1/8, r > r_d) runs out to the grid, with 800,000
+#    particles in all (half of each species), cold, on circular orbits;
+#  - the corona fills the rest outside r_rm at 1/100 of the disk density and
+#    falls in from rest at infinity (radial, the non-rotating hole's
+#    free-fall velocity);
+#  - the macro charge gives wp dt = 0.1 at the disk density (as for the
+#    other workloads), and the electrons and positrons start at the same
+#    positions with the same velocities (neutral start).
+JET = dict(nx=64, ny=64, nz=128, c=0.05, dt=1.0, steps=500, M_c=300.0, unit_charge=1.0, a_frac=0.95,
+           B0=30.0, qm=1e-3, n_disk=800000, corona_fraction=0.01, disk_cos=1.0 / 8.0)
+
+
+def jet_params():
+    """Plain parameters of the jet workload (no method arithmetic)."""
+    w = dict(JET)
+    G = (1.0 * w["c"] ** 2 / w["unit_charge"]) ** 2  # dimensionless G with dx = 1
+    m = G * w["M_c"] / w["c"] ** 2
+    a = w["a_frac"] * m
+    rp = horizon_radius(m, a)
+    w.update(m=m, a=a, r_plus=rp, r_rm=1.1 * rp, r_s=2.0 * m, r_d=6.0 * m,
+             center=(w["nx"] / 2.0, w["ny"] / 2.0, w["nz"] / 2.0))
+    # disk volume (counted on a fine lattice) sets the disk density
+    cen = np.array(w["center"])
+    h = 0.25
+    g = [np.arange(h / 2, n, h) - c0 for n, c0 in zip((w["nx"], w["ny"], w["nz"]), cen)]
+    X, Y = np.meshgrid(g[0], g[1], indexing="ij")
+    rho2 = X * X + Y * Y
+    vol = 0.0
+    for z in g[2]:
+        r2 = rho2 + z * z
+        vol += np.count_nonzero((r2 > w["r_d"] ** 2) & (z * z < w["disk_cos"] ** 2 * r2)) * h ** 3
+    w["disk_volume"] = vol
+    n_disk_species = w["n_disk"] / 2.0 / vol  # particles per cell and species in the disk
+    wp = 0.1 / w["dt"]
+    Q = wp * wp / (4.0 * math.pi * n_disk_species * w["qm"])
+    w["species"] = ((-Q, Q / w["qm"]), (Q, Q / w["qm"]))
+    return w
+
+
+def jet_particles(seed=0, n_disk=None):
+    """[(species, x[3][n], ucov[3][n])] for electrons and positrons."""
+    w = jet_params()
+    nx, ny, nz, c, m = w["nx"], w["ny"], w["nz"], w["c"], w["m"]
+    cen = np.array(w["center"])
+    nd = (n_disk or w["n_disk"]) // 2
+    g = rng(seed, PURPOSE_POS)
+    box = np.array([nx, ny, nz], dtype=float)
+
+    def draw(n, want_disk):
+        out = np.zeros((3, 0))
+        while out.shape[1] < n:
+            cand = g.random((3, max(4 * (n - out.shape[1]), 4096))) * box[:, None]
+            d = cand - cen[:, None]
+            r2 = (d * d).sum(0)
+            disk = (r2 > w["r_d"] ** 2) & (d[2] ** 2 < w["disk_cos"] ** 2 * r2)
+            keep = disk if want_disk else (~disk & (r2 > w["r_rm"] ** 2))
+            out = np.concatenate([out, cand[:, keep]], axis=1)
+        return out[:, :n]
+
+    corona_volume = nx * ny * nz - w["disk_volume"] - 4.0 / 3.0 * math.pi * w["r_rm"] ** 3
+    nc = int(round(w["corona_fraction"] * nd / w["disk_volume"] * corona_volume))
+    xd, xc = draw(nd, True), draw(nc, False)
+    # disk: circular geodesic of the non-rotating hole (coordinate speed
+    # c sqrt(m/R) along phi_hat, prograde = along the frame dragging,
+    # clockwise for a > 0; dx^4/dtau = c / sqrt(1 - 3m/R)); lowering with
+    # g = eta + f k k (f = 2m/R, k = (r_hat, 1)) gives the covariant
+    # u_i = u^4 (v/c phi_hat + f r_hat)
+    d = xd - cen[:, None]
+    R = np.sqrt((d * d).sum(0))
+    rho = np.maximum(np.hypot(d[0], d[1]), 1e-12)
+    phi_hat = -np.stack([-d[1] / rho, d[0] / rho, np.zeros_like(rho)])
+    u4 = c / np.sqrt(1.0 - 3.0 * m / R)
+    f = 2.0 * m / R
+    ud = u4 * (phi_hat * np.sqrt(m / R) + (d / R) * f)
+    # corona: free fall from rest at infinity, radial; in Kerr-Schild form
+    # (u_4 = -c) the covariant radial component is -c sqrt(f) / (1 + sqrt(f))
+    d = xc - cen[:, None]
+    R = np.sqrt((d * d).sum(0))
+    sf = np.sqrt(2.0 * m / R)
+    uc = (d / R) * (-c * sf / (1.0 + sf))
+    x = np.concatenate([xd, xc], axis=1)
+    u = np.concatenate([ud, uc], axis=1)
+    return [(0, x, u), (1, x.copy(), u.copy())]
 
 
 def horizon_radius(m, a):
