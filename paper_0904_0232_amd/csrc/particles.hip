@@ -524,6 +524,15 @@ __device__ __forceinline__ void dep_chord(const DepCtx &D, const Acc &acc, const
 
 constexpr int kDepBlock = 256;
 constexpr int kDepPPT = 4;      // particles per thread
+
+// Particle p (0 .. kDepPPT-1) of thread tid within its block's slots: the 64
+// lanes of a wave take slots kDepPPT * (kDepBlock / 64) = 16 apart.  In a
+// cell-sorted block a cell holds about that many particles, so the lanes of
+// one instruction add to different cells' edges instead of queueing on the
+// same LDS addresses (the integer sums do not depend on the order).
+__device__ __forceinline__ int dep_slot(int p, int tid) {
+    return (tid & 63) * (kDepPPT * (kDepBlock / 64)) + p * (kDepBlock / 64) + (tid >> 6);
+}
 constexpr int kDepLds = 4096;   // int64 LDS entries of the current tile (32 KiB)
 
 // Zigzag split of one chord: relay point and the two cells; false when the
@@ -563,7 +572,7 @@ __global__ __launch_bounds__(kDepBlock) void k_deposit(DepCtx D, Species cS, dou
     int lo[3] = {1 << 30, 1 << 30, 1 << 30}, hi[3] = {-(1 << 30), -(1 << 30), -(1 << 30)};
 #pragma unroll
     for (int p = 0; p < kDepPPT; p++) {
-        int64_t id = base + p * kDepBlock + tid;
+        int64_t id = base + dep_slot(p, tid);
         SP[p] = id < n ? xo.sp[id] : kDead;
         if (SP[p] != kDead) {
             double X1[3], X2[3];
@@ -614,7 +623,7 @@ __global__ __launch_bounds__(kDepBlock) void k_deposit(DepCtx D, Species cS, dou
 #pragma unroll 1
     for (int p = 0; p < kDepPPT; p++) {
         if (SP[p] == kDead) continue;
-        int64_t id = base + p * kDepBlock + tid;
+        int64_t id = base + dep_slot(p, tid);
         double Q = cS.charge[SP[p]];
         double X1[3], X2[3];
         for (int ax = 0; ax < 3; ax++) {

@@ -461,6 +461,12 @@ __device__ __forceinline__ void load_chord32(const ParticlePtrs32 &xo, const Par
 
 constexpr int kDep32Block = 256;
 constexpr int kDep32PPT = 4;
+
+// Particle p of thread tid within its block's slots, wave lanes 16 slots
+// apart (as in the FP64 deposit: lanes of one instruction in different cells).
+__device__ __forceinline__ int dep32_slot(int p, int tid) {
+    return (tid & 63) * (kDep32PPT * (kDep32Block / 64)) + p * (kDep32Block / 64) + (tid >> 6);
+}
 constexpr int kDep32Lds = 4096;
 
 // Block `blk` of the deposit (particles blk * kDep32Block * kDep32PPT ...);
@@ -476,7 +482,7 @@ __device__ __forceinline__ void deposit32_block(const Dep32 &D, const Species &c
     int lo[3] = {1 << 30, 1 << 30, 1 << 30}, hi[3] = {-(1 << 30), -(1 << 30), -(1 << 30)};
 #pragma unroll
     for (int p = 0; p < kDep32PPT; p++) {
-        int64_t id = base + p * kDep32Block + tid;
+        int64_t id = base + dep32_slot(p, tid);
         SP[p] = id < n ? xo.sp[id] : kDead;
         if (SP[p] != kDead) {
             int B1[3];
@@ -525,7 +531,7 @@ __device__ __forceinline__ void deposit32_block(const Dep32 &D, const Species &c
 #pragma unroll 1
     for (int p = 0; p < kDep32PPT; p++) {
         if (SP[p] == kDead) continue;
-        int64_t id = base + p * kDep32Block + tid;
+        int64_t id = base + dep32_slot(p, tid);
         float Q = (float)cS.charge[SP[p]];
         int B1[3];
         float X1[3], X2[3];
