@@ -140,6 +140,15 @@ __device__ __forceinline__ double ks_area_density(double m, double a, double r_e
     return N * rsqrt_nr(N * den);
 }
 
+// r < r_lim decided exactly as the correctly rounded radius decides it: the
+// refined radius (a few ulps from it) settles every case farther than 1e-12
+// relative from the limit, the correctly rounded one the rest.
+__device__ __forceinline__ bool ks_radius_below(double a, double x, double y, double z, double r_lim) {
+    const double r = ks_radius_nr(a, x, y, z);
+    if (fabs(r - r_lim) > 1e-12 * r_lim) return r < r_lim;
+    return ks_radius(a, x, y, z) < r_lim;
+}
+
 // Spatial volume density sqrt(det g_ij) = sqrt(1 + f) (|k| = 1 for the
 // spatial part of the null k) at a hole-relative point (m > 0), 1 inside
 // r < r_exc: with S4 = r^4 + a^2 z^2 and N = S4 + 2 m r^3 it is

@@ -642,13 +642,13 @@ __global__ __launch_bounds__(kDepBlock) void k_deposit(DepCtx D, Species cS, dou
             atomicOr(&counters[C_FLAGS], 1ull);
         }
         const double *x2 = X2;
-        double r = ks_radius(D.h.a, x2[0] - D.h.cx, x2[1] - D.h.cy, x2[2] - D.h.cz);
+        const bool inside_rm = ks_radius_below(D.h.a, x2[0] - D.h.cx, x2[1] - D.h.cy, x2[2] - D.h.cz, r_rm);
         bool outside = false;
         for (int ax = 0; ax < 3; ax++) {
             double nn = (double)D.G.dim(ax);
             if (!(x2[ax] >= 0.0 && x2[ax] < nn)) outside = true;
         }
-        if (r < r_rm) {
+        if (inside_rm) {
             // the removed charge stays on the nodes for the Gauss diagnostic
             int c[3];
             double w[3];

@@ -556,8 +556,7 @@ __device__ __forceinline__ void deposit32_block(const Dep32 &D, const Species &c
         float o2[3] = {xn.off[0][id], xn.off[1][id], xn.off[2][id]};
         double x, y, z;
         hole_rel(D.h, c2[0], c2[1], c2[2], o2, x, y, z);
-        double r = ks_radius(D.h.a, x, y, z);
-        if (r < r_rm) {
+        if (ks_radius_below(D.h.a, x, y, z, r_rm)) {
             bool inb = true;
             for (int ax = 0; ax < 3; ax++)
                 if (c2[ax] < -1 || c2[ax] > D.G.dim(ax)) inb = false;
