@@ -40,6 +40,7 @@ class Params(ctypes.Structure):
         ("center", ctypes.c_double * 3),
         ("r_rm", ctypes.c_double), ("r_exc", ctypes.c_double),
         ("r_damp", ctypes.c_double), ("damp_max", ctypes.c_double),
+        ("outer_layer", ctypes.c_double), ("outer_damp", ctypes.c_double),
         ("charge", ctypes.c_double * MAXSP), ("mass", ctypes.c_double * MAXSP),
     ]
 
@@ -131,11 +132,12 @@ def _f64(a):
 def make_params(nx, ny=None, nz=None, *, c=1.0, dt=0.5, m=0.0, a=0.0, center=None,
                 r_rm=None, r_exc=None, gamma_mode=0, deposit_mode=0,
                 field_iters=3, r_damp=None, damp_max=0.1, species=((-1.0, 1.0),),
-                rk_mode=0, gather_mode=0, gather_weights=0):
+                rk_mode=0, gather_mode=0, gather_weights=0, outer_layer=0.0, outer_damp=0.0):
     """species: sequence of (macro charge, macro mass).  rk_mode 1 takes the
     printed RK steps literally, gather_mode 1 gathers the fields once at x_n,
     gather_weights 1 weights the gather by the spatial volume (all ablations
-    of the default readings)."""
+    of the default readings).  outer_layer > 0 turns on the outer absorbing
+    layer of that width with relaxation fraction outer_damp at the faces."""
     ny = nx if ny is None else ny
     nz = nx if nz is None else nz
     p = Params()
@@ -152,6 +154,7 @@ def make_params(nx, ny=None, nz=None, *, c=1.0, dt=0.5, m=0.0, a=0.0, center=Non
     p.r_exc = 0.5 * rplus if r_exc is None else r_exc
     p.r_damp = rplus if r_damp is None else r_damp
     p.damp_max = damp_max
+    p.outer_layer, p.outer_damp = outer_layer, outer_damp
     p.nspecies = len(species)
     for i, (q, mass) in enumerate(species):
         p.charge[i] = q

@@ -56,6 +56,8 @@ typedef struct {
     double r_exc;         /* field points with r below this are excised          */
     double r_damp;        /* fields are relaxed to their initial values below r  */
     double damp_max;      /* relaxation fraction per step at r = r_exc           */
+    double outer_layer;   /* width in cells of the outer absorbing layer (0: off) */
+    double outer_damp;    /* its relaxation fraction per step at the outer face  */
     double charge[OR_MAXSP]; /* macro-particle charge per species                */
     double mass[OR_MAXSP];   /* macro-particle mass per species                  */
 } or_params;
@@ -696,6 +698,27 @@ static int relaxed(const or_params *p, int kind, int c, int i, int j, int k)
     return or_radius(p->a, X[0] - p->center[0], X[1] - p->center[1], X[2] - p->center[2]) < p->r_damp;
 }
 
+/* Distance of a point from the nearest outer face of the grid. */
+static double outer_distance(const or_params *p, const double X[3])
+{
+    double d = X[0];
+    for (int ax = 0; ax < 3; ax++) {
+        double lo = X[ax], hi = (double)ndim(p, ax) - X[ax];
+        if (lo < d) d = lo;
+        if (hi < d) d = hi;
+    }
+    return d;
+}
+
+/* Whether the point lies in the outer absorbing layer. */
+static int in_outer_layer(const or_params *p, int kind, int c, int i, int j, int k)
+{
+    if (!(p->outer_layer > 0.0) || !(p->outer_damp > 0.0)) return 0;
+    double X[3];
+    point_pos(kind, c, i, j, k, X);
+    return outer_distance(p, X) < p->outer_layer;
+}
+
 /* Relaxation inside the horizon (reading: the paper states no inner field
  * boundary).  Updated points with r_exc <= r < r_damp are pulled toward their
  * initial values by the fraction sigma = damp_max ((r_damp - r)/(r_damp - r_exc))^2
@@ -721,6 +744,38 @@ static void relax_inner(or_sim *s)
                         if (r >= p->r_damp) continue;
                         double t = (p->r_damp - r) / (p->r_damp - p->r_exc);
                         double sg = p->damp_max * t * t;
+                        size_t id = gidx(p, i, j, k);
+                        F[id] -= sg * (F[id] - F0[id]);
+                    }
+        }
+}
+
+/* Outer absorbing layer (reading: the paper states no outer boundary
+ * beyond the computational box; fields there are otherwise frozen, which
+ * reflects outgoing waves).  Updated points closer than outer_layer to the
+ * nearest outer face are pulled toward their initial values by
+ * sigma = outer_damp ((outer_layer - d)/outer_layer)^2 once per step, after
+ * the inner relaxation.  Pinned: a curl-free perturbation decays by exactly
+ * (1 - sigma(d)) per step, and a vacuum pulse is absorbed instead of
+ * reflected. */
+static void relax_outer(or_sim *s)
+{
+    const or_params *p = &s->p;
+    if (!(p->outer_layer > 0.0) || !(p->outer_damp > 0.0)) return;
+    for (int kind = 0; kind < 2; kind++)
+        for (int c = 0; c < 3; c++) {
+            double *F = kind == 0 ? s->D[c] : s->B[c];
+            const double *F0 = kind == 0 ? s->D0[c] : s->B0[c];
+            for (int k = 0; k <= p->nz; k++)
+                for (int j = 0; j <= p->ny; j++)
+                    for (int i = 0; i <= p->nx; i++) {
+                        if (!updated(p, kind, c, i, j, k)) continue;
+                        double X[3];
+                        point_pos(kind, c, i, j, k, X);
+                        double d = outer_distance(p, X);
+                        if (d >= p->outer_layer) continue;
+                        double t = (p->outer_layer - d) / p->outer_layer;
+                        double sg = p->outer_damp * t * t;
                         size_t id = gidx(p, i, j, k);
                         F[id] -= sg * (F[id] - F0[id]);
                     }
@@ -1468,6 +1523,7 @@ void or_sim_step(or_sim *s, int nsteps)
         }
         field_d_step(s);
         relax_inner(s);
+        relax_outer(s);
         for (int64_t i = 0; i < s->n; i++) {
             if (s->sp[i] == OR_DEAD) continue;
             double X[3];
@@ -1580,7 +1636,8 @@ void or_sim_diag(or_sim *s, or_diag *d)
                     int im[3] = {i, j, k};
                     im[c] -= 1;
                     if (!updated(p, 0, c, i, j, k) || !updated(p, 0, c, im[0], im[1], im[2]) ||
-                        relaxed(p, 0, c, i, j, k) || relaxed(p, 0, c, im[0], im[1], im[2]))
+                        relaxed(p, 0, c, i, j, k) || relaxed(p, 0, c, im[0], im[1], im[2]) ||
+                        in_outer_layer(p, 0, c, i, j, k) || in_outer_layer(p, 0, c, im[0], im[1], im[2]))
                         ok = 0;
                 }
                 if (!ok) continue;

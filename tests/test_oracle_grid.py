@@ -225,3 +225,58 @@ def test_sort_is_stable_and_tile_major():
     assert len(pairs) == len(set(lin.tolist())) == len(set(k_alive.tolist()))
     tiles = (cells[2] // T * (N // T) + cells[1] // T) * (N // T) + cells[0] // T
     assert np.all(k_alive // T ** 3 == tiles)
+
+
+# --- outer absorbing layer (a reading: the paper states no outer boundary) --
+
+def test_outer_layer_damps_a_curl_free_perturbation_exactly():
+    # a uniform perturbation of B^z has no curl, so one cycle (no particles)
+    # leaves it alone except for the layer: delta (1 - sigma(d)) with
+    # sigma = outer_damp ((L - d)/L)^2 and d the distance to the nearest face
+    N, L, damp, delta = 16, 4.0, 0.3, 1e-3
+    p = O.make_params(N, m=0.0, dt=0.5, outer_layer=L, outer_damp=damp)
+    s = O.Sim(p, 0)
+    s.init_fields([0.0, 0.0, 0.05])
+    D, B = s.get("D"), s.get("B")
+    B0z = B[2].copy()
+    B[2] += delta
+    s.set_fields(D, B)
+    s.step(1)
+    Bz = s.get("B")[2]
+    # B^z points (i+1/2, j+1/2, k), stored at [k+1, j+1, i+1]; updated for
+    # i, j in [0, N-1] and k in [1, N-1]
+    worst = 0.0
+    for k in range(1, N):
+        for j in range(N):
+            for i in range(N):
+                X = np.array([i + 0.5, j + 0.5, k])
+                d = min(X.min(), (N - X).min())
+                sg = damp * ((L - d) / L) ** 2 if d < L else 0.0
+                got = Bz[k + 1, j + 1, i + 1] - B0z[k + 1, j + 1, i + 1]
+                worst = max(worst, abs(got - delta * (1.0 - sg)))
+    assert worst < 1e-15
+
+
+def _pulse_energy(outer_layer, steps=60, N=24):
+    p = O.make_params(N, m=0.0, dt=0.5, outer_layer=outer_layer, outer_damp=0.5 if outer_layer else 0.0)
+    s = O.Sim(p, 0)
+    s.init_fields([0.0, 0.0, 0.0])
+    D, B = s.get("D"), s.get("B")
+    # B = discrete curl of A_z (a Gaussian at the centre) on the Yee grid:
+    # divergence-free and localised, so it radiates outward in vacuum
+    idx = np.arange(-1, N + 2, dtype=float)
+    K, J, I = np.meshgrid(idx, idx, idx, indexing="ij")
+    c = N / 2.0
+    Az = np.exp(-((I - c) ** 2 + (J - c) ** 2 + (K + 0.5 - c) ** 2) / 4.0)  # at (i, j, k+1/2)
+    B[0][:, :-1, :] = Az[:, 1:, :] - Az[:, :-1, :]      # F_23 at (i, j+1/2, k+1/2)
+    B[1][:, :, :-1] = -(Az[:, :, 1:] - Az[:, :, :-1])   # F_31 at (i+1/2, j, k+1/2)
+    s.set_fields(D, B)
+    e0 = s.diag()["energy_field"]
+    s.step(steps)
+    return s.diag()["energy_field"] / e0
+
+
+def test_outer_layer_absorbs_a_vacuum_pulse():
+    frozen, absorbed = _pulse_energy(0.0), _pulse_energy(6.0)
+    assert frozen > 0.5, frozen          # the frozen faces reflect it back into the box
+    assert absorbed < 0.2 * frozen, (absorbed, frozen)
