@@ -89,6 +89,9 @@ typedef struct {
     double r_exc;           /* field points with r < r_exc are frozen (flat)        */
     double r_damp;          /* fields relax to their initial values below r_damp   */
     double damp_max;        /* relaxation fraction per step at r = r_exc            */
+    double outer_layer;     /* width in cells of the outer absorbing layer (0: off, the
+                               outer faces are frozen); single runs only             */
+    double outer_damp;      /* its relaxation fraction per step at the faces, 0..1 */
     double B0[3];           /* initial (F^23, F^31, F^12), or covariant if flagged  */
     double charge[GRPIC_MAX_SPECIES]; /* macro-particle charge per species          */
     double mass[GRPIC_MAX_SPECIES];   /* macro-particle mass per species (> 0)      */
@@ -128,7 +131,7 @@ size_t grpic_config_size(void);
 /* Create a run.  Validates the configuration (grid >= 4 cells per axis,
  * 0 <= |a| <= m, c > 0, dt > 0, Courant c dt < 1/sqrt(3), r_exc < r_rm,
  * masses > 0, rk_mode, gather_mode and gather_weights at their defaults
- * unless FP64) and initialises the fields (Sec. 6: uniform contravariant
+ * unless FP64, outer_layer >= 0, 0 <= outer_damp <= 1) and initialises the fields (Sec. 6: uniform contravariant
  * field).  stream is a hipStream_t (NULL: the null stream).
  * Returns GRPIC_EINVAL, GRPIC_ENOMEM or GRPIC_EDEVICE on failure. */
 int grpic_create(const grpic_config *cfg, void *stream, grpic_t **out);
@@ -256,8 +259,8 @@ int grpic_batch_create(int64_t budget_bytes, int32_t max_slots, grpic_batch_t **
 /* Admit a run if a slot and budget_bytes allow it (else GRPIC_EAGAIN and no
  * state changes).  Particles of species s (s < cfg->nspecies): n[s] entries,
  * x[s] and ucov[s] as for grpic_load_particles; cfg->precision must be
- * GRPIC_FP32_MIXED and cfg->alloc NULL (the batch allocates), else
- * GRPIC_EINVAL.  Waits for the batch's queued work.  The run advances one cycle per grpic_batch_step until
+ * GRPIC_FP32_MIXED, cfg->alloc NULL (the batch allocates) and the outer
+ * absorbing layer off, else GRPIC_EINVAL.  Waits for the batch's queued work.  The run advances one cycle per grpic_batch_step until
  * nsteps are done.  keep_state != 0 keeps a host copy of the final particle
  * state for grpic_batch_dump. */
 int grpic_batch_submit(grpic_batch_t *b, const grpic_config *cfg, int32_t nsteps, int32_t keep_state,

@@ -40,6 +40,7 @@ class Config(ctypes.Structure):
         ("center", ctypes.c_double * 3),
         ("r_rm", ctypes.c_double), ("r_exc", ctypes.c_double),
         ("r_damp", ctypes.c_double), ("damp_max", ctypes.c_double),
+        ("outer_layer", ctypes.c_double), ("outer_damp", ctypes.c_double),
         ("B0", ctypes.c_double * 3),
         ("charge", ctypes.c_double * MAX_SPECIES), ("mass", ctypes.c_double * MAX_SPECIES),
         ("capacity", ctypes.c_int64),

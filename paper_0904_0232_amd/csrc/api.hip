@@ -185,6 +185,8 @@ int validate(const grpic_config *c) {
     if (!(c->m >= 0.0) || !(fabs(c->a) <= c->m) || !isfinite(c->m)) return GRPIC_EINVAL;
     if (c->m > 0.0 && !(c->r_exc >= 0.0 && c->r_exc < c->r_rm)) return GRPIC_EINVAL;
     if (c->damp_max < 0.0 || c->damp_max > 1.0) return GRPIC_EINVAL;
+    if (!(c->outer_layer >= 0.0) || !isfinite(c->outer_layer) || !(c->outer_damp >= 0.0) || c->outer_damp > 1.0)
+        return GRPIC_EINVAL;
     for (int s = 0; s < c->nspecies; s++) {
         if (!(c->mass[s] > 0.0) || !isfinite(c->charge[s])) return GRPIC_EINVAL;
     }
@@ -293,6 +295,7 @@ int fields_d(grpic_t *h) {
         launch_dstep<T>(h->G, F, Dsave, c.c * dtp, fpc, inv_js, s);
     }
     launch_relax<T>(h->G, h->h, F, c.r_damp, c.damp_max, s);
+    launch_relax_outer<T>(h->G, F, c.outer_layer, c.outer_damp, s);
     return GRPIC_OK;
 }
 
@@ -626,6 +629,8 @@ int grpic_batch_submit(grpic_batch_t *b, const grpic_config *cfg, int32_t nsteps
     clear_foreign_error();
     if (!b || !cfg || nsteps < 1 || !n || !x || !ucov || !run_id) return GRPIC_EINVAL;
     if (cfg->alloc || cfg->precision != GRPIC_FP32_MIXED) return GRPIC_EINVAL;
+    // the batched stage launches carry no outer absorbing layer
+    if (cfg->outer_layer > 0.0 && cfg->outer_damp > 0.0) return GRPIC_EINVAL;
     int rc = validate(cfg);
     if (rc) return rc;
     int64_t bytes = run_bytes(cfg);
@@ -1090,6 +1095,8 @@ void state_key(const grpic_config *c, grpic_config *k) {
     k->r_exc = c->r_exc;
     k->r_damp = c->r_damp;
     k->damp_max = c->damp_max;
+    k->outer_layer = c->outer_layer;
+    k->outer_damp = c->outer_damp;
     for (int i = 0; i < GRPIC_MAX_SPECIES; i++) {
         k->charge[i] = c->charge[i];
         k->mass[i] = c->mass[i];
@@ -1214,11 +1221,11 @@ int grpic_diagnostics(grpic_t *h, grpic_diag *out) {
     if (h->mixed) {
         launch_derived<float>(h->G, h->h, h->F32, true, true, true, s);
         rc = run_diag<float>(h->G, h->h, h->cfg.c, h->rscale, h->S, P, n, h->F32, h->cfg.r_damp, h->cfg.damp_max,
-                             h->rho_scratch, h->red, h->red_cap, d, s);
+                             h->cfg.outer_layer, h->cfg.outer_damp, h->rho_scratch, h->red, h->red_cap, d, s);
     } else {
         launch_derived<double>(h->G, h->h, h->F64, true, true, true, s);
         rc = run_diag<double>(h->G, h->h, h->cfg.c, h->rscale, h->S, P, n, h->F64, h->cfg.r_damp, h->cfg.damp_max,
-                              h->rho_scratch, h->red, h->red_cap, d, s);
+                              h->cfg.outer_layer, h->cfg.outer_damp, h->rho_scratch, h->red, h->red_cap, d, s);
     }
     if (rc) return GRPIC_EDEVICE;
     unsigned long long cnt[C_NCOUNTERS];

@@ -100,13 +100,21 @@ __device__ __forceinline__ bool relaxed_e(const Grid &G, const Hole &h, double r
     return ks_radius(h.a, X - h.cx, Y - h.cy, Z - h.cz) < r_damp;
 }
 
+// Whether the E point c at (i, j, k) lies in the outer absorbing layer.
+__device__ __forceinline__ bool outer_e(const Grid &G, double L, double damp, int c, int i, int j, int k) {
+    if (!(L > 0.0) || !(damp > 0.0)) return false;
+    double X = i + (c == 0 ? 0.5 : 0.0), Y = j + (c == 1 ? 0.5 : 0.0), Z = k + (c == 2 ? 0.5 : 0.0);
+    return outer_distance(G, X, Y, Z) < L;
+}
+
 // Field sums over index (i,j,k) in [0,n]^3: 0 sum -E_cov D over E points,
-// 1 sum B H over B points, 2 max Gauss residual at checked nodes.
+// 1 sum B H over B points, 2 max Gauss residual at checked nodes (not in the
+// inner relaxation layer or the outer absorbing layer).
 constexpr int kNVf = 3;
 template <typename T>
 __global__ __launch_bounds__(kDiagBlock) void k_diag_fields(Grid G, Hole h, FieldPtrsT<T> F, double rscale, double r_damp,
-                                                            double damp_max, const unsigned long long *rho,
-                                                            double *out) {
+                                                            double damp_max, double outer_layer, double outer_damp,
+                                                            const unsigned long long *rho, double *out) {
     int64_t nn = G.nnodes();
     int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     double v[kNVf] = {0.0, 0.0, 0.0};
@@ -129,7 +137,9 @@ __global__ __launch_bounds__(kDiagBlock) void k_diag_fields(Grid G, Hole h, Fiel
                 im[c] -= 1;
                 if (!(F.mask[gi] & (1u << c)) || !(F.mask[gi - st[c]] & (1u << c))) ok = false;
                 if (relaxed_e(G, h, r_damp, damp_max, c, i, j, k) ||
-                    relaxed_e(G, h, r_damp, damp_max, c, im[0], im[1], im[2]))
+                    relaxed_e(G, h, r_damp, damp_max, c, im[0], im[1], im[2]) ||
+                    outer_e(G, outer_layer, outer_damp, c, i, j, k) ||
+                    outer_e(G, outer_layer, outer_damp, c, im[0], im[1], im[2]))
                     ok = false;
                 div += (double)F.D[c][gi] - (double)F.D[c][gi - st[c]];
             }
@@ -144,8 +154,8 @@ __global__ __launch_bounds__(kDiagBlock) void k_diag_fields(Grid G, Hole h, Fiel
 
 template <typename T>
 int run_diag(const Grid &G, const Hole &h, double c, double rscale, const Species &S, ParticlePtrs P, int64_t n,
-             FieldPtrsT<T> &F, double r_damp, double damp_max, unsigned long long *rho_scratch, double *red_scratch,
-             int64_t red_cap, DiagOut &out, hipStream_t s) {
+             FieldPtrsT<T> &F, double r_damp, double damp_max, double outer_layer, double outer_damp,
+             unsigned long long *rho_scratch, double *red_scratch, int64_t red_cap, DiagOut &out, hipStream_t s) {
     int64_t nbp = n > 0 ? (n + kDiagBlock - 1) / kDiagBlock : 0;
     int64_t nbf = (G.nnodes() + kDiagBlock - 1) / kDiagBlock;
     if (nbp * kNVp + nbf * kNVf > red_cap) return -1;
@@ -156,7 +166,7 @@ int run_diag(const Grid &G, const Hole &h, double c, double rscale, const Specie
         hipLaunchKernelGGL(k_diag_particles, dim3((unsigned)nbp), dim3(kDiagBlock), 0, s, G, h, c, rscale, S, P, n,
                            rho_scratch, pp);
     hipLaunchKernelGGL(k_diag_fields<T>, dim3((unsigned)nbf), dim3(kDiagBlock), 0, s, G, h, F, rscale, r_damp,
-                       damp_max, rho_scratch, pf);
+                       damp_max, outer_layer, outer_damp, rho_scratch, pf);
     std::vector<double> hp(nbp * kNVp), hf(nbf * kNVf);
     if (nbp > 0 && hipMemcpyAsync(hp.data(), pp, hp.size() * sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess)
         return -2;
@@ -192,10 +202,10 @@ int run_diag(const Grid &G, const Hole &h, double c, double rscale, const Specie
 }
 
 template int run_diag<double>(const Grid &, const Hole &, double, double, const Species &, ParticlePtrs, int64_t,
-                              FieldPtrsT<double> &, double, double, unsigned long long *, double *, int64_t,
-                              DiagOut &, hipStream_t);
+                              FieldPtrsT<double> &, double, double, double, double, unsigned long long *, double *,
+                              int64_t, DiagOut &, hipStream_t);
 template int run_diag<float>(const Grid &, const Hole &, double, double, const Species &, ParticlePtrs, int64_t,
-                             FieldPtrsT<float> &, double, double, unsigned long long *, double *, int64_t, DiagOut &,
-                             hipStream_t);
+                             FieldPtrsT<float> &, double, double, double, double, unsigned long long *, double *,
+                             int64_t, DiagOut &, hipStream_t);
 
 }  // namespace grpic

@@ -326,6 +326,32 @@ __device__ __forceinline__ void relax_at(const Grid &G, const Hole &h, const Fie
         }
 }
 
+// Outer absorbing layer at node index id (all three components of both
+// kinds): updated points closer than L to the nearest face relax toward
+// their initial values by damp ((L - d)/L)^2.
+template <typename T>
+__device__ __forceinline__ void relax_outer_at(const Grid &G, const FieldPtrsT<T> &F, double L, double damp,
+                                               int64_t id) {
+    int i, j, k;
+    node_ijk(G, id, i, j, k);
+    int64_t gi = G.g(i, j, k);
+    uint8_t mk = F.mask[gi];
+    for (int kind = 0; kind < 2; kind++)
+        for (int c = 0; c < 3; c++) {
+            if (!(mk & (1u << (kind * 3 + c)))) continue;
+            double X = i + ((kind == 0 ? c == 0 : c != 0) ? 0.5 : 0.0);
+            double Y = j + ((kind == 0 ? c == 1 : c != 1) ? 0.5 : 0.0);
+            double Z = k + ((kind == 0 ? c == 2 : c != 2) ? 0.5 : 0.0);
+            double d = outer_distance(G, X, Y, Z);
+            if (!(d < L)) continue;
+            double tt = (L - d) / L;
+            double sg = damp * tt * tt;
+            T *Fp = kind == 0 ? F.D[c] : F.B[c];
+            const T *F0 = kind == 0 ? F.D0[c] : F.B0[c];
+            Fp[gi] -= (T)sg * (Fp[gi] - F0[gi]);
+        }
+}
+
 // Node tensor F^a_b = F^{ag} g_{gb} from the node pair completed by S.
 template <typename T>
 __device__ __forceinline__ void node_tensor_at(const Grid &G, const Hole &h, const FieldPtrsT<T> &F, int64_t id) {
@@ -396,6 +422,11 @@ __global__ void k_relax(Grid G, Hole h, FieldPtrsT<T> F, double r_damp, double d
     int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int box[6] = {i0, j0, k0, bx, by, bz};
     if (id < (int64_t)bx * by * bz) relax_at<T>(G, h, F, r_damp, damp_max, box, id);
+}
+template <typename T>
+__global__ void k_relax_outer(Grid G, FieldPtrsT<T> F, double L, double damp) {
+    int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (id < G.nnodes()) relax_outer_at(G, F, L, damp, id);
 }
 template <typename T>
 __global__ void k_node_tensor(Grid G, Hole h, FieldPtrsT<T> F) {
@@ -514,6 +545,11 @@ void launch_relax(const Grid &G, const Hole &h, FieldPtrsT<T> &F, double r_damp,
     hipLaunchKernelGGL(k_relax<T>, dim3(nblk((int64_t)box[3] * box[4] * box[5], 128)), dim3(128), 0, s, G, h, F,
                        r_damp, damp_max, box[0], box[1], box[2], box[3], box[4], box[5]);
 }
+template <typename T>
+void launch_relax_outer(const Grid &G, FieldPtrsT<T> &F, double L, double damp, hipStream_t s) {
+    if (!(L > 0.0) || !(damp > 0.0)) return;
+    hipLaunchKernelGGL(k_relax_outer<T>, dim3(nblk(G.nnodes(), 256)), dim3(256), 0, s, G, F, L, damp);
+}
 
 // ---------------------------------------------------------------------------
 // Serving batch: one persistent launch per field stage over the logical
@@ -599,6 +635,7 @@ template <typename T> void launch_node_tensor(const Grid &G, const Hole &h, Fiel
     template void launch_dstep<T>(const Grid &, FieldPtrsT<T> &, const T *const *, double, double, double,  \
                                   hipStream_t);                                                             \
     template void launch_relax<T>(const Grid &, const Hole &, FieldPtrsT<T> &, double, double, hipStream_t); \
+    template void launch_relax_outer<T>(const Grid &, FieldPtrsT<T> &, double, double, hipStream_t);          \
     template void launch_node_tensor<T>(const Grid &, const Hole &, FieldPtrsT<T> &, hipStream_t);          \
     template void launch_save<T>(const Grid &, FieldPtrsT<T> &, int, hipStream_t);
 GRPIC_FIELD_INSTANTIATE(double)

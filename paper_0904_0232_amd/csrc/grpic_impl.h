@@ -57,6 +57,13 @@ struct Species {
     double mass[kMaxSpecies];
 };
 
+// Distance of a point (node coordinates) from the nearest outer face.
+__device__ __forceinline__ double outer_distance(const Grid &G, double X, double Y, double Z) {
+    double d = fmin(X, (double)G.nx - X);
+    d = fmin(d, fmin(Y, (double)G.ny - Y));
+    return fmin(d, fmin(Z, (double)G.nz - Z));
+}
+
 // Device counters, one 64-bit word each.
 enum Counter {
     C_NALIVE = 0,      // live slots after the last compaction (unused while 0)
@@ -105,6 +112,10 @@ void launch_dstep(const Grid &G, FieldPtrsT<T> &F, const T *const Din[3], double
                   double inv_jscale, hipStream_t s);
 template <typename T>
 void launch_relax(const Grid &G, const Hole &h, FieldPtrsT<T> &F, double r_damp, double damp_max, hipStream_t s);
+// Outer absorbing layer: updated points closer than L to the nearest face
+// relax toward their initial values by damp ((L - d)/L)^2.
+template <typename T>
+void launch_relax_outer(const Grid &G, FieldPtrsT<T> &F, double L, double damp, hipStream_t s);
 template <typename T> void launch_node_tensor(const Grid &G, const Hole &h, FieldPtrsT<T> &F, hipStream_t s);
 // Bsave <- B (which = 0) or Dsave <- D (which = 1), all three components.
 template <typename T> void launch_save(const Grid &G, FieldPtrsT<T> &F, int which, hipStream_t s);
@@ -227,7 +238,7 @@ struct DiagOut {
 // P: FP64 particle view (the FP32-mixed form is widened into scratch first)
 template <typename T>
 int run_diag(const Grid &G, const Hole &h, double c, double rscale, const Species &S, ParticlePtrs P, int64_t n,
-             FieldPtrsT<T> &F, double r_damp, double damp_max, unsigned long long *rho_scratch, double *red_scratch,
-             int64_t red_cap, DiagOut &out, hipStream_t s);
+             FieldPtrsT<T> &F, double r_damp, double damp_max, double outer_layer, double outer_damp,
+             unsigned long long *rho_scratch, double *red_scratch, int64_t red_cap, DiagOut &out, hipStream_t s);
 
 }  // namespace grpic

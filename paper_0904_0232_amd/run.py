@@ -10,7 +10,7 @@ def make_config(n, *, m, a, dt, B0=(0.0, 0.0, 0.0), species=((-1.0, 1.0),), c=1.
                 deposit_mode=capi.DEPOSIT_CURVED, field_iters=3, sort_every=0, tile=8, fp_bits=44,
                 capacity=0, precision=capi.FP64, init_covariant=False, ny=None, nz=None, center=None,
                 rk_mode=capi.RK_CLASSIC, gather_mode=capi.GATHER_STAGE,
-                gather_weights=capi.WEIGHTS_TRILINEAR):
+                gather_weights=capi.WEIGHTS_TRILINEAR, outer_layer=0.0, outer_damp=0.0):
     ny = n if ny is None else ny
     nz = n if nz is None else nz
     cfg = capi.grpic_config_default(n, ny, nz)
@@ -34,6 +34,7 @@ def make_config(n, *, m, a, dt, B0=(0.0, 0.0, 0.0), species=((-1.0, 1.0),), c=1.
     cfg.r_exc = 0.5 * rp if r_exc is None else r_exc
     cfg.r_damp = rp if r_damp is None else r_damp
     cfg.damp_max = damp_max
+    cfg.outer_layer, cfg.outer_damp = outer_layer, outer_damp
     cfg.init_covariant = 1 if init_covariant else 0
     cfg.nspecies = len(species)
     for i, (q, mass) in enumerate(species):

@@ -95,11 +95,13 @@ CASES = [
     dict(m=1.5, a=1.2, gamma_mode=1, deposit_mode=1),
     # the units of the paper's application: c = 0.05, dt = 1
     dict(m=1.5, a=1.2, gamma_mode=0, deposit_mode=0, c=0.05, dt=1.0),
+    # the outer absorbing layer
+    dict(m=1.5, a=1.2, gamma_mode=0, deposit_mode=0, outer_layer=4.0, outer_damp=0.3),
 ]
 
 
-@pytest.mark.parametrize("case", CASES, ids=lambda c: "m%.1f_a%.1f_g%d_d%d_c%g" % (c["m"], c["a"], c["gamma_mode"],
-                                                                                  c["deposit_mode"], c.get("c", 1.0)))
+@pytest.mark.parametrize("case", CASES, ids=lambda c: "m%.1f_a%.1f_g%d_d%d_c%g_L%g" % (
+    c["m"], c["a"], c["gamma_mode"], c["deposit_mode"], c.get("c", 1.0), c.get("outer_layer", 0.0)))
 def test_cycle_parity_small(case):
     N = 16
     case = dict(case)
@@ -123,6 +125,26 @@ def test_cycle_parity_small(case):
     do, dg = s.diag(), r.diag()
     for k in ("n_alive", "n_removed_horizon", "n_removed_outer", "gamma_clamps", "flags"):
         assert do[k] == dg[k], (k, do[k], dg[k])
+
+
+def test_outer_layer_gauss_law_elsewhere():
+    """Flat deposit with the outer absorbing layer: on the GPU, as in the
+    oracle, Gauss's law holds to round-off at every node the diagnostic
+    checks (outside the relaxation layers), and the relaxed fields agree."""
+    N = 16
+    P = params(N, m=1.5, a=0.75, dt=0.5, B0=(0.0, 0.0, 0.05), species=((-0.01, 0.01), (0.01, 0.2)),
+               deposit_mode=1, outer_layer=4.0, outer_damp=0.3)
+    parts = _small_parts(13, 3000, N)
+    p, s = oracle_sim(P, 6000)
+    r = gpu_run(P, 6000, fp_bits=FPB)
+    _load_both(P, s, r, parts)
+    s.step(4)
+    r.step(4)
+    do, dg = s.diag(), r.diag()
+    say("outer layer: Gauss residual oracle %.2e GPU %.2e" % (do["gauss_residual_max"], dg["gauss_residual_max"]))
+    assert do["gauss_residual_max"] < 1e-12 and dg["gauss_residual_max"] < 1e-9
+    _cmp_field(r.fields("B"), s.get("B"), "B")
+    _cmp_field(r.fields("D"), s.get("D"), "D", abs_floor=4 * np.pi * P["dt"] * _j_floor(P))
 
 
 def test_schwarzschild32_parity_every_step():
