@@ -277,7 +277,8 @@ def jet_study(snapshots=(0, 50, 100, 150, 200, 250, 300, 350, 400, 450, 500)):
     qualitative: at each snapshot, the particles within 16 cells of the axis,
     more than 8 cells from the mid-plane and moving away from it faster than
     0.05 c, above and below the plane, their speeds, mean azimuthal velocity
-    and median distance from the axis, and the same with no field.
+    and median distance from the axis, the same with no field, and with an
+    8-cell outer absorbing layer instead of frozen outer faces.
     Throughput is particle-steps per second of the timed steps."""
     import numpy as np
     import torch
@@ -290,11 +291,11 @@ def jet_study(snapshots=(0, 50, 100, 150, 200, 250, 300, 350, 400, 450, 500)):
     cen = np.array(w["center"])
     out = {"workload": "jet64x64x128", "particles": ntot, "m": w["m"], "a": w["a"], "c": w["c"], "dt": w["dt"],
            "runs": {}}
-    for name, prec, b0 in (("B30_fp64", capi.FP64, w["B0"]), ("B30_fp32", capi.FP32_MIXED, w["B0"]),
-                           ("B0_fp64", capi.FP64, 0.0)):
+    for name, prec, b0, layer in (("B30_fp64", capi.FP64, w["B0"], 0.0), ("B30_fp32", capi.FP32_MIXED, w["B0"], 0.0),
+                                  ("B0_fp64", capi.FP64, 0.0, 0.0), ("B30_fp64_absorbing", capi.FP64, w["B0"], 8.0)):
         cfg = R.make_config(w["nx"], ny=w["ny"], nz=w["nz"], m=w["m"], a=w["a"], c=w["c"], dt=w["dt"],
                             B0=(0.0, 0.0, b0), species=w["species"], r_rm=w["r_rm"], sort_every=5, capacity=ntot,
-                            precision=prec, center=w["center"])
+                            precision=prec, center=w["center"], outer_layer=layer, outer_damp=0.3 if layer else 0.0)
         r = R.Run(cfg)
         for sp, x, uc in parts:
             r.load(sp, x, uc)
