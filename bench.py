@@ -536,7 +536,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--workload", default="kerr64")
     ap.add_argument("--sort-every", type=int, default=5)
-    ap.add_argument("--cpu-sample", type=int, default=1 << 20, help="particles per species for the oracle timing")
+    ap.add_argument("--cpu-sample", type=int, default=3 << 19, help="particles per species for the oracle timing")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true", help="skip the FP32-mixed measurement")
     ap.add_argument("--scale", action="store_true",
