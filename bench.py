@@ -269,6 +269,35 @@ def serving(args):
     }
 
 
+def preemption_study(args, n_runs=64, slots=8, urgent_frac=0.1, load=0.9):
+    """Urgent requests with and without preemption: n_runs requests (50-200
+    steps, otherwise the serving workload), a fraction urgent_frac of them
+    urgent, arriving at `load` of the loop's saturated capacity with `slots`
+    slots, so slots are contended.  Reports latency percentiles of urgent and
+    normal requests in both policies."""
+    from paper_0904_0232_amd import serve
+    budget = int(args.serve_budget_gb * (1 << 30))
+
+    def reqs_at(rate, seed):
+        return serve.make_requests(n_runs, seed, rate, steps_range=(50, 200), urgent_frac=urgent_frac)
+
+    probe = serve.serve(serve.make_requests(32, 1, 1e6, steps_range=(50, 200)), budget, slots)
+    capacity = probe["particle_steps_per_s"]
+    work = sum(2 * r["ppc"] * r["edge"] ** 3 * r["steps"] for r in reqs_at(1.0, 2)) / n_runs
+    rate = load * capacity / work
+    out = {"workload": "%d requests, 50-200 steps, otherwise the serving workload; %g urgent; %d slots; "
+                       "Poisson arrivals at %g of the saturated capacity (seed 2)" % (n_runs, urgent_frac, slots, load),
+           "saturated_particle_steps_per_s": capacity}
+    for name, pre in (("fifo", False), ("preempt", True)):
+        res = serve.serve(reqs_at(rate, 2), budget, slots, preempt=pre)
+        out[name] = {"urgent": res["urgent"], "normal": res["normal"], "preemptions": res["preemptions"],
+                     "makespan_s": res["makespan_s"], "particle_steps_per_s": res["particle_steps_per_s"]}
+        log("preemption study %s: urgent p50 %.3f p99 %.3f s, normal p50 %.3f p99 %.3f s, %d preemptions" %
+            (name, res["urgent"]["p50_latency_s"], res["urgent"]["p99_latency_s"], res["normal"]["p50_latency_s"],
+             res["normal"]["p99_latency_s"], res["preemptions"]))
+    return out
+
+
 def jet_study(snapshots=(0, 50, 100, 150, 200, 250, 300, 350, 400, 450, 500)):
     """The paper's application (Sec. 6, inputs.jet_params for the readings):
     500 steps of the disk + corona workload on 64 x 64 x 128 with B^z = 30,
@@ -552,6 +581,8 @@ def main():
     ap.add_argument("--serve-runs", type=int, default=256, help="requests in the serving measurement (0 skips it)")
     ap.add_argument("--serve-budget-gb", type=float, default=64.0)
     ap.add_argument("--serve-slots", type=int, default=64)
+    ap.add_argument("--preemption", action="store_true",
+                    help="add the urgent-request study (FIFO admission vs preemption, 8 slots)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -622,6 +653,8 @@ def main():
         line["ablations_kerr64"] = ablation_study()
     if args.jet:
         line["jet"] = jet_study()
+    if args.preemption:
+        line["preemption"] = preemption_study(args)
     if not args.no_cpu_baseline:
         line["cpu_baseline"], ostate = cpu_baseline(args.workload, args.cpu_sample)
         log("cpu baseline: %.4g particle-steps/s" % line["cpu_baseline"]["value"])

@@ -235,7 +235,8 @@ const char *grpic_strerror(int code);
 /* ------------------------------------------------------------------------
  * Serving: continuous batching of independent FP32-mixed runs.  A batch
  * owns up to max_slots (at most 64) runs whose device memory together stays
- * within budget_bytes.  Each admitted run keeps its state on the device.
+ * within budget_bytes.  Each admitted run keeps its state on the device
+ * until it finishes or is preempted (grpic_batch_preempt).
  * One batch iteration advances every active run by one cycle with a single
  * set of batched launches (one per stage of the cycle, each covering the
  * particles or grid points of all runs), captured once as a HIP graph and
@@ -248,7 +249,7 @@ const char *grpic_strerror(int code);
  * ------------------------------------------------------------------------ */
 typedef struct grpic_batch_s grpic_batch_t;
 
-enum { GRPIC_RUN_UNKNOWN = 0, GRPIC_RUN_ACTIVE = 1, GRPIC_RUN_DONE = 2 };
+enum { GRPIC_RUN_UNKNOWN = 0, GRPIC_RUN_ACTIVE = 1, GRPIC_RUN_DONE = 2, GRPIC_RUN_PREEMPTED = 3 };
 
 /* Device bytes a run with this configuration allocates (admission estimate). */
 int64_t grpic_run_bytes(const grpic_config *cfg);
@@ -280,8 +281,30 @@ int grpic_batch_poll(grpic_batch_t *b, int64_t run_id, int32_t *state, int32_t *
 /* Copy a finished run's kept final particle state (layout of grpic_dump_particles). */
 int grpic_batch_dump(grpic_batch_t *b, int64_t run_id, double *x, double *u, uint8_t *sp);
 
-/* Forget a finished run (its memory was already returned at completion). */
+/* Forget a finished or preempted run (its device memory was already
+ * returned at completion or preemption).  GRPIC_ESTATE for an active run. */
 int grpic_batch_release(grpic_batch_t *b, int64_t run_id);
+
+/* Preemption, built on the checkpoint format of grpic_save_state.
+ *
+ * grpic_batch_state_bytes: the size of an active run's state (< 0: an error
+ * code; GRPIC_ESTATE unless the run is active).
+ * grpic_batch_preempt: wait for the batch's queued work, save the active
+ * run's state into buf (host memory, 8-byte aligned, bytes >= the state
+ * size; the caller owns it), then free the run's device memory and slot.
+ * The run keeps its id and cycle count in state GRPIC_RUN_PREEMPTED and no
+ * longer advances.  On an error (a short or misaligned buffer: GRPIC_EINVAL)
+ * the run stays active and unchanged.
+ * grpic_batch_resume: re-admit a preempted run from the state its preemption
+ * saved, when a slot and the budget allow it (else GRPIC_EAGAIN, nothing
+ * changes).  A state that is not this run's, or was taken after a different
+ * number of cycles, gives GRPIC_EINVAL and the run stays preempted.  The run
+ * then continues bit-identically to a run that was never preempted, and
+ * finishes after the nsteps it was submitted with.
+ * Unknown ids give GRPIC_EINVAL. */
+int64_t grpic_batch_state_bytes(grpic_batch_t *b, int64_t run_id);
+int grpic_batch_preempt(grpic_batch_t *b, int64_t run_id, void *buf, int64_t bytes);
+int grpic_batch_resume(grpic_batch_t *b, int64_t run_id, const void *buf, int64_t bytes);
 
 /* Active runs and device bytes they hold. */
 int grpic_batch_stats(grpic_batch_t *b, int32_t *active, int64_t *bytes_in_use);

@@ -74,8 +74,9 @@ class GrpicError(RuntimeError):
 
 
 EINVAL = -1
+ESTATE = -5
 EAGAIN = -6
-RUN_UNKNOWN, RUN_ACTIVE, RUN_DONE = 0, 1, 2
+RUN_UNKNOWN, RUN_ACTIVE, RUN_DONE, RUN_PREEMPTED = 0, 1, 2, 3
 
 
 _lib = None
@@ -134,6 +135,10 @@ def lib():
         L.grpic_batch_dump.argtypes = [_H, ctypes.c_int64, _D, _D, _U8]
         L.grpic_batch_release.argtypes = [_H, ctypes.c_int64]
         L.grpic_batch_stats.argtypes = [_H, ctypes.POINTER(ctypes.c_int32), _I64]
+        L.grpic_batch_state_bytes.argtypes = [_H, ctypes.c_int64]
+        L.grpic_batch_state_bytes.restype = ctypes.c_int64
+        L.grpic_batch_preempt.argtypes = [_H, ctypes.c_int64, ctypes.c_void_p, ctypes.c_int64]
+        L.grpic_batch_resume.argtypes = [_H, ctypes.c_int64, ctypes.c_void_p, ctypes.c_int64]
         L.grpic_batch_destroy.argtypes = [_H]
         L.grpic_batch_destroy.restype = None
         L.grpic_destroy.argtypes = [_H]
@@ -146,7 +151,7 @@ def lib():
                      "grpic_dump_nodes", "grpic_sort", "grpic_set_timing", "grpic_read_timing",
                      "grpic_particle_steps", "grpic_batch_create", "grpic_batch_submit",
                      "grpic_batch_step", "grpic_batch_poll", "grpic_batch_dump", "grpic_batch_release",
-                     "grpic_batch_stats"):
+                     "grpic_batch_stats", "grpic_batch_preempt", "grpic_batch_resume"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -386,6 +391,29 @@ def grpic_batch_dump(b, run_id, n_slots):
 
 def grpic_batch_release(b, run_id):
     _check(lib().grpic_batch_release(b, int(run_id)))
+
+
+def grpic_batch_preempt(b, run_id):
+    """Save an active run's state and free its slot and memory; returns the
+    state as a uint8 array, the format of grpic_save_state."""
+    nb = lib().grpic_batch_state_bytes(b, int(run_id))
+    _check(int(nb) if nb < 0 else 0)
+    buf = np.zeros((nb + 7) // 8, dtype=np.uint64)  # 8-byte aligned
+    _check(lib().grpic_batch_preempt(b, int(run_id), buf.ctypes.data, nb))
+    return buf.view(np.uint8)[:nb]
+
+
+def grpic_batch_resume(b, run_id, state):
+    """Re-admit a preempted run from its saved state; False when the batch
+    has no free slot or memory right now."""
+    state = np.asarray(state, dtype=np.uint8)
+    buf = np.zeros((state.size + 7) // 8, dtype=np.uint64)
+    buf.view(np.uint8)[:state.size] = state
+    rc = lib().grpic_batch_resume(b, int(run_id), buf.ctypes.data, state.size)
+    if rc == EAGAIN:
+        return False
+    _check(rc)
+    return True
 
 
 def grpic_batch_stats(b):

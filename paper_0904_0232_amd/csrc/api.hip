@@ -6,6 +6,7 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <algorithm>
 #include <map>
 #include <new>
 #include <vector>
@@ -463,7 +464,7 @@ int64_t run_bytes(const grpic_config *c) {
         b += 2 * (3 * up(cap * 8) + 4 * up(cap * 8) + up(cap));
     b += up(kCounterWords * 8) + 4 * up(cap * 4) + up((int64_t)sort_temp_bytes(cap)) + up(gs * 8);
     b += up((((cap + 255) / 256) * 12 + ((nn + 255) / 256) * 3 + 64) * 8);
-    b += up(6 * cap * 8);  // load staging
+    b += up(7 * cap * 8);  // staging of a particle load or restore
     return b;
 }
 
@@ -477,7 +478,8 @@ int64_t run_bytes(const grpic_config *c) {
 // the replay, and finished runs are reduced and freed.
 struct BatchRun {
     int64_t id;
-    grpic_t *h;
+    grpic_t *h;                // NULL while preempted or finished
+    grpic_config cfg;          // as submitted, to re-create the run on resume
     int32_t nsteps, done, state;
     int64_t bytes;
     grpic_diag diag;
@@ -645,6 +647,7 @@ int grpic_batch_submit(grpic_batch_t *b, const grpic_config *cfg, int32_t nsteps
         return rc;
     }
     r->id = b->next_id++;
+    r->cfg = *cfg;
     r->nsteps = nsteps;
     r->done = 0;
     r->state = GRPIC_RUN_ACTIVE;
@@ -751,9 +754,60 @@ int grpic_batch_release(grpic_batch_t *b, int64_t run_id) {
     if (!b) return GRPIC_EINVAL;
     auto it = b->runs.find(run_id);
     if (it == b->runs.end()) return GRPIC_EINVAL;
-    if (it->second->state != GRPIC_RUN_DONE) return GRPIC_ESTATE;
+    if (it->second->state != GRPIC_RUN_DONE && it->second->state != GRPIC_RUN_PREEMPTED) return GRPIC_ESTATE;
     delete it->second;
     b->runs.erase(it);
+    return GRPIC_OK;
+}
+
+int64_t grpic_batch_state_bytes(grpic_batch_t *b, int64_t run_id) {
+    if (!b) return GRPIC_EINVAL;
+    auto it = b->runs.find(run_id);
+    if (it == b->runs.end()) return GRPIC_EINVAL;
+    if (it->second->state != GRPIC_RUN_ACTIVE) return GRPIC_ESTATE;
+    return grpic_state_bytes(it->second->h);
+}
+
+int grpic_batch_preempt(grpic_batch_t *b, int64_t run_id, void *buf, int64_t bytes) {
+    clear_foreign_error();
+    if (!b) return GRPIC_EINVAL;
+    auto it = b->runs.find(run_id);
+    if (it == b->runs.end()) return GRPIC_EINVAL;
+    BatchRun *r = it->second;
+    if (r->state != GRPIC_RUN_ACTIVE) return GRPIC_ESTATE;
+    // the save waits for the batch's stream, so no queued launch still
+    // reads the run's memory when it is freed below
+    int rc = grpic_save_state(r->h, buf, bytes);
+    if (rc) return rc;
+    grpic_destroy(r->h);
+    r->h = nullptr;
+    b->used -= r->bytes;
+    r->state = GRPIC_RUN_PREEMPTED;
+    b->active.erase(std::find(b->active.begin(), b->active.end(), r));
+    return GRPIC_OK;
+}
+
+int grpic_batch_resume(grpic_batch_t *b, int64_t run_id, const void *buf, int64_t bytes) {
+    clear_foreign_error();
+    if (!b) return GRPIC_EINVAL;
+    auto it = b->runs.find(run_id);
+    if (it == b->runs.end()) return GRPIC_EINVAL;
+    BatchRun *r = it->second;
+    if (r->state != GRPIC_RUN_PREEMPTED) return GRPIC_ESTATE;
+    if ((int32_t)b->active.size() >= b->max_slots || b->used + r->bytes > b->budget) return GRPIC_EAGAIN;
+    grpic_t *h = nullptr;
+    int rc = grpic_create(&r->cfg, b->stream, &h);
+    if (!rc) rc = grpic_load_state(h, buf, bytes);
+    // the state must be this run's own, taken after the cycles it has done
+    if (!rc && h->step_count != r->done) rc = GRPIC_EINVAL;
+    if (rc) {
+        if (h) grpic_destroy(h);
+        return rc;
+    }
+    r->h = h;
+    r->state = GRPIC_RUN_ACTIVE;
+    b->used += r->bytes;
+    b->active.push_back(r);
     return GRPIC_OK;
 }
 

@@ -5,11 +5,18 @@ a ~ U[0, 0.99] m with m = edge/16, 2-8 particles per cell and species,
 u_th ~ U[0.02, 0.2] c, 50-500 steps, FP32-mixed) arrive as a Poisson
 process.  The loop admits arrived requests first-come-first-served whenever
 the batch has a free slot and HBM budget (``grpic_batch_submit``), advances
-every admitted run by one cycle per iteration (``grpic_batch_step``: each
-run's captured cycle graph on its own stream, so runs overlap on the GPU),
-and records each request's completion latency (arrival -> finished).  The
-initial particles of queued requests are generated on host threads ahead of
-admission.
+every admitted run by one cycle per iteration (``grpic_batch_step``: one
+replay of the captured graph of batched launches, each stage covering all
+active runs), and records each request's completion latency (arrival ->
+finished).  The initial particles of queued requests are generated on host
+threads ahead of admission.
+
+Requests may be urgent (priority 1).  Urgent requests are admitted before
+everything else; with preemption on, an urgent request that does not fit
+preempts normal runs (``grpic_batch_preempt``: state saved to host memory,
+slot and memory freed), the one with the most cycles left first, until it
+fits.  Preempted runs resume (``grpic_batch_resume``) before new normal
+requests are admitted, and finish exactly as if never preempted.
 """
 import collections
 import itertools
@@ -27,9 +34,12 @@ DT = 0.45
 B0 = 0.1
 
 
-def make_requests(n_runs, seed, rate, steps_range=(50, 500), ppc_range=(2, 8), edges=EDGES):
-    """Seeded request list; arrival times of a Poisson process of `rate` per second."""
+def make_requests(n_runs, seed, rate, steps_range=(50, 500), ppc_range=(2, 8), edges=EDGES, urgent_frac=0.0):
+    """Seeded request list; arrival times of a Poisson process of `rate` per
+    second; a fraction urgent_frac of the requests is urgent (drawn from a
+    stream of its own, so the requests themselves do not change with it)."""
     g = inputs.rng(seed, 7)
+    gp = inputs.rng(seed, 8)
     t = 0.0
     reqs = []
     for i in range(n_runs):
@@ -40,7 +50,8 @@ def make_requests(n_runs, seed, rate, steps_range=(50, 500), ppc_range=(2, 8), e
             id=i, arrival=t, edge=edge, m=m, a=float(g.uniform(0.0, 0.99)) * m,
             ppc=int(g.integers(ppc_range[0], ppc_range[1] + 1)),
             steps=int(g.integers(steps_range[0], steps_range[1] + 1)),
-            u_th=float(g.uniform(0.02, 0.2)), seed=int(seed) * 100003 + i))
+            u_th=float(g.uniform(0.02, 0.2)), seed=int(seed) * 100003 + i,
+            priority=int(gp.uniform() < urgent_frac)))
     return reqs
 
 
@@ -61,15 +72,44 @@ def percentile(v, q):
     return float(np.percentile(np.asarray(v, dtype=float), q)) if len(v) else float("nan")
 
 
-def serve(requests, budget_bytes, max_slots, keep_ids=(), prefetch=8, log=None):
+def serve(requests, budget_bytes, max_slots, keep_ids=(), prefetch=8, log=None, preempt=False):
     """Run the request loop to completion.  Returns per-request records and totals."""
     b = capi.grpic_batch_create(budget_bytes, max_slots)
     pool = ThreadPoolExecutor(max_workers=prefetch)
     pending = collections.deque(sorted(requests, key=lambda r: r["arrival"]))
-    waiting = collections.deque()
+    waiting = collections.deque()   # arrived, not admitted (urgent ones first)
+    parked = collections.deque()    # preempted runs: (run id, request, state)
     futures = {}
     active = {}
     records = {}
+    n_preempted = 0
+
+    def nbytes(r):
+        return capi.grpic_run_bytes(request_config(r))
+
+    def make_room(r):
+        # preempt normal runs, the one with the most cycles left first, until
+        # the urgent request r fits; nothing is preempted when r would not fit
+        # beside the urgent runs alone
+        nonlocal n_preempted
+        urgent_runs = [q for q in active.values() if q.get("priority", 0)]
+        if len(urgent_runs) >= max_slots or sum(map(nbytes, urgent_runs)) + nbytes(r) > budget_bytes:
+            return
+        while True:
+            n_active, used = capi.grpic_batch_stats(b)
+            if n_active < max_slots and used + nbytes(r) <= budget_bytes:
+                return
+            left = {rid: q["steps"] - capi.grpic_batch_poll(b, rid)[1]
+                    for rid, q in active.items() if not q.get("priority", 0)}
+            if not left:
+                return
+            victim = max(left, key=lambda rid: (left[rid], -rid))
+            q = active.pop(victim)
+            parked.append((victim, q, capi.grpic_batch_preempt(b, victim)))
+            records[q["id"]]["preemptions"] += 1
+            n_preempted += 1
+            if log:
+                log("run %d preempted with %d cycles left" % (q["id"], left[victim]))
     for r in requests:
         cfg = request_config(r)
         if capi.grpic_run_bytes(cfg) > budget_bytes:
@@ -79,22 +119,41 @@ def serve(requests, budget_bytes, max_slots, keep_ids=(), prefetch=8, log=None):
     iterations = 0
     t_inputs = t_submit = t_step = 0.0  # host time waiting for inputs, admitting, stepping
     try:
-        while pending or waiting or active:
+        while pending or waiting or active or parked:
             now = time.perf_counter() - t0
             while pending and pending[0]["arrival"] <= now:
                 r = pending.popleft()
-                waiting.append(r)
+                if r.get("priority", 0):
+                    # behind the urgent requests already waiting
+                    k = sum(1 for q in waiting if q.get("priority", 0))
+                    waiting.insert(k, r)
+                else:
+                    waiting.append(r)
             # a request carries its particles: the payloads of the next few
             # requests in arrival order are drawn ahead on host threads, so
             # they are ready when the requests arrive
             for q in itertools.islice(itertools.chain(waiting, pending), prefetch):
                 if q["id"] not in futures:
                     futures[q["id"]] = pool.submit(request_particles, q)
-            while waiting:
+            while waiting or parked:
+                urgent = bool(waiting) and bool(waiting[0].get("priority", 0))
+                if parked and not urgent:
+                    # preempted runs go before new normal requests
+                    rid, q, state = parked[0]
+                    ta = time.perf_counter()
+                    ok = capi.grpic_batch_resume(b, rid, state)
+                    t_submit += time.perf_counter() - ta
+                    if not ok:
+                        break
+                    parked.popleft()
+                    active[rid] = q
+                    continue
                 for q in itertools.islice(itertools.chain(waiting, pending), prefetch):
                     if q["id"] not in futures:
                         futures[q["id"]] = pool.submit(request_particles, q)
                 r = waiting[0]
+                if urgent and preempt:
+                    make_room(r)
                 ta = time.perf_counter()
                 parts = futures[r["id"]].result()
                 tb = time.perf_counter()
@@ -107,7 +166,7 @@ def serve(requests, budget_bytes, max_slots, keep_ids=(), prefetch=8, log=None):
                 waiting.popleft()
                 del futures[r["id"]]
                 active[rid] = r
-                records[r["id"]] = dict(r, admitted=time.perf_counter() - t0)
+                records[r["id"]] = dict(r, admitted=time.perf_counter() - t0, preemptions=0)
             if active:
                 ta = time.perf_counter()
                 fin = capi.grpic_batch_step(b)
@@ -135,6 +194,8 @@ def serve(requests, budget_bytes, max_slots, keep_ids=(), prefetch=8, log=None):
         pool.shutdown(wait=False)
         capi.grpic_batch_destroy(b)
     lat = [rec["latency"] for rec in records.values()]
+    lat_u = [rec["latency"] for rec in records.values() if rec.get("priority", 0)]
+    lat_n = [rec["latency"] for rec in records.values() if not rec.get("priority", 0)]
     return {
         "records": records,
         "n_runs": len(records),
@@ -142,6 +203,9 @@ def serve(requests, budget_bytes, max_slots, keep_ids=(), prefetch=8, log=None):
         "iterations": iterations,
         "p50_latency_s": percentile(lat, 50),
         "p99_latency_s": percentile(lat, 99),
+        "urgent": {"n": len(lat_u), "p50_latency_s": percentile(lat_u, 50), "p99_latency_s": percentile(lat_u, 99)},
+        "normal": {"n": len(lat_n), "p50_latency_s": percentile(lat_n, 50), "p99_latency_s": percentile(lat_n, 99)},
+        "preemptions": n_preempted,
         "particle_steps": total_psteps,
         "particle_steps_per_s": total_psteps / makespan if makespan > 0 else 0.0,
         "runs_per_s": len(records) / makespan if makespan > 0 else 0.0,

@@ -6,7 +6,9 @@ Python request loop).
 - the captured cycle graphs replayed by the batch equal eager stepping
   through grpic_step, including a cell sort between replays;
 - admission respects the slot limit and the HBM budget, and queued requests
-  are admitted as earlier ones finish.
+  are admitted as earlier ones finish;
+- a preempted run (state saved, slot freed) resumes later and finishes
+  bit-identically to a run never preempted.
 """
 import numpy as np
 import pytest
@@ -105,3 +107,105 @@ def test_admission_by_slots_and_budget():
     assert all(rec["admitted"] >= rec["arrival"] - 1e-9 for rec in res["records"].values())
     say("budget-limited loop: makespan %.2f s, p50 %.3f s, p99 %.3f s" %
         (res["makespan_s"], res["p50_latency_s"], res["p99_latency_s"]))
+
+
+def test_preempted_runs_resume_bit_identically():
+    """grpic_batch_preempt saves a run's state and frees its slot; a run
+    admitted in its place advances alone; grpic_batch_resume re-admits the
+    preempted run, which then finishes exactly as a run never preempted
+    (diagnostics, particle pushes and final particle state, bit for bit)."""
+    from paper_0904_0232_amd import capi, serve
+    reqs = _reqs(2, seed=13, rate=1000.0, steps=(12, 16), edges=(16,))
+    cfgs = [serve.request_config(r) for r in reqs]
+    parts = [serve.request_particles(r) for r in reqs]
+
+    def result(b, rid):
+        st, done, diag, ns, ps = capi.grpic_batch_poll(b, rid)
+        assert st == capi.RUN_DONE
+        return diag, capi.grpic_batch_dump(b, rid, ns), ps
+
+    def finish(b, rid):
+        while capi.grpic_batch_poll(b, rid)[0] == capi.RUN_ACTIVE:
+            capi.grpic_batch_step(b)
+        return result(b, rid)
+
+    def expect(code, fn, *args):
+        with pytest.raises(capi.GrpicError) as e:
+            fn(*args)
+        assert e.value.code == code
+
+    # reference: both runs side by side, never preempted
+    b = capi.grpic_batch_create(1 << 34, 4)
+    ids = [capi.grpic_batch_submit(b, cfgs[i], reqs[i]["steps"], parts[i], keep_state=True) for i in range(2)]
+    while capi.grpic_batch_stats(b)[0] > 0:
+        capi.grpic_batch_step(b)
+    ref = [result(b, rid) for rid in ids]
+    capi.grpic_batch_destroy(b)
+
+    # one slot: run 0 is preempted after 5 cycles, run 1 takes the slot for 3
+    b = capi.grpic_batch_create(1 << 34, 1)
+    r0 = capi.grpic_batch_submit(b, cfgs[0], reqs[0]["steps"], parts[0], keep_state=True)
+    for _ in range(5):
+        capi.grpic_batch_step(b)
+    state0 = capi.grpic_batch_preempt(b, r0)
+    assert capi.grpic_batch_poll(b, r0)[:2] == (capi.RUN_PREEMPTED, 5)
+    assert capi.grpic_batch_stats(b) == (0, 0)
+    expect(capi.ESTATE, capi.grpic_batch_preempt, b, r0)
+    r1 = capi.grpic_batch_submit(b, cfgs[1], reqs[1]["steps"], parts[1], keep_state=True)
+    assert r1 is not None
+    for _ in range(3):
+        capi.grpic_batch_step(b)
+    assert capi.grpic_batch_poll(b, r0)[:2] == (capi.RUN_PREEMPTED, 5)
+    state1 = capi.grpic_batch_preempt(b, r1)
+    # another run's state, or a damaged one, is refused and nothing changes
+    expect(capi.EINVAL, capi.grpic_batch_resume, b, r0, state1)
+    bad = state0.copy()
+    bad[:8] = 0
+    expect(capi.EINVAL, capi.grpic_batch_resume, b, r0, bad)
+    assert capi.grpic_batch_poll(b, r0)[0] == capi.RUN_PREEMPTED and capi.grpic_batch_stats(b) == (0, 0)
+    assert capi.grpic_batch_resume(b, r0, state0)
+    assert not capi.grpic_batch_resume(b, r1, state1)  # the one slot is taken
+    expect(capi.ESTATE, capi.grpic_batch_release, b, r0)
+    got0 = finish(b, r0)
+    assert capi.grpic_batch_resume(b, r1, state1)
+    got1 = finish(b, r1)
+    capi.grpic_batch_destroy(b)
+
+    for i, (got, want) in enumerate(((got0, ref[0]), (got1, ref[1]))):
+        (dg, (xg, ug, sg), pg), (dw, (xw, uw, sw), pw) = got, want
+        say("run %d: %d slots, %d particle pushes, energy %.12e vs %.12e" %
+            (i, sg.size, pg, dg["energy_particles"], dw["energy_particles"]))
+        live = sw != O.DEAD
+        assert np.array_equal(sg, sw)
+        assert np.array_equal(xg[:, live], xw[:, live]) and np.array_equal(ug[:, live], uw[:, live])
+        assert dg == dw
+        assert pg == pw > 0
+
+
+def test_request_loop_preempts_for_urgent_requests():
+    """Two long normal runs fill both slots; an urgent request arriving just
+    after them preempts one (the loop's admission policy), finishes first,
+    and the preempted run resumes and ends bit-identically to the same
+    request served alone."""
+    from paper_0904_0232_amd import serve
+    base = _reqs(3, seed=17, edges=(16,))
+    reqs = [dict(base[0], arrival=0.0, priority=0, steps=120), dict(base[1], arrival=0.0, priority=0, steps=120),
+            dict(base[2], arrival=0.002, priority=1, steps=20)]
+    keep = (reqs[0]["id"], reqs[1]["id"])
+    res = serve.serve(reqs, 1 << 34, 2, keep_ids=keep, preempt=True)
+    recs = res["records"]
+    say("preemptions %d; finished: %s" % (res["preemptions"],
+        ", ".join("%d at %.3f s" % (k, v["finished"]) for k, v in sorted(recs.items()))))
+    assert res["n_runs"] == 3 and res["preemptions"] >= 1
+    assert recs[reqs[2]["id"]]["finished"] < max(recs[k]["finished"] for k in keep)
+    hit = [k for k in keep if recs[k]["preemptions"] > 0]
+    assert hit
+    for k in hit:
+        r = next(q for q in reqs if q["id"] == k)
+        alone = serve.serve([dict(r, arrival=0.0)], 1 << 34, 1, keep_ids=(k,))["records"][k]
+        (xa, ua, sa), (xp, up, spp) = alone["state"], recs[k]["state"]
+        live = sa != O.DEAD
+        assert np.array_equal(sa, spp)
+        assert np.array_equal(xa[:, live], xp[:, live]) and np.array_equal(ua[:, live], up[:, live])
+        assert alone["diag"] == recs[k]["diag"]
+        assert alone["particle_steps"] == recs[k]["particle_steps"] > 0
