@@ -269,7 +269,7 @@ def serving(args):
     }
 
 
-def preemption_study(args, n_runs=64, slots=8, urgent_frac=0.1, load=0.9):
+def preemption_study(args, n_runs=64, slots=4, urgent_frac=0.2, load=1.5):
     """Urgent requests with and without preemption: n_runs requests (50-200
     steps, otherwise the serving workload), a fraction urgent_frac of them
     urgent, arriving at `load` of the loop's saturated capacity with `slots`
@@ -582,7 +582,7 @@ def main():
     ap.add_argument("--serve-budget-gb", type=float, default=64.0)
     ap.add_argument("--serve-slots", type=int, default=64)
     ap.add_argument("--preemption", action="store_true",
-                    help="add the urgent-request study (FIFO admission vs preemption, 8 slots)")
+                    help="add the urgent-request study (FIFO admission vs preemption, 4 slots)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))

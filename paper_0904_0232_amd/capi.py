@@ -398,7 +398,7 @@ def grpic_batch_preempt(b, run_id):
     state as a uint8 array, the format of grpic_save_state."""
     nb = lib().grpic_batch_state_bytes(b, int(run_id))
     _check(int(nb) if nb < 0 else 0)
-    buf = np.zeros((nb + 7) // 8, dtype=np.uint64)  # 8-byte aligned
+    buf = np.empty((nb + 7) // 8, dtype=np.uint64)  # 8-byte aligned; the save writes every byte used
     _check(lib().grpic_batch_preempt(b, int(run_id), buf.ctypes.data, nb))
     return buf.view(np.uint8)[:nb]
 
@@ -407,8 +407,11 @@ def grpic_batch_resume(b, run_id, state):
     """Re-admit a preempted run from its saved state; False when the batch
     has no free slot or memory right now."""
     state = np.asarray(state, dtype=np.uint8)
-    buf = np.zeros((state.size + 7) // 8, dtype=np.uint64)
-    buf.view(np.uint8)[:state.size] = state
+    if state.flags.c_contiguous and state.ctypes.data % 8 == 0:
+        buf = state  # as returned by grpic_batch_preempt: no copy
+    else:
+        buf = np.zeros((state.size + 7) // 8, dtype=np.uint64)
+        buf.view(np.uint8)[:state.size] = state
     rc = lib().grpic_batch_resume(b, int(run_id), buf.ctypes.data, state.size)
     if rc == EAGAIN:
         return False

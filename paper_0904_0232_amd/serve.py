@@ -14,8 +14,7 @@ threads ahead of admission.
 Requests may be urgent (priority 1).  Urgent requests are admitted before
 everything else; with preemption on, an urgent request that does not fit
 preempts normal runs (``grpic_batch_preempt``: state saved to host memory,
-slot and memory freed), the one with the most cycles left first, until it
-fits.  Preempted runs resume (``grpic_batch_resume``) before new normal
+slot and memory freed), the smallest first, until it fits.  Preempted runs resume (``grpic_batch_resume``) before new normal
 requests are admitted, and finish exactly as if never preempted.
 """
 import collections
@@ -88,9 +87,11 @@ def serve(requests, budget_bytes, max_slots, keep_ids=(), prefetch=8, log=None, 
         return capi.grpic_run_bytes(request_config(r))
 
     def make_room(r):
-        # preempt normal runs, the one with the most cycles left first, until
-        # the urgent request r fits; nothing is preempted when r would not fit
-        # beside the urgent runs alone
+        # preempt normal runs until the urgent request r fits, the cheapest
+        # first (fewest device bytes: the save copies them to the host and
+        # stalls the loop meanwhile), among equals the one with the most
+        # cycles left; nothing is preempted when r would not fit beside the
+        # urgent runs alone
         nonlocal n_preempted
         urgent_runs = [q for q in active.values() if q.get("priority", 0)]
         if len(urgent_runs) >= max_slots or sum(map(nbytes, urgent_runs)) + nbytes(r) > budget_bytes:
@@ -103,7 +104,7 @@ def serve(requests, budget_bytes, max_slots, keep_ids=(), prefetch=8, log=None, 
                     for rid, q in active.items() if not q.get("priority", 0)}
             if not left:
                 return
-            victim = max(left, key=lambda rid: (left[rid], -rid))
+            victim = min(left, key=lambda rid: (nbytes(active[rid]), -left[rid], rid))
             q = active.pop(victim)
             parked.append((victim, q, capi.grpic_batch_preempt(b, victim)))
             records[q["id"]]["preemptions"] += 1

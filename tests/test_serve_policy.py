@@ -5,7 +5,8 @@ byte budget and cycle counts on the host.
 - without preemption, urgent requests jump the queue but never displace a
   running request;
 - with preemption, an urgent request that does not fit preempts normal runs,
-  the one with the most cycles left first, and only as many as it needs;
+  the smallest first (among equals the one with the most cycles left), and
+  only as many as it needs;
 - nothing is preempted when the urgent request would not fit beside the
   urgent runs alone;
 - preempted runs resume before new normal requests and every request
@@ -127,7 +128,7 @@ def test_urgent_jumps_the_queue_without_preemption(loop):
     assert [e[1] for e in log] == [3, 0, 1, 2]  # urgent first; the rest in arrival order
 
 
-def test_preemption_takes_the_run_with_most_cycles_left(loop):
+def test_preemption_among_equal_runs_takes_the_most_cycles_left(loop):
     # two normal runs fill both slots; the urgent one arrives once they run
     reqs = [req(0, 1000), req(1, 800), req(2, 10, priority=1, arrival=0.01)]
     res, log = run_loop(loop, reqs, 100, 2, preempt=True)
@@ -136,6 +137,12 @@ def test_preemption_takes_the_run_with_most_cycles_left(loop):
     assert log.index(("submit", 2)) > log.index(pre[0])
     assert log.index(("resume", 0)) > log.index(("submit", 2))
     assert res["records"][0]["preemptions"] == 1 and res["records"][1]["preemptions"] == 0
+
+
+def test_preemption_takes_the_smallest_run_first(loop):
+    reqs = [req(0, 1000, nbytes=3), req(1, 300, nbytes=1), req(2, 10, priority=1, arrival=0.01)]
+    res, log = run_loop(loop, reqs, 100, 2, preempt=True)
+    assert [e[1] for e in log if e[0] == "preempt"] == [1]
 
 
 def test_preempts_only_as_many_as_the_budget_needs(loop):
