@@ -130,7 +130,7 @@ def test_urgent_jumps_the_queue_without_preemption(loop):
 
 def test_preemption_among_equal_runs_takes_the_most_cycles_left(loop):
     # two normal runs fill both slots; the urgent one arrives once they run
-    reqs = [req(0, 1000), req(1, 800), req(2, 10, priority=1, arrival=0.01)]
+    reqs = [req(0, 1000), req(1, 800), req(2, 10, priority=1, arrival=0.03)]
     res, log = run_loop(loop, reqs, 100, 2, preempt=True)
     pre = [e for e in log if e[0] == "preempt"]
     assert res["preemptions"] == 1 and len(pre) == 1 and pre[0][1] == 0
@@ -140,7 +140,7 @@ def test_preemption_among_equal_runs_takes_the_most_cycles_left(loop):
 
 
 def test_preemption_takes_the_smallest_run_first(loop):
-    reqs = [req(0, 1000, nbytes=3), req(1, 300, nbytes=1), req(2, 10, priority=1, arrival=0.01)]
+    reqs = [req(0, 1000, nbytes=3), req(1, 500, nbytes=1), req(2, 10, priority=1, arrival=0.03)]
     res, log = run_loop(loop, reqs, 100, 2, preempt=True)
     assert [e[1] for e in log if e[0] == "preempt"] == [1]
 
@@ -148,7 +148,7 @@ def test_preemption_takes_the_smallest_run_first(loop):
 def test_preempts_only_as_many_as_the_budget_needs(loop):
     # four normal runs of 1 byte in a 4-byte budget; an urgent run of 2 bytes
     # needs two of them gone
-    reqs = [req(i, 600 + 10 * i) for i in range(4)] + [req(9, 5, priority=1, arrival=0.01, nbytes=2)]
+    reqs = [req(i, 600 + 10 * i) for i in range(4)] + [req(9, 5, priority=1, arrival=0.03, nbytes=2)]
     res, log = run_loop(loop, reqs, 4, 8, preempt=True)
     pre = [e[1] for e in log if e[0] == "preempt"]
     assert pre == [3, 2]
@@ -158,7 +158,7 @@ def test_preempts_only_as_many_as_the_budget_needs(loop):
 def test_no_preemption_when_urgent_runs_fill_the_batch(loop):
     # the second urgent run (2 bytes) cannot fit beside the first (2 bytes) in
     # 3 bytes, so preempting the normal run would not help
-    reqs = [req(0, 100), req(1, 200, priority=1, nbytes=2), req(2, 10, priority=1, arrival=0.01, nbytes=2)]
+    reqs = [req(0, 1000), req(1, 200, priority=1, nbytes=2), req(2, 10, priority=1, arrival=0.03, nbytes=2)]
     res, log = run_loop(loop, reqs, 3, 4, preempt=True)
     assert res["preemptions"] == 0
     assert log.index(("submit", 2)) == len(log) - 1
@@ -166,7 +166,7 @@ def test_no_preemption_when_urgent_runs_fill_the_batch(loop):
 
 def test_resumed_runs_go_before_new_normal_requests(loop):
     # run 2 arrives while the urgent run holds the one slot and run 0 is parked
-    reqs = [req(0, 600), req(1, 150, priority=1, arrival=0.01), req(2, 10, arrival=0.02)]
+    reqs = [req(0, 600), req(1, 150, priority=1, arrival=0.03), req(2, 10, arrival=0.04)]
     res, log = run_loop(loop, reqs, 100, 1, preempt=True)
     assert [e[1] for e in log if e[0] == "preempt"] == [0]
     assert log.index(("resume", 0)) < log.index(("submit", 2))
