@@ -297,10 +297,11 @@ int grpic_batch_release(grpic_batch_t *b, int64_t run_id);
  * the run stays active and unchanged.
  * grpic_batch_resume: re-admit a preempted run from the state its preemption
  * saved, when a slot and the budget allow it (else GRPIC_EAGAIN, nothing
- * changes).  A state that is not this run's, or was taken after a different
- * number of cycles, gives GRPIC_EINVAL and the run stays preempted.  The run
- * then continues bit-identically to a run that was never preempted, and
- * finishes after the nsteps it was submitted with.
+ * changes).  A state saved under another configuration or after a different
+ * number of cycles than the run has done gives GRPIC_EINVAL, and the run
+ * stays preempted.  Resumed from the state its preemption saved, the run
+ * continues bit-identically to a run that was never preempted, and finishes
+ * after the nsteps it was submitted with.
  * Unknown ids give GRPIC_EINVAL. */
 int64_t grpic_batch_state_bytes(grpic_batch_t *b, int64_t run_id);
 int grpic_batch_preempt(grpic_batch_t *b, int64_t run_id, void *buf, int64_t bytes);

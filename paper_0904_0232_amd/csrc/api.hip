@@ -798,7 +798,8 @@ int grpic_batch_resume(grpic_batch_t *b, int64_t run_id, const void *buf, int64_
     grpic_t *h = nullptr;
     int rc = grpic_create(&r->cfg, b->stream, &h);
     if (!rc) rc = grpic_load_state(h, buf, bytes);
-    // the state must be this run's own, taken after the cycles it has done
+    // the state must be one of this configuration, taken after the cycles the
+    // run has done
     if (!rc && h->step_count != r->done) rc = GRPIC_EINVAL;
     if (rc) {
         if (h) grpic_destroy(h);
