@@ -189,8 +189,10 @@ def test_request_loop_preempts_for_urgent_requests():
     request served alone."""
     from paper_0904_0232_amd import serve
     base = _reqs(3, seed=17, edges=(16,))
-    reqs = [dict(base[0], arrival=0.0, priority=0, steps=120), dict(base[1], arrival=0.0, priority=0, steps=120),
-            dict(base[2], arrival=0.002, priority=1, steps=20)]
+    # a cycle of these runs takes about 0.2 ms, so the normal runs are still
+    # running long after the urgent request arrives
+    reqs = [dict(base[0], arrival=0.0, priority=0, steps=1000), dict(base[1], arrival=0.0, priority=0, steps=1000),
+            dict(base[2], arrival=0.02, priority=1, steps=20)]
     keep = (reqs[0]["id"], reqs[1]["id"])
     res = serve.serve(reqs, 1 << 34, 2, keep_ids=keep, preempt=True)
     recs = res["records"]
