@@ -641,10 +641,10 @@ def main():
         for prec in ("fp32", "fp64"):
             # warm up past the first cell sort (loaded particles are in
             # generation order), as the main measurement does
-            ms = measure("shell256", prec, 20, max(2, args.sort_every), args.sort_every)
+            ms = measure("shell256", prec, 100, max(2, args.sort_every), args.sort_every)
             log("shell256 %s: %.4g particle-steps/s" % (prec, ms["value"]))
             scale[prec] = {"value": ms["value"], "ms_per_step": ms["ms_per_step"], "particles": ms["ntot"],
-                           "kernel_ms_per_launch": ms["kernel_ms_per_launch"], "steps": 20,
+                           "kernel_ms_per_launch": ms["kernel_ms_per_launch"], "steps": 100,
                            "warmup": max(2, args.sort_every)}
         line["throughput_scale_shell256"] = scale
     if args.precision:
