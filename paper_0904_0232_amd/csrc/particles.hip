@@ -12,6 +12,14 @@ namespace grpic {
 __device__ __forceinline__ int wave_min(int v) { return __ockl_wfred_min_i32(v); }
 __device__ __forceinline__ int wave_max(int v) { return __ockl_wfred_max_i32(v); }
 
+// Add a per-lane count to a device counter with one atomic per wavefront:
+// same-address atomics from many waves serialise across the XCDs.  Every
+// lane of the wave must reach the call.
+__device__ __forceinline__ void wave_count(unsigned long long *ctr, int v) {
+    const int s = __ockl_wfred_add_i32(v);
+    if (s != 0 && (threadIdx.x & 63) == 0) atomicAdd(ctr, (unsigned long long)s);
+}
+
 
 // Node tensor rows in LDS: 16 doubles per node padded to 18, so nodes one
 // apart start 4 banks apart.
@@ -227,7 +235,7 @@ __global__ __launch_bounds__(kPushBlock, 4) void k_push(PushParams P, Species cS
         for (int q = 0; q < 3; q++) out.x[q][id] = X0[q] + h6 * Sx[q];
         for (int q = 0; q < 4; q++) out.u[q][id] = U0[q] + h6 * Su[q];
     }
-    if (clamps) atomicAdd(&counters[C_GAMMA_CLAMPS], (unsigned long long)clamps);
+    wave_count(&counters[C_GAMMA_CLAMPS], clamps);
 }
 
 // ---------------------------------------------------------------------------
@@ -359,7 +367,7 @@ __global__ __launch_bounds__(kPushBlock) void k_push_ablation(PushParams P, Spec
         for (int q = 0; q < 3; q++) out.x[q][id] = X0[q] + Sx[q] / 6.0;
         for (int q = 0; q < 4; q++) out.u[q][id] = U0[q] + Su[q] / 6.0;
     }
-    if (clamps) atomicAdd(&counters[C_GAMMA_CLAMPS], (unsigned long long)clamps);
+    if (clamps) atomicAdd(&counters[C_GAMMA_CLAMPS], (unsigned long long)clamps);  // dead lanes have returned
 }
 
 template <int RK, int GA, int WT>
@@ -620,6 +628,7 @@ __global__ __launch_bounds__(kDepBlock) void k_deposit(DepCtx D, Species cS, dou
     }
     LdsAcc la{sm, blo[0], blo[1], blo[2], bx, by, V};
     GlobalAcc ga{{F.Jint[0], F.Jint[1], F.Jint[2]}, D.G};
+    int n_horizon = 0, n_outer = 0;
 #pragma unroll 1
     for (int p = 0; p < kDepPPT; p++) {
         if (SP[p] == kDead) continue;
@@ -669,12 +678,14 @@ __global__ __launch_bounds__(kDepBlock) void k_deposit(DepCtx D, Species cS, dou
                         }
             }
             xo.sp[id] = kDead;
-            atomicAdd(&counters[C_REMOVED_HORIZON], 1ull);
+            n_horizon++;
         } else if (outside) {
             xo.sp[id] = kDead;
-            atomicAdd(&counters[C_REMOVED_OUTER], 1ull);
+            n_outer++;
         }
     }
+    wave_count(&counters[C_REMOVED_HORIZON], n_horizon);
+    wave_count(&counters[C_REMOVED_OUTER], n_outer);
     if (use_lds) {
         __syncthreads();
         const float inv_bx = __builtin_amdgcn_rcpf((float)bx), inv_bxy = __builtin_amdgcn_rcpf((float)(bx * by));

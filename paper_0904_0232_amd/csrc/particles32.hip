@@ -18,6 +18,14 @@ namespace grpic {
 __device__ __forceinline__ int wave_min32(int v) { return __ockl_wfred_min_i32(v); }
 __device__ __forceinline__ int wave_max32(int v) { return __ockl_wfred_max_i32(v); }
 
+// Add a per-lane count to a device counter with one atomic per wavefront:
+// same-address atomics from many waves serialise across the XCDs.  Every
+// lane of the wave must reach the call.
+__device__ __forceinline__ void wave_count32(unsigned long long *ctr, int v) {
+    const int s = __ockl_wfred_add_i32(v);
+    if (s != 0 && (threadIdx.x & 63) == 0) atomicAdd(ctr, (unsigned long long)s);
+}
+
 __device__ __forceinline__ void hole_rel(const Hole &h, int i, int j, int k, const float X[3], double &x, double &y,
                                          double &z) {
     x = ((double)i - h.cx) + (double)X[0];
@@ -260,7 +268,7 @@ __device__ __forceinline__ void push32_block(const PushParams &P, const Mixed &M
         out.cell[id] = pack_cell(cc[0], cc[1], cc[2]);
         for (int q = 0; q < 4; q++) out.u[q][id] = U0[q] + h6 * Su[q];
     }
-    if (clamps) atomicAdd(&counters[C_GAMMA_CLAMPS], (unsigned long long)clamps);
+    wave_count32(&counters[C_GAMMA_CLAMPS], clamps);
 }
 
 __global__ __launch_bounds__(kPush32Block, 4) void k_push32(PushParams P, Mixed M, Species cS,
@@ -528,6 +536,7 @@ __device__ __forceinline__ void deposit32_block(const Dep32 &D, const Species &c
     }
     LdsAcc32 la{sm, blo[0], blo[1], blo[2], bx, by, V};
     GlobalAcc32 ga{{F.Jint[0], F.Jint[1], F.Jint[2]}, D.G};
+    int n_horizon = 0, n_outer = 0;
 #pragma unroll 1
     for (int p = 0; p < kDep32PPT; p++) {
         if (SP[p] == kDead) continue;
@@ -573,12 +582,14 @@ __device__ __forceinline__ void deposit32_block(const Dep32 &D, const Species &c
                         }
             }
             xo.sp[id] = kDead;
-            atomicAdd(&counters[C_REMOVED_HORIZON], 1ull);
+            n_horizon++;
         } else if (outside) {
             xo.sp[id] = kDead;
-            atomicAdd(&counters[C_REMOVED_OUTER], 1ull);
+            n_outer++;
         }
     }
+    wave_count32(&counters[C_REMOVED_HORIZON], n_horizon);
+    wave_count32(&counters[C_REMOVED_OUTER], n_outer);
     if (use_lds) {
         __syncthreads();
         const float inv_bx = __builtin_amdgcn_rcpf((float)bx), inv_bxy = __builtin_amdgcn_rcpf((float)(bx * by));
