@@ -719,11 +719,9 @@ void launch_deposit(const Grid &G, const Hole &h, double dt, int deposit_mode, d
 //   g^{44} u_4^2 + 2 (g^{4i} u_i) u_4 + g^{ij} u_i u_j + c^2 = 0,  u^4 = g^{4b} u_b > 0,
 // then u^a = g^{ab} u_b.  Dropped particles (non-finite, outside the grid,
 // inside r_rm) are stored as dead slots.
-__global__ void k_load(Grid G, Hole h, double c, double r_rm, const double *__restrict__ xin,
-                       const double *__restrict__ ucin, int64_t n, int species, ParticlePtrs out, int64_t off,
-                       unsigned long long *counters) {
-    int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (id >= n) return;
+__device__ __forceinline__ bool load_one(const Grid &G, const Hole &h, double c, double r_rm,
+                                         const double *__restrict__ xin, const double *__restrict__ ucin, int64_t n,
+                                         int species, const ParticlePtrs &out, int64_t off, int64_t id) {
     double X[3] = {xin[id], xin[n + id], xin[2 * n + id]};
     double uc[3] = {ucin[id], ucin[n + id], ucin[2 * n + id]};
     bool ok = true;
@@ -771,7 +769,15 @@ __global__ void k_load(Grid G, Hole h, double c, double r_rm, const double *__re
     for (int ax = 0; ax < 3; ax++) out.x[ax][o] = ok ? X[ax] : 0.0;
     for (int q = 0; q < 4; q++) out.u[q][o] = U[q];
     out.sp[o] = ok ? (uint8_t)species : kDead;
-    if (ok) atomicAdd(&counters[C_LOAD_KEPT], 1ull);
+    return ok;
+}
+
+__global__ void k_load(Grid G, Hole h, double c, double r_rm, const double *__restrict__ xin,
+                       const double *__restrict__ ucin, int64_t n, int species, ParticlePtrs out, int64_t off,
+                       unsigned long long *counters) {
+    const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const bool ok = id < n && load_one(G, h, c, r_rm, xin, ucin, n, species, out, off, id);
+    wave_count(&counters[C_LOAD_KEPT], ok ? 1 : 0);
 }
 
 void launch_load(const Grid &G, const Hole &h, double c, double r_rm, const double *xin, const double *ucin,

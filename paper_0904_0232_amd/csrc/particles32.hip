@@ -683,11 +683,10 @@ void launch_deposit32(const Grid &G, const Hole &h, const Mixed &M, double dt, i
 
 // ---------------------------------------------------------------------------
 // Load: FP64 mass shell (as in the FP64 form), then cell + FP32 offset.
-__global__ void k_load32(Grid G, Hole h, double c, double r_rm, const double *__restrict__ xin,
-                         const double *__restrict__ ucin, int64_t n, int species, ParticlePtrs32 out, int64_t off,
-                         unsigned long long *counters) {
-    int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (id >= n) return;
+__device__ __forceinline__ bool load_one32(const Grid &G, const Hole &h, double c, double r_rm,
+                                           const double *__restrict__ xin, const double *__restrict__ ucin,
+                                           int64_t n, int species, const ParticlePtrs32 &out, int64_t off,
+                                           int64_t id) {
     double X[3] = {xin[id], xin[n + id], xin[2 * n + id]};
     double uc[3] = {ucin[id], ucin[n + id], ucin[2 * n + id]};
     bool ok = true;
@@ -740,7 +739,15 @@ __global__ void k_load32(Grid G, Hole h, double c, double r_rm, const double *__
     out.cell[o] = pack_cell(ci[0], ci[1], ci[2]);
     for (int q = 0; q < 4; q++) out.u[q][o] = (float)U[q];
     out.sp[o] = ok ? (uint8_t)species : kDead;
-    if (ok) atomicAdd(&counters[C_LOAD_KEPT], 1ull);
+    return ok;
+}
+
+__global__ void k_load32(Grid G, Hole h, double c, double r_rm, const double *__restrict__ xin,
+                         const double *__restrict__ ucin, int64_t n, int species, ParticlePtrs32 out, int64_t off,
+                         unsigned long long *counters) {
+    const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const bool ok = id < n && load_one32(G, h, c, r_rm, xin, ucin, n, species, out, off, id);
+    wave_count32(&counters[C_LOAD_KEPT], ok ? 1 : 0);
 }
 
 void launch_load32(const Grid &G, const Hole &h, double c, double r_rm, const double *xin, const double *ucin,
