@@ -118,7 +118,7 @@ __device__ __forceinline__ double stage_gamma(const PushParams &P, double u4, do
 }
 
 constexpr int kPushBlock = 256;
-constexpr int kPushLdsNodes = 256;  // 36 KB of padded node tensor per block
+constexpr int kPushLdsNodes = 272;  // 38 KiB of padded node tensor per block, four blocks per CU
 
 // Stage, once per push, the node box of the cells the block's live lanes
 // start in (cell c, nodes c .. c+1), widened by one cell on every side when
