@@ -4,19 +4,24 @@
 One step = one full GRPIC cycle (magnetic half-step, gather + RK4 push,
 magnetic half-step, current deposition with removal, electric step, and the
 cell sort amortised every sort_every steps) over the resident particle set.
-The workload is the Kerr a = 0.95 m plasma on a 64^3 grid (m = 3 cells,
-8 particles per cell and species, 4,194,304 particles, u_th = 0.1 c,
-B_z = 0.1, dt = 0.45), FP64, synthetic seeded inputs already in HBM when the
-timed region starts.
+The headline workload is the throughput configuration: Kerr a = 0.99 m on a
+256^3 grid (m = 8 cells), 8 particles per cell and species (268,435,456
+particles), uniform Maxwellian plasma u_th = 0.1 c plus a shell at
+|R - 64| <= 2 falling in at v_r = -0.3 c, B_z = 0.1, dt = 0.45, in FP64
+(value) and FP32-mixed (the "fp32_mixed" object), on synthetic seeded inputs
+already in HBM when the timed region starts.  The 64^3 Kerr a = 0.95 m
+workload (4,194,304 particles) is reported as a secondary key.
 
 Prints ONE JSON line.  value = particle pushes per second over the timed
 steps (live particles summed over steps / wall time).  The roofline object
 prices the kernel that takes the most time (the pusher or the deposit; both
 are in "rooflines") by its algorithmic FP64 operation count per particle
 against the MI355X FP64 vector peak, with the average kernel time measured by
-HIP events on the run's stream.  The CPU
-baseline times the FP64 oracle (single thread) on a bounded sample of the
-same workload.
+HIP events on the run's stream.  The CPU baseline times the FP64 oracle on
+windows of the same workload (a 32^3 sub-box with its particles and its own
+field solve, the hole placed by its centre in window coordinates): one
+thread, and independent windows on all host cores.  The GPU's first cycle
+is compared with the oracle's on the window interiors.
 """
 import argparse
 import hashlib
@@ -52,36 +57,42 @@ PUSH_FLOPS_PER_PARTICLE_STEP = 2219
 # per particle.
 DEPOSIT_FLOPS_PER_PARTICLE = 1320
 
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "fp64_particle_kernels_kerr64_traffic.txt")
-PUSH_SOURCES = [os.path.join(ROOT, "paper_0904_0232_amd", "csrc", f) for f in ("particles.hip", "grpic_dev.h")]
+CSRC = os.path.join(ROOT, "paper_0904_0232_amd", "csrc")
+KERNEL_SOURCES = {"fp64": ("particles.hip", "grpic_dev.h", "grpic_impl.h"),
+                  "fp32": ("particles32.hip", "grpic_dev.h", "grpic_impl.h")}
 
 
 def log(msg):
     print("bench: " + msg, file=sys.stderr, flush=True)
 
 
-def push_source_hash():
+def traffic_file(precision, workload):
+    return os.path.join(ROOT, "profiles", "%s_particle_kernels_%s_traffic.txt" % (precision, workload))
+
+
+def kernel_source_hash(precision):
     h = hashlib.sha256()
-    for f in PUSH_SOURCES:
-        with open(f, "rb") as fh:
+    for f in KERNEL_SOURCES[precision]:
+        with open(os.path.join(CSRC, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
 
-def read_traffic(n_per_launch, key="hbm_bytes_per_particle"):
+def read_traffic(n_per_launch, precision, workload, key="hbm_bytes_per_particle"):
     """HBM bytes per launch of the pusher (or, with key
     "deposit_hbm_bytes_per_particle", of the deposit) from the committed
-    rocprofv3 counter summary, or None when the summary is missing or the
-    kernel source changed since."""
-    if not os.path.exists(TRAFFIC_FILE):
+    rocprofv3 counter summary of that precision and workload, or None when
+    the summary is missing or the kernel sources changed since."""
+    path = traffic_file(precision, workload)
+    if not os.path.exists(path):
         return None
     kv = {}
-    with open(TRAFFIC_FILE) as fh:
+    with open(path) as fh:
         for line in fh:
             if "=" in line and not line.lstrip().startswith("#"):
                 k, v = line.split("=", 1)
                 kv[k.strip()] = v.strip()
-    if kv.get("source_sha") != push_source_hash():
+    if kv.get("source_sha") != kernel_source_hash(precision):
         return None
     try:
         per_particle = float(kv[key])
@@ -90,88 +101,196 @@ def read_traffic(n_per_launch, key="hbm_bytes_per_particle"):
     return per_particle * n_per_launch
 
 
-def cpu_baseline(workload, sample_per_species):
-    """The FP64 oracle (one thread) timed on one cycle of a sample of the
-    workload: the first sample_per_species particles of each species.
-    Returns the figures and the oracle's particle state after the cycle."""
+WINDOW = 32        # oracle window edge in cells
+WINDOW_MARGIN = 8  # compared particles start and end this far inside a window
+
+
+def host_info():
+    model = None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count()
+    return {"cpu_model": model, "nproc": os.cpu_count(), "usable_cpus": usable}
+
+
+def window_origins(w, count):
+    """Origins of `count` oracle windows of the workload: the first three at
+    distance R = r_+ + 4 + WINDOW/2 from the hole along x, at n/4 along y and
+    at 0.4 n along (1,1,1) (the hole's neighbourhood, the bulk with the
+    infalling shell, further out); more along other directions at 0.3 n.
+    Every window lies inside the grid and outside r_rm, so the oracle loads
+    each window input it is given, in order."""
+    import numpy as np
+    n, c0 = w["n"], w["n"] / 2.0
+    dirs = [(w["r_plus"] + 4.0 + WINDOW / 2.0, (1.0, 0.0, 0.0)), (n / 4.0, (0.0, 1.0, 0.0)),
+            (0.4 * n, (1.0, 1.0, 1.0))]
+    extra = [(-1, 0, 0), (0, -1, 0), (0, 0, 1), (0, 0, -1), (1, -1, 0), (-1, 1, 0), (1, 1, -1), (-1, -1, 1),
+             (1, 0, 1), (0, 1, -1), (-1, 0, -1), (0, -1, 1), (1, 1, 0), (-1, -1, 0)]
+    dirs += [(0.3 * n, d) for d in extra]
+    out = []
+    for R, d in dirs[:count]:
+        d = np.array(d, dtype=float) / np.linalg.norm(d)
+        o = np.floor(c0 + R * d - WINDOW / 2.0).astype(int)
+        o = np.clip(o, 1, n - WINDOW - 1)
+        out.append(o)
+    return out
+
+
+def window_inputs(parts, o):
+    """The inputs inside window o: per species (species, input indices,
+    x in window coordinates, ucov)."""
+    import numpy as np
+    out = []
+    for sp, x, uc in parts:
+        inside = np.ones(x.shape[1], bool)
+        for ax in range(3):
+            inside &= (x[ax] >= o[ax]) & (x[ax] < o[ax] + WINDOW)
+        idx = np.nonzero(inside)[0]
+        out.append((sp, idx, x[:, idx] - o[:, None], uc[:, idx]))
+    return out
+
+
+def oracle_window_cycle(w, o, sel):
+    """One full FP64 oracle cycle (field solve, push, deposit, removal) on
+    the window at o with its inputs sel.  Returns (live particles, seconds,
+    particle state after the cycle)."""
     import oracle as O
-    from paper_0904_0232_amd import inputs
-    w = inputs.workload_params(workload)
-    parts = inputs.workload_particles(workload, seed=0)
-    p = O.make_params(w["n"], m=w["m"], a=w["a"], dt=w["dt"], r_rm=w["r_rm"], species=w["species"])
-    s = O.Sim(p, 2 * sample_per_species)
+    p = O.make_params(WINDOW, m=w["m"], a=w["a"], dt=w["dt"], center=tuple(w["n"] / 2.0 - o), r_rm=w["r_rm"],
+                      species=w["species"])
+    s = O.Sim(p, sum(idx.size for _, idx, _, _ in sel))
     s.init_fields([0.0, 0.0, w["B0"]])
     kept = 0
-    for sp, x, uc in parts:
-        kept += s.load(sp, x[:, :sample_per_species], uc[:, :sample_per_species])
+    for sp, idx, x, uc in sel:
+        k = s.load(sp, x, uc)
+        assert k == idx.size, "an oracle window dropped an input"
+        kept += k
     t0 = time.perf_counter()
     s.step(1)
     dt = time.perf_counter() - t0
-    return {
-        "value": kept / dt,
+    return kept, dt, s.particles()
+
+
+def _window_job(args):
+    w, o, sel = args
+    kept, dt, _ = oracle_window_cycle(w, o, sel)
+    return kept, dt
+
+
+def cpu_baseline(workload, w, parts, single_windows=3, all_core_windows=16):
+    """The FP64 oracle timed on windows of the workload: one thread on
+    single_windows windows (their states are kept for the error check), then
+    up to all_core_windows independent windows at once, one process per
+    usable core (at most 16).  Returns the baseline and the windows."""
+    import multiprocessing as mp
+
+    import numpy as np
+    host = host_info()
+    origins = window_origins(w, max(single_windows, all_core_windows))
+    windows, tot_kept, tot_s = [], 0, 0.0
+    for o in origins[:single_windows]:
+        sel = window_inputs(parts, o)
+        kept, dt, state = oracle_window_cycle(w, o, sel)
+        windows.append({"origin": o, "sel": [(sp, idx) for sp, idx, _, _ in sel], "state": state,
+                        "x0": np.concatenate([x for _, _, x, _ in sel], axis=1)})
+        tot_kept += kept
+        tot_s += dt
+        log("oracle window at %s: %d particles, %.2f s" % (list(o), kept, dt))
+    out = {
+        "value": tot_kept / tot_s,
         "unit": UNIT,
         "cores": 1,
         "kind": "oracle",
-        "sample": "one full FP64 oracle cycle (64^3 field solve + push/deposit) of the first %d particles "
-                  "per species of the %s workload (%d live), %.1f s" % (sample_per_species, workload, kept, dt),
-    }, s.particles()
+        "sample": "one full FP64 oracle cycle (field solve, push, deposit, removal) on %d windows of %d^3 cells "
+                  "of the %s workload with their particles (%d in all, %.1f s), single thread"
+                  % (single_windows, WINDOW, workload, tot_kept, tot_s),
+        "host": host,
+    }
+    procs = max(1, min(16, host["usable_cpus"] or 1, all_core_windows))
+    jobs = [(w, o, [(sp, idx, x, uc) for sp, idx, x, uc in window_inputs(parts, o)])
+            for o in origins[:all_core_windows]]
+    ctx = mp.get_context("spawn")
+    t0 = time.perf_counter()
+    with ctx.Pool(procs) as pool:
+        res = pool.map(_window_job, jobs, chunksize=1)
+    wall = time.perf_counter() - t0
+    kept = sum(k for k, _ in res)
+    out["all_cores"] = {"value": kept / wall, "processes": procs, "windows": len(jobs), "particles": kept,
+                        "wall_s": wall, "what": "independent oracle windows, one single-threaded process per "
+                                                "usable core; wall time includes process start-up"}
+    log("cpu baseline: %.4g particle-steps/s on 1 core, %.4g on %d processes" %
+        (out["value"], out["all_cores"]["value"], procs))
+    return out, windows
 
 
-def error_vs_oracle(workload, precision, sort_every, sample_per_species, oracle_state):
-    """Largest relative error, after the first cycle, of the GPU state against
-    the oracle's for the oracle's sample (the first sample_per_species inputs
-    of each species).  Positions after one cycle depend only on the initial
-    fields, so the oracle's smaller particle set does not matter."""
+def window_errors(w, windows, state1, n_per_species):
+    """Largest relative error, after the first cycle, of the GPU state
+    against the oracle's windows, over the particles that start and end at
+    least WINDOW_MARGIN cells inside a window (there the window's frozen
+    faces do not reach the particles' fields within one cycle).  GPU slot of
+    input i of species s = s * n_per_species + i (loads keep a slot for every
+    input)."""
     import numpy as np
     import oracle as O
-    from paper_0904_0232_amd import capi, inputs
-    from paper_0904_0232_amd import run as R
-    w = inputs.workload_params(workload)
-    parts = inputs.workload_particles(workload, seed=0)
-    ntot = sum(p[1].shape[1] for p in parts)
-    cfg = R.make_config(w["n"], m=w["m"], a=w["a"], dt=w["dt"], B0=(0.0, 0.0, w["B0"]), species=w["species"],
-                        r_rm=w["r_rm"], sort_every=sort_every, capacity=ntot,
-                        precision=capi.FP32_MIXED if precision == "fp32" else capi.FP64)
-    run = R.Run(cfg)
-    slots, off = [], 0
-    for sp, x, uc in parts:
-        run.load(sp, x, uc)
-        slots.append(off + np.arange(min(sample_per_species, x.shape[1])))
-        off += x.shape[1]
-    sp0 = run.particles()[2]
-    run.step(1)
-    x1, u1, sp1 = run.particles()
-    run.close()
-    slots = np.concatenate(slots)
-    slots = slots[sp0[slots] != O.DEAD]  # the oracle keeps the same inputs, in input order
-    xo, uo, spo = oracle_state
-    live_o = spo != O.DEAD
-    same_removal = bool(np.array_equal(sp1[slots] != O.DEAD, live_o))
-    both = (sp1[slots] != O.DEAD) & live_o
-    ex = np.abs(x1[:, slots][:, both] - xo[:, both]) / np.maximum(np.abs(xo[:, both]), 1.0)
-    eu = np.abs(u1[:, slots][:, both] - uo[:, both]) / np.maximum(np.abs(uo[:, both]), 1.0)
-    return {"x_rel": float(ex.max()), "u_rel": float(eu.max()), "particles": int(both.sum()),
-            "same_removals": same_removal}
+    x1, u1, sp1 = state1
+    ex_max = eu_max = 0.0
+    count, same = 0, True
+    for win in windows:
+        o = win["origin"]
+        xo, uo, spo = win["state"]
+        slots = np.concatenate([sp * n_per_species + idx for sp, idx in win["sel"]])
+        xg = x1[:, slots] - o[:, None]
+        ug = u1[:, slots]
+        live = (spo != O.DEAD) & (sp1[slots] != O.DEAD)
+        same &= bool(np.array_equal(spo != O.DEAD, sp1[slots] != O.DEAD))
+        inner = live.copy()
+        for ax in range(3):
+            for xs in (win["x0"], xo):
+                inner &= (xs[ax] >= WINDOW_MARGIN) & (xs[ax] < WINDOW - WINDOW_MARGIN)
+        ex = np.abs(xg[:, inner] - xo[:, inner]) / np.maximum(np.abs(xo[:, inner] + o[:, None]), 1.0)
+        eu = np.abs(ug[:, inner] - uo[:, inner]) / np.maximum(np.abs(uo[:, inner]), 1.0)
+        if inner.any():
+            ex_max = max(ex_max, float(ex.max()))
+            eu_max = max(eu_max, float(eu.max()))
+        count += int(inner.sum())
+    return {"x_rel": ex_max, "u_rel": eu_max, "particles": count, "same_removals": same}
 
 
-def measure(workload, precision, steps, warmup, sort_every):
-    """Time `steps` cycles of one run; returns the figures of the timed region."""
+def measure(workload, precision, steps, warmup, sort_every, parts, first_cycle_state=False):
+    """Time `steps` cycles of one run; returns the figures of the timed
+    region (and, with first_cycle_state, the particle state after the first
+    warmup cycle, before any cell sort)."""
     import torch
     from paper_0904_0232_amd import capi, inputs
     from paper_0904_0232_amd import run as R
 
     w = inputs.workload_params(workload)
-    parts = inputs.workload_particles(workload, seed=0)
     ntot = sum(p[1].shape[1] for p in parts)
     cfg = R.make_config(w["n"], m=w["m"], a=w["a"], dt=w["dt"], B0=(0.0, 0.0, w["B0"]), species=w["species"],
                         r_rm=w["r_rm"], sort_every=sort_every, capacity=ntot,
-                        precision=capi.FP32_MIXED if precision == "fp32" else capi.FP64)
+                        precision=capi.FP32_MIXED if precision == "fp32" else capi.FP64,
+                        density=w["ppc"] if w["plasma"] != "torus" else None)
     run = R.Run(cfg)
+    t0 = time.perf_counter()
     for sp, x, uc in parts:
         run.load(sp, x, uc)
-    del parts
+    log("%s %s: loaded %d particles in %.1f s" % (workload, precision, ntot, time.perf_counter() - t0))
     h = run.h
-    capi.grpic_step(h, warmup)
+    state1 = None
+    if first_cycle_state and warmup > 0 and (sort_every == 0 or sort_every > 1):
+        capi.grpic_step(h, 1)
+        state1 = run.particles()
+        capi.grpic_step(h, warmup - 1)
+    else:
+        capi.grpic_step(h, warmup)
     torch.cuda.synchronize()
     ps0 = capi.grpic_particle_steps(h)
     capi.grpic_set_timing(h, True)
@@ -192,7 +311,8 @@ def measure(workload, precision, steps, warmup, sort_every):
         "w": w, "ntot": ntot, "wall": wall, "psteps": psteps, "value": psteps / wall,
         "ms_per_step": wall * 1e3 / steps, "timers": timers,
         "kernel_ms_per_launch": {k: (v[0] / max(v[1], 1)) for k, v in timers.items()},
-        "live_end": int(sum(d["n_alive"])),
+        "live_end": int(sum(d["n_alive"])), "state1": state1,
+        "deposit_blocks": {"lds": d["deposit_blocks_lds"], "global": d["deposit_blocks_global"]},
     }
 
 
@@ -203,10 +323,12 @@ KERNELS = {
 }
 
 
-def kernel_roofline(m, name, peak, with_traffic):
+def kernel_roofline(m, name, peak, with_traffic, workload, precision):
     """Algorithmic FLOP/s of one kernel over its event-timed launches
     (particles per launch = particle-steps of the timed region / launches)."""
     label, flops, tkey = KERNELS[name]
+    if precision == "fp32":
+        label = label.replace("k_push", "k_push32").replace("k_deposit", "k_deposit32")
     ms, n = m["timers"][name]
     avg_s = ms / 1e3 / max(n, 1)
     per_launch = m["psteps"] / max(n, 1)
@@ -218,17 +340,17 @@ def kernel_roofline(m, name, peak, with_traffic):
         "peak": peak,
         "unit": "TFLOP/s",
         "frac": achieved / peak,
-        "traffic": read_traffic(per_launch, tkey) if with_traffic else None,
+        "traffic": read_traffic(per_launch, precision, workload, tkey) if with_traffic else None,
         "avg_launch_ms": avg_s * 1e3,
         "flops_per_particle": flops,
         "particles_per_launch": per_launch,
     }
 
 
-def rooflines(m, peak, with_traffic):
+def rooflines(m, peak, with_traffic, workload, precision="fp64"):
     """Both particle kernels' rooflines and the one of the kernel that takes
     the most time (each launches once per cycle)."""
-    both = {k: kernel_roofline(m, k, peak, with_traffic) for k in KERNELS}
+    both = {k: kernel_roofline(m, k, peak, with_traffic, workload, precision) for k in KERNELS}
     dominant = max(both, key=lambda k: both[k]["avg_launch_ms"])
     return both[dominant], both
 
@@ -558,18 +680,28 @@ def precision_study(workload, checkpoints=(1, 10, 100, 300, 1000), modes=("geode
     return out
 
 
+def describe(workload, w, ntot, sort_every):
+    plasma = {"uniform": "uniform Maxwellian", "shell": "uniform Maxwellian plus a shell |R - n/4| <= 2 at "
+              "v_r = -0.3c", "torus": "torus"}[w["plasma"]]
+    return ("%s: Kerr a=%.2fm, m=%g cells, %d^3 grid, %d particles (%d ppc x 2 species), %s u_th=%gc, B_z=%g, "
+            "dt=%g, curved deposit, paper gamma, sort every %d steps"
+            % (workload, w["a_frac"], w["m"], w["n"], ntot, w["ppc"], plasma, w["u_th"], w["B0"], w["dt"],
+               sort_every))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200)
-    ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--workload", default="kerr64")
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="shell256")
     ap.add_argument("--sort-every", type=int, default=5)
-    ap.add_argument("--cpu-sample", type=int, default=3 << 19, help="particles per species for the oracle timing")
+    ap.add_argument("--secondary", default="kerr64",
+                    help="second workload timed in both precisions ('' skips it)")
+    ap.add_argument("--secondary-steps", type=int, default=100)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-windows", type=int, default=3, help="oracle windows timed on one thread")
     ap.add_argument("--no-fp32", action="store_true", help="skip the FP32-mixed measurement")
-    ap.add_argument("--scale", action="store_true",
-                    help="also time the 256^3 throughput workload (268M particles) in both precisions")
     ap.add_argument("--precision", action="store_true",
                     help="also run the FP32-mixed vs FP64 precision study on the torus workload (1000 steps)")
     ap.add_argument("--jet", action="store_true",
@@ -591,13 +723,28 @@ def main():
               "(multi-GPU sharding is a design note, not a measured path); use --gpus 1", file=sys.stderr)
         sys.exit(2)
 
+    from paper_0904_0232_amd import inputs
+    w = inputs.workload_params(args.workload)
+    t0 = time.perf_counter()
+    parts = inputs.workload_particles(args.workload, seed=0)
+    ntot = sum(p[1].shape[1] for p in parts)
+    nps = parts[0][1].shape[1]
+    log("%s: generated %d particles in %.1f s" % (args.workload, ntot, time.perf_counter() - t0))
+    # the oracle's windows first: host work only, before the GPU is touched
+    cpu, windows = (None, None) if args.no_cpu_baseline else cpu_baseline(args.workload, w, parts, args.cpu_windows)
+
     import torch
     torch.cuda.set_device(0)
 
-    m64 = measure(args.workload, "fp64", args.steps, args.warmup, args.sort_every)
+    errs = {}
+    m64 = measure(args.workload, "fp64", args.steps, args.warmup, args.sort_every, parts,
+                  first_cycle_state=windows is not None)
     log("fp64 %s: %.4g particle-steps/s" % (args.workload, m64["value"]))
-    w = m64["w"]
-    roofline, rooflines64 = rooflines(m64, FP64_PEAK_TFLOPS, True)
+    if windows is not None and m64["state1"] is not None:
+        errs["fp64"] = window_errors(w, windows, m64["state1"], nps)
+        log("fp64 error vs oracle windows: %s" % json.dumps(errs["fp64"]))
+    m64["state1"] = None
+    roofline, rooflines64 = rooflines(m64, FP64_PEAK_TFLOPS, True, args.workload)
     line = {
         "metric": METRIC,
         "value": m64["value"],
@@ -612,41 +759,55 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {
-            "workload": "%s: Kerr a=%.2fm, m=%g cells, %d^3 grid, %d particles (%d ppc x 2 species), "
-                        "uniform Maxwellian u_th=%gc, B_z=%g, dt=%g, curved deposit, paper gamma, "
-                        "sort every %d steps" % (args.workload, w["a_frac"], w["m"], w["n"], m64["ntot"], w["ppc"],
-                                                 w["u_th"], w["B0"], w["dt"], args.sort_every),
+            "workload": describe(args.workload, w, ntot, args.sort_every),
             "precision": "fp64",
             "live_particles_end": m64["live_end"],
         },
         "kernel_ms_per_launch": m64["kernel_ms_per_launch"],
+        "deposit_blocks": m64["deposit_blocks"],
         "roofline": roofline,
         "rooflines": rooflines64,
-        "cpu_baseline": None,
+        "cpu_baseline": cpu,
     }
     if not args.no_fp32:
-        m32 = measure(args.workload, "fp32", args.steps, args.warmup, args.sort_every)
+        m32 = measure(args.workload, "fp32", args.steps, args.warmup, args.sort_every, parts,
+                      first_cycle_state=windows is not None)
         log("fp32-mixed %s: %.4g particle-steps/s" % (args.workload, m32["value"]))
+        if windows is not None and m32["state1"] is not None:
+            errs["fp32_mixed"] = window_errors(w, windows, m32["state1"], nps)
+            log("fp32-mixed error vs oracle windows: %s" % json.dumps(errs["fp32_mixed"]))
+        m32["state1"] = None
         line["fp32_mixed"] = {
             "value": m32["value"], "unit": UNIT, "ms_per_step": m32["ms_per_step"], "dtype": "f32 (FP64 quartic, "
             "near-horizon metric and diagnostics)", "kernel_ms_per_launch": m32["kernel_ms_per_launch"],
             "speedup_vs_fp64": m32["value"] / m64["value"], "live_particles_end": m32["live_end"],
+            "deposit_blocks": m32["deposit_blocks"],
         }
-        line["fp32_mixed"]["roofline"], line["fp32_mixed"]["rooflines"] = rooflines(m32, FP32_PEAK_TFLOPS, False)
+        line["fp32_mixed"]["roofline"], line["fp32_mixed"]["rooflines"] = rooflines(m32, FP32_PEAK_TFLOPS, True,
+                                                                                      args.workload, "fp32")
+    if errs:
+        errs["what"] = ("largest relative error after the first cycle against the FP64 oracle's windows, over the "
+                        "particles at least %d cells inside a %d^3 window at the start and end of the cycle "
+                        "(positions relative to max(|x|, 1 cell), four-velocities to max(|u|, c))"
+                        % (WINDOW_MARGIN, WINDOW))
+        line["error_vs_oracle"] = errs
+    del parts, windows
+    if args.secondary:
+        sparts = inputs.workload_particles(args.secondary, seed=0)
+        sw = inputs.workload_params(args.secondary)
+        sec = {"workload": describe(args.secondary, sw, sum(p[1].shape[1] for p in sparts), args.sort_every)}
+        for prec in ("fp64", "fp32"):
+            ms = measure(args.secondary, prec, args.secondary_steps, args.warmup, args.sort_every, sparts)
+            log("%s %s: %.4g particle-steps/s" % (args.secondary, prec, ms["value"]))
+            sec[prec] = {"value": ms["value"], "ms_per_step": ms["ms_per_step"], "steps": args.secondary_steps,
+                         "kernel_ms_per_launch": ms["kernel_ms_per_launch"], "live_particles_end": ms["live_end"],
+                         "roofline": rooflines(ms, FP64_PEAK_TFLOPS if prec == "fp64" else FP32_PEAK_TFLOPS, False,
+                                               args.secondary)[0]}
+        line["secondary_" + args.secondary] = sec
+        del sparts
     if args.serve_runs > 0:
         line["serving"] = serving(args)
         log("serving: p50 %.3f s p99 %.3f s" % (line["serving"]["p50_latency_s"], line["serving"]["p99_latency_s"]))
-    if args.scale:
-        scale = {}
-        for prec in ("fp32", "fp64"):
-            # warm up past the first cell sort (loaded particles are in
-            # generation order), as the main measurement does
-            ms = measure("shell256", prec, 100, max(2, args.sort_every), args.sort_every)
-            log("shell256 %s: %.4g particle-steps/s" % (prec, ms["value"]))
-            scale[prec] = {"value": ms["value"], "ms_per_step": ms["ms_per_step"], "particles": ms["ntot"],
-                           "kernel_ms_per_launch": ms["kernel_ms_per_launch"], "steps": 100,
-                           "warmup": max(2, args.sort_every)}
-        line["throughput_scale_shell256"] = scale
     if args.precision:
         line["precision_torus128"] = precision_study("torus128", n_override=args.precision_particles or None)
     if args.ablations:
@@ -655,16 +816,6 @@ def main():
         line["jet"] = jet_study()
     if args.preemption:
         line["preemption"] = preemption_study(args)
-    if not args.no_cpu_baseline:
-        line["cpu_baseline"], ostate = cpu_baseline(args.workload, args.cpu_sample)
-        log("cpu baseline: %.4g particle-steps/s" % line["cpu_baseline"]["value"])
-        errs = {"fp64": error_vs_oracle(args.workload, "fp64", args.sort_every, args.cpu_sample, ostate)}
-        if not args.no_fp32:
-            errs["fp32_mixed"] = error_vs_oracle(args.workload, "fp32", args.sort_every, args.cpu_sample, ostate)
-        errs["what"] = ("largest relative error after the first cycle against the FP64 oracle, on the oracle's "
-                        "sample (positions relative to max(|x|, 1 cell), four-velocities to max(|u|, c))")
-        line["error_vs_oracle"] = errs
-        log("error vs oracle: %s" % json.dumps(errs))
     print(json.dumps(line), flush=True)
 
 

@@ -95,6 +95,9 @@ typedef struct {
     double B0[3];           /* initial (F^23, F^31, F^12), or covariant if flagged  */
     double charge[GRPIC_MAX_SPECIES]; /* macro-particle charge per species          */
     double mass[GRPIC_MAX_SPECIES];   /* macro-particle mass per species (> 0)      */
+    double density[GRPIC_MAX_SPECIES];/* nominal macro-particles per unit cell volume
+                                         per species, for the plasma-frequency check
+                                         (Sec. 5.1); 0: not checked                */
     int64_t capacity;       /* particle slots to allocate                          */
     grpic_alloc_fn alloc;   /* optional device allocator (NULL: hipMalloc)          */
     grpic_free_fn free;
@@ -106,13 +109,18 @@ typedef struct {
     int64_t n_removed_horizon; /* cumulative removals inside r_rm          */
     int64_t n_removed_outer;   /* cumulative removals at the outer boundary */
     int64_t gamma_clamps;      /* negative gamma discriminants clamped       */
-    int64_t flags;             /* bit 0: move > 1 cell; bit 1: fixed-point range */
+    int64_t flags;             /* bit 0: a move > 1 cell (not deposited);
+                                  bit 1: an int64 fixed-point sum (current or
+                                  absorbed charge) left the int64 range     */
     double charge_total;
     double energy_particles;   /* sum M c (-u_4)                              */
     double lz_particles;       /* sum M (x u_y - y u_x), covariant u          */
     double energy_field;       /* (1/8pi)[sum -E_cov D + sum B_cov H]         */
     double gauss_residual_max; /* max |-div D - 4 pi rho| at checked nodes    */
     double mass_shell_residual_max; /* max |g(u,u) + c^2|                    */
+    int64_t deposit_blocks_lds;    /* cumulative deposit blocks whose current was
+                                      summed in an LDS box, then flushed       */
+    int64_t deposit_blocks_global; /* ... added with global atomics instead     */
 } grpic_diag;
 
 typedef struct grpic_s grpic_t;
@@ -128,11 +136,23 @@ void grpic_config_default(grpic_config *cfg, int32_t nx, int32_t ny, int32_t nz)
  * their copy of the layout. */
 size_t grpic_config_size(void);
 
+/* The validation of grpic_create without creating a run (host only, no
+ * device call): GRPIC_OK or GRPIC_EINVAL.  Besides the limits listed at
+ * grpic_create it applies the plasma-frequency criterion of Sec. 5.1,
+ * omega_p dt < 2 with omega_p^2 = 4 pi n q^2 / m for every species whose
+ * nominal density n = cfg->density[s] is set (> 0), with the macro-particle
+ * charge and mass.  The general-relativistic form of the criterion,
+ * gamma^(-1/2) omega_p dt < 2, holds wherever the flat one does, since the
+ * time-dilation factor gamma is at least 1. */
+int grpic_config_check(const grpic_config *cfg);
+
 /* Create a run.  Validates the configuration (grid >= 4 cells per axis,
- * 0 <= |a| <= m, c > 0, dt > 0, Courant c dt < 1/sqrt(3), r_exc < r_rm,
- * masses > 0, rk_mode, gather_mode and gather_weights at their defaults
- * unless FP64, outer_layer >= 0, 0 <= outer_damp <= 1) and initialises the fields (Sec. 6: uniform contravariant
- * field).  stream is a hipStream_t (NULL: the null stream).
+ * 0 <= |a| <= m, c > 0, dt > 0, the Courant condition c dt < 1/sqrt(3) of
+ * Sec. 5.2, the plasma-frequency criterion of Sec. 5.1 where densities are
+ * given (grpic_config_check), r_exc < r_rm, masses > 0, rk_mode, gather_mode
+ * and gather_weights at their defaults unless FP64, outer_layer >= 0,
+ * 0 <= outer_damp <= 1) and initialises the fields (Sec. 6: uniform
+ * contravariant field).  stream is a hipStream_t (NULL: the null stream).
  * Returns GRPIC_EINVAL, GRPIC_ENOMEM or GRPIC_EDEVICE on failure. */
 int grpic_create(const grpic_config *cfg, void *stream, grpic_t **out);
 
@@ -147,10 +167,19 @@ int grpic_load_particles(grpic_t *h, int32_t species, int64_t n, const double *x
 
 /* Enqueue nsteps full cycles (Sec. 2.2 and Sec. 3): magnetic half-step,
  * RK4 push, magnetic half-step, current deposition, electric step, removal,
- * and a cell sort every sort_every steps.  Asynchronous. */
+ * and a cell sort every sort_every steps.  Asynchronous.
+ * Errors are sticky: once a call has failed, every later call returns the
+ * same code.  GRPIC_EOVERFLOW: an int64 fixed-point sum of an earlier step
+ * (the current of Sec. 4, or the charge absorbed at removal) left the int64
+ * range, so the run's fields can no longer be trusted.  The device raises
+ * the flag during the step; its value is copied to the host at the end of
+ * each call, so the next call after that copy has completed (at the latest
+ * once the stream has synchronised), or grpic_diagnostics, reports it. */
 int grpic_step(grpic_t *h, int32_t nsteps);
 
-/* Synchronise and compute the diagnostics (FP64, deterministic order). */
+/* Synchronise and compute the diagnostics (FP64, deterministic order).
+ * *out is filled in every case; the return value is the run's sticky error,
+ * GRPIC_EOVERFLOW when flags bit 1 is set. */
 int grpic_diagnostics(grpic_t *h, grpic_diag *out);
 
 /* Number of particle slots in use (alive or dead) and capacity. */
@@ -186,6 +215,10 @@ int grpic_restore_fields(grpic_t *h, const double *D, const double *B);
  * header with the configuration it was saved under.  A run created with the
  * same configuration (capacity may differ, allocator ignored) that loads the
  * state continues bit-identically to the run that saved it.
+ *
+ * The particles are kept as the run stores them (FP64: positions and
+ * four-velocities as doubles; FP32-mixed: the packed cell, FP32 offsets and
+ * FP32 four-velocity), so a resumed run holds the same bits.
  *
  * grpic_state_bytes: the size of the run's current state in bytes (< 0: an
  * error code).

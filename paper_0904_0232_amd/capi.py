@@ -43,6 +43,7 @@ class Config(ctypes.Structure):
         ("outer_layer", ctypes.c_double), ("outer_damp", ctypes.c_double),
         ("B0", ctypes.c_double * 3),
         ("charge", ctypes.c_double * MAX_SPECIES), ("mass", ctypes.c_double * MAX_SPECIES),
+        ("density", ctypes.c_double * MAX_SPECIES),
         ("capacity", ctypes.c_int64),
         ("alloc", ALLOC_FN), ("free", FREE_FN), ("alloc_ctx", ctypes.c_void_p),
     ]
@@ -57,6 +58,7 @@ class Diag(ctypes.Structure):
         ("lz_particles", ctypes.c_double), ("energy_field", ctypes.c_double),
         ("gauss_residual_max", ctypes.c_double),
         ("mass_shell_residual_max", ctypes.c_double),
+        ("deposit_blocks_lds", ctypes.c_int64), ("deposit_blocks_global", ctypes.c_int64),
     ]
 
     def as_dict(self):
@@ -74,6 +76,7 @@ class GrpicError(RuntimeError):
 
 
 EINVAL = -1
+EOVERFLOW = -4
 ESTATE = -5
 EAGAIN = -6
 RUN_UNKNOWN, RUN_ACTIVE, RUN_DONE, RUN_PREEMPTED = 0, 1, 2, 3
@@ -103,6 +106,8 @@ def lib():
         if L.grpic_config_size() != ctypes.sizeof(Config):
             raise GrpicError("grpic_config layout mismatch: library %d bytes, binding %d"
                              % (L.grpic_config_size(), ctypes.sizeof(Config)))
+        L.grpic_config_check.argtypes = [ctypes.POINTER(Config)]
+        L.grpic_config_check.restype = ctypes.c_int
         L.grpic_create.argtypes = [ctypes.POINTER(Config), ctypes.c_void_p, ctypes.POINTER(_H)]
         L.grpic_load_particles.argtypes = [_H, ctypes.c_int32, ctypes.c_int64, _D, _D, _I64]
         L.grpic_step.argtypes = [_H, ctypes.c_int32]
@@ -232,9 +237,18 @@ def grpic_push_only(h, nsteps=1):
     _check(lib().grpic_push_only(h, int(nsteps)))
 
 
-def grpic_diagnostics(h):
+def grpic_config_check(cfg):
+    """0 (valid) or a negative error code; no device call."""
+    return lib().grpic_config_check(ctypes.byref(cfg))
+
+
+def grpic_diagnostics(h, allow_overflow=False):
+    """The diagnostics as a dict.  GRPIC_EOVERFLOW raises unless
+    allow_overflow (the filled diagnostics are returned then)."""
     d = Diag()
-    _check(lib().grpic_diagnostics(h, ctypes.byref(d)))
+    rc = lib().grpic_diagnostics(h, ctypes.byref(d))
+    if not (allow_overflow and rc == EOVERFLOW):
+        _check(rc)
     return d.as_dict()
 
 

@@ -49,6 +49,9 @@ struct grpic_s {
     std::vector<void *> allocs;
     int64_t step_count;
     int sticky;
+    // C_FLAGS as last copied to the host (pinned; written by an asynchronous
+    // copy at the end of every grpic_step call)
+    volatile unsigned long long *flags_host;
     // event timing
     int timing;
     std::vector<hipEvent_t> ev_pool;
@@ -189,7 +192,16 @@ int validate(const grpic_config *c) {
     if (!(c->outer_layer >= 0.0) || !isfinite(c->outer_layer) || !(c->outer_damp >= 0.0) || c->outer_damp > 1.0)
         return GRPIC_EINVAL;
     for (int s = 0; s < c->nspecies; s++) {
-        if (!(c->mass[s] > 0.0) || !isfinite(c->charge[s])) return GRPIC_EINVAL;
+        if (!(c->mass[s] > 0.0) || !isfinite(c->mass[s]) || !isfinite(c->charge[s])) return GRPIC_EINVAL;
+        // plasma-frequency criterion (Sec. 5.1): omega_p dt < 2 with
+        // omega_p^2 = 4 pi n q^2 / m at the species' nominal density n
+        // (macro-particles per unit cell volume; 0: not checked).  Its
+        // general-relativistic form gamma^(-1/2) omega_p dt < 2 follows for
+        // every gamma >= 1.
+        const double n = c->density[s];
+        if (!(n >= 0.0) || !isfinite(n)) return GRPIC_EINVAL;
+        if (n > 0.0 && !(sqrt(4.0 * M_PI * n * c->charge[s] * c->charge[s] / c->mass[s]) * c->dt < 2.0))
+            return GRPIC_EINVAL;
     }
     if (c->capacity < 0 || c->capacity > ((int64_t)1 << 31) - 1) return GRPIC_EINVAL;
     return GRPIC_OK;
@@ -582,6 +594,8 @@ int capture_iteration(grpic_batch_t *b, int iters) {
 int finish_run(grpic_batch_t *b, BatchRun *r) {
     grpic_t *h = r->h;
     int rc = grpic_diagnostics(h, &r->diag);
+    // a fixed-point overflow is reported in the run's diagnostics (flags bit 1)
+    if (rc == GRPIC_EOVERFLOW) rc = GRPIC_OK;
     if (!rc) rc = grpic_particle_steps(h, &r->particle_steps);
     if (!rc && r->keep) {
         r->n_slots = h->n_slots;
@@ -863,6 +877,8 @@ void grpic_config_default(grpic_config *cfg, int32_t nx, int32_t ny, int32_t nz)
 
 size_t grpic_config_size(void) { return sizeof(grpic_config); }
 
+int grpic_config_check(const grpic_config *cfg) { return validate(cfg); }
+
 const char *grpic_strerror(int code) {
     switch (code) {
     case GRPIC_OK: return "ok";
@@ -886,6 +902,7 @@ void grpic_destroy(grpic_t *h) {
             (void)hipEventDestroy(pr.second);
         }
     for (void *p : h->allocs) raw_free(h, p);
+    if (h->flags_host) (void)hipHostFree((void *)h->flags_host);
     delete h;
 }
 
@@ -958,6 +975,12 @@ int grpic_create(const grpic_config *cfg, void *stream, grpic_t **out) {
     h->rho_scratch = (unsigned long long *)A(gs * 8);
     h->red_cap = ((cap + 255) / 256) * 12 + ((nn + 255) / 256) * 3 + 64;
     h->red = (double *)A(h->red_cap * 8);
+    void *fh = nullptr;
+    if (FAILS(hipHostMalloc(&fh, 8, hipHostMallocDefault)))
+        ok = false;
+    else
+        *(unsigned long long *)fh = 0ull;
+    h->flags_host = (volatile unsigned long long *)fh;
     if (!ok) {
         grpic_destroy(h);
         return GRPIC_ENOMEM;
@@ -1024,6 +1047,7 @@ int grpic_load_particles(grpic_t *h, int32_t species, int64_t n, const double *x
 int grpic_step(grpic_t *h, int32_t nsteps) {
     clear_foreign_error();
     if (!h || nsteps < 0) return GRPIC_EINVAL;
+    if (*h->flags_host & kFlagFixedRange) h->sticky = GRPIC_EOVERFLOW;
     if (h->sticky) return h->sticky;
     for (int i = 0; i < nsteps; i++) {
         int rc = one_step(h);
@@ -1032,7 +1056,10 @@ int grpic_step(grpic_t *h, int32_t nsteps) {
             return rc;
         }
     }
-    return GRPIC_OK;
+    // the flags reach the host asynchronously; a later call reports them
+    int rc = check(hipMemcpyAsync((void *)h->flags_host, h->counters + C_FLAGS, 8, hipMemcpyDeviceToHost, h->stream));
+    if (rc) h->sticky = rc;
+    return rc;
 }
 
 int grpic_push_only(grpic_t *h, int32_t nsteps) {
@@ -1110,8 +1137,11 @@ int grpic_restore_fields(grpic_t *h, const double *D, const double *B) {
 namespace {
 // Checkpoint layout (host, 8-byte aligned): StateHeader, then D [3][gs] and
 // B [3][gs] as doubles, rho_abs [gs] and the counters [kCounterWords] as
-// uint64, x [3][n] and u [4][n] as doubles, sp [n] bytes.
-const char kStateMagic[8] = {'G', 'R', 'P', 'I', 'C', 'S', 'T', '1'};
+// uint64, then the particles as the run stores them: FP64 runs x [3][n] and
+// u [4][n] as doubles; FP32-mixed runs the packed cell [n] as int32, the
+// offsets [3][n] and u [4][n] as floats (so a resumed run holds the same bits);
+// then sp [n] bytes.
+const char kStateMagic[8] = {'G', 'R', 'P', 'I', 'C', 'S', 'T', '2'};
 struct StateHeader {
     char magic[8];
     int64_t total_bytes;
@@ -1158,21 +1188,46 @@ void state_key(const grpic_config *c, grpic_config *k) {
     }
 }
 
-int64_t state_bytes_for(int64_t gs, int64_t n) {
-    int64_t b = (int64_t)sizeof(StateHeader) + 8 * (6 * gs + gs + kCounterWords + 7 * n) + n;
+int64_t state_bytes_for(int64_t gs, int64_t n, bool mixed) {
+    int64_t b = (int64_t)sizeof(StateHeader) + 8 * (6 * gs + gs + kCounterWords) + (mixed ? 32 : 56) * n + n;
     return (b + 7) & ~(int64_t)7;
+}
+
+// Particle section of a state: copy the stored representation out or in.
+int state_particles(grpic_t *h, char *p, int64_t n, bool out) {
+    hipStream_t s = h->stream;
+    const hipMemcpyKind kind = out ? hipMemcpyDeviceToHost : hipMemcpyHostToDevice;
+    std::vector<std::pair<void *, size_t>> parts;  // device pointer, bytes
+    if (h->mixed) {
+        parts.push_back({h->pcell[h->xc], (size_t)n * 4});
+        for (int q = 0; q < 3; q++) parts.push_back({h->poff[h->xc][q], (size_t)n * 4});
+        for (int q = 0; q < 4; q++) parts.push_back({h->pu32[h->uc][q], (size_t)n * 4});
+    } else {
+        for (int q = 0; q < 3; q++) parts.push_back({h->px[h->xc][q], (size_t)n * 8});
+        for (int q = 0; q < 4; q++) parts.push_back({h->pu[h->uc][q], (size_t)n * 8});
+    }
+    parts.push_back({h->psp[h->uc], (size_t)n});
+    int rc = GRPIC_OK;
+    for (auto &pr : parts) {
+        if (!rc && pr.second)
+            rc = out ? check(hipMemcpyAsync(p, pr.first, pr.second, kind, s))
+                     : check(hipMemcpyAsync(pr.first, p, pr.second, kind, s));
+        p += pr.second;
+    }
+    if (!rc) rc = check(hipStreamSynchronize(s));
+    return rc;
 }
 }  // namespace
 
 int64_t grpic_state_bytes(grpic_t *h) {
     if (!h) return GRPIC_EINVAL;
-    return state_bytes_for(h->G.gsize(), h->n_slots);
+    return state_bytes_for(h->G.gsize(), h->n_slots, h->mixed);
 }
 
 int grpic_save_state(grpic_t *h, void *buf, int64_t bytes) {
     clear_foreign_error();
     if (!h || !buf || ((uintptr_t)buf & 7)) return GRPIC_EINVAL;
-    const int64_t gs = h->G.gsize(), n = h->n_slots, total = state_bytes_for(gs, n);
+    const int64_t gs = h->G.gsize(), n = h->n_slots, total = state_bytes_for(gs, n, h->mixed);
     if (bytes < total) return GRPIC_EINVAL;
     char *b = (char *)buf;
     StateHeader *hd = (StateHeader *)b;
@@ -1187,9 +1242,7 @@ int grpic_save_state(grpic_t *h, void *buf, int64_t bytes) {
     double *B = D + 3 * gs;
     unsigned long long *rho = (unsigned long long *)(B + 3 * gs);
     unsigned long long *cnt = rho + gs;
-    double *x = (double *)(cnt + kCounterWords);
-    double *u = x + 3 * n;
-    uint8_t *sp = (uint8_t *)(u + 4 * n);
+    char *parts = (char *)(cnt + kCounterWords);
     int rc = grpic_dump_fields(h, 0, D);
     if (!rc) rc = grpic_dump_fields(h, 1, B);
     hipStream_t s = h->stream;
@@ -1197,7 +1250,7 @@ int grpic_save_state(grpic_t *h, void *buf, int64_t bytes) {
     if (!rc) rc = check(hipMemcpyAsync(rho, rho_dev, gs * 8, hipMemcpyDeviceToHost, s));
     if (!rc) rc = check(hipMemcpyAsync(cnt, h->counters, kCounterWords * 8, hipMemcpyDeviceToHost, s));
     if (!rc) rc = check(hipStreamSynchronize(s));
-    if (!rc && n > 0) rc = grpic_dump_particles(h, x, u, sp);
+    if (!rc && n > 0) rc = state_particles(h, parts, n, true);
     return rc;
 }
 
@@ -1211,24 +1264,25 @@ int grpic_load_state(grpic_t *h, const void *buf, int64_t bytes) {
     const int64_t gs = h->G.gsize();
     if (memcmp(hd->magic, kStateMagic, 8) || memcmp(&hd->key, &key, sizeof(key)) || hd->field_size != gs ||
         hd->counter_words != kCounterWords || hd->n_slots < 0 || hd->n_slots > h->cap || hd->step_count < 0 ||
-        hd->total_bytes != state_bytes_for(gs, hd->n_slots) || bytes < hd->total_bytes)
+        hd->total_bytes != state_bytes_for(gs, hd->n_slots, h->mixed) || bytes < hd->total_bytes)
         return GRPIC_EINVAL;
     const int64_t n = hd->n_slots;
     const double *D = (const double *)(b + sizeof(StateHeader));
     const double *B = D + 3 * gs;
     const unsigned long long *rho = (const unsigned long long *)(B + 3 * gs);
     const unsigned long long *cnt = rho + gs;
-    const double *x = (const double *)(cnt + kCounterWords);
-    const double *u = x + 3 * n;
-    const uint8_t *sp = (const uint8_t *)(u + 4 * n);
+    char *parts = (char *)(cnt + kCounterWords);
     int rc = grpic_restore_fields(h, D, B);
     hipStream_t s = h->stream;
     unsigned long long *rho_dev = h->mixed ? h->F32.rho_abs : h->F64.rho_abs;
     if (!rc) rc = check(hipMemcpyAsync(rho_dev, rho, gs * 8, hipMemcpyHostToDevice, s));
     if (!rc) rc = check(hipMemcpyAsync(h->counters, cnt, kCounterWords * 8, hipMemcpyHostToDevice, s));
     if (!rc) rc = check(hipStreamSynchronize(s));
-    if (!rc) rc = grpic_restore_particles(h, n, x, u, sp);
-    if (!rc) h->step_count = hd->step_count;
+    if (!rc) rc = state_particles(h, parts, n, false);
+    if (!rc) {
+        h->n_slots = n;
+        h->step_count = hd->step_count;
+    }
     return rc;
 }
 
@@ -1298,6 +1352,9 @@ int grpic_diagnostics(grpic_t *h, grpic_diag *out) {
     out->energy_field = d.energy_field;
     out->gauss_residual_max = d.gauss_max;
     out->mass_shell_residual_max = d.shell_max;
+    out->deposit_blocks_lds = (int64_t)cnt[C_DEP_LDS];
+    out->deposit_blocks_global = (int64_t)cnt[C_DEP_GLOBAL];
+    if ((cnt[C_FLAGS] & kFlagFixedRange) && !h->sticky) h->sticky = GRPIC_EOVERFLOW;
     return h->sticky ? h->sticky : GRPIC_OK;
 }
 

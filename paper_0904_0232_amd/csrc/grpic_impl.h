@@ -72,8 +72,58 @@ enum Counter {
     C_REMOVED_OUTER = 3,
     C_FLAGS = 4,
     C_LOAD_KEPT = 5,
+    C_DEP_LDS = 6,     // deposit blocks that summed their current in an LDS box
+    C_DEP_GLOBAL = 7,  // deposit blocks that added it with global atomics
     C_NCOUNTERS = 8
 };
+
+// Bits of C_FLAGS (sticky).
+constexpr unsigned long long kFlagLongMove = 1ull;    // a move longer than a cell (not deposited)
+constexpr unsigned long long kFlagFixedRange = 2ull;  // an int64 fixed-point sum left the int64 range
+
+// Add v to an int64 fixed-point sum in device memory.  When the partial sum
+// leaves the int64 range (old and v of one sign, the result of the other)
+// flags bit kFlagFixedRange is raised.  A sum whose partial sums never wrap,
+// in the order the atomics happened, is exact; a flagged sum may be wrong.
+__device__ __forceinline__ bool fixed_wrapped(long long old, long long v) {
+    const long long res = (long long)((unsigned long long)old + (unsigned long long)v);
+    return ((old ^ res) & (v ^ res)) < 0;
+}
+__device__ __forceinline__ void fixed_add_checked(unsigned long long *p, long long v, unsigned long long *flags) {
+    const long long old = (long long)atomicAdd(p, (unsigned long long)v);
+    if (fixed_wrapped(old, v)) atomicOr(flags, kFlagFixedRange);
+}
+
+// Flush of a block's LDS current box (3 V int64 sums, edge direction
+// major, then z, y, x within the box at blo) into the global sums.  The box
+// sums themselves cannot wrap: a deposit block holds at most 1024
+// particles, each adding less than 2^(fp_bits + 1) <= 2^51 to an edge.  The
+// global additions return the old value for the range check, four per thread
+// in flight before their results are examined.
+__device__ __forceinline__ void flush_box(const unsigned long long *sm, int V, int bx, int by, const int blo[3],
+                                          unsigned long long *const J[3], const Grid &G, unsigned long long *flags) {
+    const float inv_bx = __builtin_amdgcn_rcpf((float)bx), inv_bxy = __builtin_amdgcn_rcpf((float)(bx * by));
+    bool wrapped = false;
+    for (int e0 = threadIdx.x; e0 < 3 * V; e0 += 4 * (int)blockDim.x) {
+        long long v[4], old[4];
+#pragma unroll
+        for (int q = 0; q < 4; q++) {
+            const int e = e0 + q * (int)blockDim.x;
+            v[q] = e < 3 * V ? (long long)sm[e] : 0ll;
+            old[q] = 0;
+            if (v[q] != 0) {
+                const int K = e >= 2 * V ? 2 : (e >= V ? 1 : 0), l = e - K * V;
+                const int lk = small_div(l, inv_bxy), r = l - lk * bx * by, lj = small_div(r, inv_bx),
+                          li = r - lj * bx;
+                old[q] = (long long)atomicAdd(&J[K][G.g(blo[0] + li, blo[1] + lj, blo[2] + lk)],
+                                              (unsigned long long)v[q]);
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < 4; q++) wrapped |= fixed_wrapped(old[q], v[q]);
+    }
+    if (wrapped) atomicOr(flags, kFlagFixedRange);
+}
 
 // The particle-step counter (live particles pushed, summed over steps) gets
 // one increment per wave of every push: it is spread over kPushedSlots cache

@@ -426,8 +426,9 @@ __device__ __forceinline__ double area_density(const DepCtx &D, int K, double X,
 struct GlobalAcc {
     unsigned long long *J[3];
     Grid G;
+    unsigned long long *flags;
     __device__ __forceinline__ void add(int K, int i, int j, int k, long long v) const {
-        atomicAdd(&J[K][G.g(i, j, k)], (unsigned long long)v);
+        fixed_add_checked(&J[K][G.g(i, j, k)], v, flags);
     }
 };
 
@@ -626,8 +627,9 @@ __global__ __launch_bounds__(kDepBlock) void k_deposit(DepCtx D, Species cS, dou
         for (int e = tid; e < 3 * V; e += kDepBlock) sm[e] = 0ull;
         __syncthreads();
     }
+    if (tid == 0 && any) atomicAdd(&counters[use_lds ? C_DEP_LDS : C_DEP_GLOBAL], 1ull);
     LdsAcc la{sm, blo[0], blo[1], blo[2], bx, by, V};
-    GlobalAcc ga{{F.Jint[0], F.Jint[1], F.Jint[2]}, D.G};
+    GlobalAcc ga{{F.Jint[0], F.Jint[1], F.Jint[2]}, D.G, &counters[C_FLAGS]};
     int n_horizon = 0, n_outer = 0;
 #pragma unroll 1
     for (int p = 0; p < kDepPPT; p++) {
@@ -648,7 +650,7 @@ __global__ __launch_bounds__(kDepBlock) void k_deposit(DepCtx D, Species cS, dou
             else
                 dep_chord(D, ga, X1, xr, X2, c1, c2, Q);
         } else if (!ok) {
-            atomicOr(&counters[C_FLAGS], 1ull);
+            atomicOr(&counters[C_FLAGS], kFlagLongMove);
         }
         const double *x2 = X2;
         const bool inside_rm = ks_radius_below(D.h.a, x2[0] - D.h.cx, x2[1] - D.h.cy, x2[2] - D.h.cz, r_rm);
@@ -673,8 +675,8 @@ __global__ __launch_bounds__(kDepBlock) void k_deposit(DepCtx D, Species cS, dou
                     for (int dj = 0; dj < 2; dj++)
                         for (int di = 0; di < 2; di++) {
                             double W = (di ? w[0] : 1.0 - w[0]) * (dj ? w[1] : 1.0 - w[1]) * (dk ? w[2] : 1.0 - w[2]);
-                            atomicAdd(&F.rho_abs[D.G.g(c[0] + di, c[1] + dj, c[2] + dk)],
-                                      (unsigned long long)__double2ll_rn(sc * W));
+                            fixed_add_checked(&F.rho_abs[D.G.g(c[0] + di, c[1] + dj, c[2] + dk)],
+                                              __double2ll_rn(sc * W), &counters[C_FLAGS]);
                         }
             }
             xo.sp[id] = kDead;
@@ -688,14 +690,7 @@ __global__ __launch_bounds__(kDepBlock) void k_deposit(DepCtx D, Species cS, dou
     wave_count(&counters[C_REMOVED_OUTER], n_outer);
     if (use_lds) {
         __syncthreads();
-        const float inv_bx = __builtin_amdgcn_rcpf((float)bx), inv_bxy = __builtin_amdgcn_rcpf((float)(bx * by));
-        for (int e = tid; e < 3 * V; e += kDepBlock) {
-            unsigned long long v = sm[e];
-            if (v == 0ull) continue;
-            const int K = e >= 2 * V ? 2 : (e >= V ? 1 : 0), l = e - K * V;
-            const int lk = small_div(l, inv_bxy), r = l - lk * bx * by, lj = small_div(r, inv_bx), li = r - lj * bx;
-            atomicAdd(&F.Jint[K][D.G.g(blo[0] + li, blo[1] + lj, blo[2] + lk)], v);
-        }
+        flush_box(sm, V, bx, by, blo, F.Jint, D.G, &counters[C_FLAGS]);
     }
 }
 

@@ -257,11 +257,17 @@ __device__ __forceinline__ void push32_block(const PushParams &P, const Mixed &M
         for (int q = 0; q < 3; q++) {
             float xo = X0[q] + h6 * Sx[q];
             float fl = floorf(xo);
+            xo -= fl;
+            // xo in (-2^-25, 0) gives xo - fl = 1.0f after rounding: that
+            // point is the next cell's face, offset 0, so offsets stay in [0, 1)
+            if (xo >= 1.0f) {
+                xo = 0.0f;
+                fl += 1.0f;
+            }
             int nc = cc[q] + (int)fl;
             // a cell outside the ghost layer cannot be packed; the particle is
             // removed as outside by the deposition kernel either way
             nc = nc < -1 ? -1 : (nc > 1022 ? 1022 : nc);
-            xo -= fl;
             cc[q] = nc;
             out.off[q][id] = xo;
         }
@@ -327,8 +333,9 @@ __device__ __forceinline__ float area_density32(const Dep32 &D, int K, const int
 struct GlobalAcc32 {
     unsigned long long *J[3];
     Grid G;
+    unsigned long long *flags;
     __device__ __forceinline__ void add(int K, int i, int j, int k, long long v) const {
-        atomicAdd(&J[K][G.g(i, j, k)], (unsigned long long)v);
+        fixed_add_checked(&J[K][G.g(i, j, k)], v, flags);
     }
 };
 
@@ -534,8 +541,9 @@ __device__ __forceinline__ void deposit32_block(const Dep32 &D, const Species &c
         for (int e = tid; e < 3 * V; e += kDep32Block) sm[e] = 0ull;
         __syncthreads();
     }
+    if (tid == 0 && any) atomicAdd(&counters[use_lds ? C_DEP_LDS : C_DEP_GLOBAL], 1ull);
     LdsAcc32 la{sm, blo[0], blo[1], blo[2], bx, by, V};
-    GlobalAcc32 ga{{F.Jint[0], F.Jint[1], F.Jint[2]}, D.G};
+    GlobalAcc32 ga{{F.Jint[0], F.Jint[1], F.Jint[2]}, D.G, &counters[C_FLAGS]};
     int n_horizon = 0, n_outer = 0;
 #pragma unroll 1
     for (int p = 0; p < kDep32PPT; p++) {
@@ -554,7 +562,7 @@ __device__ __forceinline__ void deposit32_block(const Dep32 &D, const Species &c
             else
                 dep_chord32(D, ga, B1, X1, xr, X2, l1, l2, Q);
         } else if (!ok) {
-            atomicOr(&counters[C_FLAGS], 1ull);
+            atomicOr(&counters[C_FLAGS], kFlagLongMove);
         }
         // removal after the final move is deposited
         int c2[3];
@@ -577,8 +585,8 @@ __device__ __forceinline__ void deposit32_block(const Dep32 &D, const Species &c
                             double W = (di ? (double)o2[0] : 1.0 - (double)o2[0]) *
                                        (dj ? (double)o2[1] : 1.0 - (double)o2[1]) *
                                        (dk ? (double)o2[2] : 1.0 - (double)o2[2]);
-                            atomicAdd(&F.rho_abs[D.G.g(c2[0] + di, c2[1] + dj, c2[2] + dk)],
-                                      (unsigned long long)__double2ll_rn(sc * W));
+                            fixed_add_checked(&F.rho_abs[D.G.g(c2[0] + di, c2[1] + dj, c2[2] + dk)],
+                                              __double2ll_rn(sc * W), &counters[C_FLAGS]);
                         }
             }
             xo.sp[id] = kDead;
@@ -592,14 +600,7 @@ __device__ __forceinline__ void deposit32_block(const Dep32 &D, const Species &c
     wave_count32(&counters[C_REMOVED_OUTER], n_outer);
     if (use_lds) {
         __syncthreads();
-        const float inv_bx = __builtin_amdgcn_rcpf((float)bx), inv_bxy = __builtin_amdgcn_rcpf((float)(bx * by));
-        for (int e = tid; e < 3 * V; e += kDep32Block) {
-            unsigned long long v = sm[e];
-            if (v == 0ull) continue;
-            const int K = e >= 2 * V ? 2 : (e >= V ? 1 : 0), l = e - K * V;
-            const int lk = small_div(l, inv_bxy), r = l - lk * bx * by, lj = small_div(r, inv_bx), li = r - lj * bx;
-            atomicAdd(&F.Jint[K][D.G.g(blo[0] + li, blo[1] + lj, blo[2] + lk)], v);
-        }
+        flush_box(sm, V, bx, by, blo, F.Jint, D.G, &counters[C_FLAGS]);
     }
 }
 
@@ -733,8 +734,14 @@ __device__ __forceinline__ bool load_one32(const Grid &G, const Hole &h, double 
     int ci[3] = {0, 0, 0};
     for (int ax = 0; ax < 3; ax++) {
         double fl = ok ? floor(X[ax]) : 0.0;
+        float of = ok ? (float)(X[ax] - fl) : 0.0f;
+        // X just below an integer rounds to offset 1.0f: the next cell's face
+        if (of >= 1.0f) {
+            of = 0.0f;
+            fl += 1.0;
+        }
         ci[ax] = (int)fl;
-        out.off[ax][o] = ok ? (float)(X[ax] - fl) : 0.0f;
+        out.off[ax][o] = of;
     }
     out.cell[o] = pack_cell(ci[0], ci[1], ci[2]);
     for (int q = 0; q < 4; q++) out.u[q][o] = (float)U[q];
@@ -775,9 +782,15 @@ __global__ void k_from_f64(const double *x, const double *u, ParticlePtrs32 out,
     for (int q = 0; q < 3; q++) {
         double v = x[q * n + id];
         double fl = floor(v);
-        c[q] = (int)fl;
-        c[q] = c[q] < -1 ? -1 : (c[q] > 1022 ? 1022 : c[q]);
-        out.off[q][id] = (float)(v - (double)c[q]);
+        float of = (float)(v - fl);
+        if (of >= 1.0f) {  // offsets stay in [0, 1), as the pusher keeps them
+            of = 0.0f;
+            fl += 1.0;
+        }
+        const int ci = (int)fl;
+        c[q] = ci < -1 ? -1 : (ci > 1022 ? 1022 : ci);
+        // a cell outside the packable range keeps the offset from the clamped cell
+        out.off[q][id] = c[q] == ci ? of : (float)(v - (double)c[q]);
     }
     out.cell[id] = pack_cell(c[0], c[1], c[2]);
     for (int q = 0; q < 4; q++) out.u[q][id] = (float)u[q * n + id];

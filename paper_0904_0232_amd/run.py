@@ -10,7 +10,7 @@ def make_config(n, *, m, a, dt, B0=(0.0, 0.0, 0.0), species=((-1.0, 1.0),), c=1.
                 deposit_mode=capi.DEPOSIT_CURVED, field_iters=3, sort_every=0, tile=8, fp_bits=44,
                 capacity=0, precision=capi.FP64, init_covariant=False, ny=None, nz=None, center=None,
                 rk_mode=capi.RK_CLASSIC, gather_mode=capi.GATHER_STAGE,
-                gather_weights=capi.WEIGHTS_TRILINEAR, outer_layer=0.0, outer_damp=0.0):
+                gather_weights=capi.WEIGHTS_TRILINEAR, outer_layer=0.0, outer_damp=0.0, density=None):
     ny = n if ny is None else ny
     nz = n if nz is None else nz
     cfg = capi.grpic_config_default(n, ny, nz)
@@ -40,6 +40,8 @@ def make_config(n, *, m, a, dt, B0=(0.0, 0.0, 0.0), species=((-1.0, 1.0),), c=1.
     for i, (q, mass) in enumerate(species):
         cfg.charge[i] = q
         cfg.mass[i] = mass
+        # nominal macro-particles per cell for the plasma-frequency check (0: none)
+        cfg.density[i] = 0.0 if density is None else float(density[i] if hasattr(density, "__len__") else density)
     cfg.capacity = int(capacity)
     return cfg
 
@@ -66,8 +68,8 @@ class Run:
     def push_only(self, n=1):
         capi.grpic_push_only(self.h, n)
 
-    def diag(self):
-        return capi.grpic_diagnostics(self.h)
+    def diag(self, allow_overflow=False):
+        return capi.grpic_diagnostics(self.h, allow_overflow)
 
     def particles(self):
         return capi.grpic_dump_particles(self.h)

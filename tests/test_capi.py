@@ -69,3 +69,47 @@ def test_strerror_codes():
     L.grpic_strerror.restype = ctypes.c_char_p
     assert L.grpic_strerror(0) == b"ok"
     assert L.grpic_strerror(-1) == b"invalid argument"
+
+
+def test_config_check_plasma_frequency():
+    """grpic_config_check (host only) applies the plasma-frequency criterion
+    of Sec. 5.1, omega_p dt < 2 with omega_p^2 = 4 pi n q^2 / m, per species
+    with a nominal density set, besides the other limits."""
+    import math
+    from paper_0904_0232_amd import capi
+    _lib()
+    cfg = capi.grpic_config_default(16)
+    cfg.dt = 0.5
+    cfg.nspecies = 2
+    cfg.charge[0], cfg.mass[0] = -0.02, 0.02
+    cfg.charge[1], cfg.mass[1] = 0.02, 0.4
+    assert capi.grpic_config_check(cfg) == 0  # no density: not checked
+
+    def density_for(wdt, q, m):
+        w = wdt / cfg.dt
+        return w * w * m / (4.0 * math.pi * q * q)
+
+    for s, (q, m) in enumerate(((-0.02, 0.02), (0.02, 0.4))):
+        cfg.density[0] = cfg.density[1] = 0.0
+        cfg.density[s] = density_for(1.99, q, m)
+        assert capi.grpic_config_check(cfg) == 0, s
+        cfg.density[s] = density_for(2.01, q, m)
+        assert capi.grpic_config_check(cfg) == capi.EINVAL, s
+    cfg.density[0], cfg.density[1] = -1.0, 0.0
+    assert capi.grpic_config_check(cfg) == capi.EINVAL
+    cfg.density[0] = float("nan")
+    assert capi.grpic_config_check(cfg) == capi.EINVAL
+    # the workloads' own species tables sit at omega_pe dt = 0.1
+    from paper_0904_0232_amd import inputs
+    sp = inputs.species_table(0.45, 8)
+    cfg = capi.grpic_config_default(32)
+    cfg.dt, cfg.nspecies = 0.45, 2
+    for s, (q, m) in enumerate(sp):
+        cfg.charge[s], cfg.mass[s], cfg.density[s] = q, m, 8.0
+    assert capi.grpic_config_check(cfg) == 0
+    cfg.density[0] = 8.0 * 401.0  # omega_pe dt = 0.1 sqrt(401) > 2
+    assert capi.grpic_config_check(cfg) == capi.EINVAL
+    # the Courant condition c dt < 1/sqrt(3) (Sec. 5.2)
+    cfg.density[0] = 8.0
+    cfg.dt = 0.58
+    assert capi.grpic_config_check(cfg) == capi.EINVAL

@@ -65,6 +65,52 @@ def test_batch_graph_replay_equals_eager_steps():
         run.close()
 
 
+def test_served_run_matches_oracle():
+    """A request served through the batch (the captured graph of batched
+    FP32-mixed launches, beside a second run in the mix) against the FP64
+    oracle on the same inputs: particle state within 1e-5 (positions relative
+    to max(|x|, 1 cell), four-velocities to max(|u|, c)) and the particle
+    diagnostics within 1e-5, after 3 cycles.  Sorting is off in this request
+    so slots compare one to one (the batch's sorts are covered by the
+    eager-equality test above and the sort's own bit-exact tests)."""
+    from paper_0904_0232_amd import capi, inputs, serve
+    req = dict(_reqs(1, seed=23, edges=(16,))[0], ppc=3)
+    other = _reqs(1, seed=29, edges=(16,))[0]
+    cfg = serve.request_config(req)
+    cfg.sort_every = 0
+    parts = serve.request_particles(req)
+    nsteps = 3
+    b = capi.grpic_batch_create(1 << 34, 4)
+    assert capi.grpic_batch_submit(b, serve.request_config(other), 10, serve.request_particles(other)) is not None
+    rid = capi.grpic_batch_submit(b, cfg, nsteps, parts, keep_state=True)
+    assert rid is not None
+    while capi.grpic_batch_poll(b, rid)[0] == capi.RUN_ACTIVE:
+        capi.grpic_batch_step(b)
+    st, done, dg, ns, ps = capi.grpic_batch_poll(b, rid)
+    xg, ug, sg = capi.grpic_batch_dump(b, rid, ns)
+    capi.grpic_batch_destroy(b)
+    assert st == capi.RUN_DONE and done == nsteps
+    species = inputs.species_table(serve.DT, req["ppc"])
+    p = O.make_params(req["edge"], m=req["m"], a=req["a"], dt=serve.DT, species=species)
+    s = O.Sim(p, sum(x.shape[1] for x, _ in parts))
+    s.init_fields([0.0, 0.0, serve.B0])
+    for sp, (x, u) in enumerate(parts):
+        s.load(sp, x, u)
+    s.step(nsteps)
+    xo, uo, so = s.particles()
+    live = so != O.DEAD
+    assert np.array_equal(so, sg)
+    ex = float(np.max(np.abs(xg[:, live] - xo[:, live]) / np.maximum(np.abs(xo[:, live]), 1.0)))
+    eu = float(np.max(np.abs(ug[:, live] - uo[:, live]) / np.maximum(np.abs(uo[:, live]), 1.0)))
+    do = s.diag()
+    say("served run vs oracle after %d cycles: %d live, x %.2e u %.2e; energy %.9e vs %.9e" %
+        (nsteps, int(live.sum()), ex, eu, dg["energy_particles"], do["energy_particles"]))
+    assert ex < 1e-5 and eu < 1e-5
+    assert dg["n_alive"] == do["n_alive"]
+    for k in ("charge_total", "energy_particles", "lz_particles"):
+        assert abs(dg[k] - do[k]) <= 1e-5 * max(abs(do[k]), 1e-30), k
+
+
 def test_result_is_the_same_alone_and_in_the_mix():
     from paper_0904_0232_amd import serve
     reqs = _reqs(6, seed=5, rate=200.0)
