@@ -250,11 +250,15 @@ def window_errors(w, windows, state1, n_per_species):
         xg = x1[:, slots] - o[:, None]
         ug = u1[:, slots]
         live = (spo != O.DEAD) & (sp1[slots] != O.DEAD)
-        same &= bool(np.array_equal(spo != O.DEAD, sp1[slots] != O.DEAD))
-        inner = live.copy()
+        start_inner = np.ones(live.size, bool)
         for ax in range(3):
-            for xs in (win["x0"], xo):
-                inner &= (xs[ax] >= WINDOW_MARGIN) & (xs[ax] < WINDOW - WINDOW_MARGIN)
+            start_inner &= (win["x0"][ax] >= WINDOW_MARGIN) & (win["x0"][ax] < WINDOW - WINDOW_MARGIN)
+        # removal decisions of the particles that start inside the margin (the
+        # window's own faces remove the others in the oracle)
+        same &= bool(np.array_equal((spo != O.DEAD)[start_inner], (sp1[slots] != O.DEAD)[start_inner]))
+        inner = live & start_inner
+        for ax in range(3):
+            inner &= (xo[ax] >= WINDOW_MARGIN) & (xo[ax] < WINDOW - WINDOW_MARGIN)
         ex = np.abs(xg[:, inner] - xo[:, inner]) / np.maximum(np.abs(xo[:, inner] + o[:, None]), 1.0)
         eu = np.abs(ug[:, inner] - uo[:, inner]) / np.maximum(np.abs(uo[:, inner]), 1.0)
         if inner.any():
