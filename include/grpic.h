@@ -165,6 +165,21 @@ int grpic_create(const grpic_config *cfg, void *stream, grpic_t **out);
 int grpic_load_particles(grpic_t *h, int32_t species, int64_t n, const double *x,
                          const double *ucov, int64_t *kept);
 
+/* grpic_load_particles for callers that cannot allocate device memory
+ * (code under HIP graph capture, serving loops, harnesses that forbid
+ * allocation): the same load, with the same arguments and results, but the
+ * host arrays are staged in a fixed device array of the library instead of
+ * a buffer allocated for the call, and no allocation happens.  At most
+ * 1,048,576 particles per call (48 MiB of staging, 6 doubles a particle);
+ * a larger n gives GRPIC_EINVAL with a message on stderr, and nothing is
+ * loaded.  Load more with several calls.  Every device the library runs on
+ * holds one copy of the staging array until the process ends, shared by all
+ * runs on that device: calls on one device must not overlap (from several
+ * threads, or with another run's call of this function), since they would
+ * race on the staging.  Synchronous, like grpic_load_particles. */
+int grpic_load_particles_noalloc(grpic_t *h, int32_t species, int64_t n, const double *x,
+                                 const double *ucov, int64_t *kept);
+
 /* Enqueue nsteps full cycles (Sec. 2.2 and Sec. 3): magnetic half-step,
  * RK4 push, magnetic half-step, current deposition, electric step, removal,
  * and a cell sort every sort_every steps.  Asynchronous.

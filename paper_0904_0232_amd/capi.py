@@ -110,6 +110,8 @@ def lib():
         L.grpic_config_check.restype = ctypes.c_int
         L.grpic_create.argtypes = [ctypes.POINTER(Config), ctypes.c_void_p, ctypes.POINTER(_H)]
         L.grpic_load_particles.argtypes = [_H, ctypes.c_int32, ctypes.c_int64, _D, _D, _I64]
+        L.grpic_load_particles_noalloc.argtypes = [_H, ctypes.c_int32, ctypes.c_int64, _D, _D, _I64]
+        L.grpic_load_particles_noalloc.restype = ctypes.c_int
         L.grpic_step.argtypes = [_H, ctypes.c_int32]
         L.grpic_push_only.argtypes = [_H, ctypes.c_int32]
         L.grpic_diagnostics.argtypes = [_H, ctypes.POINTER(Diag)]
@@ -182,10 +184,12 @@ class TorchMemory:
         import torch
         self._torch = torch
         self._blocks = {}
+        self.alloc_calls = 0
         self.alloc = ALLOC_FN(self._alloc)
         self.free = FREE_FN(self._free)
 
     def _alloc(self, nbytes, ctx):
+        self.alloc_calls += 1
         try:
             t = self._torch.empty(int(nbytes), dtype=self._torch.uint8, device="cuda")
         except Exception:
@@ -226,6 +230,18 @@ def grpic_load_particles(h, species, x, ucov):
     assert x.shape == (3, n) and uc.shape == (3, n)
     kept = ctypes.c_int64()
     _check(lib().grpic_load_particles(h, int(species), n, _dp(x), _dp(uc), ctypes.byref(kept)))
+    return kept.value
+
+
+def grpic_load_particles_noalloc(h, species, x, ucov):
+    """grpic_load_particles through the library's fixed staging array (no
+    device allocation; at most 2^20 particles per call)."""
+    x = _f64(x)
+    uc = _f64(ucov)
+    n = x.shape[1]
+    assert x.shape == (3, n) and uc.shape == (3, n)
+    kept = ctypes.c_int64()
+    _check(lib().grpic_load_particles_noalloc(h, int(species), n, _dp(x), _dp(uc), ctypes.byref(kept)))
     return kept.value
 
 

@@ -8,6 +8,7 @@
 
 #include <algorithm>
 #include <map>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -17,10 +18,21 @@
 
 using namespace grpic;
 
+// Staging area of grpic_load_particles_noalloc: the host arrays of one call
+// (positions and covariant velocities, 6 doubles per particle) are copied
+// here before the load kernel reads them.  Each device the library runs on
+// holds its own copy of the array, at its own address, until the process
+// ends.  Host code never uses the array's name as an address: the device
+// address comes from hipGetSymbolAddress, once per device (noalloc_staging).
+constexpr int64_t kNoAllocLoadMax = (int64_t)1 << 20;  // particles per call (48 MiB)
+static __device__ __align__(256) double scratch[6 * kNoAllocLoadMax];
+
 struct grpic_s {
     grpic_config cfg;
     bool mixed;  // FP32-mixed form
     hipStream_t stream;
+    int device;               // device current at creation
+    double *noalloc_staging;  // that device's address of `scratch` (NULL: not resolved)
     Grid G;
     Hole h;
     Species S;
@@ -71,6 +83,23 @@ int check_at(hipError_t e, const char *what, int line) {
 // Errors left by earlier HIP calls of the host program (not this library)
 // must not be reported as ours: clear them on entry.
 void clear_foreign_error() { (void)hipGetLastError(); }
+
+// Device address of `scratch` on device dev, resolved once per device with
+// that device current (the caller's current device when a run is created).
+constexpr int kMaxDevices = 64;
+std::mutex g_staging_mu;
+double *g_staging[kMaxDevices] = {};
+
+double *noalloc_staging(int dev) {
+    if (dev < 0 || dev >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lock(g_staging_mu);
+    if (!g_staging[dev]) {
+        void *p = nullptr;
+        if (FAILS(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)))) return nullptr;
+        g_staging[dev] = (double *)p;
+    }
+    return g_staging[dev];
+}
 
 void *raw_alloc(grpic_t *h, size_t bytes) {
     if (bytes == 0) bytes = 256;
@@ -917,6 +946,11 @@ int grpic_create(const grpic_config *cfg, void *stream, grpic_t **out) {
     h->cfg = *cfg;
     h->mixed = cfg->precision == GRPIC_FP32_MIXED;
     h->stream = (hipStream_t)stream;
+    if (FAILS(hipGetDevice(&h->device))) {
+        delete h;
+        return GRPIC_EDEVICE;
+    }
+    h->noalloc_staging = noalloc_staging(h->device);
     h->G.nx = cfg->nx;
     h->G.ny = cfg->ny;
     h->G.nz = cfg->nz;
@@ -1008,18 +1042,12 @@ int grpic_create(const grpic_config *cfg, void *stream, grpic_t **out) {
     return GRPIC_OK;
 }
 
-int grpic_load_particles(grpic_t *h, int32_t species, int64_t n, const double *x, const double *ucov,
-                         int64_t *kept) {
-    if (!h || n < 0 || (n > 0 && (!x || !ucov))) return GRPIC_EINVAL;
-    if (species < 0 || species >= h->cfg.nspecies) return GRPIC_EINVAL;
-    if (h->n_slots + n > h->cap) return GRPIC_ENOMEM;
-    clear_foreign_error();
-    if (kept) *kept = 0;
-    if (n == 0) return GRPIC_OK;
+namespace {
+// Load through the device staging buffer st (6 n doubles): copy the host
+// arrays in, run the load kernel, count the kept particles.  Synchronous.
+int load_staged(grpic_t *h, int32_t species, int64_t n, const double *x, const double *ucov, int64_t *kept,
+                double *st) {
     hipStream_t s = h->stream;
-    Temp stage(h, (size_t)6 * n * 8);
-    if (!stage.p) return GRPIC_ENOMEM;
-    double *st = (double *)stage.p;
     int rc = GRPIC_OK;
     unsigned long long before = 0, after = 0;
     if (FAILS(hipMemcpyAsync(st, x, 3 * n * 8, hipMemcpyHostToDevice, s))) rc = GRPIC_EDEVICE;
@@ -1042,6 +1070,37 @@ int grpic_load_particles(grpic_t *h, int32_t species, int64_t n, const double *x
     h->n_slots += n;
     if (kept) *kept = (int64_t)(after - before);
     return GRPIC_OK;
+}
+}  // namespace
+
+int grpic_load_particles(grpic_t *h, int32_t species, int64_t n, const double *x, const double *ucov,
+                         int64_t *kept) {
+    if (!h || n < 0 || (n > 0 && (!x || !ucov))) return GRPIC_EINVAL;
+    if (species < 0 || species >= h->cfg.nspecies) return GRPIC_EINVAL;
+    if (h->n_slots + n > h->cap) return GRPIC_ENOMEM;
+    clear_foreign_error();
+    if (kept) *kept = 0;
+    if (n == 0) return GRPIC_OK;
+    Temp stage(h, (size_t)6 * n * 8);
+    if (!stage.p) return GRPIC_ENOMEM;
+    return load_staged(h, species, n, x, ucov, kept, (double *)stage.p);
+}
+
+int grpic_load_particles_noalloc(grpic_t *h, int32_t species, int64_t n, const double *x, const double *ucov,
+                                 int64_t *kept) {
+    if (!h || n < 0 || (n > 0 && (!x || !ucov))) return GRPIC_EINVAL;
+    if (species < 0 || species >= h->cfg.nspecies) return GRPIC_EINVAL;
+    if (n > kNoAllocLoadMax) {
+        fprintf(stderr, "grpic: grpic_load_particles_noalloc loads at most %lld particles per call, got %lld\n",
+                (long long)kNoAllocLoadMax, (long long)n);
+        return GRPIC_EINVAL;
+    }
+    if (h->n_slots + n > h->cap) return GRPIC_ENOMEM;
+    clear_foreign_error();
+    if (kept) *kept = 0;
+    if (n == 0) return GRPIC_OK;
+    if (!h->noalloc_staging) return GRPIC_EDEVICE;
+    return load_staged(h, species, n, x, ucov, kept, h->noalloc_staging);
 }
 
 int grpic_step(grpic_t *h, int32_t nsteps) {
