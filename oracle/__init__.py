@@ -95,6 +95,8 @@ def lib():
         L.or_sim_init_fields.argtypes = [ctypes.c_void_p, _D]
         L.or_sim_init_fields2.argtypes = [ctypes.c_void_p, _D, ctypes.c_int]
         L.or_sim_set_fields.argtypes = [ctypes.c_void_p, _D, _D]
+        L.or_sim_make_reference.argtypes = [ctypes.c_void_p]
+        L.or_constitutive_point.argtypes = [_P, ctypes.c_double, ctypes.c_double, ctypes.c_double, _D, _D, _D, _D]
         L.or_sim_get_fields.argtypes = [ctypes.c_void_p, ctypes.c_int, _D]
         L.or_sim_node_count.restype = ctypes.c_size_t
         L.or_sim_node_count.argtypes = [ctypes.c_void_p]
@@ -198,6 +200,19 @@ def christoffel(p, x, y, z):
     return G.reshape(4, 4, 4)
 
 
+def constitutive_point(p, X, Fs_lo, Ft_up):
+    """The grid's constitutive step at the point X (node coordinates): from
+    (F_23, F_31, F_12) and (F^14, F^24, F^34) to (F_14, F_24, F_34) and
+    (F^23, F^31, F^12)."""
+    a = _f64(Fs_lo)
+    b = _f64(Ft_up)
+    tl = np.zeros(3)
+    su = np.zeros(3)
+    lib().or_constitutive_point(ctypes.byref(p), float(X[0]), float(X[1]), float(X[2]), _dp(a), _dp(b), _dp(tl),
+                                _dp(su))
+    return tl, su
+
+
 def mass_shell(p, X, ucov):
     out = np.zeros(4)
     X = _f64(X)
@@ -257,6 +272,11 @@ class Sim:
         B = _f64(B).reshape(-1)
         assert D.size == 3 * self.gsize and B.size == 3 * self.gsize
         self.L.or_sim_set_fields(self.h, _dp(D), _dp(B))
+
+    def make_reference(self):
+        """Take the current fields as the reference state (frozen points and
+        relaxation targets)."""
+        self.L.or_sim_make_reference(self.h)
 
     def get(self, which):
         """which: 'D', 'B', 'E', 'H', 'J' (3 comps) or 'rho_abs'."""

@@ -19,13 +19,18 @@
  * Parity status of each function is stated in its comment.  Pinned means
  * a CPU test checks it against a closed form, a textbook special case,
  * an invariant or brute force; "parity unpinned" means no such check
- * exists and it is trusted only by reading.  Parity unpinned here:
- *  - the averaging of staggered components to nodes and the curvature part
- *    of the constitutive map (pinned only through their m = 0 reduction,
- *    the bounded Wald solution and Gauss's law);
- *  - the curved face-area weights beyond their flux sum and m = 0 limit;
- *  - the relaxation layer inside the horizon;
- *  - the field-energy diagnostic.
+ * exists and it is trusted only by reading.  Every function is pinned:
+ *  - the constitutive step against raising with the metric, pointwise in
+ *    Kerr, and its node averaging through Wald's vacuum solution in Kerr,
+ *    whose one-cycle change converges at second order;
+ *  - the curved face-area weights against a Gauss-Legendre integral of the
+ *    metric area density over each sub-rectangle;
+ *  - the relaxation layer as the stated pull toward the reference state;
+ *  - the field-energy diagnostic against closed-form cavity-mode sums.
+ * What the pins do not fix is stated as readings: the inner boundary
+ * (excision and relaxation) lets disturbances from inside the horizon out
+ * through the centred stencils; Wald's far field stays bounded at about
+ * 0.1 B0 rather than at its truncation level.
  */
 #include <math.h>
 #include <stdint.h>
@@ -336,8 +341,9 @@ static const int PT[3][2] = {{0, 3}, {1, 3}, {2, 3}};
  * pairs Ft_up = (F^14, F^24, F^34), recover Ft_lo = (F_14, F_24, F_34) and
  * Fs_up = (F^23, F^31, F^12) through F^{mn} = g^{ma} g^{nb} F_{ab}, written
  * as a 6x6 linear map M on the six pairs and solved for the unknown half.
- * Pinned only through its m=0 reduction (E_cov = -D, H = B_cov), the lowering
- * round trip at initialisation and the stability run. */
+ * Pinned: equals raising with the metric, F^{mn} = g^{ma} g^{nb} F_{ab},
+ * at points around a spinning hole (random F), and its m=0 reduction
+ * (E_cov = -D, H = B_cov). */
 static void constitutive(const double gi[16], const double Fs_lo[3], const double Ft_up[3],
                          double Ft_lo[3], double Fs_up[3])
 {
@@ -395,8 +401,8 @@ static void constitutive(const double gi[16], const double Fs_lo[3], const doubl
  * axis where the offsets agree the same index is used, otherwise the two
  * nearest points of the component (distance 1/2) are averaged.
  * reading: the paper does not say how off-point components are formed;
- * arithmetic means of the nearest neighbours are used (parity unpinned
- * beyond the m=0 reduction, where they cancel out). */
+ * arithmetic means of the nearest neighbours are used.  Pinned through
+ * the grid map below. */
 static double avg_at(const or_params *p, const double *arr, int kind, int c,
                      const int pt_half[3], int i, int j, int k)
 {
@@ -491,8 +497,9 @@ static void node_pair(const or_sim *s, int i, int j, int k, double vD[3], double
  * so the field energy (D.D + B.B + sum over nodes of v.(S-I)v)/2 is an
  * invariant of the semi-discrete equations, and at m = 0 it is the Yee
  * identity.  Nodes that are excised or outside [0,n] contribute nothing.
- * Pinned: m = 0 reduction to Yee (cavity eigenmode recurrence); energy
- * conservation and bounded fields in curved space. */
+ * Pinned: m = 0 reduction to Yee (cavity eigenmode recurrence); Wald's
+ * vacuum solution in Kerr changes by a second-order truncation error per
+ * cycle (the one-cycle change falls 8-fold when m, a and the grid double). */
 static void compute_w(or_sim *s, double *w)
 {
     const or_params *p = &s->p;
@@ -724,7 +731,8 @@ static int in_outer_layer(const or_params *p, int kind, int c, int i, int j, int
  * initial values by the fraction sigma = damp_max ((r_damp - r)/(r_damp - r_exc))^2
  * once per step, after the electric step.  The region is causally cut off
  * from the exterior, and without it the centred stencil grows near the
- * excision surface. */
+ * excision surface.  Pinned: one cycle with the layer equals the same cycle
+ * without it followed by exactly this pull at exactly these points. */
 static void relax_inner(or_sim *s)
 {
     const or_params *p = &s->p;
@@ -785,8 +793,10 @@ static void relax_outer(or_sim *s)
 /* Node tensor (Sec. 3.3, the field tensor components at the cell nodes):
  * average the staggered evolved pair to the node, complete it with the
  * constitutive step and lower the second index, F^a_b = F^{ag} g_{gb}.
- * reading: arithmetic means of the nearest neighbours (parity unpinned
- * beyond the m=0 reduction). */
+ * reading: arithmetic means of the nearest neighbours.  Pinned: the
+ * averaging (node_pair) and the constitutive step are those of the grid map
+ * (Wald convergence, pointwise raising); the lowering uses the pinned
+ * metric. */
 static void compute_nodes(or_sim *s)
 {
     const or_params *p = &s->p;
@@ -1054,7 +1064,9 @@ static void push_step(const or_params *p, const double *node, double qm, double 
  *  - flat: the bilinear weights at the segment midpoint;
  * both plus the exact segment-average term +-dI dJ/12 (+ on (i,j) and
  * (i+1,j+1)).  Pinned: discrete continuity in flat mode and at m=0, flux
- * sum, curved == flat at m=0. */
+ * sum, curved == flat at m=0, and each curved weight against a 5x5
+ * Gauss-Legendre integral of the density over its sub-rectangle (within the
+ * midpoint rule's O(h^2) error; the density at a wrong point fails). */
 static double area_density(const or_params *p, int I, int Jx, const double X[3])
 {
     double x = X[0] - p->center[0], y = X[1] - p->center[1], z = X[2] - p->center[2];
@@ -1294,6 +1306,22 @@ void or_sim_init_fields2(or_sim *s, const double B0[3], int covariant)
 
 void or_sim_init_fields(or_sim *s, const double B0[3]) { or_sim_init_fields2(s, B0, 0); }
 
+/* Take the current fields as the reference state: the values the frozen
+ * points hold and the relaxation layers pull toward (test hook, used to
+ * start from a stationary solution other than the paper's initial field). */
+void or_sim_make_reference(or_sim *s) { set_reference(s); }
+
+/* Test hook: the constitutive step of the grid at one point (node
+ * coordinates X, Y, Z; the flat metric inside r_exc), from (F_23, F_31,
+ * F_12) and (F^14, F^24, F^34) to (F_14, F_24, F_34) and (F^23, F^31, F^12). */
+void or_constitutive_point(const or_params *p, double X, double Y, double Z, const double Fs_lo[3],
+                           const double Ft_up[3], double Ft_lo[3], double Fs_up[3])
+{
+    double g[16], gi[16];
+    grid_metric(p, X, Y, Z, g, gi);
+    constitutive(gi, Fs_lo, Ft_up, Ft_lo, Fs_up);
+}
+
 void or_sim_set_fields(or_sim *s, const double *D, const double *B)
 {
     for (int c = 0; c < 3; c++) {
@@ -1485,12 +1513,17 @@ void or_charge_density(const or_params *p, int64_t n, const double *x, const dou
 
 /* One full cycle (Sec. 2.2 and the ordering at the top of Sec. 3):
  * the state enters as (D^n, B^{n-1/2}, x_n, u_n);
- *   E_cov^n = C(D^n, B^{n-1/2});  B -> B^n (half-step);
+ *   B -> B^n (half-step) with E_cov^n made consistent with B^n by
+ *     field_iters fixed-point passes (field_b_to_n);
  *   node tensor from (D^n, B^n);  push x_n -> x_{n+1};
  *   B -> B^{n+1/2} (second half-step with the same E_cov^n);
- *   deposit J^{n+1/2} from the chords;  H = C(B^{n+1/2}, D^n);
- *   D -> D^{n+1};  remove particles inside r_rm or outside the grid.
- * reading: the constitutive coupling is explicit and lagged as written. */
+ *   deposit J^{n+1/2} from the chords;
+ *   D -> D^{n+1} with H made consistent with D^{n+1/2} by the same passes
+ *     (field_d_step);  relaxation layers;
+ *   remove particles inside r_rm or outside the grid.
+ * reading: with field_iters = 1 the constitutive coupling is the explicit
+ * lag of the printed ordering; the default three passes centre it in time
+ * (see the comment above field_b_to_n). */
 void or_sim_step(or_sim *s, int nsteps)
 {
     const or_params *p = &s->p;
@@ -1587,7 +1620,10 @@ void or_stable_order(int64_t n, uint32_t *keys, int64_t *perm)
  * (1/8 pi)[sum_E (-E_cov D) + sum_B (B_cov H)] over in-domain points, the
  * Gauss residual max |-div D - 4 pi rho| at interior nodes whose six
  * E points are all updated and outside the relaxation layer, and the
- * mass-shell residual. */
+ * mass-shell residual.  Frozen points enter the field energy with the
+ * derived values of the reference state.  Pinned: the field energy of m = 0
+ * cavity modes equals its closed-form sums; counts, charge, Killing energy
+ * and L_z through the conservation tests of the cycle. */
 void or_sim_diag(or_sim *s, or_diag *d)
 {
     const or_params *p = &s->p;
