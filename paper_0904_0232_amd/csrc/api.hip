@@ -53,7 +53,6 @@ struct grpic_s {
     double jscale, rscale;
     uint32_t *keys, *keys_alt, *idx, *idx_alt;
     void *sort_temp;
-    size_t sort_temp_bytes;
     int key_bits;
     unsigned long long *rho_scratch;
     double *red;
@@ -380,16 +379,17 @@ void deposit_particles(grpic_t *h) {
                        pp(h, 1 - h->xc, h->uc), h->n_slots, h->F64, h->counters, h->stream);
 }
 
-int do_sort(grpic_t *h) {
+// keep: leave the sorted keys and the permutation for grpic_sort.
+int do_sort(grpic_t *h, bool keep = false, uint32_t **final_keys = nullptr, uint32_t **final_idx = nullptr) {
     TimedGroup tg(h, GRPIC_TIMER_SORT);
     if (h->mixed)
         launch_sort32(h->G, h->cfg.tile, h->n_slots, pp32(h, h->xc, h->uc), pp32(h, 1 - h->xc, 1 - h->uc), h->keys,
-                      h->keys_alt, h->idx, h->idx_alt, h->sort_temp, h->sort_temp_bytes, h->key_bits, h->counters,
-                      h->stream);
+                      h->keys_alt, h->idx, h->idx_alt, h->sort_temp, h->key_bits, keep, final_keys, final_idx,
+                      h->counters, h->stream);
     else
         launch_sort(h->G, h->cfg.tile, h->n_slots, pp(h, h->xc, h->uc), pp(h, 1 - h->xc, 1 - h->uc), h->keys,
-                    h->keys_alt, h->idx, h->idx_alt, h->sort_temp, h->sort_temp_bytes, h->key_bits, h->counters,
-                    h->stream);
+                    h->keys_alt, h->idx, h->idx_alt, h->sort_temp, h->key_bits, keep, final_keys, final_idx,
+                    h->counters, h->stream);
     h->xc = 1 - h->xc;
     h->uc = 1 - h->uc;
     return check(hipGetLastError());
@@ -1004,8 +1004,7 @@ int grpic_create(const grpic_config *cfg, void *stream, grpic_t **out) {
     h->keys_alt = (uint32_t *)A(cap * 4);
     h->idx = (uint32_t *)A(cap * 4);
     h->idx_alt = (uint32_t *)A(cap * 4);
-    h->sort_temp_bytes = sort_temp_bytes(cap);
-    h->sort_temp = A(h->sort_temp_bytes);
+    h->sort_temp = A(sort_temp_bytes(cap));
     h->rho_scratch = (unsigned long long *)A(gs * 8);
     h->red_cap = ((cap + 255) / 256) * 12 + ((nn + 255) / 256) * 3 + 64;
     h->red = (double *)A(h->red_cap * 8);
@@ -1355,13 +1354,15 @@ int grpic_sort(grpic_t *h, uint32_t *keys_out, int64_t *perm_out) {
     clear_foreign_error();
     if (!h) return GRPIC_EINVAL;
     int64_t n = h->n_slots;
-    int rc = do_sort(h);
+    uint32_t *fk = nullptr, *fi = nullptr;
+    int rc = do_sort(h, true, &fk, &fi);
     if (rc) return rc;
+    if (n == 0) return GRPIC_OK;
     hipStream_t s = h->stream;
     std::vector<uint32_t> k(n), p(n);
     unsigned long long cnt[C_NCOUNTERS];
-    rc = check(hipMemcpyAsync(k.data(), h->keys_alt, n * 4, hipMemcpyDeviceToHost, s));
-    if (!rc) rc = check(hipMemcpyAsync(p.data(), h->idx_alt, n * 4, hipMemcpyDeviceToHost, s));
+    rc = check(hipMemcpyAsync(k.data(), fk, n * 4, hipMemcpyDeviceToHost, s));
+    if (!rc) rc = check(hipMemcpyAsync(p.data(), fi, n * 4, hipMemcpyDeviceToHost, s));
     if (!rc) rc = check(hipMemcpyAsync(cnt, h->counters, sizeof(cnt), hipMemcpyDeviceToHost, s));
     if (!rc) rc = check(hipStreamSynchronize(s));
     if (rc) return rc;

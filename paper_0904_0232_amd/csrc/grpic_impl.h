@@ -272,13 +272,20 @@ int64_t batch_blocks(int kind, const Grid &G, const int relax_box[6], int64_t n_
 void relax_box_of(const Grid &G, const Hole &h, double r_damp, double damp_max, int box[6]);
 
 // sort
+// Scratch bytes of the sort for up to `capacity` slots (digit counts per
+// tile and the scan's chunk sums).
 size_t sort_temp_bytes(int64_t capacity);
+// Stable sort of the n slots by tile-major cell key into `out`, removed
+// particles last; counters[C_NALIVE] receives the live count.  keys, keys_alt,
+// idx and idx_alt (n entries each) carry the keys and slot indices between
+// passes.  keep: *final_keys and *final_idx point at the sorted keys and the
+// original slot of each sorted position (else NULL).
 void launch_sort(const Grid &G, int tile, int64_t n, ParticlePtrs in, ParticlePtrs out, uint32_t *keys,
-                 uint32_t *keys_alt, uint32_t *idx, uint32_t *idx_alt, void *temp, size_t temp_bytes,
-                 int key_bits, unsigned long long *counters, hipStream_t s);
+                 uint32_t *keys_alt, uint32_t *idx, uint32_t *idx_alt, void *temp, int key_bits, bool keep,
+                 uint32_t **final_keys, uint32_t **final_idx, unsigned long long *counters, hipStream_t s);
 void launch_sort32(const Grid &G, int tile, int64_t n, ParticlePtrs32 in, ParticlePtrs32 out, uint32_t *keys,
-                   uint32_t *keys_alt, uint32_t *idx, uint32_t *idx_alt, void *temp, size_t temp_bytes,
-                   int key_bits, unsigned long long *counters, hipStream_t s);
+                   uint32_t *keys_alt, uint32_t *idx, uint32_t *idx_alt, void *temp, int key_bits, bool keep,
+                   uint32_t **final_keys, uint32_t **final_idx, unsigned long long *counters, hipStream_t s);
 
 // diagnostics: fills host-side partial sums (see diag.hip)
 struct DiagOut {

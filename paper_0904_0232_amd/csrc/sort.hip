@@ -1,83 +1,102 @@
 // Stable tile-major cell sort of the particle slots and compaction of the
 // removed ones.  Key = ((tz nTy + ty) nTx + tx) T^3 + (lz T + ly) T + lx with
-// (i,j,k) = floor(x); removed particles take the all-ones key of key_bits bits
-// and so sort to the end.  The ordering primitive is rocPRIM's stable LSD
-// radix sort (through hipCUB) on key_bits bits only; keys, the gather of the
-// SoA state and the live count are computed here.
-#include <hipcub/hipcub.hpp>
-
+// (i,j,k) = floor(x) (FP64) or the packed cell (FP32-mixed); removed
+// particles take the all-ones key of key_bits bits and so sort to the end.
+//
+// The ordering is a least-significant-digit radix sort over digits of at most
+// 9 bits (ceil(key_bits / 9) passes, 3 at 256^3).  Each pass is
+//   upsweep:   per tile of 4096 slots, a histogram of the digit in LDS,
+//              written digit-major, counts[d * ntiles + tile];
+//   scan:      one exclusive scan over that array gives, for every (digit,
+//              tile), where the tile's elements of that digit start;
+//   downsweep: the tile re-reads its keys and ranks each element among the
+//              earlier elements of its digit (wave ballots give the rank
+//              inside a wave, a per-wave count table in LDS the rank across
+//              the block's waves, a running count across the tile's rounds),
+//              stages the tile in LDS in digit order and writes it out, so
+//              consecutive lanes write consecutive addresses.
+// Ranks follow slot order within a tile and tiles follow slot order within a
+// digit, so every pass is stable, and the whole sort equals a stable sort on
+// the key.  The last pass moves the particle records themselves (the SoA
+// gather) instead of writing an index array.  No pass waits on another
+// block, and every loop is bounded by the tile.
 #include "grpic_dev.h"
 #include "grpic_impl.h"
 
 namespace grpic {
 
+constexpr int kSortBlock = 256;
+constexpr int kSortItems = 16;
+constexpr int kSortTile = kSortBlock * kSortItems;  // slots per tile
+constexpr int kSortWaves = kSortBlock / 64;
+constexpr int kSortMaxBits = 9;
+constexpr int kSortMaxBins = 1 << kSortMaxBits;
+constexpr int kScanItems = 16;
+constexpr int kScanChunk = kSortBlock * kScanItems;  // scan entries per block
+constexpr int kScanTopBlock = 1024;
+
+struct SortPlan {
+    int passes;
+    int shift[4];
+    int bits[4];
+};
+
+// Digits of at most 9 bits, as even as possible, low digits first.
+SortPlan sort_plan(int key_bits) {
+    SortPlan P;
+    P.passes = (key_bits + kSortMaxBits - 1) / kSortMaxBits;
+    if (P.passes < 1) P.passes = 1;
+    const int base = key_bits / P.passes, extra = key_bits % P.passes;
+    int sh = 0;
+    for (int p = 0; p < P.passes; p++) {
+        P.bits[p] = base + (p < extra ? 1 : 0);
+        P.shift[p] = sh;
+        sh += P.bits[p];
+    }
+    return P;
+}
+
+int64_t sort_tiles(int64_t n) { return (n + kSortTile - 1) / kSortTile; }
+
+size_t sort_temp_bytes(int64_t capacity) {
+    const int64_t entries = (int64_t)kSortMaxBins * sort_tiles(capacity > 0 ? capacity : 1);
+    const int64_t chunks = (entries + kScanChunk - 1) / kScanChunk;
+    return (size_t)(entries + chunks + 64) * 4;
+}
+
+// ---------------------------------------------------------------------------
+// Keys.  The first block also resets the live count, which the last pass
+// lowers to the position of the first removed particle.
+
+__device__ __forceinline__ uint32_t tile_key(int T, int nTx, int nTy, const int c[3]) {
+    const uint32_t tx = c[0] / T, ty = c[1] / T, tz = c[2] / T;
+    const uint32_t lx = c[0] % T, ly = c[1] % T, lz = c[2] % T;
+    return ((tz * nTy + ty) * nTx + tx) * (uint32_t)(T * T * T) + (lz * T + ly) * T + lx;
+}
+
 __global__ void k_sort_keys(Grid G, int T, int nTx, int nTy, uint32_t sentinel, ParticlePtrs in, int64_t n,
-                            uint32_t *__restrict__ keys, uint32_t *__restrict__ idx) {
-    int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+                            uint32_t *__restrict__ keys, unsigned long long *counters) {
+    const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (id == 0) counters[C_NALIVE] = (unsigned long long)n;
     if (id >= n) return;
-    idx[id] = (uint32_t)id;
     if (in.sp[id] == kDead) {
         keys[id] = sentinel;
         return;
     }
     int c[3];
     for (int ax = 0; ax < 3; ax++) {
-        int ci = (int)floor(in.x[ax][id]);
-        int nn = G.dim(ax);
+        const int ci = (int)floor(in.x[ax][id]);
+        const int nn = G.dim(ax);
         c[ax] = ci < 0 ? 0 : (ci > nn - 1 ? nn - 1 : ci);
     }
-    uint32_t tx = c[0] / T, ty = c[1] / T, tz = c[2] / T;
-    uint32_t lx = c[0] % T, ly = c[1] % T, lz = c[2] % T;
-    keys[id] = ((tz * nTy + ty) * nTx + tx) * (uint32_t)(T * T * T) + (lz * T + ly) * T + lx;
+    keys[id] = tile_key(T, nTx, nTy, c);
 }
 
-__global__ void k_sort_gather(ParticlePtrs in, ParticlePtrs out, const uint32_t *__restrict__ idx, int64_t n) {
-    int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (id >= n) return;
-    uint32_t s = idx[id];
-    for (int q = 0; q < 3; q++) out.x[q][id] = in.x[q][s];
-    for (int q = 0; q < 4; q++) out.u[q][id] = in.u[q][s];
-    out.sp[id] = in.sp[s];
-}
-
-// live count = position of the first sentinel key
-__global__ void k_sort_count(const uint32_t *__restrict__ keys, int64_t n, uint32_t sentinel,
-                             unsigned long long *counters) {
-    int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (id >= n) return;
-    bool here = keys[id] == sentinel;
-    bool prev = id == 0 ? false : keys[id - 1] == sentinel;
-    if (here && !prev) counters[C_NALIVE] = (unsigned long long)id;
-    if (id == n - 1 && !here) counters[C_NALIVE] = (unsigned long long)n;
-}
-
-size_t sort_temp_bytes(int64_t capacity) {
-    size_t bytes = 0;
-    hipcub::DeviceRadixSort::SortPairs(nullptr, bytes, (const uint32_t *)nullptr, (uint32_t *)nullptr,
-                                       (const uint32_t *)nullptr, (uint32_t *)nullptr, (int)capacity, 0, 32);
-    return bytes;
-}
-
-void launch_sort(const Grid &G, int tile, int64_t n, ParticlePtrs in, ParticlePtrs out, uint32_t *keys,
-                 uint32_t *keys_alt, uint32_t *idx, uint32_t *idx_alt, void *temp, size_t temp_bytes,
-                 int key_bits, unsigned long long *counters, hipStream_t s) {
-    if (n <= 0) return;
-    int nTx = (G.nx + tile - 1) / tile, nTy = (G.ny + tile - 1) / tile;
-    uint32_t sentinel = key_bits >= 32 ? 0xFFFFFFFFu : ((1u << key_bits) - 1u);
-    unsigned nb = (unsigned)((n + 255) / 256);
-    hipLaunchKernelGGL(k_sort_keys, dim3(nb), dim3(256), 0, s, G, tile, nTx, nTy, sentinel, in, n, keys, idx);
-    size_t tb = temp_bytes;
-    hipcub::DeviceRadixSort::SortPairs(temp, tb, keys, keys_alt, idx, idx_alt, (int)n, 0, key_bits, s);
-    hipLaunchKernelGGL(k_sort_gather, dim3(nb), dim3(256), 0, s, in, out, idx_alt, n);
-    hipLaunchKernelGGL(k_sort_count, dim3(nb), dim3(256), 0, s, keys_alt, n, sentinel, counters);
-}
-
-// FP32-mixed: keys from the packed cell.
 __global__ void k_sort_keys32(Grid G, int T, int nTx, int nTy, uint32_t sentinel, ParticlePtrs32 in, int64_t n,
-                              uint32_t *__restrict__ keys, uint32_t *__restrict__ idx) {
-    int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+                              uint32_t *__restrict__ keys, unsigned long long *counters) {
+    const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (id == 0) counters[C_NALIVE] = (unsigned long long)n;
     if (id >= n) return;
-    idx[id] = (uint32_t)id;
     if (in.sp[id] == kDead) {
         keys[id] = sentinel;
         return;
@@ -85,36 +104,314 @@ __global__ void k_sort_keys32(Grid G, int T, int nTx, int nTy, uint32_t sentinel
     int c[3];
     unpack_cell(in.cell[id], c[0], c[1], c[2]);
     for (int ax = 0; ax < 3; ax++) {
-        int nn = G.dim(ax);
+        const int nn = G.dim(ax);
         c[ax] = c[ax] < 0 ? 0 : (c[ax] > nn - 1 ? nn - 1 : c[ax]);
     }
-    uint32_t tx = c[0] / T, ty = c[1] / T, tz = c[2] / T;
-    uint32_t lx = c[0] % T, ly = c[1] % T, lz = c[2] % T;
-    keys[id] = ((tz * nTy + ty) * nTx + tx) * (uint32_t)(T * T * T) + (lz * T + ly) * T + lx;
+    keys[id] = tile_key(T, nTx, nTy, c);
 }
 
-__global__ void k_sort_gather32(ParticlePtrs32 in, ParticlePtrs32 out, const uint32_t *__restrict__ idx, int64_t n) {
-    int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (id >= n) return;
-    uint32_t s = idx[id];
-    out.cell[id] = in.cell[s];
-    for (int q = 0; q < 3; q++) out.off[q][id] = in.off[q][s];
-    for (int q = 0; q < 4; q++) out.u[q][id] = in.u[q][s];
-    out.sp[id] = in.sp[s];
+// ---------------------------------------------------------------------------
+// Upsweep: digit histogram of one tile.
+
+__global__ __launch_bounds__(kSortBlock) void k_sort_upsweep(const uint32_t *__restrict__ keys, int64_t n, int shift,
+                                                              int bits, int64_t ntiles, uint32_t *__restrict__ counts) {
+    __shared__ uint32_t hist[kSortMaxBins];
+    const int R = 1 << bits;
+    for (int d = threadIdx.x; d < R; d += kSortBlock) hist[d] = 0u;
+    __syncthreads();
+    const int64_t base = (int64_t)blockIdx.x * kSortTile;
+#pragma unroll 4
+    for (int q = 0; q < kSortItems; q++) {
+        const int64_t i = base + q * kSortBlock + threadIdx.x;
+        if (i < n) atomicAdd(&hist[(keys[i] >> shift) & (uint32_t)(R - 1)], 1u);
+    }
+    __syncthreads();
+    for (int d = threadIdx.x; d < R; d += kSortBlock) counts[(int64_t)d * ntiles + blockIdx.x] = hist[d];
+}
+
+// ---------------------------------------------------------------------------
+// Exclusive scan of m uint32 entries in place (the totals fit 32 bits: they
+// sum to the slot count).  Chunks of kScanChunk entries: chunk sums, a scan
+// of the sums in one block, then each chunk scanned from its base.
+
+// Exclusive scan of one value per thread over the block; *total receives
+// the block's sum.  Every thread of the block calls it.
+__device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t *total) {
+    __shared__ uint32_t wsum[kScanTopBlock / 64];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    uint32_t x = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t y = __shfl_up(x, o, 64);
+        if (lane >= o) x += y;
+    }
+    if (lane == 63) wsum[w] = x;
+    __syncthreads();
+    uint32_t before = 0, all = 0;
+    for (int k = 0; k < nw; k++) {
+        const uint32_t s = wsum[k];
+        if (k < w) before += s;
+        all += s;
+    }
+    __syncthreads();  // wsum may be reused by the next call
+    *total = all;
+    return before + x - v;
+}
+
+__global__ __launch_bounds__(kSortBlock) void k_scan_reduce(const uint32_t *__restrict__ a, int64_t m,
+                                                            uint32_t *__restrict__ sums) {
+    const int64_t base = (int64_t)blockIdx.x * kScanChunk;
+    uint32_t s = 0;
+    for (int q = 0; q < kScanItems; q++) {
+        const int64_t i = base + (int64_t)threadIdx.x * kScanItems + q;
+        if (i < m) s += a[i];
+    }
+    uint32_t total;
+    (void)block_exclusive_scan(s, &total);
+    if (threadIdx.x == 0) sums[blockIdx.x] = total;
+}
+
+// One block of kScanTopBlock threads: exclusive scan of the chunk sums.
+__global__ __launch_bounds__(kScanTopBlock) void k_scan_top(uint32_t *__restrict__ sums, int64_t nchunks) {
+    const int64_t per = (nchunks + kScanTopBlock - 1) / kScanTopBlock;
+    const int64_t lo = (int64_t)threadIdx.x * per;
+    uint32_t s = 0;
+    for (int64_t i = lo; i < lo + per && i < nchunks; i++) s += sums[i];
+    uint32_t total;
+    uint32_t run = block_exclusive_scan(s, &total);
+    for (int64_t i = lo; i < lo + per && i < nchunks; i++) {
+        const uint32_t v = sums[i];
+        sums[i] = run;
+        run += v;
+    }
+}
+
+__global__ __launch_bounds__(kSortBlock) void k_scan_down(uint32_t *__restrict__ a, int64_t m,
+                                                          const uint32_t *__restrict__ sums) {
+    const int64_t base = (int64_t)blockIdx.x * kScanChunk + (int64_t)threadIdx.x * kScanItems;
+    uint32_t v[kScanItems], s = 0;
+#pragma unroll
+    for (int q = 0; q < kScanItems; q++) {
+        v[q] = base + q < m ? a[base + q] : 0u;
+        s += v[q];
+    }
+    uint32_t total;
+    uint32_t run = sums[blockIdx.x] + block_exclusive_scan(s, &total);
+#pragma unroll
+    for (int q = 0; q < kScanItems; q++) {
+        if (base + q < m) a[base + q] = run;
+        run += v[q];
+    }
+}
+
+void launch_scan(uint32_t *a, int64_t m, uint32_t *sums, hipStream_t s) {
+    const int64_t nchunks = (m + kScanChunk - 1) / kScanChunk;
+    hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nchunks), dim3(kSortBlock), 0, s, a, m, sums);
+    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kScanTopBlock), 0, s, sums, nchunks);
+    hipLaunchKernelGGL(k_scan_down, dim3((unsigned)nchunks), dim3(kSortBlock), 0, s, a, m, sums);
+}
+
+// ---------------------------------------------------------------------------
+// Downsweep.  Out writes one element to its sorted position:
+//   PassOut: the key and value arrays of the next pass;
+//   GatherOut / GatherOut32: the particle record of slot `val` (and, when
+//   asked, the final keys and the permutation).
+
+struct PassOut {
+    uint32_t *keys, *vals;
+    __device__ __forceinline__ void operator()(int64_t dest, uint32_t key, uint32_t val) const {
+        keys[dest] = key;
+        vals[dest] = val;
+    }
+};
+
+struct GatherOut {
+    ParticlePtrs in, out;
+    uint32_t *keys, *vals;  // NULL: not kept
+    __device__ __forceinline__ void operator()(int64_t dest, uint32_t key, uint32_t val) const {
+        for (int q = 0; q < 3; q++) out.x[q][dest] = in.x[q][val];
+        for (int q = 0; q < 4; q++) out.u[q][dest] = in.u[q][val];
+        out.sp[dest] = in.sp[val];
+        if (keys) {
+            keys[dest] = key;
+            vals[dest] = val;
+        }
+    }
+};
+
+struct GatherOut32 {
+    ParticlePtrs32 in, out;
+    uint32_t *keys, *vals;
+    __device__ __forceinline__ void operator()(int64_t dest, uint32_t key, uint32_t val) const {
+        out.cell[dest] = in.cell[val];
+        for (int q = 0; q < 3; q++) out.off[q][dest] = in.off[q][val];
+        for (int q = 0; q < 4; q++) out.u[q][dest] = in.u[q][val];
+        out.sp[dest] = in.sp[val];
+        if (keys) {
+            keys[dest] = key;
+            vals[dest] = val;
+        }
+    }
+};
+
+// FIRST: the values are the slot indices (not read).  LAST: lower the live
+// count to the sorted position of the first removed particle.
+template <bool FIRST, bool LAST, class Out>
+__global__ __launch_bounds__(kSortBlock) void k_sort_downsweep(const uint32_t *__restrict__ keys_in,
+                                                                const uint32_t *__restrict__ vals_in, int64_t n,
+                                                                int shift, int bits, int64_t ntiles,
+                                                                const uint32_t *__restrict__ offsets, Out out,
+                                                                uint32_t sentinel, unsigned long long *counters) {
+    __shared__ uint32_t s_key[kSortTile];
+    __shared__ uint32_t s_val[kSortTile];
+    __shared__ uint32_t s_run[kSortMaxBins];    // elements of each digit in the rounds done
+    __shared__ uint32_t s_start[kSortMaxBins];  // where each digit starts in the staged tile
+    __shared__ uint32_t s_goff[kSortMaxBins];   // where the tile's digit starts in the output
+    __shared__ uint16_t s_wc[kSortWaves][kSortMaxBins];  // per-wave counts of the current round
+    const int R = 1 << bits, tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const uint32_t mask = (uint32_t)(R - 1);
+    const int64_t base = (int64_t)blockIdx.x * kSortTile;
+    const int tile_n = (int)(n - base < kSortTile ? n - base : kSortTile);
+    for (int d = tid; d < R; d += kSortBlock) {
+        s_run[d] = 0u;
+        s_goff[d] = offsets[(int64_t)d * ntiles + blockIdx.x];
+        for (int k = 0; k < kSortWaves; k++) s_wc[k][d] = 0;
+    }
+    __syncthreads();
+    uint32_t key[kSortItems], val[kSortItems], rank[kSortItems];
+    const unsigned long long below = (1ull << lane) - 1ull;
+    for (int q = 0; q < kSortItems; q++) {
+        const int l = q * kSortBlock + tid;
+        const bool valid = l < tile_n;
+        key[q] = valid ? keys_in[base + l] : 0u;
+        val[q] = valid ? (FIRST ? (uint32_t)(base + l) : vals_in[base + l]) : 0u;
+        const uint32_t d = (key[q] >> shift) & mask;
+        // lanes of this wave with the same digit
+        unsigned long long peers = __ballot(valid);
+        for (int b = 0; b < bits; b++) {
+            const bool on = (d >> b) & 1u;
+            const unsigned long long bal = __ballot(on);
+            peers &= on ? bal : ~bal;
+        }
+        const unsigned long long lower = peers & below;
+        if (valid && lower == 0ull) s_wc[w][d] = (uint16_t)__popcll(peers);
+        __syncthreads();
+        if (valid) {
+            uint32_t r = s_run[d] + (uint32_t)__popcll(lower);
+            for (int k = 0; k < w; k++) r += s_wc[k][d];
+            rank[q] = r;
+        }
+        __syncthreads();
+        for (int dd = tid; dd < R; dd += kSortBlock) {
+            uint32_t add = 0;
+            for (int k = 0; k < kSortWaves; k++) {
+                add += s_wc[k][dd];
+                s_wc[k][dd] = 0;
+            }
+            s_run[dd] += add;
+        }
+        __syncthreads();
+    }
+    // digit starts inside the staged tile: exclusive scan of the tile histogram
+    {
+        uint32_t c0 = 0, c1 = 0;
+        const int d0 = 2 * tid, d1 = 2 * tid + 1;
+        if (d0 < R) c0 = s_run[d0];
+        if (d1 < R) c1 = s_run[d1];
+        uint32_t total;
+        const uint32_t ex = block_exclusive_scan(c0 + c1, &total);
+        if (d0 < R) s_start[d0] = ex;
+        if (d1 < R) s_start[d1] = ex + c0;
+    }
+    __syncthreads();
+    for (int q = 0; q < kSortItems; q++) {
+        if (q * kSortBlock + tid < tile_n) {
+            const uint32_t d = (key[q] >> shift) & mask;
+            const uint32_t pos = s_start[d] + rank[q];
+            s_key[pos] = key[q];
+            s_val[pos] = val[q];
+        }
+    }
+    __syncthreads();
+    for (int l = tid; l < tile_n; l += kSortBlock) {
+        const uint32_t k = s_key[l];
+        const uint32_t d = (k >> shift) & mask;
+        const int64_t dest = (int64_t)s_goff[d] + (int64_t)(l - (int)s_start[d]);
+        out(dest, k, s_val[l]);
+        if (LAST && k == sentinel && (l == 0 || s_key[l - 1] != sentinel))
+            atomicMin(&counters[C_NALIVE], (unsigned long long)dest);
+    }
+}
+
+template <class Final>
+void run_passes(int64_t n, int key_bits, uint32_t *keys, uint32_t *keys_alt, uint32_t *idx, uint32_t *idx_alt,
+                void *temp, uint32_t sentinel, unsigned long long *counters, Final fin, bool keep,
+                uint32_t **final_keys, uint32_t **final_idx, hipStream_t s) {
+    const SortPlan P = sort_plan(key_bits);
+    const int64_t ntiles = sort_tiles(n);
+    uint32_t *counts = (uint32_t *)temp;
+    uint32_t *sums = counts + (int64_t)kSortMaxBins * ntiles;
+    uint32_t *kin = keys, *vin = nullptr, *kout = keys_alt, *vout = idx_alt;
+    for (int p = 0; p < P.passes; p++) {
+        const int R = 1 << P.bits[p];
+        hipLaunchKernelGGL(k_sort_upsweep, dim3((unsigned)ntiles), dim3(kSortBlock), 0, s, kin, n, P.shift[p],
+                           P.bits[p], ntiles, counts);
+        launch_scan(counts, (int64_t)R * ntiles, sums, s);
+        const bool first = p == 0, last = p == P.passes - 1;
+        if (last) {
+            fin.keys = keep ? kout : nullptr;
+            fin.vals = keep ? vout : nullptr;
+            if (first)
+                hipLaunchKernelGGL((k_sort_downsweep<true, true, Final>), dim3((unsigned)ntiles), dim3(kSortBlock), 0,
+                                   s, kin, vin, n, P.shift[p], P.bits[p], ntiles, counts, fin, sentinel, counters);
+            else
+                hipLaunchKernelGGL((k_sort_downsweep<false, true, Final>), dim3((unsigned)ntiles), dim3(kSortBlock), 0,
+                                   s, kin, vin, n, P.shift[p], P.bits[p], ntiles, counts, fin, sentinel, counters);
+            if (final_keys) *final_keys = keep ? kout : nullptr;
+            if (final_idx) *final_idx = keep ? vout : nullptr;
+        } else {
+            PassOut po{kout, vout};
+            if (first)
+                hipLaunchKernelGGL((k_sort_downsweep<true, false, PassOut>), dim3((unsigned)ntiles), dim3(kSortBlock),
+                                   0, s, kin, vin, n, P.shift[p], P.bits[p], ntiles, counts, po, sentinel, counters);
+            else
+                hipLaunchKernelGGL((k_sort_downsweep<false, false, PassOut>), dim3((unsigned)ntiles), dim3(kSortBlock),
+                                   0, s, kin, vin, n, P.shift[p], P.bits[p], ntiles, counts, po, sentinel, counters);
+            // the next pass reads what this one wrote and writes the pair this
+            // one read (pass 0 read keys, with implicit values: idx is free)
+            uint32_t *nk = kin, *nv = kin == keys ? idx : idx_alt;
+            kin = kout;
+            vin = vout;
+            kout = nk;
+            vout = nv;
+        }
+    }
+}
+
+void launch_sort(const Grid &G, int tile, int64_t n, ParticlePtrs in, ParticlePtrs out, uint32_t *keys,
+                 uint32_t *keys_alt, uint32_t *idx, uint32_t *idx_alt, void *temp, int key_bits, bool keep,
+                 uint32_t **final_keys, uint32_t **final_idx, unsigned long long *counters, hipStream_t s) {
+    if (n <= 0) return;
+    const int nTx = (G.nx + tile - 1) / tile, nTy = (G.ny + tile - 1) / tile;
+    const uint32_t sentinel = key_bits >= 32 ? 0xFFFFFFFFu : ((1u << key_bits) - 1u);
+    hipLaunchKernelGGL(k_sort_keys, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, G, tile, nTx, nTy, sentinel,
+                       in, n, keys, counters);
+    GatherOut fin{in, out, nullptr, nullptr};
+    run_passes(n, key_bits, keys, keys_alt, idx, idx_alt, temp, sentinel, counters, fin, keep, final_keys, final_idx,
+               s);
 }
 
 void launch_sort32(const Grid &G, int tile, int64_t n, ParticlePtrs32 in, ParticlePtrs32 out, uint32_t *keys,
-                   uint32_t *keys_alt, uint32_t *idx, uint32_t *idx_alt, void *temp, size_t temp_bytes,
-                   int key_bits, unsigned long long *counters, hipStream_t s) {
+                   uint32_t *keys_alt, uint32_t *idx, uint32_t *idx_alt, void *temp, int key_bits, bool keep,
+                   uint32_t **final_keys, uint32_t **final_idx, unsigned long long *counters, hipStream_t s) {
     if (n <= 0) return;
-    int nTx = (G.nx + tile - 1) / tile, nTy = (G.ny + tile - 1) / tile;
-    uint32_t sentinel = key_bits >= 32 ? 0xFFFFFFFFu : ((1u << key_bits) - 1u);
-    unsigned nb = (unsigned)((n + 255) / 256);
-    hipLaunchKernelGGL(k_sort_keys32, dim3(nb), dim3(256), 0, s, G, tile, nTx, nTy, sentinel, in, n, keys, idx);
-    size_t tb = temp_bytes;
-    hipcub::DeviceRadixSort::SortPairs(temp, tb, keys, keys_alt, idx, idx_alt, (int)n, 0, key_bits, s);
-    hipLaunchKernelGGL(k_sort_gather32, dim3(nb), dim3(256), 0, s, in, out, idx_alt, n);
-    hipLaunchKernelGGL(k_sort_count, dim3(nb), dim3(256), 0, s, keys_alt, n, sentinel, counters);
+    const int nTx = (G.nx + tile - 1) / tile, nTy = (G.ny + tile - 1) / tile;
+    const uint32_t sentinel = key_bits >= 32 ? 0xFFFFFFFFu : ((1u << key_bits) - 1u);
+    hipLaunchKernelGGL(k_sort_keys32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, G, tile, nTx, nTy,
+                       sentinel, in, n, keys, counters);
+    GatherOut32 fin{in, out, nullptr, nullptr};
+    run_passes(n, key_bits, keys, keys_alt, idx, idx_alt, temp, sentinel, counters, fin, keep, final_keys, final_idx,
+               s);
 }
 
 }  // namespace grpic
