@@ -268,7 +268,7 @@ def window_errors(w, windows, state1, n_per_species):
     return {"x_rel": ex_max, "u_rel": eu_max, "particles": count, "same_removals": same}
 
 
-def measure(workload, precision, steps, warmup, sort_every, parts, first_cycle_state=False):
+def measure(workload, precision, steps, warmup, sort_every, parts, first_cycle_state=False, tile=8):
     """Time `steps` cycles of one run; returns the figures of the timed
     region (and, with first_cycle_state, the particle state after the first
     warmup cycle, before any cell sort)."""
@@ -279,7 +279,7 @@ def measure(workload, precision, steps, warmup, sort_every, parts, first_cycle_s
     w = inputs.workload_params(workload)
     ntot = sum(p[1].shape[1] for p in parts)
     cfg = R.make_config(w["n"], m=w["m"], a=w["a"], dt=w["dt"], B0=(0.0, 0.0, w["B0"]), species=w["species"],
-                        r_rm=w["r_rm"], sort_every=sort_every, capacity=ntot,
+                        r_rm=w["r_rm"], sort_every=sort_every, capacity=ntot, tile=tile,
                         precision=capi.FP32_MIXED if precision == "fp32" else capi.FP64,
                         density=w["ppc"] if w["plasma"] != "torus" else None)
     run = R.Run(cfg)
@@ -684,13 +684,13 @@ def precision_study(workload, checkpoints=(1, 10, 100, 300, 1000), modes=("geode
     return out
 
 
-def describe(workload, w, ntot, sort_every):
+def describe(workload, w, ntot, sort_every, tile):
     plasma = {"uniform": "uniform Maxwellian", "shell": "uniform Maxwellian plus a shell |R - n/4| <= 2 at "
               "v_r = -0.3c", "torus": "torus"}[w["plasma"]]
     return ("%s: Kerr a=%.2fm, m=%g cells, %d^3 grid, %d particles (%d ppc x 2 species), %s u_th=%gc, B_z=%g, "
-            "dt=%g, curved deposit, paper gamma, sort every %d steps"
+            "dt=%g, curved deposit, paper gamma, sort every %d steps (tiles of %d^3 cells)"
             % (workload, w["a_frac"], w["m"], w["n"], ntot, w["ppc"], plasma, w["u_th"], w["B0"], w["dt"],
-               sort_every))
+               sort_every, tile))
 
 
 def main():
@@ -700,6 +700,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="shell256")
     ap.add_argument("--sort-every", type=int, default=5)
+    ap.add_argument("--tile", type=int, default=8, help="edge in cells of the sort's tiles")
     ap.add_argument("--secondary", default="kerr64",
                     help="second workload timed in both precisions ('' skips it)")
     ap.add_argument("--secondary-steps", type=int, default=100)
@@ -742,7 +743,7 @@ def main():
 
     errs = {}
     m64 = measure(args.workload, "fp64", args.steps, args.warmup, args.sort_every, parts,
-                  first_cycle_state=windows is not None)
+                  first_cycle_state=windows is not None, tile=args.tile)
     log("fp64 %s: %.4g particle-steps/s" % (args.workload, m64["value"]))
     if windows is not None and m64["state1"] is not None:
         errs["fp64"] = window_errors(w, windows, m64["state1"], nps)
@@ -763,7 +764,7 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {
-            "workload": describe(args.workload, w, ntot, args.sort_every),
+            "workload": describe(args.workload, w, ntot, args.sort_every, args.tile),
             "precision": "fp64",
             "live_particles_end": m64["live_end"],
         },
@@ -775,7 +776,7 @@ def main():
     }
     if not args.no_fp32:
         m32 = measure(args.workload, "fp32", args.steps, args.warmup, args.sort_every, parts,
-                      first_cycle_state=windows is not None)
+                      first_cycle_state=windows is not None, tile=args.tile)
         log("fp32-mixed %s: %.4g particle-steps/s" % (args.workload, m32["value"]))
         if windows is not None and m32["state1"] is not None:
             errs["fp32_mixed"] = window_errors(w, windows, m32["state1"], nps)
@@ -799,9 +800,11 @@ def main():
     if args.secondary:
         sparts = inputs.workload_particles(args.secondary, seed=0)
         sw = inputs.workload_params(args.secondary)
-        sec = {"workload": describe(args.secondary, sw, sum(p[1].shape[1] for p in sparts), args.sort_every)}
+        sec = {"workload": describe(args.secondary, sw, sum(p[1].shape[1] for p in sparts), args.sort_every,
+                                    args.tile)}
         for prec in ("fp64", "fp32"):
-            ms = measure(args.secondary, prec, args.secondary_steps, args.warmup, args.sort_every, sparts)
+            ms = measure(args.secondary, prec, args.secondary_steps, args.warmup, args.sort_every, sparts,
+                         tile=args.tile)
             log("%s %s: %.4g particle-steps/s" % (args.secondary, prec, ms["value"]))
             sec[prec] = {"value": ms["value"], "ms_per_step": ms["ms_per_step"], "steps": args.secondary_steps,
                          "kernel_ms_per_launch": ms["kernel_ms_per_launch"], "live_particles_end": ms["live_end"],

@@ -11,10 +11,10 @@
 //              tile), where the tile's elements of that digit start;
 //   downsweep: the tile re-reads its keys and ranks each element among the
 //              earlier elements of its digit (wave ballots give the rank
-//              inside a wave, a per-wave count table in LDS the rank across
-//              the block's waves, a running count across the tile's rounds),
-//              stages the tile in LDS in digit order and writes it out, so
-//              consecutive lanes write consecutive addresses.
+//              inside 64 slots, a wave-private count table in LDS the rank
+//              across the wave's rounds, a prefix over the waves the rank in
+//              the tile), stages the tile in LDS in digit order and writes it
+//              out, so consecutive lanes write consecutive addresses.
 // Ranks follow slot order within a tile and tiles follow slot order within a
 // digit, so every pass is stable, and the whole sort equals a stable sort on
 // the key.  The last pass moves the particle records themselves (the SoA
@@ -120,11 +120,15 @@ __global__ __launch_bounds__(kSortBlock) void k_sort_upsweep(const uint32_t *__r
     for (int d = threadIdx.x; d < R; d += kSortBlock) hist[d] = 0u;
     __syncthreads();
     const int64_t base = (int64_t)blockIdx.x * kSortTile;
-#pragma unroll 4
+    uint32_t k[kSortItems];
+#pragma unroll
     for (int q = 0; q < kSortItems; q++) {
         const int64_t i = base + q * kSortBlock + threadIdx.x;
-        if (i < n) atomicAdd(&hist[(keys[i] >> shift) & (uint32_t)(R - 1)], 1u);
+        k[q] = i < n ? keys[i] : 0u;
     }
+#pragma unroll
+    for (int q = 0; q < kSortItems; q++)
+        if (base + q * kSortBlock + threadIdx.x < n) atomicAdd(&hist[(k[q] >> shift) & (uint32_t)(R - 1)], 1u);
     __syncthreads();
     for (int d = threadIdx.x; d < R; d += kSortBlock) counts[(int64_t)d * ntiles + blockIdx.x] = hist[d];
 }
@@ -256,35 +260,46 @@ struct GatherOut32 {
 
 // FIRST: the values are the slot indices (not read).  LAST: lower the live
 // count to the sorted position of the first removed particle.
+//
+// Wave w ranks the tile's slots [w * kSortTile / 4, (w + 1) * kSortTile / 4)
+// in rounds of 64 consecutive slots against its own count table: the lanes
+// of one digit (wave ballots) read the table entry, and the lowest of them
+// adds their number.  LDS instructions of one wave complete in order, so no
+// barrier is needed inside the rounds; one barrier, then per digit a prefix
+// over the four waves and a scan over the digits place every element.
 template <bool FIRST, bool LAST, class Out>
 __global__ __launch_bounds__(kSortBlock) void k_sort_downsweep(const uint32_t *__restrict__ keys_in,
                                                                 const uint32_t *__restrict__ vals_in, int64_t n,
                                                                 int shift, int bits, int64_t ntiles,
                                                                 const uint32_t *__restrict__ offsets, Out out,
                                                                 uint32_t sentinel, unsigned long long *counters) {
+    constexpr int kWaveSpan = kSortTile / kSortWaves;  // slots ranked by one wave
     __shared__ uint32_t s_key[kSortTile];
     __shared__ uint32_t s_val[kSortTile];
-    __shared__ uint32_t s_run[kSortMaxBins];    // elements of each digit in the rounds done
     __shared__ uint32_t s_start[kSortMaxBins];  // where each digit starts in the staged tile
     __shared__ uint32_t s_goff[kSortMaxBins];   // where the tile's digit starts in the output
-    __shared__ uint16_t s_wc[kSortWaves][kSortMaxBins];  // per-wave counts of the current round
+    __shared__ uint16_t s_wc[kSortWaves][kSortMaxBins];  // per-wave counts, then per-wave prefixes
     const int R = 1 << bits, tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const uint32_t mask = (uint32_t)(R - 1);
     const int64_t base = (int64_t)blockIdx.x * kSortTile;
     const int tile_n = (int)(n - base < kSortTile ? n - base : kSortTile);
     for (int d = tid; d < R; d += kSortBlock) {
-        s_run[d] = 0u;
         s_goff[d] = offsets[(int64_t)d * ntiles + blockIdx.x];
         for (int k = 0; k < kSortWaves; k++) s_wc[k][d] = 0;
     }
-    __syncthreads();
     uint32_t key[kSortItems], val[kSortItems], rank[kSortItems];
-    const unsigned long long below = (1ull << lane) - 1ull;
+#pragma unroll
     for (int q = 0; q < kSortItems; q++) {
-        const int l = q * kSortBlock + tid;
+        const int l = w * kWaveSpan + q * 64 + lane;
         const bool valid = l < tile_n;
         key[q] = valid ? keys_in[base + l] : 0u;
         val[q] = valid ? (FIRST ? (uint32_t)(base + l) : vals_in[base + l]) : 0u;
+    }
+    __syncthreads();
+    const unsigned long long below = (1ull << lane) - 1ull;
+#pragma unroll
+    for (int q = 0; q < kSortItems; q++) {
+        const bool valid = w * kWaveSpan + q * 64 + lane < tile_n;
         const uint32_t d = (key[q] >> shift) & mask;
         // lanes of this wave with the same digit
         unsigned long long peers = __ballot(valid);
@@ -294,40 +309,38 @@ __global__ __launch_bounds__(kSortBlock) void k_sort_downsweep(const uint32_t *_
             peers &= on ? bal : ~bal;
         }
         const unsigned long long lower = peers & below;
-        if (valid && lower == 0ull) s_wc[w][d] = (uint16_t)__popcll(peers);
-        __syncthreads();
-        if (valid) {
-            uint32_t r = s_run[d] + (uint32_t)__popcll(lower);
-            for (int k = 0; k < w; k++) r += s_wc[k][d];
-            rank[q] = r;
-        }
-        __syncthreads();
-        for (int dd = tid; dd < R; dd += kSortBlock) {
-            uint32_t add = 0;
-            for (int k = 0; k < kSortWaves; k++) {
-                add += s_wc[k][dd];
-                s_wc[k][dd] = 0;
-            }
-            s_run[dd] += add;
-        }
-        __syncthreads();
-    }
-    // digit starts inside the staged tile: exclusive scan of the tile histogram
-    {
-        uint32_t c0 = 0, c1 = 0;
-        const int d0 = 2 * tid, d1 = 2 * tid + 1;
-        if (d0 < R) c0 = s_run[d0];
-        if (d1 < R) c1 = s_run[d1];
-        uint32_t total;
-        const uint32_t ex = block_exclusive_scan(c0 + c1, &total);
-        if (d0 < R) s_start[d0] = ex;
-        if (d1 < R) s_start[d1] = ex + c0;
+        const uint32_t before = valid ? (uint32_t)s_wc[w][d] : 0u;
+        rank[q] = before + (uint32_t)__popcll(lower);
+        if (valid && lower == 0ull) s_wc[w][d] = (uint16_t)(before + (uint32_t)__popcll(peers));
     }
     __syncthreads();
+    // per digit: the waves' prefixes and the tile's count; then the digits'
+    // starts in the staged tile (exclusive scan over the digits)
+    {
+        uint32_t c[2] = {0u, 0u};
+        for (int h = 0; h < 2; h++) {
+            const int d = 2 * tid + h;
+            if (d < R) {
+                uint32_t run = 0;
+                for (int k = 0; k < kSortWaves; k++) {
+                    const uint32_t v = s_wc[k][d];
+                    s_wc[k][d] = (uint16_t)run;
+                    run += v;
+                }
+                c[h] = run;
+            }
+        }
+        uint32_t total;
+        const uint32_t ex = block_exclusive_scan(c[0] + c[1], &total);
+        if (2 * tid < R) s_start[2 * tid] = ex;
+        if (2 * tid + 1 < R) s_start[2 * tid + 1] = ex + c[0];
+    }
+    __syncthreads();
+#pragma unroll
     for (int q = 0; q < kSortItems; q++) {
-        if (q * kSortBlock + tid < tile_n) {
+        if (w * kWaveSpan + q * 64 + lane < tile_n) {
             const uint32_t d = (key[q] >> shift) & mask;
-            const uint32_t pos = s_start[d] + rank[q];
+            const uint32_t pos = s_start[d] + s_wc[w][d] + rank[q];
             s_key[pos] = key[q];
             s_val[pos] = val[q];
         }
