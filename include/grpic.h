@@ -255,7 +255,14 @@ int grpic_dump_nodes(grpic_t *h, double *out);
  * node tensor from the current fields first. */
 int grpic_push_only(grpic_t *h, int32_t nsteps);
 
-/* Stable tile-major cell sort now: keys (tile T) then particle order.
+/* Stable cell sort now, by key then particle order.  The key of a live
+ * particle in cell (i,j,k) is rank * T^3 + (lz T + ly) T + lx with T =
+ * cfg->tile, (lx, ly, lz) its cell inside the tile and rank the tile's place
+ * on a path through all tiles on which consecutive tiles share a face (the
+ * planes of tiles in z order; rows of tiles in y order in even planes and
+ * reversed in odd ones; tiles in x order in even rows and reversed in odd
+ * ones, counting rows across the planes).  The paper has no sort; it keeps
+ * the particles of a block of threads in a few neighbouring cells.
  * If keys_out is not NULL it receives the sorted keys of all slots
  * (dead particles: 0xFFFFFFFF), and perm_out the original slot index of each
  * sorted position.  Dead particles are compacted away afterwards. */

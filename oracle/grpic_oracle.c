@@ -1575,9 +1575,14 @@ void or_sim_step(or_sim *s, int nsteps)
     }
 }
 
-/* Tile-major cell key (reading: the paper has no sort; tile edge T):
- * key = ((tz*nTy + ty)*nTx + tx)*T^3 + (lz*T + ly)*T + lx with (i,j,k) =
- * floor(X); dead particles get 0xFFFFFFFF. */
+/* Cell key (reading: the paper has no sort; tile edge T).  Tiles of T^3
+ * cells are ranked along a boustrophedon path, so consecutive tiles share a
+ * face: the planes tz in order; within plane tz the rows ty ascend when tz is
+ * even and descend when it is odd; along the r-th row visited (r = tz nTy +
+ * the row's place in its plane) the tiles tx ascend when r is even and
+ * descend when it is odd.  Inside a tile the cells go x fastest, then y, then
+ * z:  key = rank * T^3 + (lz*T + ly)*T + lx with (i,j,k) = floor(X); dead
+ * particles get 0xFFFFFFFF. */
 void or_sort_keys(const or_params *p, int tile, int64_t n, const double *x, const uint8_t *sp,
                   uint32_t *keys)
 {
@@ -1590,9 +1595,13 @@ void or_sort_keys(const or_params *p, int tile, int64_t n, const double *x, cons
         }
         int c[3];
         for (int ax = 0; ax < 3; ax++) c[ax] = (int)floor(x[ax * n + i]);
-        uint32_t tx = c[0] / T, ty = c[1] / T, tz = c[2] / T;
-        uint32_t lx = c[0] % T, ly = c[1] % T, lz = c[2] % T;
-        keys[i] = ((tz * nTy + ty) * nTx + tx) * (uint32_t)(T * T * T) + (lz * T + ly) * T + lx;
+        int tx = c[0] / T, ty = c[1] / T, tz = c[2] / T;
+        int lx = c[0] % T, ly = c[1] % T, lz = c[2] % T;
+        int row_in_plane = (tz % 2 == 0) ? ty : nTy - 1 - ty;
+        int row = tz * nTy + row_in_plane;
+        int along = (row % 2 == 0) ? tx : nTx - 1 - tx;
+        uint32_t rank = (uint32_t)row * (uint32_t)nTx + (uint32_t)along;
+        keys[i] = rank * (uint32_t)(T * T * T) + (uint32_t)((lz * T + ly) * T + lx);
     }
 }
 

@@ -542,7 +542,7 @@ constexpr int kDepPPT = 4;      // particles per thread
 __device__ __forceinline__ int dep_slot(int p, int tid) {
     return (tid & 63) * (kDepPPT * (kDepBlock / 64)) + p * (kDepBlock / 64) + (tid >> 6);
 }
-constexpr int kDepLds = 6144;   // int64 LDS entries of the current tile (48 KiB: three blocks per CU)
+constexpr int kDepLds = 6656;  // int64 LDS entries of the current box (52 KiB: three blocks per CU)
 
 // Zigzag split of one chord: relay point and the two cells; false when the
 // move is longer than a cell or leaves the ghost layer.

@@ -482,7 +482,7 @@ constexpr int kDep32PPT = 4;
 __device__ __forceinline__ int dep32_slot(int p, int tid) {
     return (tid & 63) * (kDep32PPT * (kDep32Block / 64)) + p * (kDep32Block / 64) + (tid >> 6);
 }
-constexpr int kDep32Lds = 6144;
+constexpr int kDep32Lds = 6656;  // int64 LDS entries of the current box (52 KiB: three blocks per CU)
 
 // Block `blk` of the deposit (particles blk * kDep32Block * kDep32PPT ...);
 // LDS scratch sm and sred come from the calling kernel.  Every thread of the

@@ -1,7 +1,8 @@
-// Stable tile-major cell sort of the particle slots and compaction of the
-// removed ones.  Key = ((tz nTy + ty) nTx + tx) T^3 + (lz T + ly) T + lx with
-// (i,j,k) = floor(x) (FP64) or the packed cell (FP32-mixed); removed
-// particles take the all-ones key of key_bits bits and so sort to the end.
+// Stable cell sort of the particle slots and compaction of the removed ones.
+// Key = rank(tile) T^3 + (lz T + ly) T + lx with (i,j,k) = floor(x) (FP64) or
+// the packed cell (FP32-mixed), tiles of T^3 cells ranked along a path of
+// face-adjacent tiles (tile_key); removed particles take the all-ones key of
+// key_bits bits and so sort to the end.
 //
 // The ordering is a least-significant-digit radix sort over digits of at most
 // 9 bits (ceil(key_bits / 9) passes, 3 at 256^3).  Each pass is
@@ -17,9 +18,9 @@
 //              out, so consecutive lanes write consecutive addresses.
 // Ranks follow slot order within a tile and tiles follow slot order within a
 // digit, so every pass is stable, and the whole sort equals a stable sort on
-// the key.  The last pass moves the particle records themselves (the SoA
-// gather) instead of writing an index array.  No pass waits on another
-// block, and every loop is bounded by the tile.
+// the key.  A last kernel moves the particle records (the SoA gather) in
+// output order.  No pass waits on another block, and every loop is bounded
+// by the tile.
 #include "grpic_dev.h"
 #include "grpic_impl.h"
 
@@ -68,10 +69,16 @@ size_t sort_temp_bytes(int64_t capacity) {
 // Keys.  The first block also resets the live count, which the last pass
 // lowers to the position of the first removed particle.
 
+// Tiles ranked along a boustrophedon path (planes tz in order, rows ty
+// reversed in odd planes, tiles tx reversed in odd rows), so consecutive
+// tiles share a face and a block of consecutive sorted particles that spans
+// two tiles stays compact; cells x fastest, then y, then z inside a tile.
 __device__ __forceinline__ uint32_t tile_key(int T, int nTx, int nTy, const int c[3]) {
-    const uint32_t tx = c[0] / T, ty = c[1] / T, tz = c[2] / T;
-    const uint32_t lx = c[0] % T, ly = c[1] % T, lz = c[2] % T;
-    return ((tz * nTy + ty) * nTx + tx) * (uint32_t)(T * T * T) + (lz * T + ly) * T + lx;
+    const int tx = c[0] / T, ty = c[1] / T, tz = c[2] / T;
+    const int lx = c[0] % T, ly = c[1] % T, lz = c[2] % T;
+    const int row = tz * nTy + ((tz & 1) ? nTy - 1 - ty : ty);
+    const int along = (row & 1) ? nTx - 1 - tx : tx;
+    return ((uint32_t)row * (uint32_t)nTx + (uint32_t)along) * (uint32_t)(T * T * T) + (uint32_t)((lz * T + ly) * T + lx);
 }
 
 __global__ void k_sort_keys(Grid G, int T, int nTx, int nTy, uint32_t sentinel, ParticlePtrs in, int64_t n,
@@ -216,10 +223,8 @@ void launch_scan(uint32_t *a, int64_t m, uint32_t *sums, hipStream_t s) {
 }
 
 // ---------------------------------------------------------------------------
-// Downsweep.  Out writes one element to its sorted position:
-//   PassOut: the key and value arrays of the next pass;
-//   GatherOut / GatherOut32: the particle record of slot `val` (and, when
-//   asked, the final keys and the permutation).
+// Downsweep.  Out writes one element to its sorted position (PassOut: the
+// key and value arrays of the next pass).
 
 struct PassOut {
     uint32_t *keys, *vals;
@@ -229,34 +234,27 @@ struct PassOut {
     }
 };
 
-struct GatherOut {
-    ParticlePtrs in, out;
-    uint32_t *keys, *vals;  // NULL: not kept
-    __device__ __forceinline__ void operator()(int64_t dest, uint32_t key, uint32_t val) const {
-        for (int q = 0; q < 3; q++) out.x[q][dest] = in.x[q][val];
-        for (int q = 0; q < 4; q++) out.u[q][dest] = in.u[q][val];
-        out.sp[dest] = in.sp[val];
-        if (keys) {
-            keys[dest] = key;
-            vals[dest] = val;
-        }
-    }
-};
+// The particle records in sorted order: out[i] = in[idx[i]].  Reads follow
+// the output order, which for particles sorted a few steps earlier is close
+// to the input order, so they stay nearly coalesced.
+__global__ void k_sort_gather(ParticlePtrs in, ParticlePtrs out, const uint32_t *__restrict__ idx, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const uint32_t s = idx[i];
+    for (int q = 0; q < 3; q++) out.x[q][i] = in.x[q][s];
+    for (int q = 0; q < 4; q++) out.u[q][i] = in.u[q][s];
+    out.sp[i] = in.sp[s];
+}
 
-struct GatherOut32 {
-    ParticlePtrs32 in, out;
-    uint32_t *keys, *vals;
-    __device__ __forceinline__ void operator()(int64_t dest, uint32_t key, uint32_t val) const {
-        out.cell[dest] = in.cell[val];
-        for (int q = 0; q < 3; q++) out.off[q][dest] = in.off[q][val];
-        for (int q = 0; q < 4; q++) out.u[q][dest] = in.u[q][val];
-        out.sp[dest] = in.sp[val];
-        if (keys) {
-            keys[dest] = key;
-            vals[dest] = val;
-        }
-    }
-};
+__global__ void k_sort_gather32(ParticlePtrs32 in, ParticlePtrs32 out, const uint32_t *__restrict__ idx, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const uint32_t s = idx[i];
+    out.cell[i] = in.cell[s];
+    for (int q = 0; q < 3; q++) out.off[q][i] = in.off[q][s];
+    for (int q = 0; q < 4; q++) out.u[q][i] = in.u[q][s];
+    out.sp[i] = in.sp[s];
+}
 
 // FIRST: the values are the slot indices (not read).  LAST: lower the live
 // count to the sorted position of the first removed particle.
@@ -356,10 +354,11 @@ __global__ __launch_bounds__(kSortBlock) void k_sort_downsweep(const uint32_t *_
     }
 }
 
-template <class Final>
+// The passes over the keys; returns where the sorted keys and the original
+// slot of each sorted position are.
 void run_passes(int64_t n, int key_bits, uint32_t *keys, uint32_t *keys_alt, uint32_t *idx, uint32_t *idx_alt,
-                void *temp, uint32_t sentinel, unsigned long long *counters, Final fin, bool keep,
-                uint32_t **final_keys, uint32_t **final_idx, hipStream_t s) {
+                void *temp, uint32_t sentinel, unsigned long long *counters, uint32_t **final_keys,
+                uint32_t **final_idx, hipStream_t s) {
     const SortPlan P = sort_plan(key_bits);
     const int64_t ntiles = sort_tiles(n);
     uint32_t *counts = (uint32_t *)temp;
@@ -371,34 +370,29 @@ void run_passes(int64_t n, int key_bits, uint32_t *keys, uint32_t *keys_alt, uin
                            P.bits[p], ntiles, counts);
         launch_scan(counts, (int64_t)R * ntiles, sums, s);
         const bool first = p == 0, last = p == P.passes - 1;
-        if (last) {
-            fin.keys = keep ? kout : nullptr;
-            fin.vals = keep ? vout : nullptr;
-            if (first)
-                hipLaunchKernelGGL((k_sort_downsweep<true, true, Final>), dim3((unsigned)ntiles), dim3(kSortBlock), 0,
-                                   s, kin, vin, n, P.shift[p], P.bits[p], ntiles, counts, fin, sentinel, counters);
-            else
-                hipLaunchKernelGGL((k_sort_downsweep<false, true, Final>), dim3((unsigned)ntiles), dim3(kSortBlock), 0,
-                                   s, kin, vin, n, P.shift[p], P.bits[p], ntiles, counts, fin, sentinel, counters);
-            if (final_keys) *final_keys = keep ? kout : nullptr;
-            if (final_idx) *final_idx = keep ? vout : nullptr;
-        } else {
-            PassOut po{kout, vout};
-            if (first)
-                hipLaunchKernelGGL((k_sort_downsweep<true, false, PassOut>), dim3((unsigned)ntiles), dim3(kSortBlock),
-                                   0, s, kin, vin, n, P.shift[p], P.bits[p], ntiles, counts, po, sentinel, counters);
-            else
-                hipLaunchKernelGGL((k_sort_downsweep<false, false, PassOut>), dim3((unsigned)ntiles), dim3(kSortBlock),
-                                   0, s, kin, vin, n, P.shift[p], P.bits[p], ntiles, counts, po, sentinel, counters);
-            // the next pass reads what this one wrote and writes the pair this
-            // one read (pass 0 read keys, with implicit values: idx is free)
-            uint32_t *nk = kin, *nv = kin == keys ? idx : idx_alt;
-            kin = kout;
-            vin = vout;
-            kout = nk;
-            vout = nv;
-        }
+        PassOut po{kout, vout};
+        if (first && last)
+            hipLaunchKernelGGL((k_sort_downsweep<true, true, PassOut>), dim3((unsigned)ntiles), dim3(kSortBlock), 0, s,
+                               kin, vin, n, P.shift[p], P.bits[p], ntiles, counts, po, sentinel, counters);
+        else if (first)
+            hipLaunchKernelGGL((k_sort_downsweep<true, false, PassOut>), dim3((unsigned)ntiles), dim3(kSortBlock), 0,
+                               s, kin, vin, n, P.shift[p], P.bits[p], ntiles, counts, po, sentinel, counters);
+        else if (last)
+            hipLaunchKernelGGL((k_sort_downsweep<false, true, PassOut>), dim3((unsigned)ntiles), dim3(kSortBlock), 0,
+                               s, kin, vin, n, P.shift[p], P.bits[p], ntiles, counts, po, sentinel, counters);
+        else
+            hipLaunchKernelGGL((k_sort_downsweep<false, false, PassOut>), dim3((unsigned)ntiles), dim3(kSortBlock), 0,
+                               s, kin, vin, n, P.shift[p], P.bits[p], ntiles, counts, po, sentinel, counters);
+        // the next pass reads what this one wrote and writes the pair this
+        // one read (pass 0 read keys, with implicit values: idx is free)
+        uint32_t *nk = kin, *nv = kin == keys ? idx : idx_alt;
+        kin = kout;
+        vin = vout;
+        kout = nk;
+        vout = nv;
     }
+    *final_keys = kin;
+    *final_idx = vin;
 }
 
 void launch_sort(const Grid &G, int tile, int64_t n, ParticlePtrs in, ParticlePtrs out, uint32_t *keys,
@@ -409,9 +403,11 @@ void launch_sort(const Grid &G, int tile, int64_t n, ParticlePtrs in, ParticlePt
     const uint32_t sentinel = key_bits >= 32 ? 0xFFFFFFFFu : ((1u << key_bits) - 1u);
     hipLaunchKernelGGL(k_sort_keys, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, G, tile, nTx, nTy, sentinel,
                        in, n, keys, counters);
-    GatherOut fin{in, out, nullptr, nullptr};
-    run_passes(n, key_bits, keys, keys_alt, idx, idx_alt, temp, sentinel, counters, fin, keep, final_keys, final_idx,
-               s);
+    uint32_t *fk, *fi;
+    run_passes(n, key_bits, keys, keys_alt, idx, idx_alt, temp, sentinel, counters, &fk, &fi, s);
+    hipLaunchKernelGGL(k_sort_gather, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, in, out, fi, n);
+    if (final_keys) *final_keys = keep ? fk : nullptr;
+    if (final_idx) *final_idx = keep ? fi : nullptr;
 }
 
 void launch_sort32(const Grid &G, int tile, int64_t n, ParticlePtrs32 in, ParticlePtrs32 out, uint32_t *keys,
@@ -422,9 +418,11 @@ void launch_sort32(const Grid &G, int tile, int64_t n, ParticlePtrs32 in, Partic
     const uint32_t sentinel = key_bits >= 32 ? 0xFFFFFFFFu : ((1u << key_bits) - 1u);
     hipLaunchKernelGGL(k_sort_keys32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, G, tile, nTx, nTy,
                        sentinel, in, n, keys, counters);
-    GatherOut32 fin{in, out, nullptr, nullptr};
-    run_passes(n, key_bits, keys, keys_alt, idx, idx_alt, temp, sentinel, counters, fin, keep, final_keys, final_idx,
-               s);
+    uint32_t *fk, *fi;
+    run_passes(n, key_bits, keys, keys_alt, idx, idx_alt, temp, sentinel, counters, &fk, &fi, s);
+    hipLaunchKernelGGL(k_sort_gather32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, in, out, fi, n);
+    if (final_keys) *final_keys = keep ? fk : nullptr;
+    if (final_idx) *final_idx = keep ? fi : nullptr;
 }
 
 }  // namespace grpic

@@ -6,7 +6,8 @@
   obeys the exact leapfrog recurrence with the Yee dispersion relation;
 - Wald's uniform-field solution of Schwarzschild stays bounded (no growth);
 - the whole cycle keeps Gauss's law in flat-deposit mode;
-- the stable sort equals numpy's stable argsort on the same keys.
+- the stable sort equals numpy's stable argsort on the same keys, and its
+  tiles follow a path of face-adjacent tiles.
 """
 import numpy as np
 import pytest
@@ -207,8 +208,8 @@ def test_neutral_particles_conserve_energy_and_lz_in_cycle():
     assert 10.0 < dL1 / dL2 < 25.0
 
 
-def test_sort_is_stable_and_tile_major():
-    N, T = 16, 8
+@pytest.mark.parametrize("N,T", [(16, 8), (24, 4), (20, 8)])
+def test_sort_is_stable_and_tiles_follow_a_face_adjacent_path(N, T):
     p = O.make_params(N, m=0.0)
     rng = np.random.default_rng(15)
     n = 5000
@@ -227,8 +228,21 @@ def test_sort_is_stable_and_tile_major():
     k_alive = keys[alive]
     pairs = set(zip(lin.tolist(), k_alive.tolist()))
     assert len(pairs) == len(set(lin.tolist())) == len(set(k_alive.tolist()))
-    tiles = (cells[2] // T * (N // T) + cells[1] // T) * (N // T) + cells[0] // T
-    assert np.all(k_alive // T ** 3 == tiles)
+    # each tile is one contiguous block of T^3 keys (cells x fastest, then y,
+    # then z inside it), the blocks are a bijection onto the tiles, and
+    # consecutive blocks are tiles that share a face
+    local = ((cells[2] % T) * T + cells[1] % T) * T + cells[0] % T
+    assert np.all(k_alive % T ** 3 == local)
+    nT = (N + T - 1) // T
+    tile_of_rank = {}
+    for rank, tc in zip((k_alive // T ** 3).tolist(), map(tuple, (cells // T).T.tolist())):
+        assert tile_of_rank.setdefault(rank, tc) == tc
+    # every tile is hit by the random positions at these sizes
+    assert sorted(tile_of_rank) == list(range(nT ** 3))
+    assert len(set(tile_of_rank.values())) == nT ** 3
+    for r in range(nT ** 3 - 1):
+        d = np.abs(np.array(tile_of_rank[r + 1]) - np.array(tile_of_rank[r]))
+        assert d.sum() == 1, (r, tile_of_rank[r], tile_of_rank[r + 1])
 
 
 # --- outer absorbing layer (a reading: the paper states no outer boundary) --
