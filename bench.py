@@ -268,7 +268,7 @@ def window_errors(w, windows, state1, n_per_species):
     return {"x_rel": ex_max, "u_rel": eu_max, "particles": count, "same_removals": same}
 
 
-def measure(workload, precision, steps, warmup, sort_every, parts, first_cycle_state=False, tile=8):
+def measure(workload, precision, steps, warmup, sort_every, parts, first_cycle_state=False, tile=4):
     """Time `steps` cycles of one run; returns the figures of the timed
     region (and, with first_cycle_state, the particle state after the first
     warmup cycle, before any cell sort)."""
@@ -700,7 +700,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="shell256")
     ap.add_argument("--sort-every", type=int, default=5)
-    ap.add_argument("--tile", type=int, default=8, help="edge in cells of the sort's tiles")
+    ap.add_argument("--tile", type=int, default=4, help="edge in cells of the sort's tiles")
     ap.add_argument("--secondary", default="kerr64",
                     help="second workload timed in both precisions ('' skips it)")
     ap.add_argument("--secondary-steps", type=int, default=100)

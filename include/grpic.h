@@ -75,7 +75,7 @@ typedef struct {
     int32_t deposit_mode;   /* GRPIC_DEPOSIT_*                                      */
     int32_t field_iters;    /* constitutive passes per half-cycle, >= 1 (3)         */
     int32_t sort_every;     /* steps between cell sorts; 0 = never                 */
-    int32_t tile;           /* sort tile edge in cells (8)                         */
+    int32_t tile;           /* sort tile edge in cells (4)                         */
     int32_t fp_bits;        /* fraction bits of the int64 current accumulator, 16..50 (44) */
     int32_t nspecies;       /* 1..GRPIC_MAX_SPECIES                                 */
     int32_t init_covariant; /* 0: uniform contravariant B0 (paper); 1: covariant    */
@@ -127,7 +127,7 @@ typedef struct grpic_s grpic_t;
 
 /* Fill *cfg with the defaults for an nx x ny x nz grid: c = 1, dt = 0.5,
  * m = a = 0, centre at the grid centre, r_rm = 1.1 r_+, r_exc = 0.5 r_+,
- * r_damp = r_+, damp_max = 0.1, field_iters = 3, sort_every = 10, tile = 8,
+ * r_damp = r_+, damp_max = 0.1, field_iters = 3, sort_every = 10, tile = 4,
  * fp_bits = 44, FP64, PAPER gamma, CURVED deposit, CLASSIC RK, STAGE gather,
  * TRILINEAR weights, one species (-1, 1). */
 void grpic_config_default(grpic_config *cfg, int32_t nx, int32_t ny, int32_t nz);

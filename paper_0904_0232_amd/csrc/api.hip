@@ -888,7 +888,7 @@ void grpic_config_default(grpic_config *cfg, int32_t nx, int32_t ny, int32_t nz)
     cfg->deposit_mode = GRPIC_DEPOSIT_CURVED;
     cfg->field_iters = 3;
     cfg->sort_every = 10;
-    cfg->tile = 8;
+    cfg->tile = 4;
     cfg->fp_bits = 44;
     cfg->nspecies = 1;
     cfg->c = 1.0;

@@ -7,7 +7,7 @@ from . import capi
 
 def make_config(n, *, m, a, dt, B0=(0.0, 0.0, 0.0), species=((-1.0, 1.0),), c=1.0, r_rm=None,
                 r_exc=None, r_damp=None, damp_max=0.1, gamma_mode=capi.GAMMA_PAPER,
-                deposit_mode=capi.DEPOSIT_CURVED, field_iters=3, sort_every=0, tile=8, fp_bits=44,
+                deposit_mode=capi.DEPOSIT_CURVED, field_iters=3, sort_every=0, tile=4, fp_bits=44,
                 capacity=0, precision=capi.FP64, init_covariant=False, ny=None, nz=None, center=None,
                 rk_mode=capi.RK_CLASSIC, gather_mode=capi.GATHER_STAGE,
                 gather_weights=capi.WEIGHTS_TRILINEAR, outer_layer=0.0, outer_damp=0.0, density=None):

@@ -26,12 +26,12 @@ def oracle_sim(P, ncap):
     return p, s
 
 
-def gpu_run(P, capacity, sort_every=0, fp_bits=44):
+def gpu_run(P, capacity, sort_every=0, fp_bits=44, tile=4):
     from paper_0904_0232_amd import run as R
     cfg = R.make_config(P["n"], m=P["m"], a=P["a"], dt=P["dt"], c=P.get("c", 1.0), B0=P["B0"], species=P["species"],
                         r_rm=P["r_rm"], gamma_mode=P["gamma_mode"], deposit_mode=P["deposit_mode"],
                         field_iters=P["field_iters"], damp_max=P["damp_max"], sort_every=sort_every,
-                        capacity=capacity, fp_bits=fp_bits, init_covariant=P["init_covariant"],
+                        capacity=capacity, fp_bits=fp_bits, init_covariant=P["init_covariant"], tile=tile,
                         rk_mode=P.get("rk_mode", 0), gather_mode=P.get("gather_mode", 0),
                       gather_weights=P.get("gather_weights", 0), outer_layer=P.get("outer_layer", 0.0),
                       outer_damp=P.get("outer_damp", 0.0))

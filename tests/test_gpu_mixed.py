@@ -124,7 +124,7 @@ def test_mixed_sort_keys_bit_exact():
     x, u, sp = r.particles()
     keys, perm = r.sort()
     p = O.make_params(32, m=P["m"], a=P["a"])
-    ko = O.sort_keys(p, 8, x, sp)
+    ko = O.sort_keys(p, r.cfg.tile, x, sp)
     po = O.stable_order(ko)
     assert np.array_equal(keys, ko[po])
     assert np.array_equal(perm, po)

@@ -232,18 +232,23 @@ def test_kerr64_full_size_sampled_push():
         assert abs(J[K].sum() - ref) <= 1e-12 * np.abs(J[K]).sum() + floor, K
 
 
-def test_sort_bit_exact():
-    N = 16
+@pytest.mark.parametrize("N,tile,n", [(16, 8, 3000), (16, 4, 3000), (20, 8, 70000), (36, 4, 150000),
+                                        (64, 4, 200000), (64, 8, 200000)])
+def test_sort_bit_exact(N, tile, n):
+    # one to 98 sort tiles of 4096 slots, a ragged last tile, grids that are
+    # not a multiple of the cell tile, particles removed near the hole; keys
+    # of 14 to 19 bits (two and three radix passes)
     P = params(N, m=1.5, a=0.9, dt=0.5, species=((-0.02, 0.02), (0.02, 0.4)))
-    parts = _small_parts(9, 3000, N)
-    r = gpu_run(P, 8000, fp_bits=FPB)
+    parts = _small_parts(9, n, N)
+    r = gpu_run(P, 2 * n, fp_bits=FPB, tile=tile)
     for sp, x, uc in parts:
         r.load(sp, x, uc)
     r.step(3)
     x, u, sp = r.particles()
+    say("case sort N=%d tile=%d: %d slots, %d removed" % (N, tile, sp.size, int((sp == O.DEAD).sum())))
     keys, perm = r.sort()
     p = O.make_params(N, m=1.5, a=0.9)
-    ko = O.sort_keys(p, 8, x, sp)
+    ko = O.sort_keys(p, tile, x, sp)
     po = O.stable_order(ko)
     assert np.array_equal(keys, ko[po])
     assert np.array_equal(perm, po)
