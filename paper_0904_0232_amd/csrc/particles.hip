@@ -35,11 +35,12 @@ struct NodeBox {
 
 // L^a += sum over the 8 nodes of W_n (F_n u)^a, nodes addressed from the
 // (0,0,0) node `p` with strides (in double2) si, sj, sk; the contraction with
-// u is taken node by node, so only four accumulators stay live; two (j, k)
-// pairs per loop pass give the scheduler more loads to overlap.
+// u is taken node by node, so only four accumulators stay live.  A node's 16
+// components are read before any is used, so its eight 16-byte reads are in
+// flight together instead of two at a time.
 __device__ __forceinline__ void gather_rows(const double2 *p, int64_t si, int64_t sj, int64_t sk, const double w[3],
                                             const double U[4], double L[4]) {
-#pragma unroll 2
+#pragma unroll 1
     for (int q = 0; q < 4; q++) {
         const int dj = q & 1, dk = q >> 1;
         const double wyz = (dj ? w[1] : 1.0 - w[1]) * (dk ? w[2] : 1.0 - w[2]);
@@ -48,10 +49,12 @@ __device__ __forceinline__ void gather_rows(const double2 *p, int64_t si, int64_
         for (int di = 0; di < 2; di++) {
             const double W = (di ? w[0] : 1.0 - w[0]) * wyz;
             const double2 *pn = pq + di * si;
+            double2 f[8];
+#pragma unroll
+            for (int e = 0; e < 8; e++) f[e] = pn[e];
 #pragma unroll
             for (int a = 0; a < 4; a++) {
-                double2 f01 = pn[2 * a], f23 = pn[2 * a + 1];
-                double row = f01.x * U[0] + f01.y * U[1] + f23.x * U[2] + f23.y * U[3];
+                const double row = f[2 * a].x * U[0] + f[2 * a].y * U[1] + f[2 * a + 1].x * U[2] + f[2 * a + 1].y * U[3];
                 L[a] += W * row;
             }
         }
