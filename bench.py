@@ -307,6 +307,14 @@ def measure(workload, precision, steps, warmup, sort_every, parts, first_cycle_s
     timers = capi.grpic_read_timing(h)
     capi.grpic_set_timing(h, False)
     ps1 = capi.grpic_particle_steps(h)
+    # the same number of cycles again without events: each cycle's kernels
+    # replay as one captured graph
+    torch.cuda.synchronize()
+    g0 = time.perf_counter()
+    capi.grpic_step(h, steps)
+    torch.cuda.synchronize()
+    g1 = time.perf_counter()
+    ps2 = capi.grpic_particle_steps(h)
     d = run.diag()
     run.close()
     wall = t1 - t0
@@ -316,6 +324,9 @@ def measure(workload, precision, steps, warmup, sort_every, parts, first_cycle_s
         "ms_per_step": wall * 1e3 / steps, "timers": timers,
         "kernel_ms_per_launch": {k: (v[0] / max(v[1], 1)) for k, v in timers.items()},
         "live_end": int(sum(d["n_alive"])), "state1": state1,
+        "graphs": {"value": (ps2 - ps1) / (g1 - g0), "ms_per_step": (g1 - g0) * 1e3 / steps,
+                   "what": "the next %d cycles with each cycle's kernels replayed as one captured graph, "
+                           "without kernel events" % steps},
         "deposit_blocks": {"lds": d["deposit_blocks_lds"], "global": d["deposit_blocks_global"]},
     }
 
@@ -769,6 +780,7 @@ def main():
             "live_particles_end": m64["live_end"],
         },
         "kernel_ms_per_launch": m64["kernel_ms_per_launch"],
+        "graph_replay": m64["graphs"],
         "deposit_blocks": m64["deposit_blocks"],
         "roofline": roofline,
         "rooflines": rooflines64,
@@ -786,7 +798,7 @@ def main():
             "value": m32["value"], "unit": UNIT, "ms_per_step": m32["ms_per_step"], "dtype": "f32 (FP64 quartic, "
             "near-horizon metric and diagnostics)", "kernel_ms_per_launch": m32["kernel_ms_per_launch"],
             "speedup_vs_fp64": m32["value"] / m64["value"], "live_particles_end": m32["live_end"],
-            "deposit_blocks": m32["deposit_blocks"],
+            "deposit_blocks": m32["deposit_blocks"], "graph_replay": m32["graphs"],
         }
         line["fp32_mixed"]["roofline"], line["fp32_mixed"]["rooflines"] = rooflines(m32, FP32_PEAK_TFLOPS, True,
                                                                                       args.workload, "fp32")
@@ -807,6 +819,7 @@ def main():
                          tile=args.tile)
             log("%s %s: %.4g particle-steps/s" % (args.secondary, prec, ms["value"]))
             sec[prec] = {"value": ms["value"], "ms_per_step": ms["ms_per_step"], "steps": args.secondary_steps,
+                         "graph_replay": ms["graphs"],
                          "kernel_ms_per_launch": ms["kernel_ms_per_launch"], "live_particles_end": ms["live_end"],
                          "roofline": rooflines(ms, FP64_PEAK_TFLOPS if prec == "fp64" else FP32_PEAK_TFLOPS, False,
                                                args.secondary)[0]}

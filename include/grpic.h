@@ -275,6 +275,16 @@ enum { GRPIC_TIMER_PUSH = 0, GRPIC_TIMER_DEPOSIT = 1, GRPIC_TIMER_FIELDS = 2, GR
        GRPIC_NTIMERS = 4 };
 int grpic_set_timing(grpic_t *h, int32_t enable);
 
+/* Launch each cycle's kernels (all but the cell sort) as one captured HIP
+ * graph (enable != 0, the default) or one by one.  A run captures the cycle
+ * once per buffer parity and slot count and replays it, which removes the
+ * host's launch work from the steps; while timing is on the kernels are
+ * launched one by one, so every group can be bracketed with events.  The
+ * results are bit-identical either way.  Capture needs a stream other than
+ * the null stream; on the null stream the kernels go one by one.
+ * Disabling synchronises the run's stream and frees the graphs. */
+int grpic_set_graphs(grpic_t *h, int32_t enable);
+
 /* Synchronise; ms[t] receives the summed event time of timer t and
  * launches[t] the number of timed groups since the previous read (both
  * arrays of GRPIC_NTIMERS entries, either may be NULL).  Resets the sums. */

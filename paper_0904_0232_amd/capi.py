@@ -129,6 +129,8 @@ def lib():
         L.grpic_load_state.argtypes = [_H, ctypes.c_void_p, ctypes.c_int64]
         L.grpic_sort.argtypes = [_H, _U32, _I64]
         L.grpic_set_timing.argtypes = [_H, ctypes.c_int32]
+        L.grpic_set_graphs.argtypes = [_H, ctypes.c_int32]
+        L.grpic_set_graphs.restype = ctypes.c_int
         L.grpic_read_timing.argtypes = [_H, _D, _I64]
         L.grpic_particle_steps.argtypes = [_H, _I64]
         L.grpic_run_bytes.argtypes = [ctypes.POINTER(Config)]
@@ -346,6 +348,10 @@ TIMER_NAMES = ("push", "deposit", "fields", "sort")
 
 def grpic_set_timing(h, enable=True):
     _check(lib().grpic_set_timing(h, 1 if enable else 0))
+
+
+def grpic_set_graphs(h, enable=True):
+    _check(lib().grpic_set_graphs(h, 1 if enable else 0))
 
 
 def grpic_read_timing(h):

@@ -63,6 +63,11 @@ struct grpic_s {
     // C_FLAGS as last copied to the host (pinned; written by an asynchronous
     // copy at the end of every grpic_step call)
     volatile unsigned long long *flags_host;
+    // the kernels of one cycle captured as a graph per buffer parity
+    // (xc, uc), each for the slot count it was captured with
+    int use_graphs;
+    hipGraphExec_t cycle_exec[2][2];
+    int64_t cycle_slots[2][2];
     // event timing
     int timing;
     std::vector<hipEvent_t> ev_pool;
@@ -395,23 +400,74 @@ int do_sort(grpic_t *h, bool keep = false, uint32_t **final_keys = nullptr, uint
     return check(hipGetLastError());
 }
 
+// The kernels of one cycle (everything but the cell sort), enqueued on the
+// run's stream.
 template <typename T>
-int one_step_t(grpic_t *h, bool allow_sort) {
+int cycle_kernels(grpic_t *h) {
     int rc = fields_to_n<T>(h);
     if (rc) return rc;
     push_particles(h);
     fields_mid<T>(h);
     deposit_particles(h);
-    rc = fields_d<T>(h);
+    return fields_d<T>(h);
+}
+
+int cycle_kernels(grpic_t *h) { return h->mixed ? cycle_kernels<float>(h) : cycle_kernels<double>(h); }
+
+void drop_cycle_graphs(grpic_t *h) {
+    for (int a = 0; a < 2; a++)
+        for (int b = 0; b < 2; b++) {
+            if (h->cycle_exec[a][b]) (void)hipGraphExecDestroy(h->cycle_exec[a][b]);
+            h->cycle_exec[a][b] = nullptr;
+        }
+}
+
+// The captured cycle of the current buffer parity and slot count, captured
+// now if there is none (the launches' pointers and grid sizes depend only on
+// them; the configuration and the buffers are fixed for the run).
+int cycle_graph(grpic_t *h, hipGraphExec_t *out) {
+    hipGraphExec_t &ex = h->cycle_exec[h->xc][h->uc];
+    if (ex && h->cycle_slots[h->xc][h->uc] == h->n_slots) {
+        *out = ex;
+        return GRPIC_OK;
+    }
+    if (ex) (void)hipGraphExecDestroy(ex);
+    ex = nullptr;
+    int rc = check(hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
+    if (rc) return rc;
+    int krc = cycle_kernels(h);
+    hipGraph_t g = nullptr;
+    rc = check(hipStreamEndCapture(h->stream, &g));
+    if (!rc) rc = krc;
+    if (!rc) rc = check(hipGraphInstantiate(&ex, g, nullptr, nullptr, 0));
+    if (g) (void)hipGraphDestroy(g);
+    if (rc) {
+        ex = nullptr;
+        return rc;
+    }
+    h->cycle_slots[h->xc][h->uc] = h->n_slots;
+    *out = ex;
+    return GRPIC_OK;
+}
+
+// One cycle: the captured graph of its kernels when graphs are on and no
+// kernel is being timed (the timing brackets each kernel group with events
+// recorded per launch), else the kernels launched one by one; then the cell
+// sort when it is due.
+int one_step(grpic_t *h, bool allow_sort = true) {
+    int rc;
+    if (h->use_graphs && !h->timing && h->stream) {
+        hipGraphExec_t ex = nullptr;
+        rc = cycle_graph(h, &ex);
+        if (!rc) rc = check(hipGraphLaunch(ex, h->stream));
+    } else {
+        rc = cycle_kernels(h);
+    }
     if (rc) return rc;
     h->xc = 1 - h->xc;
     h->step_count++;
     if (allow_sort && h->cfg.sort_every > 0 && h->step_count % h->cfg.sort_every == 0) return do_sort(h);
     return check(hipGetLastError());
-}
-
-int one_step(grpic_t *h, bool allow_sort = true) {
-    return h->mixed ? one_step_t<float>(h, allow_sort) : one_step_t<double>(h, allow_sort);
 }
 
 bool sort_due(const grpic_t *h) { return h->cfg.sort_every > 0 && h->step_count % h->cfg.sort_every == 0; }
@@ -924,6 +980,7 @@ const char *grpic_strerror(int code) {
 void grpic_destroy(grpic_t *h) {
     if (!h) return;
     (void)hipStreamSynchronize(h->stream);
+    drop_cycle_graphs(h);
     for (auto e : h->ev_pool) (void)hipEventDestroy(e);
     for (int t = 0; t < GRPIC_NTIMERS; t++)
         for (auto &pr : h->ev_used[t]) {
@@ -978,6 +1035,7 @@ int grpic_create(const grpic_config *cfg, void *stream, grpic_t **out) {
     h->rscale = ldexp(1.0, cfg->fp_bits) / qmax;
     h->jscale = ldexp(1.0, cfg->fp_bits) * cfg->dt / qmax;
     h->cap = cfg->capacity;
+    h->use_graphs = 1;
 
     const Grid &G = h->G;
     int64_t gs = G.gsize(), nn = G.nnodes();
@@ -1421,6 +1479,17 @@ int grpic_diagnostics(grpic_t *h, grpic_diag *out) {
 int grpic_set_timing(grpic_t *h, int32_t enable) {
     if (!h) return GRPIC_EINVAL;
     h->timing = enable ? 1 : 0;
+    return GRPIC_OK;
+}
+
+int grpic_set_graphs(grpic_t *h, int32_t enable) {
+    if (!h) return GRPIC_EINVAL;
+    h->use_graphs = enable ? 1 : 0;
+    if (!h->use_graphs) {
+        int rc = check(hipStreamSynchronize(h->stream));
+        drop_cycle_graphs(h);
+        return rc;
+    }
     return GRPIC_OK;
 }
 

@@ -259,6 +259,43 @@ def test_sort_bit_exact(N, tile, n):
     assert np.array_equal(sp2, sp[po[:nl]])
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_graph_replay_equals_launches(precision):
+    """A run whose cycles replay captured graphs (the default) equals, bit for
+    bit after every cycle, a run that launches the kernels one by one; the
+    cell sort falls between replays (every 5 cycles), and each replay is
+    followed by host work (dumps, diagnostics)."""
+    from paper_0904_0232_amd import capi
+    from paper_0904_0232_amd import run as R
+    N = 16
+    P = params(N, m=1.5, a=1.2, dt=0.5, species=((-0.02, 0.02), (0.02, 0.4)))
+    parts = _small_parts(5, 3000, N)
+    runs = []
+    for graphs in (False, True):
+        r = gpu_run(P, 8000, sort_every=5, fp_bits=FPB)
+        if precision == "fp32":
+            r.close()
+            cfg = R.make_config(N, m=P["m"], a=P["a"], dt=P["dt"], B0=P["B0"], species=P["species"], sort_every=5,
+                                capacity=8000, fp_bits=FPB, precision=capi.FP32_MIXED)
+            r = R.Run(cfg)
+        capi.grpic_set_graphs(r.h, graphs)
+        for sp, x, uc in parts:
+            r.load(sp, x, uc)
+        runs.append(r)
+    for it in range(12):
+        for r in runs:
+            r.step(1)
+        (xa, ua, sa), (xb, ub, sb) = runs[0].particles(), runs[1].particles()
+        assert np.array_equal(sa, sb), it
+        live = sa != O.DEAD
+        assert np.array_equal(xa[:, live], xb[:, live]) and np.array_equal(ua[:, live], ub[:, live]), it
+        for f in ("D", "B", "J"):
+            assert np.array_equal(runs[0].fields(f), runs[1].fields(f)), (it, f)
+        assert runs[0].diag() == runs[1].diag(), it
+    for r in runs:
+        r.close()
+
+
 def test_deterministic_repeat():
     N = 16
     P = params(N, m=1.5, a=1.2, dt=0.5, species=((-0.02, 0.02), (0.02, 0.4)))
