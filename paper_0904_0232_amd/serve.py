@@ -212,3 +212,26 @@ def serve(requests, budget_bytes, max_slots, keep_ids=(), prefetch=8, log=None, 
         "runs_per_s": len(records) / makespan if makespan > 0 else 0.0,
         "host_s": {"waiting_for_inputs": t_inputs, "admitting": t_submit, "stepping": t_step},
     }
+
+
+def main(argv=None):
+    """Serve a seeded request mix and print its figures as one JSON line:
+    python -m paper_0904_0232_amd.serve [--requests N] [--rate R] [--seed S]
+    (rate in requests per second; a large rate makes every request arrive at
+    once, which measures the loop's saturated capacity)."""
+    import argparse
+    import json
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--requests", type=int, default=32)
+    ap.add_argument("--rate", type=float, default=1e6)
+    ap.add_argument("--seed", type=int, default=1)
+    ap.add_argument("--budget-gb", type=float, default=64.0)
+    ap.add_argument("--slots", type=int, default=64)
+    args = ap.parse_args(argv)
+    res = serve(make_requests(args.requests, args.seed, args.rate), int(args.budget_gb * (1 << 30)), args.slots)
+    res.pop("records")
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()
