@@ -152,7 +152,10 @@ int grpic_config_check(const grpic_config *cfg);
  * given (grpic_config_check), r_exc < r_rm, masses > 0, rk_mode, gather_mode
  * and gather_weights at their defaults unless FP64, outer_layer >= 0,
  * 0 <= outer_damp <= 1) and initialises the fields (Sec. 6: uniform
- * contravariant field).  stream is a hipStream_t (NULL: the null stream).
+ * contravariant field).  stream is a hipStream_t on which every call of the
+ * run enqueues its work; NULL: the run creates a stream of its own (blocking,
+ * so it stays ordered with the null stream both ways; default priority) and
+ * destroys it in grpic_destroy.
  * Returns GRPIC_EINVAL, GRPIC_ENOMEM or GRPIC_EDEVICE on failure. */
 int grpic_create(const grpic_config *cfg, void *stream, grpic_t **out);
 
@@ -281,7 +284,7 @@ int grpic_set_timing(grpic_t *h, int32_t enable);
  * host's launch work from the steps; while timing is on the kernels are
  * launched one by one, so every group can be bracketed with events.  The
  * results are bit-identical either way.  Capture needs a stream other than
- * the null stream; on the null stream the kernels go one by one.
+ * the null stream, which every run has (grpic_create).
  * Disabling synchronises the run's stream and frees the graphs. */
 int grpic_set_graphs(grpic_t *h, int32_t enable);
 

@@ -68,6 +68,8 @@ struct grpic_s {
     int use_graphs;
     hipGraphExec_t cycle_exec[2][2];
     int64_t cycle_slots[2][2];
+    // the run created its stream itself (the caller passed the null stream)
+    bool own_stream;
     // event timing
     int timing;
     std::vector<hipEvent_t> ev_pool;
@@ -470,7 +472,10 @@ int one_step(grpic_t *h, bool allow_sort = true) {
     return check(hipGetLastError());
 }
 
-bool sort_due(const grpic_t *h) { return h->cfg.sort_every > 0 && h->step_count % h->cfg.sort_every == 0; }
+// The cell sort of grpic_step falls due at the end of the next cycle.
+bool sort_due_after_cycle(const grpic_t *h) {
+    return h->cfg.sort_every > 0 && (h->step_count + 1) % h->cfg.sort_every == 0;
+}
 
 // FP64 view of the particle state (the FP32-mixed form is widened into
 // tmp, which must hold 7 n doubles).
@@ -597,8 +602,9 @@ struct grpic_batch_s {
     hipEvent_t copied[2];      // the copy out of h_table[k] has completed
     bool copy_pending[2];
     int ring;
-    hipGraphExec_t exec;       // one iteration for up to exec_iters fixed-point passes
-    int exec_iters;
+    // captured iterations, per (fixed-point passes, radix passes of the
+    // sorts that fall due; 0: none)
+    std::map<std::pair<int, int>, hipGraphExec_t> execs;
     std::vector<BatchRun *> active;
     std::map<int64_t, BatchRun *> runs;
 };
@@ -636,8 +642,10 @@ void fill_table_entry(grpic_t *h, BatchRun32 &R) {
     R.rscale = h->rscale;
 }
 
-// Enqueue one batched iteration (captured into a graph by the caller).
-void enqueue_iteration(grpic_batch_t *b, int iters) {
+// Enqueue one batched iteration (captured into a graph by the caller): the
+// cycle of every active run, then the sorts of the runs whose sort falls due
+// at the end of this cycle (up to sort_passes radix passes).
+void enqueue_iteration(grpic_batch_t *b, int iters, int sort_passes) {
     const BatchTable *T = b->d_table;
     hipStream_t s = b->stream;
     launch_batch_field(BF_SAVE_B, T, 0, kBatchGridField, s);
@@ -658,22 +666,29 @@ void enqueue_iteration(grpic_batch_t *b, int iters) {
         launch_batch_field(BF_DSTEP, T, it, kBatchGridField, s);
     }
     launch_batch_field(BF_RELAX, T, 0, kBatchGridField, s);
+    launch_batch_sort(T, sort_passes, s);
 }
 
-int capture_iteration(grpic_batch_t *b, int iters) {
-    if (b->exec) {
-        (void)hipGraphExecDestroy(b->exec);
-        b->exec = nullptr;
+// The captured iteration for (iters, sort_passes), captured now if new.
+int iteration_graph(grpic_batch_t *b, int iters, int sort_passes, hipGraphExec_t *out) {
+    const auto key = std::make_pair(iters, sort_passes);
+    auto it = b->execs.find(key);
+    if (it != b->execs.end()) {
+        *out = it->second;
+        return GRPIC_OK;
     }
     int rc = check(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
     if (rc) return rc;
-    enqueue_iteration(b, iters);
+    enqueue_iteration(b, iters, sort_passes);
     hipGraph_t g = nullptr;
     rc = check(hipStreamEndCapture(b->stream, &g));
-    if (!rc) rc = check(hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0));
+    hipGraphExec_t ex = nullptr;
+    if (!rc) rc = check(hipGraphInstantiate(&ex, g, nullptr, nullptr, 0));
     if (g) (void)hipGraphDestroy(g);
-    if (!rc) b->exec_iters = iters;
-    return rc;
+    if (rc) return rc;
+    b->execs[key] = ex;
+    *out = ex;
+    return GRPIC_OK;
 }
 
 int finish_run(grpic_batch_t *b, BatchRun *r) {
@@ -772,15 +787,25 @@ int grpic_batch_step(grpic_batch_t *b, int32_t *finished) {
     BatchTable *T = b->h_table[k];
     const int nr = (int)b->active.size();
     T->nruns = nr;
-    int64_t off[BK_NKINDS] = {0, 0, 0, 0, 0};
-    int iters = 1;
+    int64_t off[BK_NKINDS] = {};
+    int iters = 1, sort_passes = 0;
     for (int i = 0; i < nr; i++) {
         grpic_t *h = b->active[i]->h;
         BatchRun32 &R = T->run[i];
         fill_table_entry(h, R);
+        // the sort that falls due at the end of this cycle (as in
+        // grpic_step): it reads the cycle's output buffers and writes the
+        // other pair
+        if (sort_due_after_cycle(h)) {
+            batch_sort_job(h->G, h->cfg.tile, h->n_slots, pp32(h, 1 - h->xc, h->uc), pp32(h, h->xc, 1 - h->uc),
+                           h->keys, h->keys_alt, h->idx, h->idx_alt, h->sort_temp, h->key_bits, R.sort);
+            sort_passes = R.sort.passes > sort_passes ? R.sort.passes : sort_passes;
+        } else {
+            R.sort = BatchSort{};
+        }
         for (int kd = 0; kd < BK_NKINDS; kd++) {
             R.off[kd] = off[kd];
-            off[kd] += batch_blocks(kd, h->G, R.relax_box, h->n_slots);
+            off[kd] += kd >= BK_SORT_SLOT ? batch_sort_blocks(kd, R.sort) : batch_blocks(kd, h->G, R.relax_box, h->n_slots);
         }
         iters = h->cfg.field_iters > iters ? h->cfg.field_iters : iters;
     }
@@ -791,19 +816,19 @@ int grpic_batch_step(grpic_batch_t *b, int32_t *finished) {
     if (rc) return rc;
     b->copy_pending[k] = true;
     b->ring = 1 - k;
-    if (!b->exec || b->exec_iters != iters) {
-        rc = capture_iteration(b, iters);
-        if (rc) return rc;
-    }
-    rc = check(hipGraphLaunch(b->exec, b->stream));
+    hipGraphExec_t ex = nullptr;
+    rc = iteration_graph(b, iters, sort_passes, &ex);
+    if (rc) return rc;
+    rc = check(hipGraphLaunch(ex, b->stream));
     if (rc) return rc;
     for (BatchRun *r : b->active) {
         grpic_t *h = r->h;
+        const bool sorted = sort_due_after_cycle(h);
         h->xc = 1 - h->xc;
         h->step_count++;
-        if (sort_due(h)) {
-            rc = do_sort(h);
-            if (rc) return rc;
+        if (sorted) {
+            h->xc = 1 - h->xc;
+            h->uc = 1 - h->uc;
         }
         r->done++;
     }
@@ -923,7 +948,7 @@ void grpic_batch_destroy(grpic_batch_t *b) {
     if (b->stream) (void)hipStreamSynchronize(b->stream);
     for (BatchRun *r : b->active)
         if (r->h) grpic_destroy(r->h);
-    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    for (auto &kv : b->execs) (void)hipGraphExecDestroy(kv.second);
     for (int k = 0; k < 2; k++) {
         if (b->h_table[k]) (void)hipHostFree(b->h_table[k]);
         if (b->copied[k]) (void)hipEventDestroy(b->copied[k]);
@@ -989,6 +1014,7 @@ void grpic_destroy(grpic_t *h) {
         }
     for (void *p : h->allocs) raw_free(h, p);
     if (h->flags_host) (void)hipHostFree((void *)h->flags_host);
+    if (h->own_stream) (void)hipStreamDestroy(h->stream);
     delete h;
 }
 
@@ -1006,6 +1032,16 @@ int grpic_create(const grpic_config *cfg, void *stream, grpic_t **out) {
     if (FAILS(hipGetDevice(&h->device))) {
         delete h;
         return GRPIC_EDEVICE;
+    }
+    if (!h->stream) {
+        // a stream of the run's own, blocking (ordered with the null stream
+        // both ways) and at the default priority, so the cycle can be
+        // captured as a graph while the caller keeps the null stream's order
+        if (FAILS(hipStreamCreate(&h->stream))) {
+            delete h;
+            return GRPIC_EDEVICE;
+        }
+        h->own_stream = true;
     }
     h->noalloc_staging = noalloc_staging(h->device);
     h->G.nx = cfg->nx;

@@ -216,9 +216,29 @@ void launch_from_f64(const double *x, const double *u, ParticlePtrs32 out, int64
 // The run table lives in device memory and is rewritten before every
 // iteration, so a captured iteration replays unchanged while runs come and
 // go and their buffers swap.
-enum BatchKind { BK_NODE = 0, BK_GRID, BK_RELAX, BK_PUSH, BK_DEP, BK_NKINDS };
+enum BatchKind { BK_NODE = 0, BK_GRID, BK_RELAX, BK_PUSH, BK_DEP, BK_SORT_SLOT, BK_SORT_TILE, BK_SORT_SCAN,
+                 BK_NKINDS };
 constexpr int kBatchBlock = 256;     // threads per block of the field kinds
 constexpr int kMaxBatchRuns = 64;
+
+constexpr int kSortMaxPasses = 4;  // digits of at most 9 bits cover 32-bit keys
+
+// One run's cell sort inside a batched iteration (n = 0: no sort is due):
+// the pass plan and, per pass, the key and value arrays read and written
+// (the same ping-pong as a single run's sort).
+struct BatchSort {
+    int64_t n;        // slots
+    int64_t ntiles;   // tiles of the radix passes
+    int64_t nchunks;  // scan chunks of the widest pass
+    int tile, nTx, nTy;
+    uint32_t sentinel;
+    int passes;
+    int shift[kSortMaxPasses], bits[kSortMaxPasses];
+    uint32_t *kin[kSortMaxPasses], *vin[kSortMaxPasses], *kout[kSortMaxPasses], *vout[kSortMaxPasses];
+    uint32_t *counts, *sums;
+    const uint32_t *final_idx;
+    ParticlePtrs32 in, out;
+};
 
 struct BatchRun32 {
     int64_t off[BK_NKINDS];  // first logical block of this run per kind
@@ -239,6 +259,7 @@ struct BatchRun32 {
     unsigned long long *counters;
     Dep32 D;
     double r_rm, rscale;
+    BatchSort sort;
 };
 
 struct BatchTable {
@@ -286,6 +307,14 @@ void launch_sort(const Grid &G, int tile, int64_t n, ParticlePtrs in, ParticlePt
 void launch_sort32(const Grid &G, int tile, int64_t n, ParticlePtrs32 in, ParticlePtrs32 out, uint32_t *keys,
                    uint32_t *keys_alt, uint32_t *idx, uint32_t *idx_alt, void *temp, int key_bits, bool keep,
                    uint32_t **final_keys, uint32_t **final_idx, unsigned long long *counters, hipStream_t s);
+// The batched form of launch_sort32: J describes the sort of one run (the
+// same arguments), and the batched launches sort every run of the table
+// whose J.n > 0, up to `passes` radix passes (the most any of them needs).
+void batch_sort_job(const Grid &G, int tile, int64_t n, ParticlePtrs32 in, ParticlePtrs32 out, uint32_t *keys,
+                    uint32_t *keys_alt, uint32_t *idx, uint32_t *idx_alt, void *temp, int key_bits, BatchSort &J);
+// logical blocks of a run's sort per kind (BK_SORT_*)
+int64_t batch_sort_blocks(int kind, const BatchSort &J);
+void launch_batch_sort(const BatchTable *table, int passes, hipStream_t s);
 
 // diagnostics: fills host-side partial sums (see diag.hip)
 struct DiagOut {

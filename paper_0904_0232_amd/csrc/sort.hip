@@ -81,9 +81,10 @@ __device__ __forceinline__ uint32_t tile_key(int T, int nTx, int nTy, const int 
     return ((uint32_t)row * (uint32_t)nTx + (uint32_t)along) * (uint32_t)(T * T * T) + (uint32_t)((lz * T + ly) * T + lx);
 }
 
-__global__ void k_sort_keys(Grid G, int T, int nTx, int nTy, uint32_t sentinel, ParticlePtrs in, int64_t n,
-                            uint32_t *__restrict__ keys, unsigned long long *counters) {
-    const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+// Key of slot id (every slot below n); slot 0 also resets the live count.
+__device__ __forceinline__ void sort_key_slot(const Grid &G, int T, int nTx, int nTy, uint32_t sentinel,
+                                              const ParticlePtrs &in, int64_t n, uint32_t *__restrict__ keys,
+                                              unsigned long long *counters, int64_t id) {
     if (id == 0) counters[C_NALIVE] = (unsigned long long)n;
     if (id >= n) return;
     if (in.sp[id] == kDead) {
@@ -99,9 +100,9 @@ __global__ void k_sort_keys(Grid G, int T, int nTx, int nTy, uint32_t sentinel, 
     keys[id] = tile_key(T, nTx, nTy, c);
 }
 
-__global__ void k_sort_keys32(Grid G, int T, int nTx, int nTy, uint32_t sentinel, ParticlePtrs32 in, int64_t n,
-                              uint32_t *__restrict__ keys, unsigned long long *counters) {
-    const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void sort_key_slot32(const Grid &G, int T, int nTx, int nTy, uint32_t sentinel,
+                                                const ParticlePtrs32 &in, int64_t n, uint32_t *__restrict__ keys,
+                                                unsigned long long *counters, int64_t id) {
     if (id == 0) counters[C_NALIVE] = (unsigned long long)n;
     if (id >= n) return;
     if (in.sp[id] == kDead) {
@@ -117,16 +118,28 @@ __global__ void k_sort_keys32(Grid G, int T, int nTx, int nTy, uint32_t sentinel
     keys[id] = tile_key(T, nTx, nTy, c);
 }
 
+__global__ void k_sort_keys(Grid G, int T, int nTx, int nTy, uint32_t sentinel, ParticlePtrs in, int64_t n,
+                            uint32_t *__restrict__ keys, unsigned long long *counters) {
+    sort_key_slot(G, T, nTx, nTy, sentinel, in, n, keys, counters, (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
+}
+
+__global__ void k_sort_keys32(Grid G, int T, int nTx, int nTy, uint32_t sentinel, ParticlePtrs32 in, int64_t n,
+                              uint32_t *__restrict__ keys, unsigned long long *counters) {
+    sort_key_slot32(G, T, nTx, nTy, sentinel, in, n, keys, counters, (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
+}
+
 // ---------------------------------------------------------------------------
 // Upsweep: digit histogram of one tile.
 
-__global__ __launch_bounds__(kSortBlock) void k_sort_upsweep(const uint32_t *__restrict__ keys, int64_t n, int shift,
-                                                              int bits, int64_t ntiles, uint32_t *__restrict__ counts) {
-    __shared__ uint32_t hist[kSortMaxBins];
+// Digit histogram of tile t.  hist: kSortMaxBins LDS entries.  Every thread
+// of the block calls it; the caller orders earlier uses of hist before it.
+__device__ __forceinline__ void upsweep_tile(const uint32_t *__restrict__ keys, int64_t n, int shift, int bits,
+                                             int64_t ntiles, uint32_t *__restrict__ counts, int64_t t,
+                                             uint32_t *hist) {
     const int R = 1 << bits;
     for (int d = threadIdx.x; d < R; d += kSortBlock) hist[d] = 0u;
     __syncthreads();
-    const int64_t base = (int64_t)blockIdx.x * kSortTile;
+    const int64_t base = t * kSortTile;
     uint32_t k[kSortItems];
 #pragma unroll
     for (int q = 0; q < kSortItems; q++) {
@@ -137,7 +150,13 @@ __global__ __launch_bounds__(kSortBlock) void k_sort_upsweep(const uint32_t *__r
     for (int q = 0; q < kSortItems; q++)
         if (base + q * kSortBlock + threadIdx.x < n) atomicAdd(&hist[(k[q] >> shift) & (uint32_t)(R - 1)], 1u);
     __syncthreads();
-    for (int d = threadIdx.x; d < R; d += kSortBlock) counts[(int64_t)d * ntiles + blockIdx.x] = hist[d];
+    for (int d = threadIdx.x; d < R; d += kSortBlock) counts[(int64_t)d * ntiles + t] = hist[d];
+}
+
+__global__ __launch_bounds__(kSortBlock) void k_sort_upsweep(const uint32_t *__restrict__ keys, int64_t n, int shift,
+                                                              int bits, int64_t ntiles, uint32_t *__restrict__ counts) {
+    __shared__ uint32_t hist[kSortMaxBins];
+    upsweep_tile(keys, n, shift, bits, ntiles, counts, blockIdx.x, hist);
 }
 
 // ---------------------------------------------------------------------------
@@ -169,9 +188,10 @@ __device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t *t
     return before + x - v;
 }
 
-__global__ __launch_bounds__(kSortBlock) void k_scan_reduce(const uint32_t *__restrict__ a, int64_t m,
-                                                            uint32_t *__restrict__ sums) {
-    const int64_t base = (int64_t)blockIdx.x * kScanChunk;
+// Sum of chunk c of a[0, m).
+__device__ __forceinline__ void scan_reduce_chunk(const uint32_t *__restrict__ a, int64_t m,
+                                                  uint32_t *__restrict__ sums, int64_t c) {
+    const int64_t base = c * kScanChunk;
     uint32_t s = 0;
     for (int q = 0; q < kScanItems; q++) {
         const int64_t i = base + (int64_t)threadIdx.x * kScanItems + q;
@@ -179,12 +199,12 @@ __global__ __launch_bounds__(kSortBlock) void k_scan_reduce(const uint32_t *__re
     }
     uint32_t total;
     (void)block_exclusive_scan(s, &total);
-    if (threadIdx.x == 0) sums[blockIdx.x] = total;
+    if (threadIdx.x == 0) sums[c] = total;
 }
 
-// One block of kScanTopBlock threads: exclusive scan of the chunk sums.
-__global__ __launch_bounds__(kScanTopBlock) void k_scan_top(uint32_t *__restrict__ sums, int64_t nchunks) {
-    const int64_t per = (nchunks + kScanTopBlock - 1) / kScanTopBlock;
+// Exclusive scan of the nchunks chunk sums by one block.
+__device__ __forceinline__ void scan_top_sums(uint32_t *__restrict__ sums, int64_t nchunks) {
+    const int64_t per = (nchunks + blockDim.x - 1) / blockDim.x;
     const int64_t lo = (int64_t)threadIdx.x * per;
     uint32_t s = 0;
     for (int64_t i = lo; i < lo + per && i < nchunks; i++) s += sums[i];
@@ -197,9 +217,10 @@ __global__ __launch_bounds__(kScanTopBlock) void k_scan_top(uint32_t *__restrict
     }
 }
 
-__global__ __launch_bounds__(kSortBlock) void k_scan_down(uint32_t *__restrict__ a, int64_t m,
-                                                          const uint32_t *__restrict__ sums) {
-    const int64_t base = (int64_t)blockIdx.x * kScanChunk + (int64_t)threadIdx.x * kScanItems;
+// Chunk c of a[0, m) scanned in place from its base sums[c].
+__device__ __forceinline__ void scan_down_chunk(uint32_t *__restrict__ a, int64_t m,
+                                                const uint32_t *__restrict__ sums, int64_t c) {
+    const int64_t base = c * kScanChunk + (int64_t)threadIdx.x * kScanItems;
     uint32_t v[kScanItems], s = 0;
 #pragma unroll
     for (int q = 0; q < kScanItems; q++) {
@@ -207,12 +228,27 @@ __global__ __launch_bounds__(kSortBlock) void k_scan_down(uint32_t *__restrict__
         s += v[q];
     }
     uint32_t total;
-    uint32_t run = sums[blockIdx.x] + block_exclusive_scan(s, &total);
+    uint32_t run = sums[c] + block_exclusive_scan(s, &total);
 #pragma unroll
     for (int q = 0; q < kScanItems; q++) {
         if (base + q < m) a[base + q] = run;
         run += v[q];
     }
+}
+
+__global__ __launch_bounds__(kSortBlock) void k_scan_reduce(const uint32_t *__restrict__ a, int64_t m,
+                                                            uint32_t *__restrict__ sums) {
+    scan_reduce_chunk(a, m, sums, blockIdx.x);
+}
+
+// One block of kScanTopBlock threads: exclusive scan of the chunk sums.
+__global__ __launch_bounds__(kScanTopBlock) void k_scan_top(uint32_t *__restrict__ sums, int64_t nchunks) {
+    scan_top_sums(sums, nchunks);
+}
+
+__global__ __launch_bounds__(kSortBlock) void k_scan_down(uint32_t *__restrict__ a, int64_t m,
+                                                          const uint32_t *__restrict__ sums) {
+    scan_down_chunk(a, m, sums, blockIdx.x);
 }
 
 void launch_scan(uint32_t *a, int64_t m, uint32_t *sums, hipStream_t s) {
@@ -237,8 +273,8 @@ struct PassOut {
 // The particle records in sorted order: out[i] = in[idx[i]].  Reads follow
 // the output order, which for particles sorted a few steps earlier is close
 // to the input order, so they stay nearly coalesced.
-__global__ void k_sort_gather(ParticlePtrs in, ParticlePtrs out, const uint32_t *__restrict__ idx, int64_t n) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void gather_slot(const ParticlePtrs &in, const ParticlePtrs &out,
+                                            const uint32_t *__restrict__ idx, int64_t n, int64_t i) {
     if (i >= n) return;
     const uint32_t s = idx[i];
     for (int q = 0; q < 3; q++) out.x[q][i] = in.x[q][s];
@@ -246,14 +282,22 @@ __global__ void k_sort_gather(ParticlePtrs in, ParticlePtrs out, const uint32_t 
     out.sp[i] = in.sp[s];
 }
 
-__global__ void k_sort_gather32(ParticlePtrs32 in, ParticlePtrs32 out, const uint32_t *__restrict__ idx, int64_t n) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void gather_slot32(const ParticlePtrs32 &in, const ParticlePtrs32 &out,
+                                              const uint32_t *__restrict__ idx, int64_t n, int64_t i) {
     if (i >= n) return;
     const uint32_t s = idx[i];
     out.cell[i] = in.cell[s];
     for (int q = 0; q < 3; q++) out.off[q][i] = in.off[q][s];
     for (int q = 0; q < 4; q++) out.u[q][i] = in.u[q][s];
     out.sp[i] = in.sp[s];
+}
+
+__global__ void k_sort_gather(ParticlePtrs in, ParticlePtrs out, const uint32_t *__restrict__ idx, int64_t n) {
+    gather_slot(in, out, idx, n, (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
+}
+
+__global__ void k_sort_gather32(ParticlePtrs32 in, ParticlePtrs32 out, const uint32_t *__restrict__ idx, int64_t n) {
+    gather_slot32(in, out, idx, n, (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
 }
 
 // FIRST: the values are the slot indices (not read).  LAST: lower the live
@@ -265,24 +309,31 @@ __global__ void k_sort_gather32(ParticlePtrs32 in, ParticlePtrs32 out, const uin
 // adds their number.  LDS instructions of one wave complete in order, so no
 // barrier is needed inside the rounds; one barrier, then per digit a prefix
 // over the four waves and a scan over the digits place every element.
+struct DownLds {
+    uint32_t key[kSortTile];
+    uint32_t val[kSortTile];
+    uint32_t start[kSortMaxBins];            // where each digit starts in the staged tile
+    uint32_t goff[kSortMaxBins];             // where the tile's digit starts in the output
+    uint16_t wc[kSortWaves][kSortMaxBins];   // per-wave counts, then per-wave prefixes
+};
+
+// Tile t of one pass.  Every thread of the block calls it; the caller orders
+// earlier uses of L before it.
 template <bool FIRST, bool LAST, class Out>
-__global__ __launch_bounds__(kSortBlock) void k_sort_downsweep(const uint32_t *__restrict__ keys_in,
-                                                                const uint32_t *__restrict__ vals_in, int64_t n,
-                                                                int shift, int bits, int64_t ntiles,
-                                                                const uint32_t *__restrict__ offsets, Out out,
-                                                                uint32_t sentinel, unsigned long long *counters) {
+__device__ __forceinline__ void downsweep_tile(const uint32_t *__restrict__ keys_in,
+                                               const uint32_t *__restrict__ vals_in, int64_t n, int shift, int bits,
+                                               int64_t ntiles, const uint32_t *__restrict__ offsets, const Out &out,
+                                               uint32_t sentinel, unsigned long long *counters, int64_t t,
+                                               DownLds &L) {
     constexpr int kWaveSpan = kSortTile / kSortWaves;  // slots ranked by one wave
-    __shared__ uint32_t s_key[kSortTile];
-    __shared__ uint32_t s_val[kSortTile];
-    __shared__ uint32_t s_start[kSortMaxBins];  // where each digit starts in the staged tile
-    __shared__ uint32_t s_goff[kSortMaxBins];   // where the tile's digit starts in the output
-    __shared__ uint16_t s_wc[kSortWaves][kSortMaxBins];  // per-wave counts, then per-wave prefixes
+    uint32_t *s_key = L.key, *s_val = L.val, *s_start = L.start, *s_goff = L.goff;
+    uint16_t(*s_wc)[kSortMaxBins] = L.wc;
     const int R = 1 << bits, tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const uint32_t mask = (uint32_t)(R - 1);
-    const int64_t base = (int64_t)blockIdx.x * kSortTile;
+    const int64_t base = t * kSortTile;
     const int tile_n = (int)(n - base < kSortTile ? n - base : kSortTile);
     for (int d = tid; d < R; d += kSortBlock) {
-        s_goff[d] = offsets[(int64_t)d * ntiles + blockIdx.x];
+        s_goff[d] = offsets[(int64_t)d * ntiles + t];
         for (int k = 0; k < kSortWaves; k++) s_wc[k][d] = 0;
     }
     uint32_t key[kSortItems], val[kSortItems], rank[kSortItems];
@@ -354,6 +405,17 @@ __global__ __launch_bounds__(kSortBlock) void k_sort_downsweep(const uint32_t *_
     }
 }
 
+template <bool FIRST, bool LAST, class Out>
+__global__ __launch_bounds__(kSortBlock) void k_sort_downsweep(const uint32_t *__restrict__ keys_in,
+                                                                const uint32_t *__restrict__ vals_in, int64_t n,
+                                                                int shift, int bits, int64_t ntiles,
+                                                                const uint32_t *__restrict__ offsets, Out out,
+                                                                uint32_t sentinel, unsigned long long *counters) {
+    __shared__ DownLds L;
+    downsweep_tile<FIRST, LAST, Out>(keys_in, vals_in, n, shift, bits, ntiles, offsets, out, sentinel, counters,
+                                     blockIdx.x, L);
+}
+
 // The passes over the keys; returns where the sorted keys and the original
 // slot of each sorted position are.
 void run_passes(int64_t n, int key_bits, uint32_t *keys, uint32_t *keys_alt, uint32_t *idx, uint32_t *idx_alt,
@@ -423,6 +485,173 @@ void launch_sort32(const Grid &G, int tile, int64_t n, ParticlePtrs32 in, Partic
     hipLaunchKernelGGL(k_sort_gather32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, in, out, fi, n);
     if (final_keys) *final_keys = keep ? fk : nullptr;
     if (final_idx) *final_idx = keep ? fi : nullptr;
+}
+
+// ---------------------------------------------------------------------------
+// Serving batch: the sorts of every run that falls due in an iteration, as
+// persistent launches over the logical blocks of those runs (slots in blocks
+// of kSortBlock, tiles, scan chunks), captured with the rest of the
+// iteration.  The bodies are the ones above, so a run sorts exactly as alone.
+
+void batch_sort_job(const Grid &G, int tile, int64_t n, ParticlePtrs32 in, ParticlePtrs32 out, uint32_t *keys,
+                    uint32_t *keys_alt, uint32_t *idx, uint32_t *idx_alt, void *temp, int key_bits, BatchSort &J) {
+    J = BatchSort{};
+    if (n <= 0) return;
+    const SortPlan P = sort_plan(key_bits);
+    J.n = n;
+    J.ntiles = sort_tiles(n);
+    J.tile = tile;
+    J.nTx = (G.nx + tile - 1) / tile;
+    J.nTy = (G.ny + tile - 1) / tile;
+    J.sentinel = key_bits >= 32 ? 0xFFFFFFFFu : ((1u << key_bits) - 1u);
+    J.passes = P.passes;
+    int widest = 0;
+    J.counts = (uint32_t *)temp;
+    J.sums = J.counts + (int64_t)kSortMaxBins * J.ntiles;
+    // the ping-pong of run_passes
+    uint32_t *kin = keys, *vin = nullptr, *kout = keys_alt, *vout = idx_alt;
+    for (int p = 0; p < P.passes; p++) {
+        J.shift[p] = P.shift[p];
+        J.bits[p] = P.bits[p];
+        widest = P.bits[p] > widest ? P.bits[p] : widest;
+        J.kin[p] = kin;
+        J.vin[p] = vin;
+        J.kout[p] = kout;
+        J.vout[p] = vout;
+        uint32_t *nk = kin, *nv = kin == keys ? idx : idx_alt;
+        kin = kout;
+        vin = vout;
+        kout = nk;
+        vout = nv;
+    }
+    J.final_idx = vin;
+    J.nchunks = (((int64_t)1 << widest) * J.ntiles + kScanChunk - 1) / kScanChunk;
+    J.in = in;
+    J.out = out;
+}
+
+int64_t batch_sort_blocks(int kind, const BatchSort &J) {
+    if (J.n <= 0) return 0;
+    switch (kind) {
+    case BK_SORT_SLOT: return (J.n + kSortBlock - 1) / kSortBlock;
+    case BK_SORT_TILE: return J.ntiles;
+    case BK_SORT_SCAN: return J.nchunks;
+    }
+    return 0;
+}
+
+namespace {
+
+__device__ __forceinline__ int64_t scan_entries(const BatchSort &J, int p) {
+    return ((int64_t)1 << J.bits[p]) * J.ntiles;
+}
+
+__global__ __launch_bounds__(kSortBlock) void k_batch_sort_keys32(const BatchTable *__restrict__ T) {
+    const int64_t total = T->total[BK_SORT_SLOT];
+    for (int64_t lb = blockIdx.x; lb < total; lb += gridDim.x) {
+        const BatchRun32 &R = T->run[batch_run_of(T, BK_SORT_SLOT, lb)];
+        const BatchSort &J = R.sort;
+        sort_key_slot32(R.G, J.tile, J.nTx, J.nTy, J.sentinel, J.in, J.n, J.kin[0], R.counters,
+                        (lb - R.off[BK_SORT_SLOT]) * kSortBlock + threadIdx.x);
+    }
+}
+
+__global__ __launch_bounds__(kSortBlock) void k_batch_sort_upsweep(const BatchTable *__restrict__ T, int p) {
+    __shared__ uint32_t hist[kSortMaxBins];
+    const int64_t total = T->total[BK_SORT_TILE];
+    for (int64_t lb = blockIdx.x; lb < total; lb += gridDim.x) {
+        const BatchRun32 &R = T->run[batch_run_of(T, BK_SORT_TILE, lb)];
+        const BatchSort &J = R.sort;
+        if (p >= J.passes) continue;  // the same for the whole block
+        __syncthreads();              // the previous tile is done with hist
+        upsweep_tile(J.kin[p], J.n, J.shift[p], J.bits[p], J.ntiles, J.counts, lb - R.off[BK_SORT_TILE], hist);
+    }
+}
+
+__global__ __launch_bounds__(kSortBlock) void k_batch_scan_reduce(const BatchTable *__restrict__ T, int p) {
+    const int64_t total = T->total[BK_SORT_SCAN];
+    for (int64_t lb = blockIdx.x; lb < total; lb += gridDim.x) {
+        const BatchRun32 &R = T->run[batch_run_of(T, BK_SORT_SCAN, lb)];
+        const BatchSort &J = R.sort;
+        if (p >= J.passes) continue;
+        const int64_t m = scan_entries(J, p), c = lb - R.off[BK_SORT_SCAN];
+        if (c * kScanChunk >= m) continue;
+        scan_reduce_chunk(J.counts, m, J.sums, c);
+    }
+}
+
+// One block per run.
+__global__ __launch_bounds__(kScanTopBlock) void k_batch_scan_top(const BatchTable *__restrict__ T, int p) {
+    for (int r = blockIdx.x; r < T->nruns; r += gridDim.x) {
+        const BatchSort &J = T->run[r].sort;
+        if (J.n <= 0 || p >= J.passes) continue;
+        const int64_t m = scan_entries(J, p);
+        scan_top_sums(J.sums, (m + kScanChunk - 1) / kScanChunk);
+    }
+}
+
+__global__ __launch_bounds__(kSortBlock) void k_batch_scan_down(const BatchTable *__restrict__ T, int p) {
+    const int64_t total = T->total[BK_SORT_SCAN];
+    for (int64_t lb = blockIdx.x; lb < total; lb += gridDim.x) {
+        const BatchRun32 &R = T->run[batch_run_of(T, BK_SORT_SCAN, lb)];
+        const BatchSort &J = R.sort;
+        if (p >= J.passes) continue;
+        const int64_t m = scan_entries(J, p), c = lb - R.off[BK_SORT_SCAN];
+        if (c * kScanChunk >= m) continue;
+        scan_down_chunk(J.counts, m, J.sums, c);
+    }
+}
+
+template <bool FIRST>
+__global__ __launch_bounds__(kSortBlock) void k_batch_sort_downsweep(const BatchTable *__restrict__ T, int p) {
+    __shared__ DownLds L;
+    const int64_t total = T->total[BK_SORT_TILE];
+    for (int64_t lb = blockIdx.x; lb < total; lb += gridDim.x) {
+        const BatchRun32 &R = T->run[batch_run_of(T, BK_SORT_TILE, lb)];
+        const BatchSort &J = R.sort;
+        if (p >= J.passes) continue;
+        __syncthreads();  // the previous tile is done with L
+        const PassOut po{J.kout[p], J.vout[p]};
+        const int64_t t = lb - R.off[BK_SORT_TILE];
+        if (p == J.passes - 1)
+            downsweep_tile<FIRST, true, PassOut>(J.kin[p], J.vin[p], J.n, J.shift[p], J.bits[p], J.ntiles, J.counts,
+                                                 po, J.sentinel, R.counters, t, L);
+        else
+            downsweep_tile<FIRST, false, PassOut>(J.kin[p], J.vin[p], J.n, J.shift[p], J.bits[p], J.ntiles, J.counts,
+                                                  po, J.sentinel, R.counters, t, L);
+    }
+}
+
+__global__ __launch_bounds__(kSortBlock) void k_batch_sort_gather32(const BatchTable *__restrict__ T) {
+    const int64_t total = T->total[BK_SORT_SLOT];
+    for (int64_t lb = blockIdx.x; lb < total; lb += gridDim.x) {
+        const BatchRun32 &R = T->run[batch_run_of(T, BK_SORT_SLOT, lb)];
+        const BatchSort &J = R.sort;
+        gather_slot32(J.in, J.out, J.final_idx, J.n, (lb - R.off[BK_SORT_SLOT]) * kSortBlock + threadIdx.x);
+    }
+}
+
+// Persistent grids: 8 blocks per compute unit, 3 for the downsweep (40 KiB
+// of LDS each), one block per run for the scan of the chunk sums.
+constexpr int kBatchSortGrid = 256 * 8;
+constexpr int kBatchDownGrid = 256 * 3;
+
+}  // namespace
+
+void launch_batch_sort(const BatchTable *table, int passes, hipStream_t s) {
+    if (passes <= 0) return;
+    hipLaunchKernelGGL(k_batch_sort_keys32, dim3(kBatchSortGrid), dim3(kSortBlock), 0, s, table);
+    for (int p = 0; p < passes; p++) {
+        hipLaunchKernelGGL(k_batch_sort_upsweep, dim3(kBatchSortGrid), dim3(kSortBlock), 0, s, table, p);
+        hipLaunchKernelGGL(k_batch_scan_reduce, dim3(kBatchSortGrid), dim3(kSortBlock), 0, s, table, p);
+        hipLaunchKernelGGL(k_batch_scan_top, dim3(kMaxBatchRuns), dim3(kScanTopBlock), 0, s, table, p);
+        hipLaunchKernelGGL(k_batch_scan_down, dim3(kBatchSortGrid), dim3(kSortBlock), 0, s, table, p);
+        if (p == 0)
+            hipLaunchKernelGGL(k_batch_sort_downsweep<true>, dim3(kBatchDownGrid), dim3(kSortBlock), 0, s, table, p);
+        else
+            hipLaunchKernelGGL(k_batch_sort_downsweep<false>, dim3(kBatchDownGrid), dim3(kSortBlock), 0, s, table, p);
+    }
+    hipLaunchKernelGGL(k_batch_sort_gather32, dim3(kBatchSortGrid), dim3(kSortBlock), 0, s, table);
 }
 
 }  // namespace grpic

@@ -9,7 +9,9 @@ every admitted run by one cycle per iteration (``grpic_batch_step``: one
 replay of the captured graph of batched launches, each stage covering all
 active runs), and records each request's completion latency (arrival ->
 finished).  The initial particles of queued requests are generated on host
-threads ahead of admission.
+threads ahead of admission; while runs are stepping, a request whose
+particles are not ready yet waits for a later iteration instead of holding
+up the device.
 
 Requests may be urgent (priority 1).  Urgent requests are admitted before
 everything else; with preemption on, an urgent request that does not fit
@@ -153,6 +155,10 @@ def serve(requests, budget_bytes, max_slots, keep_ids=(), prefetch=8, log=None, 
                     if q["id"] not in futures:
                         futures[q["id"]] = pool.submit(request_particles, q)
                 r = waiting[0]
+                if active and not futures[r["id"]].done():
+                    # the payload is still being drawn: step the active runs
+                    # meanwhile instead of leaving the device idle
+                    break
                 if urgent and preempt:
                     make_room(r)
                 ta = time.perf_counter()
@@ -214,6 +220,30 @@ def serve(requests, budget_bytes, max_slots, keep_ids=(), prefetch=8, log=None, 
     }
 
 
+def one_by_one(requests):
+    """The same requests run alone, one after another, each as a single run
+    (``grpic_create``/``grpic_load_particles``/``grpic_step`` with its cycle
+    replayed as a captured graph), the reference for the batch's throughput.
+    The particles are drawn before the clock starts; each run's time covers
+    creation, loading, its steps and the final diagnostics.  Returns
+    particle-steps, seconds and particle-steps/s."""
+    total_ps = 0
+    total_s = 0.0
+    for r in requests:
+        parts = request_particles(r)
+        t0 = time.perf_counter()
+        run = R.Run(request_config(r))
+        for sp, (x, u) in enumerate(parts):
+            run.load(sp, x, u)
+        run.step(r["steps"])
+        run.diag()
+        total_s += time.perf_counter() - t0
+        total_ps += capi.grpic_particle_steps(run.h)
+        run.close()
+    return {"particle_steps": total_ps, "seconds": total_s,
+            "particle_steps_per_s": total_ps / total_s if total_s > 0 else 0.0}
+
+
 def main(argv=None):
     """Serve a seeded request mix and print its figures as one JSON line:
     python -m paper_0904_0232_amd.serve [--requests N] [--rate R] [--seed S]
@@ -227,9 +257,14 @@ def main(argv=None):
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--budget-gb", type=float, default=64.0)
     ap.add_argument("--slots", type=int, default=64)
+    ap.add_argument("--one-by-one", action="store_true",
+                    help="also run the same requests alone, one after another")
     args = ap.parse_args(argv)
-    res = serve(make_requests(args.requests, args.seed, args.rate), int(args.budget_gb * (1 << 30)), args.slots)
+    reqs = make_requests(args.requests, args.seed, args.rate)
+    res = serve(reqs, int(args.budget_gb * (1 << 30)), args.slots)
     res.pop("records")
+    if args.one_by_one:
+        res["one_by_one"] = one_by_one(reqs)
     print(json.dumps(res), flush=True)
 
 
