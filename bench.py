@@ -373,7 +373,8 @@ def rooflines(m, peak, with_traffic, workload, precision="fp64"):
 def serving(args):
     """Continuous batching of independent FP32-mixed runs with Poisson
     arrivals.  A saturated probe (32 requests arriving at once) measures the
-    loop's own capacity in particle-steps/s; the measured workload then
+    loop's own capacity in particle-steps/s, beside the same 32 requests run
+    alone one after another as single runs; the measured workload then
     arrives at 0.7 of that capacity."""
     from paper_0904_0232_amd import serve
     budget = int(args.serve_budget_gb * (1 << 30))
@@ -381,9 +382,12 @@ def serving(args):
     def work(reqs):
         return sum(2 * r["ppc"] * r["edge"] ** 3 * r["steps"] for r in reqs) / len(reqs)
 
-    probe = serve.serve(serve.make_requests(32, 1, 1e6), budget, args.serve_slots)
+    probe_reqs = serve.make_requests(32, 1, 1e6)
+    probe = serve.serve(probe_reqs, budget, args.serve_slots)
     capacity = probe["particle_steps_per_s"]
-    log("serving probe: %.4g particle-steps/s saturated" % capacity)
+    alone = serve.one_by_one(probe_reqs)
+    log("serving probe: %.4g particle-steps/s saturated; the same requests alone, one after another: %.4g" %
+        (capacity, alone["particle_steps_per_s"]))
     rate = 0.7 * capacity / work(serve.make_requests(args.serve_runs, 0, 1.0))
     reqs = serve.make_requests(args.serve_runs, 0, rate)
     res = serve.serve(reqs, budget, args.serve_slots)
@@ -395,6 +399,9 @@ def serving(args):
         "runs_per_s": res["runs_per_s"],
         "particle_steps_per_s": res["particle_steps_per_s"],
         "saturated_particle_steps_per_s": capacity,
+        "saturated_host_s": probe["host_s"],
+        "one_by_one_particle_steps_per_s": alone["particle_steps_per_s"],
+        "saturated_vs_one_by_one": capacity / alone["particle_steps_per_s"],
         "makespan_s": res["makespan_s"],
         "iterations": res["iterations"],
         "host_s": res["host_s"],
@@ -606,7 +613,9 @@ def precision_study(workload, checkpoints=(1, 10, 100, 300, 1000), modes=("geode
     C-A is the whole FP32-mixed error; C-B isolates the FP32 arithmetic of
     the steps; B-A is the control: how far FP64 itself carries a perturbation
     of the size of one FP32 rounding of the start (the dynamics' own
-    divergence).  "geodesic" runs test particles with no field, "push" test
+    divergence).  At every checkpoint the particles' current is also
+    coarse-grained over 8^3-cell blocks (per species and net, from their
+    coordinate velocities) and compared in L2.  "geodesic" runs test particles with no field, "push" test
     particles in the frozen initial fields, "cycle" the self-consistent cycle.  A particle is "regular" while its A
     path stays inside the grid and outside R = 3m."""
     import numpy as np
@@ -645,6 +654,39 @@ def precision_study(workload, checkpoints=(1, 10, 100, 300, 1000), modes=("geode
         return {"l2_rel": float(np.linalg.norm(J2 - J1) / np.linalg.norm(J1)),
                 "max_rel": float(np.abs(J2 - J1).max() / np.abs(J1).max())}
 
+    def coarse_current(P, mask=None, block=8):
+        """Per species and net: sum over the particles a cycle would keep
+        (alive, finite, inside the grid, outside r_rm; push-only steps do not
+        remove particles), and in `mask` when given, in each block^3-cell
+        block of q c u^i / u^4 (c = 1)."""
+        x, u, sp = P
+        n = w["n"]
+        nb = n // block
+        with np.errstate(invalid="ignore", over="ignore"):
+            fin = np.isfinite(x).all(0) & np.isfinite(u).all(0)
+            xs = np.where(fin, x, -1.0)
+            inside = np.all((xs >= 0) & (xs < n), axis=0)
+            X, Y, Z = xs - n / 2.0
+            b = X * X + Y * Y + Z * Z - w["a"] ** 2
+            r = np.sqrt(0.5 * (b + np.sqrt(b * b + 4.0 * w["a"] ** 2 * Z * Z)))
+        kept = (sp != 255) & fin & inside & (r > w["r_rm"])
+        if mask is not None:
+            kept &= mask
+        idx = np.clip(np.floor(xs[:, kept] / block).astype(np.int64), 0, nb - 1)
+        flat = (idx[2] * nb + idx[1]) * nb + idx[0]
+        v = u[:3, kept] / u[3, kept]
+        out = np.zeros((len(w["species"]) + 1, 3, nb ** 3))
+        for s_, (q, _) in enumerate(w["species"]):
+            sel = sp[kept] == s_
+            for i in range(3):
+                out[s_, i] = np.bincount(flat[sel], weights=q * v[i, sel], minlength=nb ** 3)
+        out[-1] = out[:-1].sum(axis=0)
+        return out
+
+    def cdiff(J1, J2):
+        return {k: float(np.linalg.norm(J2[s_] - J1[s_]) / np.linalg.norm(J1[s_]))
+                for s_, k in enumerate(("electrons", "ions", "net"))}
+
     out = {"workload": workload, "particles": ntot}
     for mode in modes:
         b0 = 0.0 if mode == "geodesic" else w["B0"]
@@ -679,7 +721,14 @@ def precision_study(workload, checkpoints=(1, 10, 100, 300, 1000), modes=("geode
                    "fp32_vs_fp64": diff(st["A"], st["C"], regular),
                    "fp32_arith": diff(st["B"], st["C"], regular),
                    "fp64_control": diff(st["A"], st["B"], regular)}
-            del st
+            Jc = {k: coarse_current(v) for k, v in st.items()}
+            row["coarse_J_8cells"] = {"fp32_vs_fp64": cdiff(Jc["A"], Jc["C"]), "fp32_arith": cdiff(Jc["B"], Jc["C"]),
+                                      "fp64_control": cdiff(Jc["A"], Jc["B"])}
+            Jc = {k: coarse_current(v, regular) for k, v in st.items()}
+            row["coarse_J_8cells_regular"] = {"fp32_vs_fp64": cdiff(Jc["A"], Jc["C"]),
+                                              "fp32_arith": cdiff(Jc["B"], Jc["C"]),
+                                              "fp64_control": cdiff(Jc["A"], Jc["B"])}
+            del st, Jc
             if mode == "cycle":
                 J = {k: r.fields("J") for k, r in runs.items()}
                 row["J_fp32_vs_fp64"] = jdiff(J["A"], J["C"])

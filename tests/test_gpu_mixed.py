@@ -184,6 +184,118 @@ def test_mixed_torus_geodesic_1000_steps():
     assert frac > 0.95
 
 
+def _ks_radius(a, x, y, z):
+    b = x * x + y * y + z * z - a * a
+    return np.sqrt(0.5 * (b + np.sqrt(b * b + 4.0 * a * a * z * z)))
+
+
+def _coarse_current(x, u, sp, w, mask, block=8):
+    """Current of the particles in `mask` coarse-grained over blocks of
+    block^3 cells: per species s, J_s^i(b) = sum over those particles in
+    block b of q_s c u^i / u^4 (c = 1), and the net current; shape
+    (nspecies + 1, 3, nblocks)."""
+    n = w["n"]
+    nb = n // block
+    with np.errstate(invalid="ignore", over="ignore"):
+        fin = np.isfinite(x).all(0) & np.isfinite(u).all(0)
+        xs = np.where(fin, x, -1.0)
+        inside = np.all((xs >= 0) & (xs < n), axis=0)
+    kept = mask & (sp != O.DEAD) & fin & inside
+    idx = np.clip(np.floor(xs[:, kept] / block).astype(np.int64), 0, nb - 1)
+    flat = (idx[2] * nb + idx[1]) * nb + idx[0]
+    v = u[:3, kept] / u[3, kept]
+    out = np.zeros((len(w["species"]) + 1, 3, nb ** 3))
+    for s, (q, _) in enumerate(w["species"]):
+        sel = sp[kept] == s
+        for i in range(3):
+            out[s, i] = np.bincount(flat[sel], weights=q * v[i, sel], minlength=nb ** 3)
+    out[-1] = out[:-1].sum(axis=0)
+    return out
+
+
+def test_mixed_torus_frozen_field_1000_steps():
+    """Test particles of the torus workload in the frozen initial field
+    (B_z = 0.1) for 1000 RK4 steps, 100,000 per species.  Three runs keep
+    particle identity: A FP64 from the exact inputs, B FP64 from the inputs
+    rounded to the mixed representation, C FP32-mixed.  The field dominates
+    gravity here (the electrons' gyration radius is about 4.5 cells and
+    their E x B drift tens of cells over the run), so most particles reach
+    the hole or the faces, where nothing removes them in push-only steps;
+    "regular" orbits are those whose FP64 path stays in the grid and
+    outside 3m throughout (under 1% of them).  C - B (the FP32 arithmetic
+    of the steps), over the regular orbits: at least 80% within 1e-4 and
+    median below 3e-5 (about 45 radians of gyration phase at FP32's
+    relative rounding); the current of the regular orbits of each species
+    that has at least 200 of them, coarse-grained over 8^3-cell blocks,
+    within 1e-4 in L2 at step 1000.
+    C - A and the control B - A (how far FP64 carries one FP32 rounding of
+    the start) are printed, and so is the coarse-grained current of every
+    particle a cycle would keep (alive, in the grid, outside r_rm), which
+    the plunging orbits dominate."""
+    w, rb, r32 = _torus_runs(100000, 0.1, True)
+    _, ra, r32b = _torus_runs(100000, 0.1, False)
+    r32b.close()
+    runs = {"A": ra, "B": rb, "C": r32}
+    cen = np.full(3, w["n"] / 2.0)
+    regular = None
+    for block in range(10):
+        for r in runs.values():
+            r.push_only(100)
+        xa, ua, sa = ra.particles()
+        with np.errstate(invalid="ignore"):
+            R = np.sqrt(((xa - cen[:, None]) ** 2).sum(0))
+            ok = np.all((xa >= 0) & (xa < w["n"]), axis=0) & (R > 3.0 * w["m"]) & np.isfinite(ua).all(0)
+        ok &= sa != O.DEAD
+        regular = ok if regular is None else (regular & ok)
+    st = {k: r.particles() for k, r in runs.items()}
+
+    def err(P, Q):
+        (x1, u1, s1), (x2, u2, s2) = P, Q
+        both = regular & (s1 != O.DEAD) & (s2 != O.DEAD)
+        with np.errstate(invalid="ignore", over="ignore"):
+            ex = (np.abs(x2 - x1) / np.maximum(np.abs(x1), 1.0)).max(axis=0)[both]
+            eu = (np.abs(u2 - u1) / np.maximum(np.abs(u1), 1.0)).max(axis=0)[both]
+        e = np.maximum(ex, eu)
+        return np.where(np.isfinite(e), e, np.inf)  # a non-finite particle counts as far off
+
+    def kept_mask(x, u, sp):
+        with np.errstate(invalid="ignore", over="ignore"):
+            xs = np.where(np.isfinite(x).all(0), x, -1.0)
+            return _ks_radius(w["a"], *(xs - w["n"] / 2.0)) > w["r_rm"]
+
+    Jreg = {k: _coarse_current(*v, w, regular) for k, v in st.items()}
+    Jall = {k: _coarse_current(*v, w, kept_mask(*v)) for k, v in st.items()}
+
+    def jerr(J, a, b):
+        return [float(np.linalg.norm(J[b][s] - J[a][s]) / np.linalg.norm(J[a][s])) for s in range(3)]
+
+    e = {}
+    for name, (a, b) in (("fp32 arithmetic C-B", ("B", "C")), ("FP32-mixed C-A", ("A", "C")),
+                         ("FP64 control B-A", ("A", "B"))):
+        e[name] = err(st[a], st[b])
+        say("torus frozen field, 1000 steps, %s: %d regular of %d, median %.2e p99 %.2e, within 1e-4 %.4f; "
+            "coarse J L2 (electrons, ions, net) of the regular orbits %s, of every kept particle %s" % (
+                name, e[name].size, regular.size, np.median(e[name]), np.quantile(e[name], 0.99),
+                float((e[name] < 1e-4).mean()), ["%.2e" % v for v in jerr(Jreg, a, b)],
+                ["%.2e" % v for v in jerr(Jall, a, b)]))
+    arith = e["fp32 arithmetic C-B"]
+    sp = st["A"][2]
+    nreg = [int((regular & (sp == s)).sum()) for s in range(2)]
+    say("regular orbits per species (electrons, ions): %s" % nreg)
+    assert regular.sum() >= 500
+    assert np.median(arith) < 3e-5
+    assert float((arith < 1e-4).mean()) > 0.80
+    je = jerr(Jreg, "B", "C")
+    # the current of a species is compared where it has enough regular
+    # orbits to be a current (the electrons' gyration and drift leave few)
+    checked = [s for s in range(2) if nreg[s] >= 200]
+    assert checked
+    for s in checked:
+        assert je[s] < 1e-4, (s, je)
+    for r in runs.values():
+        r.close()
+
+
 def test_mixed_torus_current_one_step():
     """One self-consistent cycle of the torus workload (1M particles per
     species, field B_z = 0.1): the FP32-mixed current against FP64 from the
