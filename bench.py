@@ -268,10 +268,13 @@ def window_errors(w, windows, state1, n_per_species):
     return {"x_rel": ex_max, "u_rel": eu_max, "particles": count, "same_removals": same}
 
 
-def measure(workload, precision, steps, warmup, sort_every, parts, first_cycle_state=False, tile=4):
-    """Time `steps` cycles of one run; returns the figures of the timed
-    region (and, with first_cycle_state, the particle state after the first
-    warmup cycle, before any cell sort)."""
+def measure(workload, precision, steps, warmup, sort_every, parts, first_cycle_state=False, tile=4, repeat=True):
+    """Time `steps` cycles of one run with HIP events around each kernel
+    group; returns the figures of the timed region (and, with
+    first_cycle_state, the particle state after the first warmup cycle,
+    before any cell sort).  With repeat, the state after the warm-up is saved
+    and the same cycles are timed twice more without events: replayed as
+    captured graphs, and launched one by one."""
     import torch
     from paper_0904_0232_amd import capi, inputs
     from paper_0904_0232_amd import run as R
@@ -297,6 +300,7 @@ def measure(workload, precision, steps, warmup, sort_every, parts, first_cycle_s
         capi.grpic_step(h, warmup)
     torch.cuda.synchronize()
     ps0 = capi.grpic_particle_steps(h)
+    state = run.save_state() if repeat else None
     capi.grpic_set_timing(h, True)
     capi.grpic_read_timing(h)  # reset
     torch.cuda.synchronize()
@@ -307,26 +311,36 @@ def measure(workload, precision, steps, warmup, sort_every, parts, first_cycle_s
     timers = capi.grpic_read_timing(h)
     capi.grpic_set_timing(h, False)
     ps1 = capi.grpic_particle_steps(h)
-    # the same number of cycles again without events: each cycle's kernels
-    # replay as one captured graph
-    torch.cuda.synchronize()
-    g0 = time.perf_counter()
-    capi.grpic_step(h, steps)
-    torch.cuda.synchronize()
-    g1 = time.perf_counter()
-    ps2 = capi.grpic_particle_steps(h)
     d = run.diag()
-    run.close()
     wall = t1 - t0
     psteps = ps1 - ps0
+    # the same cycles again from the same state, without kernel events: once
+    # with each cycle's kernels replayed as one captured graph, once launched
+    # one by one
+    again = {}
+    if state is not None:
+        for name, graphs in (("graphs", True), ("launches", False)):
+            run.load_state(state)
+            capi.grpic_set_graphs(h, graphs)
+            torch.cuda.synchronize()
+            g0 = time.perf_counter()
+            capi.grpic_step(h, steps)
+            torch.cuda.synchronize()
+            g1 = time.perf_counter()
+            again[name] = {"value": psteps / (g1 - g0), "ms_per_step": (g1 - g0) * 1e3 / steps}
+            assert capi.grpic_particle_steps(h) == ps1, "a repeat of the timed cycles did other work"
+        del state
+    run.close()
+    what = {k: "the timed cycles again from the same state without kernel events, " + v
+            for k, v in (("graphs", "each cycle's kernels replayed as one captured graph"),
+                         ("launches", "kernels launched one by one"))}
     return {
         "w": w, "ntot": ntot, "wall": wall, "psteps": psteps, "value": psteps / wall,
         "ms_per_step": wall * 1e3 / steps, "timers": timers,
         "kernel_ms_per_launch": {k: (v[0] / max(v[1], 1)) for k, v in timers.items()},
         "live_end": int(sum(d["n_alive"])), "state1": state1,
-        "graphs": {"value": (ps2 - ps1) / (g1 - g0), "ms_per_step": (g1 - g0) * 1e3 / steps,
-                   "what": "the next %d cycles with each cycle's kernels replayed as one captured graph, "
-                           "without kernel events" % steps},
+        "graphs": dict(again["graphs"], what=what["graphs"]) if again else None,
+        "launches": dict(again["launches"], what=what["launches"]) if again else None,
         "deposit_blocks": {"lds": d["deposit_blocks_lds"], "global": d["deposit_blocks_global"]},
     }
 
@@ -829,7 +843,7 @@ def main():
             "live_particles_end": m64["live_end"],
         },
         "kernel_ms_per_launch": m64["kernel_ms_per_launch"],
-        "graph_replay": m64["graphs"],
+        "graph_replay": m64["graphs"], "launches_no_events": m64["launches"],
         "deposit_blocks": m64["deposit_blocks"],
         "roofline": roofline,
         "rooflines": rooflines64,
@@ -848,6 +862,7 @@ def main():
             "near-horizon metric and diagnostics)", "kernel_ms_per_launch": m32["kernel_ms_per_launch"],
             "speedup_vs_fp64": m32["value"] / m64["value"], "live_particles_end": m32["live_end"],
             "deposit_blocks": m32["deposit_blocks"], "graph_replay": m32["graphs"],
+            "launches_no_events": m32["launches"],
         }
         line["fp32_mixed"]["roofline"], line["fp32_mixed"]["rooflines"] = rooflines(m32, FP32_PEAK_TFLOPS, True,
                                                                                       args.workload, "fp32")
@@ -868,7 +883,7 @@ def main():
                          tile=args.tile)
             log("%s %s: %.4g particle-steps/s" % (args.secondary, prec, ms["value"]))
             sec[prec] = {"value": ms["value"], "ms_per_step": ms["ms_per_step"], "steps": args.secondary_steps,
-                         "graph_replay": ms["graphs"],
+                         "graph_replay": ms["graphs"], "launches_no_events": ms["launches"],
                          "kernel_ms_per_launch": ms["kernel_ms_per_launch"], "live_particles_end": ms["live_end"],
                          "roofline": rooflines(ms, FP64_PEAK_TFLOPS if prec == "fp64" else FP32_PEAK_TFLOPS, False,
                                                args.secondary)[0]}
