@@ -352,9 +352,11 @@ __device__ __forceinline__ void relax_outer_at(const Grid &G, const FieldPtrsT<T
         }
 }
 
-// Node tensor F^a_b = F^{ag} g_{gb} from the node pair completed by S.
+// Node tensor F^a_b = F^{ag} g_{gb} from the node pair completed by S, row
+// a at o[4a .. 4a+3].
 template <typename T>
-__device__ __forceinline__ void node_tensor_at(const Grid &G, const Hole &h, const FieldPtrsT<T> &F, int64_t id) {
+__device__ __forceinline__ void node_tensor_values(const Grid &G, const Hole &h, const FieldPtrsT<T> &F, int64_t id,
+                                                   T o[16]) {
     int i, j, k;
     node_ijk(G, id, i, j, k);
     const T *D[3] = {F.D[0], F.D[1], F.D[2]};
@@ -377,13 +379,19 @@ __device__ __forceinline__ void node_tensor_at(const Grid &G, const Hole &h, con
     }
     T g[10];
     for (int q = 0; q < 10; q++) g[q] = (T)gd[q];
-    T *o = F.node + 16 * id;
     for (int a = 0; a < 4; a++)
         for (int b = 0; b < 4; b++) {
             T s = (T)0;
             for (int c = 0; c < 4; c++) s += Fu[a][c] * g[sym4(c, b)];
             o[a * 4 + b] = s;
         }
+}
+
+template <typename T>
+__device__ __forceinline__ void node_tensor_at(const Grid &G, const Hole &h, const FieldPtrsT<T> &F, int64_t id) {
+    T o[16];
+    node_tensor_values<T>(G, h, F, id, o);
+    for (int q = 0; q < 16; q++) F.node[16 * id + q] = o[q];
 }
 
 // Single-run kernels: one thread per index.
@@ -428,10 +436,25 @@ __global__ void k_relax_outer(Grid G, FieldPtrsT<T> F, double L, double damp) {
     int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (id < G.nnodes()) relax_outer_at(G, F, L, damp, id);
 }
+// The block's nodes are contiguous in the output, 16 values each: the
+// values go through LDS so that consecutive lanes store consecutive
+// addresses (one thread's 16 values are 64 or 128 bytes apart from the
+// next thread's).
+constexpr int kNodeTensorBlock = 128;
 template <typename T>
-__global__ void k_node_tensor(Grid G, Hole h, FieldPtrsT<T> F) {
-    int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (id < G.nnodes()) node_tensor_at<T>(G, h, F, id);
+__global__ __launch_bounds__(kNodeTensorBlock) void k_node_tensor(Grid G, Hole h, FieldPtrsT<T> F) {
+    __shared__ T tile[kNodeTensorBlock * 17];  // row stride 17: no bank conflicts
+    const int64_t first = (int64_t)blockIdx.x * kNodeTensorBlock;
+    const int64_t id = first + threadIdx.x;
+    const int64_t nn = G.nnodes();
+    if (id < nn) {
+        T o[16];
+        node_tensor_values<T>(G, h, F, id, o);
+        for (int q = 0; q < 16; q++) tile[threadIdx.x * 17 + q] = o[q];
+    }
+    __syncthreads();
+    const int64_t count = (nn - first < kNodeTensorBlock ? nn - first : kNodeTensorBlock) * 16;
+    for (int e = threadIdx.x; e < count; e += kNodeTensorBlock) F.node[16 * first + e] = tile[(e >> 4) * 17 + (e & 15)];
 }
 
 // Initial fields: uniform F (contravariant or covariant B0) lowered/raised
@@ -622,7 +645,8 @@ void launch_batch_field(int op, const BatchTable *table, int it, int grid, hipSt
 }
 
 template <typename T> void launch_node_tensor(const Grid &G, const Hole &h, FieldPtrsT<T> &F, hipStream_t s) {
-    hipLaunchKernelGGL(k_node_tensor<T>, dim3(nblk(G.nnodes(), 128)), dim3(128), 0, s, G, h, F);
+    hipLaunchKernelGGL(k_node_tensor<T>, dim3(nblk(G.nnodes(), kNodeTensorBlock)), dim3(kNodeTensorBlock), 0, s, G, h,
+                       F);
 }
 
 #define GRPIC_FIELD_INSTANTIATE(T)                                                                          \

@@ -114,6 +114,53 @@ def test_served_run_matches_oracle():
         assert abs(dg[k] - do[k]) <= 1e-5 * max(abs(do[k]), 1e-30), k
 
 
+def test_batched_sorts_of_runs_with_different_pass_counts():
+    """Two runs whose cell sorts need different numbers of radix passes
+    (16^3: 13-bit keys, two passes; 64^3: 19-bit keys, three passes) fall due
+    in the same iterations, so the batched sort launches of one captured
+    iteration serve both, the smaller run skipping the third pass.  Each run
+    ends bit-identical to the same request stepped alone through grpic_step
+    (13 cycles: sorts after cycles 5 and 10)."""
+    from paper_0904_0232_amd import capi, serve
+    from paper_0904_0232_amd import run as R
+    reqs = [dict(_reqs(1, seed=31, edges=(16,))[0], ppc=2), dict(_reqs(1, seed=37, edges=(64,))[0], ppc=2)]
+    nsteps = 13
+
+    def cfg(r):
+        c = serve.request_config(r)
+        c.sort_every = 5
+        return c
+
+    b = capi.grpic_batch_create(1 << 35, 4)
+    parts = [serve.request_particles(r) for r in reqs]
+    rids = [capi.grpic_batch_submit(b, cfg(r), nsteps, p, keep_state=True) for r, p in zip(reqs, parts)]
+    assert None not in rids
+    it = 0
+    while any(capi.grpic_batch_poll(b, rid)[0] == capi.RUN_ACTIVE for rid in rids):
+        capi.grpic_batch_step(b)
+        it += 1
+    assert it == nsteps
+    for r, p, rid in zip(reqs, parts, rids):
+        st, done, dg, ns, ps = capi.grpic_batch_poll(b, rid)
+        assert st == capi.RUN_DONE and done == nsteps
+        xb, ub, sb = capi.grpic_batch_dump(b, rid, ns)
+        run = R.Run(cfg(r))
+        for sp, (x, u) in enumerate(p):
+            run.load(sp, x, u)
+        run.step(nsteps)
+        de = run.diag()
+        xe, ue, se = run.particles()
+        run.close()
+        live = se != O.DEAD
+        say("edge %d: %d slots, %d live; batch vs alone identical: %s" %
+            (r["edge"], ns, int(live.sum()), np.array_equal(sb, se)))
+        assert np.array_equal(sb, se)
+        assert np.array_equal(xb[:, live], xe[:, live]) and np.array_equal(ub[:, live], ue[:, live])
+        for k in ("n_alive", "energy_particles", "lz_particles", "energy_field"):
+            assert dg[k] == de[k], k
+    capi.grpic_batch_destroy(b)
+
+
 def test_result_is_the_same_alone_and_in_the_mix():
     from paper_0904_0232_amd import serve
     reqs = _reqs(6, seed=5, rate=200.0)
