@@ -298,3 +298,28 @@ def test_outer_layer_absorbs_a_vacuum_pulse():
     frozen, absorbed = _pulse_energy(0.0), _pulse_energy(6.0)
     assert frozen > 0.5, frozen          # the frozen faces reflect it back into the box
     assert absorbed < 0.2 * frozen, (absorbed, frozen)
+
+
+def test_state_transfer_reproduces_a_cycle():
+    """D, B and the particle slots are the whole state a cycle carries: a
+    second oracle given them (after initialising its own reference fields)
+    advances bit-identically.  The GPU parity tests that start the oracle
+    from a GPU-evolved state rely on this."""
+    p = O.make_params(16, m=1.5, a=1.2, dt=0.5, species=((-0.02, 0.02), (0.02, 0.4)))
+    g = np.random.default_rng(9)
+    x = g.uniform(2.0, 14.0, (3, 400))
+    a = O.Sim(p, 800)
+    a.init_fields([0.0, 0.0, 0.05])
+    a.load(0, x, g.normal(0.0, 0.1, (3, 400)))
+    a.load(1, x, g.normal(0.0, 0.02, (3, 400)))
+    a.step(3)
+    b = O.Sim(p, 800)
+    b.init_fields([0.0, 0.0, 0.05])
+    b.set_fields(a.get("D"), a.get("B"))
+    b.set_particles(*a.particles())
+    a.step(2)
+    b.step(2)
+    for u, v in zip(a.particles(), b.particles()):
+        assert np.array_equal(u, v)
+    for f in ("D", "B", "J"):
+        assert np.array_equal(a.get(f), b.get(f)), f
