@@ -179,6 +179,70 @@ def test_schwarzschild32_parity_every_step():
     assert abs(do["mass_shell_residual_max"] - dg["mass_shell_residual_max"]) < 1e-12
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_kerr64_one_cycle_parity_from_evolved_states(precision):
+    """The 64^3 Kerr a = 0.95m workload at its full 4,194,304 particles,
+    from states the GPU itself evolved: after 20 and after 40 cycles (cell
+    sorts every 5 cycles, removals at the hole and the faces, the fields
+    developed), the oracle takes the GPU's D, B and every particle slot, and
+    both advance one cycle.  Particles, J, B and D are compared element by
+    element: FP64 at the parity bar; FP32-mixed particles and B within 1e-5
+    (max norm).  The FP32-mixed current: a particle that ends within an FP32
+    rounding of a cell face can land in the other cell than in FP64, and the
+    zigzag relay point jumps there (mid-chord inside one cell, the face when
+    the chord crosses it), so that particle's share of J differs at the
+    scale of its own flux.  J and D are therefore compared in L2 within
+    1e-5 plus 1e-4 per particle whose end cell differs (counted)."""
+    from paper_0904_0232_amd import capi, inputs
+    from paper_0904_0232_amd import run as R
+    w = inputs.workload_params("kerr64")
+    P = params(w["n"], m=w["m"], a=w["a"], dt=w["dt"], B0=(0.0, 0.0, w["B0"]), species=w["species"],
+               r_rm=w["r_rm"])
+    parts = inputs.workload_particles("kerr64", seed=0)
+    ntot = sum(x.shape[1] for _, x, _ in parts)
+    cfg = R.make_config(P["n"], m=P["m"], a=P["a"], dt=P["dt"], B0=P["B0"], species=P["species"], r_rm=P["r_rm"],
+                        sort_every=5, capacity=ntot, fp_bits=FPB,
+                        precision=capi.FP32_MIXED if precision == "fp32" else capi.FP64)
+    r = R.Run(cfg)
+    for sp, x, uc in parts:
+        r.load(sp, x, uc)
+    done = 0
+    for target in (20, 40):
+        say("case kerr64 %s: GPU cycles to %d" % (precision, target))
+        r.step(target - done)
+        done = target
+        x, u, sp = r.particles()
+        p, s = oracle_sim(P, x.shape[1])
+        s.set_fields(r.fields("D"), r.fields("B"))
+        s.set_particles(x, u, sp)
+        live0 = int((sp != O.DEAD).sum())
+        s.step(1)
+        r.step(1)
+        done += 1
+        tag = "kerr64 %s from cycle %d (%d live)" % (precision, target, live0)
+        Jg, Jo = r.fields("J"), s.get("J")
+        Dg, Do = r.fields("D"), s.get("D")
+        if precision == "fp64":
+            _cmp_particles(s, r, tag=tag)
+            _cmp_field(Jg, Jo, "J", abs_floor=_j_floor(P, 256))
+            _cmp_field(r.fields("B"), s.get("B"), "B")
+            _cmp_field(Dg, Do, "D", abs_floor=4 * np.pi * P["dt"] * _j_floor(P, 256))
+        else:
+            _cmp_particles(s, r, tol=1e-5, tag=tag)
+            _cmp_field(r.fields("B"), s.get("B"), "B", tol=1e-5)
+            xg, _, sg = r.particles()
+            xo, _, so = s.particles()
+            both = (sg != O.DEAD) & (so != O.DEAD)
+            flips = int(np.any(np.floor(xg[:, both]) != np.floor(xo[:, both]), axis=0).sum())
+            for name, a, b in (("J", Jg, Jo), ("D", Dg, Do)):
+                l2 = float(np.linalg.norm(a - b) / np.linalg.norm(b))
+                mx = float(np.abs(a - b).max() / np.abs(b).max())
+                say(name, "L2 err %.2e, max err %.2e of max; particles ending in another cell: %d" % (l2, mx, flips))
+                assert l2 < 1e-5 + 1e-4 * flips, (name, l2, flips)
+        del s
+    r.close()
+
+
 def _sample_inputs(parts, sp_gpu, per_species, rng):
     """Pick per_species inputs of each species that the GPU kept; returns the
     picked (species, x, ucov) sub-arrays and the GPU slots they occupy (the
