@@ -122,6 +122,7 @@ __device__ __forceinline__ double stage_gamma(const PushParams &P, double u4, do
 
 constexpr int kPushBlock = 256;
 constexpr int kPushLdsNodes = 272;  // 38 KiB of padded node tensor per block, four blocks per CU
+constexpr int kStageInFlight = 8;   // node pieces per thread in flight while the box is staged
 
 // Stage, once per push, the node box of the cells the block's live lanes
 // start in (cell c, nodes c .. c+1), widened by one cell on every side when
@@ -165,10 +166,23 @@ __device__ __forceinline__ void stage_box(const Grid &G, const double *__restric
         const double2 *src = reinterpret_cast<const double2 *>(node);
         const int nb0 = B.n[0], nb01 = B.n[0] * B.n[1];
         const float inv0 = __builtin_amdgcn_rcpf((float)nb0), inv01 = __builtin_amdgcn_rcpf((float)nb01);
-        for (int q = tid; q < count[e] * 8; q += kPushBlock) {
-            const int l = q >> 3, part = q & 7;
-            const int lk = small_div(l, inv01), r = l - lk * nb01, lj = small_div(r, inv0), li = r - lj * nb0;
-            snode[kNodeStride2 * l + part] = src[8 * G.node(B.lo[0] + li, B.lo[1] + lj, B.lo[2] + lk) + part];
+        // kStageInFlight pieces per thread are read before any is stored, so
+        // the copy takes one or two memory round trips instead of one per piece
+        const int total = count[e] * 8;
+        for (int q0 = tid; q0 < total; q0 += kPushBlock * kStageInFlight) {
+            double2 v[kStageInFlight];
+#pragma unroll
+            for (int t = 0; t < kStageInFlight; t++) {
+                const int q = q0 + t * kPushBlock < total ? q0 + t * kPushBlock : total - 1;
+                const int l = q >> 3, part = q & 7;
+                const int lk = small_div(l, inv01), r = l - lk * nb01, lj = small_div(r, inv0), li = r - lj * nb0;
+                v[t] = src[8 * G.node(B.lo[0] + li, B.lo[1] + lj, B.lo[2] + lk) + part];
+            }
+#pragma unroll
+            for (int t = 0; t < kStageInFlight; t++) {  // a clamped slot rewrites piece total - 1 with its own value
+                const int q = q0 + t * kPushBlock < total ? q0 + t * kPushBlock : total - 1;
+                snode[kNodeStride2 * (q >> 3) + (q & 7)] = v[t];
+            }
         }
     }
     __syncthreads();
@@ -187,21 +201,26 @@ __global__ __launch_bounds__(kPushBlock, 4) void k_push(PushParams P, Species cS
                                                      unsigned long long *counters) {
     __shared__ double2 snode[kPushLdsNodes * kNodeStride2];
     __shared__ int sred[6][kPushBlock / 64];
+    __shared__ double sqm[kMaxSpecies];
     const int tid = threadIdx.x;
-    const int64_t id = (int64_t)blockIdx.x * kPushBlock + tid;
+    const int64_t id = (int64_t)blockIdx.x * kPushBlock + tid, idc = id < P.n ? id : P.n - 1;
     int clamps = 0;
-    const uint8_t sp = id < P.n ? in.sp[id] : kDead;
+    // the slot's species and state are read together (slots past n read
+    // slot n - 1 and count as dead); q/m comes from the block's table
+    const uint8_t sp_in = in.sp[idc];
+    double X0[3], U0[4];
+    for (int q = 0; q < 3; q++) X0[q] = in.x[q][idc];
+    for (int q = 0; q < 4; q++) U0[q] = in.u[q][idc];
+    if (tid == 0)
+#pragma unroll
+        for (int q = 0; q < kMaxSpecies; q++) sqm[q] = cS.qm[q];
+    const uint8_t sp = id < P.n ? sp_in : kDead;
     const bool live = sp != kDead;
     const unsigned long long ballot = __ballot(live);
     if ((tid & 63) == 0 && ballot)
         atomicAdd(&counters[pushed_index(blockIdx.x)], (unsigned long long)__popcll(ballot));
-    double X0[3] = {0.0, 0.0, 0.0}, U0[4] = {0.0, 0.0, 0.0, 0.0};
-    double qm = 0.0;
-    if (live) {
-        qm = cS.qm[sp];
-        for (int q = 0; q < 3; q++) X0[q] = in.x[q][id];
-        for (int q = 0; q < 4; q++) U0[q] = in.u[q][id];
-    }
+    for (int q = 0; q < 3; q++) X0[q] = live ? X0[q] : 0.0;
+    for (int q = 0; q < 4; q++) U0[q] = live ? U0[q] : 0.0;
     double Xs[3] = {X0[0], X0[1], X0[2]};
     double Us[4] = {U0[0], U0[1], U0[2], U0[3]};
     double Sx[3] = {0.0, 0.0, 0.0}, Su[4] = {0.0, 0.0, 0.0, 0.0};
@@ -212,6 +231,7 @@ __global__ __launch_bounds__(kPushBlock, 4) void k_push(PushParams P, Species cS
         gather_cell(P.G, X0, c0);
         stage_box(P.G, node, live, c0, snode, sred, B);
     }
+    const double qm = live ? sqm[sp] : 0.0;  // the table is written before the box's barriers
 #pragma unroll 1
     for (int st = 0; st < 4; st++) {
         int c[3];
@@ -578,23 +598,34 @@ __global__ __launch_bounds__(kDepBlock) void k_deposit(DepCtx D, Species cS, dou
                                                        unsigned long long *counters) {
     __shared__ unsigned long long sm[kDepLds];
     __shared__ int sred[6][kDepBlock / 64];
+    __shared__ double sQ[kMaxSpecies];
     const int tid = threadIdx.x;
     const int64_t base = (int64_t)blockIdx.x * (kDepBlock * kDepPPT);
+    // Every slot's chord is read at once (slots past n read slot n - 1 and
+    // count as dead), so the loads are in flight together.
     uint8_t SP[kDepPPT];
+    double P1[kDepPPT][3], P2[kDepPPT][3];
+#pragma unroll
+    for (int p = 0; p < kDepPPT; p++) {
+        const int64_t id = base + dep_slot(p, tid), idc = id < n ? id : n - 1;
+        const uint8_t s = xo.sp[idc];
+        SP[p] = id < n ? s : kDead;
+        for (int ax = 0; ax < 3; ax++) {
+            P1[p][ax] = xo.x[ax][idc];
+            P2[p][ax] = xn.x[ax][idc];
+        }
+    }
+    if (tid == 0)
+#pragma unroll
+        for (int q = 0; q < kMaxSpecies; q++) sQ[q] = cS.charge[q];
+    __syncthreads();
     int lo[3] = {1 << 30, 1 << 30, 1 << 30}, hi[3] = {-(1 << 30), -(1 << 30), -(1 << 30)};
 #pragma unroll
     for (int p = 0; p < kDepPPT; p++) {
-        int64_t id = base + dep_slot(p, tid);
-        SP[p] = id < n ? xo.sp[id] : kDead;
         if (SP[p] != kDead) {
-            double X1[3], X2[3];
-            for (int ax = 0; ax < 3; ax++) {
-                X1[ax] = xo.x[ax][id];
-                X2[ax] = xn.x[ax][id];
-            }
             double xr[3];
             int c1[3], c2[3];
-            if (zigzag(D.G, X1, X2, xr, c1, c2) && cS.charge[SP[p]] != 0.0)
+            if (zigzag(D.G, P1[p], P2[p], xr, c1, c2) && sQ[SP[p]] != 0.0)
                 for (int ax = 0; ax < 3; ax++) {
                     int a = c1[ax] < c2[ax] ? c1[ax] : c2[ax];
                     int b = (c1[ax] > c2[ax] ? c1[ax] : c2[ax]) + 1;
@@ -634,16 +665,26 @@ __global__ __launch_bounds__(kDepBlock) void k_deposit(DepCtx D, Species cS, dou
     LdsAcc la{sm, blo[0], blo[1], blo[2], bx, by, V};
     GlobalAcc ga{{F.Jint[0], F.Jint[1], F.Jint[2]}, D.G, &counters[C_FLAGS]};
     int n_horizon = 0, n_outer = 0;
+    // the first chord is kept from above; the next slot's chord is read
+    // while this one is deposited
+    double nX1[3] = {P1[0][0], P1[0][1], P1[0][2]}, nX2[3] = {P2[0][0], P2[0][1], P2[0][2]};
 #pragma unroll 1
     for (int p = 0; p < kDepPPT; p++) {
-        if (SP[p] == kDead) continue;
-        int64_t id = base + dep_slot(p, tid);
-        double Q = cS.charge[SP[p]];
         double X1[3], X2[3];
         for (int ax = 0; ax < 3; ax++) {
-            X1[ax] = xo.x[ax][id];
-            X2[ax] = xn.x[ax][id];
+            X1[ax] = nX1[ax];
+            X2[ax] = nX2[ax];
         }
+        if (p + 1 < kDepPPT) {
+            const int64_t idn = base + dep_slot(p + 1, tid), idc = idn < n ? idn : n - 1;
+            for (int ax = 0; ax < 3; ax++) {
+                nX1[ax] = xo.x[ax][idc];
+                nX2[ax] = xn.x[ax][idc];
+            }
+        }
+        if (SP[p] == kDead) continue;
+        int64_t id = base + dep_slot(p, tid);
+        double Q = sQ[SP[p]];
         double xr[3];
         int c1[3], c2[3];
         bool ok = zigzag(D.G, X1, X2, xr, c1, c2);

@@ -140,6 +140,7 @@ __device__ __forceinline__ float stage_gamma32(const PushParams &P, float u4, fl
 
 constexpr int kPush32Block = 256;
 constexpr int kPush32LdsNodes = 448;  // 35 KB of padded FP32 node tensor per block
+constexpr int kStage32InFlight = 8;    // node pieces per thread in flight while the box is staged
 
 // Stage, once per push, the FP32 node box of the cells the block's live
 // lanes start in, widened by one cell on every side when that still fits (as
@@ -182,10 +183,23 @@ __device__ __forceinline__ void stage_box32(const Grid &G, const float *__restri
         const float4 *src = reinterpret_cast<const float4 *>(node);
         const int nb0 = B.n[0], nb01 = B.n[0] * B.n[1];
         const float inv0 = __builtin_amdgcn_rcpf((float)nb0), inv01 = __builtin_amdgcn_rcpf((float)nb01);
-        for (int q = tid; q < count[e] * 4; q += kPush32Block) {
-            const int l = q >> 2, part = q & 3;
-            const int lk = small_div(l, inv01), r = l - lk * nb01, lj = small_div(r, inv0), li = r - lj * nb0;
-            snode[kNode32Stride4 * l + part] = src[4 * G.node(B.lo[0] + li, B.lo[1] + lj, B.lo[2] + lk) + part];
+        // kStage32InFlight pieces per thread are read before any is stored,
+        // so the copy takes one or two memory round trips instead of one per piece
+        const int total = count[e] * 4;
+        for (int q0 = tid; q0 < total; q0 += kPush32Block * kStage32InFlight) {
+            float4 v[kStage32InFlight];
+#pragma unroll
+            for (int t = 0; t < kStage32InFlight; t++) {
+                const int q = q0 + t * kPush32Block < total ? q0 + t * kPush32Block : total - 1;
+                const int l = q >> 2, part = q & 3;
+                const int lk = small_div(l, inv01), r = l - lk * nb01, lj = small_div(r, inv0), li = r - lj * nb0;
+                v[t] = src[4 * G.node(B.lo[0] + li, B.lo[1] + lj, B.lo[2] + lk) + part];
+            }
+#pragma unroll
+            for (int t = 0; t < kStage32InFlight; t++) {  // a clamped slot rewrites piece total - 1 with its own value
+                const int q = q0 + t * kPush32Block < total ? q0 + t * kPush32Block : total - 1;
+                snode[kNode32Stride4 * (q >> 2) + (q & 3)] = v[t];
+            }
         }
     }
     __syncthreads();
@@ -200,24 +214,30 @@ __device__ __forceinline__ void stage_box32(const Grid &G, const float *__restri
 __device__ __forceinline__ void push32_block(const PushParams &P, const Mixed &M, const Species &cS,
                                              const float *__restrict__ node, const ParticlePtrs32 &in,
                                              const ParticlePtrs32 &out, unsigned long long *counters, int64_t blk,
-                                             float4 *snode, int (*sred)[kPush32Block / 64]) {
+                                             float4 *snode, int (*sred)[kPush32Block / 64], double *sqm) {
+    if (P.n <= 0) return;  // uniform over the block
     const int tid = threadIdx.x;
-    const int64_t id = blk * kPush32Block + tid;
+    const int64_t id = blk * kPush32Block + tid, idc = id < P.n ? id : P.n - 1;
     int clamps = 0;
-    const uint8_t sp = id < P.n ? in.sp[id] : kDead;
+    // the slot's species and state are read together (slots past n read
+    // slot n - 1 and count as dead); q/m comes from the block's table
+    const uint8_t sp_in = in.sp[idc];
+    const int32_t cell_in = in.cell[idc];
+    float X0[3], U0[4];
+    for (int q = 0; q < 3; q++) X0[q] = in.off[q][idc];
+    for (int q = 0; q < 4; q++) U0[q] = in.u[q][idc];
+    if (tid == 0)
+#pragma unroll
+        for (int q = 0; q < kMaxSpecies; q++) sqm[q] = cS.qm[q];
+    const uint8_t sp = id < P.n ? sp_in : kDead;
     const bool alive = sp != kDead;
     const unsigned long long live = __ballot(alive);
     if ((tid & 63) == 0 && live)
         atomicAdd(&counters[pushed_index((unsigned)blk)], (unsigned long long)__popcll(live));
     int i = 0, j = 0, k = 0;
-    float qm = 0.0f;
-    float X0[3] = {0.0f, 0.0f, 0.0f}, U0[4] = {0.0f, 0.0f, 0.0f, 0.0f};
-    if (alive) {
-        qm = (float)cS.qm[sp];
-        unpack_cell(in.cell[id], i, j, k);
-        for (int q = 0; q < 3; q++) X0[q] = in.off[q][id];
-        for (int q = 0; q < 4; q++) U0[q] = in.u[q][id];
-    }
+    if (alive) unpack_cell(cell_in, i, j, k);
+    for (int q = 0; q < 3; q++) X0[q] = alive ? X0[q] : 0.0f;
+    for (int q = 0; q < 4; q++) U0[q] = alive ? U0[q] : 0.0f;
     const int base[3] = {i, j, k};
     float Xs[3] = {X0[0], X0[1], X0[2]};
     float Us[4] = {U0[0], U0[1], U0[2], U0[3]};
@@ -230,6 +250,7 @@ __device__ __forceinline__ void push32_block(const PushParams &P, const Mixed &M
         gather_cell32(P.G, base, X0, c0);
         stage_box32(P.G, node, alive, c0, snode, sred, B);
     }
+    const float qm = alive ? (float)sqm[sp] : 0.0f;  // the table is written before the box's barriers
 #pragma unroll 1
     for (int st = 0; st < 4; st++) {
         int c[3];
@@ -282,7 +303,8 @@ __global__ __launch_bounds__(kPush32Block, 4) void k_push32(PushParams P, Mixed 
                                                            ParticlePtrs32 out, unsigned long long *counters) {
     __shared__ float4 snode[kPush32LdsNodes * kNode32Stride4];
     __shared__ int sred[6][kPush32Block / 64];
-    push32_block(P, M, cS, node, in, out, counters, blockIdx.x, snode, sred);
+    __shared__ double sqm[kMaxSpecies];
+    push32_block(P, M, cS, node, in, out, counters, blockIdx.x, snode, sred, sqm);
 }
 
 void launch_push32(const PushParams &P, const Mixed &M, const Species &S, const float *node, ParticlePtrs32 in,
@@ -462,15 +484,29 @@ __device__ __forceinline__ bool zigzag32(const Grid &G, const int base[3], const
     return ok;
 }
 
-// Old cell, old offset and the new position relative to the old cell.
-__device__ __forceinline__ void load_chord32(const ParticlePtrs32 &xo, const ParticlePtrs32 &xn, int64_t id, int B1[3],
-                                             float X1[3], float X2[3]) {
-    int c2[3];
-    unpack_cell(xo.cell[id], B1[0], B1[1], B1[2]);
-    unpack_cell(xn.cell[id], c2[0], c2[1], c2[2]);
+// A chord as stored: packed old and new cells and offsets.
+struct Chord32 {
+    int32_t cell1, cell2;
+    float off1[3], off2[3];
+};
+__device__ __forceinline__ void read_chord32(const ParticlePtrs32 &xo, const ParticlePtrs32 &xn, int64_t id,
+                                             Chord32 &R) {
+    R.cell1 = xo.cell[id];
+    R.cell2 = xn.cell[id];
     for (int ax = 0; ax < 3; ax++) {
-        X1[ax] = xo.off[ax][id];
-        X2[ax] = (float)(c2[ax] - B1[ax]) + xn.off[ax][id];
+        R.off1[ax] = xo.off[ax][id];
+        R.off2[ax] = xn.off[ax][id];
+    }
+}
+
+// Old cell, old offset and the new position relative to the old cell.
+__device__ __forceinline__ void load_chord32(const Chord32 &R, int B1[3], float X1[3], float X2[3]) {
+    int c2[3];
+    unpack_cell(R.cell1, B1[0], B1[1], B1[2]);
+    unpack_cell(R.cell2, c2[0], c2[1], c2[2]);
+    for (int ax = 0; ax < 3; ax++) {
+        X1[ax] = R.off1[ax];
+        X2[ax] = (float)(c2[ax] - B1[ax]) + R.off2[ax];
     }
 }
 
@@ -490,22 +526,35 @@ constexpr int kDep32Lds = 6656;  // int64 LDS entries of the current box (52 KiB
 __device__ __forceinline__ void deposit32_block(const Dep32 &D, const Species &cS, double r_rm, double rscale,
                                                 const ParticlePtrs32 &xo, const ParticlePtrs32 &xn, int64_t n,
                                                 const FieldPtrsT<float> &F, unsigned long long *counters, int64_t blk,
-                                                unsigned long long *sm, int (*sred)[kDep32Block / 64]) {
+                                                unsigned long long *sm, int (*sred)[kDep32Block / 64], double *sQ) {
+    if (n <= 0) return;  // uniform over the block
     const int tid = threadIdx.x;
     const int64_t base = blk * (kDep32Block * kDep32PPT);
+    // Every slot's record is read at once (slots past n read slot n - 1 and
+    // count as dead), so the loads are in flight together.
     uint8_t SP[kDep32PPT];
+    Chord32 R[kDep32PPT];
+#pragma unroll
+    for (int p = 0; p < kDep32PPT; p++) {
+        const int64_t id = base + dep32_slot(p, tid), idc = id < n ? id : n - 1;
+        const uint8_t s = xo.sp[idc];
+        SP[p] = id < n ? s : kDead;
+        read_chord32(xo, xn, idc, R[p]);
+    }
+    if (tid == 0)
+#pragma unroll
+        for (int q = 0; q < kMaxSpecies; q++) sQ[q] = cS.charge[q];
+    __syncthreads();
     int lo[3] = {1 << 30, 1 << 30, 1 << 30}, hi[3] = {-(1 << 30), -(1 << 30), -(1 << 30)};
 #pragma unroll
     for (int p = 0; p < kDep32PPT; p++) {
-        int64_t id = base + dep32_slot(p, tid);
-        SP[p] = id < n ? xo.sp[id] : kDead;
         if (SP[p] != kDead) {
             int B1[3];
             float X1[3], X2[3];
-            load_chord32(xo, xn, id, B1, X1, X2);
+            load_chord32(R[p], B1, X1, X2);
             float xr[3];
             int l1[3], l2[3];
-            if (zigzag32(D.G, B1, X1, X2, xr, l1, l2) && cS.charge[SP[p]] != 0.0)
+            if (zigzag32(D.G, B1, X1, X2, xr, l1, l2) && sQ[SP[p]] != 0.0)
                 for (int ax = 0; ax < 3; ax++) {
                     int a = B1[ax] + (l1[ax] < l2[ax] ? l1[ax] : l2[ax]);
                     int b = B1[ax] + (l1[ax] > l2[ax] ? l1[ax] : l2[ax]) + 1;
@@ -545,14 +594,21 @@ __device__ __forceinline__ void deposit32_block(const Dep32 &D, const Species &c
     LdsAcc32 la{sm, blo[0], blo[1], blo[2], bx, by, V};
     GlobalAcc32 ga{{F.Jint[0], F.Jint[1], F.Jint[2]}, D.G, &counters[C_FLAGS]};
     int n_horizon = 0, n_outer = 0;
+    // the next slot's record is read while this one is deposited
+    Chord32 next = R[0];
 #pragma unroll 1
     for (int p = 0; p < kDep32PPT; p++) {
+        const Chord32 cur = next;
+        if (p + 1 < kDep32PPT) {
+            const int64_t idn = base + dep32_slot(p + 1, tid);
+            read_chord32(xo, xn, idn < n ? idn : n - 1, next);
+        }
         if (SP[p] == kDead) continue;
         int64_t id = base + dep32_slot(p, tid);
-        float Q = (float)cS.charge[SP[p]];
+        float Q = (float)sQ[SP[p]];
         int B1[3];
         float X1[3], X2[3];
-        load_chord32(xo, xn, id, B1, X1, X2);
+        load_chord32(cur, B1, X1, X2);
         float xr[3];
         int l1[3], l2[3];
         bool ok = zigzag32(D.G, B1, X1, X2, xr, l1, l2);
@@ -566,11 +622,11 @@ __device__ __forceinline__ void deposit32_block(const Dep32 &D, const Species &c
         }
         // removal after the final move is deposited
         int c2[3];
-        unpack_cell(xn.cell[id], c2[0], c2[1], c2[2]);
+        unpack_cell(cur.cell2, c2[0], c2[1], c2[2]);
         bool outside = false;
         for (int ax = 0; ax < 3; ax++)
             if (c2[ax] < 0 || c2[ax] > D.G.dim(ax) - 1) outside = true;
-        float o2[3] = {xn.off[0][id], xn.off[1][id], xn.off[2][id]};
+        float o2[3] = {cur.off2[0], cur.off2[1], cur.off2[2]};
         double x, y, z;
         hole_rel(D.h, c2[0], c2[1], c2[2], o2, x, y, z);
         if (ks_radius_below(D.h.a, x, y, z, r_rm)) {
@@ -578,7 +634,7 @@ __device__ __forceinline__ void deposit32_block(const Dep32 &D, const Species &c
             for (int ax = 0; ax < 3; ax++)
                 if (c2[ax] < -1 || c2[ax] > D.G.dim(ax)) inb = false;
             if (inb && Q != 0.0f) {
-                double sc = (double)cS.charge[SP[p]] * rscale;
+                double sc = sQ[SP[p]] * rscale;
                 for (int dk = 0; dk < 2; dk++)
                     for (int dj = 0; dj < 2; dj++)
                         for (int di = 0; di < 2; di++) {
@@ -609,7 +665,8 @@ __global__ __launch_bounds__(kDep32Block) void k_deposit32(Dep32 D, Species cS, 
                                                            FieldPtrsT<float> F, unsigned long long *counters) {
     __shared__ unsigned long long sm[kDep32Lds];
     __shared__ int sred[6][kDep32Block / 64];
-    deposit32_block(D, cS, r_rm, rscale, xo, xn, n, F, counters, blockIdx.x, sm, sred);
+    __shared__ double sQ[kMaxSpecies];
+    deposit32_block(D, cS, r_rm, rscale, xo, xn, n, F, counters, blockIdx.x, sm, sred, sQ);
 }
 
 Dep32 make_dep32(const Grid &G, const Hole &h, const Mixed &M, double dt, int deposit_mode, double jscale) {
@@ -632,23 +689,25 @@ Dep32 make_dep32(const Grid &G, const Hole &h, const Mixed &M, double dt, int de
 __global__ __launch_bounds__(kPush32Block, 4) void k_batch_push32(const BatchTable *__restrict__ T) {
     __shared__ float4 snode[kPush32LdsNodes * kNode32Stride4];
     __shared__ int sred[6][kPush32Block / 64];
+    __shared__ double sqm[kMaxSpecies];
     const int64_t total = T->total[BK_PUSH];
     for (int64_t lb = blockIdx.x; lb < total; lb += gridDim.x) {
         __syncthreads();  // the previous logical block is done with the LDS scratch
         const BatchRun32 &R = T->run[batch_run_of(T, BK_PUSH, lb)];
-        push32_block(R.P, R.M, R.S, R.F.node, R.cur, R.nxt, R.counters, lb - R.off[BK_PUSH], snode, sred);
+        push32_block(R.P, R.M, R.S, R.F.node, R.cur, R.nxt, R.counters, lb - R.off[BK_PUSH], snode, sred, sqm);
     }
 }
 
 __global__ __launch_bounds__(kDep32Block) void k_batch_deposit32(const BatchTable *__restrict__ T) {
     __shared__ unsigned long long sm[kDep32Lds];
     __shared__ int sred[6][kDep32Block / 64];
+    __shared__ double sQ[kMaxSpecies];
     const int64_t total = T->total[BK_DEP];
     for (int64_t lb = blockIdx.x; lb < total; lb += gridDim.x) {
         __syncthreads();  // the previous logical block is done with the LDS scratch
         const BatchRun32 &R = T->run[batch_run_of(T, BK_DEP, lb)];
         deposit32_block(R.D, R.S, R.r_rm, R.rscale, R.cur, R.nxt, R.P.n, R.F, R.counters, lb - R.off[BK_DEP], sm,
-                        sred);
+                        sred, sQ);
     }
 }
 
