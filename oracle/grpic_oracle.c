@@ -1580,9 +1580,15 @@ void or_sim_step(or_sim *s, int nsteps)
  * face: the planes tz in order; within plane tz the rows ty ascend when tz is
  * even and descend when it is odd; along the r-th row visited (r = tz nTy +
  * the row's place in its plane) the tiles tx ascend when r is even and
- * descend when it is odd.  Inside a tile the cells go x fastest, then y, then
- * z:  key = rank * T^3 + (lz*T + ly)*T + lx with (i,j,k) = floor(X); dead
- * particles get 0xFFFFFFFF. */
+ * descend when it is odd.  The path leaves a tile along its row, or, for the
+ * last tile of a row, towards the next row (along y, in the plane's row
+ * direction), or, for the last tile of a plane, towards the next plane (+z).
+ * Inside a tile the cells are numbered in T layers across that exit axis,
+ * counted from the side facing away from the exit (the exit side last);
+ * within a layer the larger of the two remaining axes is the slow index and
+ * the smaller the fast one:
+ *   key = rank * T^3 + (layer*T + slow)*T + fast,  (i,j,k) = floor(X);
+ * dead particles get 0xFFFFFFFF. */
 void or_sort_keys(const or_params *p, int tile, int64_t n, const double *x, const uint8_t *sp,
                   uint32_t *keys)
 {
@@ -1593,15 +1599,31 @@ void or_sort_keys(const or_params *p, int tile, int64_t n, const double *x, cons
             keys[i] = 0xFFFFFFFFu;
             continue;
         }
-        int c[3];
-        for (int ax = 0; ax < 3; ax++) c[ax] = (int)floor(x[ax * n + i]);
-        int tx = c[0] / T, ty = c[1] / T, tz = c[2] / T;
-        int lx = c[0] % T, ly = c[1] % T, lz = c[2] % T;
-        int row_in_plane = (tz % 2 == 0) ? ty : nTy - 1 - ty;
-        int row = tz * nTy + row_in_plane;
-        int along = (row % 2 == 0) ? tx : nTx - 1 - tx;
+        int c[3], t[3], l[3];
+        for (int ax = 0; ax < 3; ax++) {
+            c[ax] = (int)floor(x[ax * n + i]);
+            t[ax] = c[ax] / T;
+            l[ax] = c[ax] % T;
+        }
+        int row_in_plane = (t[2] % 2 == 0) ? t[1] : nTy - 1 - t[1];
+        int row = t[2] * nTy + row_in_plane;
+        int along = (row % 2 == 0) ? t[0] : nTx - 1 - t[0];
         uint32_t rank = (uint32_t)row * (uint32_t)nTx + (uint32_t)along;
-        keys[i] = rank * (uint32_t)(T * T * T) + (uint32_t)((lz * T + ly) * T + lx);
+        int exit_axis, exit_up;
+        if (along < nTx - 1) {
+            exit_axis = 0;
+            exit_up = (row % 2 == 0);
+        } else if (row_in_plane < nTy - 1) {
+            exit_axis = 1;
+            exit_up = (t[2] % 2 == 0);
+        } else {
+            exit_axis = 2;
+            exit_up = 1;
+        }
+        int layer = exit_up ? l[exit_axis] : T - 1 - l[exit_axis];
+        int fast = (exit_axis == 0) ? l[1] : l[0];
+        int slow = (exit_axis == 2) ? l[1] : l[2];
+        keys[i] = rank * (uint32_t)(T * T * T) + (uint32_t)((layer * T + slow) * T + fast);
     }
 }
 

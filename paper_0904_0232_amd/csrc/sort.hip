@@ -1,8 +1,9 @@
 // Stable cell sort of the particle slots and compaction of the removed ones.
-// Key = rank(tile) T^3 + (lz T + ly) T + lx with (i,j,k) = floor(x) (FP64) or
-// the packed cell (FP32-mixed), tiles of T^3 cells ranked along a path of
-// face-adjacent tiles (tile_key); removed particles take the all-ones key of
-// key_bits bits and so sort to the end.
+// Key = rank(tile) T^3 + the cell's place in its tile, with (i,j,k) = floor(x)
+// (FP64) or the packed cell (FP32-mixed), tiles of T^3 cells ranked along a
+// path of face-adjacent tiles and cells in layers across the path
+// (tile_key); removed particles take the all-ones key of key_bits bits and
+// so sort to the end.
 //
 // The ordering is a least-significant-digit radix sort over digits of at most
 // 9 bits (ceil(key_bits / 9) passes, 3 at 256^3).  Each pass is
@@ -71,14 +72,35 @@ size_t sort_temp_bytes(int64_t capacity) {
 
 // Tiles ranked along a boustrophedon path (planes tz in order, rows ty
 // reversed in odd planes, tiles tx reversed in odd rows), so consecutive
-// tiles share a face and a block of consecutive sorted particles that spans
-// two tiles stays compact; cells x fastest, then y, then z inside a tile.
+// tiles share a face.  Inside a tile the cells go in layers across the
+// direction in which the path leaves it (along the row; at a row's end to
+// the next row; at a plane's end to the next plane), from the face it
+// entered by to the face it leaves by; inside a layer the lower remaining
+// axis runs fastest.  So the last layer of a tile and the first layer of the
+// next one are neighbours, and a block of consecutive sorted particles that
+// spans two tiles covers two or three thin layers instead of both tiles.
 __device__ __forceinline__ uint32_t tile_key(int T, int nTx, int nTy, const int c[3]) {
     const int tx = c[0] / T, ty = c[1] / T, tz = c[2] / T;
-    const int lx = c[0] % T, ly = c[1] % T, lz = c[2] % T;
-    const int row = tz * nTy + ((tz & 1) ? nTy - 1 - ty : ty);
+    const int lx = c[0] - tx * T, ly = c[1] - ty * T, lz = c[2] - tz * T;
+    const int in_plane = (tz & 1) ? nTy - 1 - ty : ty;
+    const int row = tz * nTy + in_plane;
     const int along = (row & 1) ? nTx - 1 - tx : tx;
-    return ((uint32_t)row * (uint32_t)nTx + (uint32_t)along) * (uint32_t)(T * T * T) + (uint32_t)((lz * T + ly) * T + lx);
+    int layer, slow, fast;
+    if (along < nTx - 1) {  // leaves along x
+        layer = (row & 1) ? T - 1 - lx : lx;
+        slow = lz;
+        fast = ly;
+    } else if (in_plane < nTy - 1) {  // leaves to the next row, along y
+        layer = (tz & 1) ? T - 1 - ly : ly;
+        slow = lz;
+        fast = lx;
+    } else {  // leaves to the next plane, along z
+        layer = lz;
+        slow = ly;
+        fast = lx;
+    }
+    return ((uint32_t)row * (uint32_t)nTx + (uint32_t)along) * (uint32_t)(T * T * T) +
+           (uint32_t)((layer * T + slow) * T + fast);
 }
 
 // Key of slot id (every slot below n); slot 0 also resets the live count.

@@ -6,8 +6,10 @@
   obeys the exact leapfrog recurrence with the Yee dispersion relation;
 - Wald's uniform-field solution of Schwarzschild stays bounded (no growth);
 - the whole cycle keeps Gauss's law in flat-deposit mode;
-- the stable sort equals numpy's stable argsort on the same keys, and its
-  tiles follow a path of face-adjacent tiles.
+- the stable sort equals numpy's stable argsort on the same keys, its
+  tiles follow a path of face-adjacent tiles, and inside a tile the cells go
+  in layers across the path, so every run of T^2 consecutive cells stays
+  within T + 1 cells along each axis, across tile boundaries too.
 """
 import numpy as np
 import pytest
@@ -228,11 +230,9 @@ def test_sort_is_stable_and_tiles_follow_a_face_adjacent_path(N, T):
     k_alive = keys[alive]
     pairs = set(zip(lin.tolist(), k_alive.tolist()))
     assert len(pairs) == len(set(lin.tolist())) == len(set(k_alive.tolist()))
-    # each tile is one contiguous block of T^3 keys (cells x fastest, then y,
-    # then z inside it), the blocks are a bijection onto the tiles, and
-    # consecutive blocks are tiles that share a face
-    local = ((cells[2] % T) * T + cells[1] % T) * T + cells[0] % T
-    assert np.all(k_alive % T ** 3 == local)
+    # each tile is one contiguous block of T^3 keys, the blocks are a
+    # bijection onto the tiles, and consecutive blocks are tiles that share a
+    # face
     nT = (N + T - 1) // T
     tile_of_rank = {}
     for rank, tc in zip((k_alive // T ** 3).tolist(), map(tuple, (cells // T).T.tolist())):
@@ -243,6 +243,41 @@ def test_sort_is_stable_and_tiles_follow_a_face_adjacent_path(N, T):
     for r in range(nT ** 3 - 1):
         d = np.abs(np.array(tile_of_rank[r + 1]) - np.array(tile_of_rank[r]))
         assert d.sum() == 1, (r, tile_of_rank[r], tile_of_rank[r + 1])
+    # inside a tile: layers across the axis along which the path moves on to
+    # the next tile (the last tile: on to the next plane), the exit side
+    # last; within a layer the larger remaining axis slow, the smaller fast
+    rank = k_alive // T ** 3
+    tiles = np.array([tile_of_rank[r] for r in range(nT ** 3)] + [(0, 0, 0)])
+    step = tiles[rank + 1] - tiles[rank]
+    step[rank == nT ** 3 - 1] = (0, 0, 1)
+    axis = np.argmax(np.abs(step), axis=1)
+    up = step[np.arange(step.shape[0]), axis] > 0
+    loc = cells % T
+    la = loc[axis, np.arange(axis.size)]
+    layer = np.where(up, la, T - 1 - la)
+    fast = np.where(axis == 0, loc[1], loc[0])
+    slow = np.where(axis == 2, loc[1], loc[2])
+    assert np.all(k_alive % T ** 3 == (layer * T + slow) * T + fast)
+
+
+@pytest.mark.parametrize("N,T", [(16, 4), (24, 4), (16, 8)])
+def test_runs_of_sorted_cells_stay_compact(N, T):
+    """Every cell of the grid once, in key order: any T^2 consecutive cells
+    (one layer's worth) span at most T + 1 cells along each axis, also where
+    they straddle two tiles, on a straight stretch of the path or at a turn.
+    With the cells of a tile in x-fastest order, runs that straddle two tiles
+    span 2T cells along the path."""
+    p = O.make_params(N, m=0.0)
+    g = np.arange(N)
+    cells = np.stack(np.meshgrid(g, g, g, indexing="ij")).reshape(3, -1)
+    x = cells + 0.5
+    keys = O.sort_keys(p, T, np.ascontiguousarray(x, dtype=np.float64), np.zeros(x.shape[1], np.uint8))
+    assert len(set(keys.tolist())) == N ** 3
+    c = cells[:, np.argsort(keys, kind="stable")]
+    W = T * T
+    for s in range(0, N ** 3 - W + 1):
+        ext = c[:, s:s + W].max(1) - c[:, s:s + W].min(1) + 1
+        assert np.all(ext <= T + 1), (s, ext)
 
 
 # --- outer absorbing layer (a reading: the paper states no outer boundary) --
