@@ -259,16 +259,22 @@ int grpic_dump_nodes(grpic_t *h, double *out);
 int grpic_push_only(grpic_t *h, int32_t nsteps);
 
 /* Stable cell sort now, by key then particle order.  The key of a live
- * particle in cell (i,j,k) is rank * T^3 + (lz T + ly) T + lx with T =
- * cfg->tile, (lx, ly, lz) its cell inside the tile and rank the tile's place
- * on a path through all tiles on which consecutive tiles share a face (the
- * planes of tiles in z order; rows of tiles in y order in even planes and
- * reversed in odd ones; tiles in x order in even rows and reversed in odd
- * ones, counting rows across the planes).  The paper has no sort; it keeps
- * the particles of a block of threads in a few neighbouring cells.
+ * particle in cell (i,j,k) is rank * T^3 + local with T = cfg->tile, rank
+ * the tile's place on a path through all tiles on which consecutive tiles
+ * share a face (the planes of tiles in z order; rows of tiles in y order in
+ * even planes and reversed in odd ones; tiles in x order in even rows and
+ * reversed in odd ones, counting rows across the planes), and local =
+ * (layer T + slow) T + fast the cell's place inside its tile: layer counts
+ * the tile's T cell layers across the axis along which the path leaves the
+ * tile (along its row; from a row's last tile along y; from a plane's last
+ * tile along +z), the exit side last; slow and fast are the cell's other two
+ * tile coordinates, the larger axis slow.  The paper has no sort; this one
+ * keeps the particles of a block of threads in a few neighbouring cells, also
+ * where the block straddles two tiles.
  * If keys_out is not NULL it receives the sorted keys of all slots
  * (dead particles: 0xFFFFFFFF), and perm_out the original slot index of each
- * sorted position.  Dead particles are compacted away afterwards. */
+ * sorted position; with both NULL nothing is copied to the host.  Dead
+ * particles are compacted away afterwards. */
 int grpic_sort(grpic_t *h, uint32_t *keys_out, int64_t *perm_out);
 
 /* Kernel timing with HIP events recorded on the run's stream around each

@@ -334,7 +334,10 @@ def grpic_dump_nodes(h, nnodes):
     return out
 
 
-def grpic_sort(h):
+def grpic_sort(h, outputs=True):
+    if not outputs:
+        _check(lib().grpic_sort(h, None, None))
+        return None
     n, _ = grpic_particle_count(h)
     keys = np.zeros(n, dtype=np.uint32)
     perm = np.zeros(n, dtype=np.int64)

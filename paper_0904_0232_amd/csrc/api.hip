@@ -1453,15 +1453,16 @@ int grpic_sort(grpic_t *h, uint32_t *keys_out, int64_t *perm_out) {
     if (rc) return rc;
     if (n == 0) return GRPIC_OK;
     hipStream_t s = h->stream;
-    std::vector<uint32_t> k(n), p(n);
+    const bool out = keys_out || perm_out;
+    std::vector<uint32_t> k(out ? n : 0), p(out ? n : 0);
     unsigned long long cnt[C_NCOUNTERS];
-    rc = check(hipMemcpyAsync(k.data(), fk, n * 4, hipMemcpyDeviceToHost, s));
-    if (!rc) rc = check(hipMemcpyAsync(p.data(), fi, n * 4, hipMemcpyDeviceToHost, s));
+    rc = out ? check(hipMemcpyAsync(k.data(), fk, n * 4, hipMemcpyDeviceToHost, s)) : GRPIC_OK;
+    if (!rc && out) rc = check(hipMemcpyAsync(p.data(), fi, n * 4, hipMemcpyDeviceToHost, s));
     if (!rc) rc = check(hipMemcpyAsync(cnt, h->counters, sizeof(cnt), hipMemcpyDeviceToHost, s));
     if (!rc) rc = check(hipStreamSynchronize(s));
     if (rc) return rc;
     uint32_t sentinel = h->key_bits >= 32 ? 0xFFFFFFFFu : ((1u << h->key_bits) - 1u);
-    for (int64_t i = 0; i < n; i++) {
+    for (int64_t i = 0; out && i < n; i++) {
         if (keys_out) keys_out[i] = k[i] == sentinel ? 0xFFFFFFFFu : k[i];
         if (perm_out) perm_out[i] = (int64_t)p[i];
     }

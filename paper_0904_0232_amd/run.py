@@ -96,8 +96,8 @@ class Run:
         return capi.grpic_dump_nodes(self.h, self.nnodes).reshape(
             self.cfg.nz + 1, self.cfg.ny + 1, self.cfg.nx + 1, 4, 4)
 
-    def sort(self):
-        return capi.grpic_sort(self.h)
+    def sort(self, outputs=True):
+        return capi.grpic_sort(self.h, outputs)
 
     def close(self):
         if self.h:
