@@ -1147,6 +1147,8 @@ int load_staged(grpic_t *h, int32_t species, int64_t n, const double *x, const d
     if (!rc && FAILS(hipMemcpyAsync(st + 3 * n, ucov, 3 * n * 8, hipMemcpyHostToDevice, s))) rc = GRPIC_EDEVICE;
     if (!rc && FAILS(hipMemcpyAsync(&before, h->counters + C_LOAD_KEPT, 8, hipMemcpyDeviceToHost, s)))
         rc = GRPIC_EDEVICE;
+    // new slots past the last sort's live count: the kernels visit all slots again
+    if (!rc && FAILS(hipMemsetAsync(h->counters + C_NALIVE, 0, 8, s))) rc = GRPIC_EDEVICE;
     if (!rc) {
         if (h->mixed)
             launch_load32(h->G, h->h, h->cfg.c, h->cfg.r_rm, st, st + 3 * n, n, species, pp32(h, h->xc, h->uc),
@@ -1269,6 +1271,8 @@ int grpic_restore_particles(grpic_t *h, int64_t n, const double *x, const double
             rc = check(hipMemcpyAsync(h->pu[h->uc][q], u + q * n, n * 8, hipMemcpyHostToDevice, s));
     }
     if (!rc) rc = check(hipMemcpyAsync(h->psp[h->uc], sp, n, hipMemcpyHostToDevice, s));
+    // removed particles may now sit anywhere: the kernels visit all slots
+    if (!rc) rc = check(hipMemsetAsync(h->counters + C_NALIVE, 0, 8, s));
     if (!rc) rc = check(hipStreamSynchronize(s));
     if (!rc) h->n_slots = n;
     return rc;

@@ -66,7 +66,7 @@ __device__ __forceinline__ double outer_distance(const Grid &G, double X, double
 
 // Device counters, one 64-bit word each.
 enum Counter {
-    C_NALIVE = 0,      // live slots after the last compaction (unused while 0)
+    C_NALIVE = 0,      // live slots after the last cell sort (0: none since the slots last changed)
     C_GAMMA_CLAMPS = 1,
     C_REMOVED_HORIZON = 2,
     C_REMOVED_OUTER = 3,
@@ -76,6 +76,16 @@ enum Counter {
     C_DEP_GLOBAL = 7,  // deposit blocks that added it with global atomics
     C_NCOUNTERS = 8
 };
+
+// Slots the particle kernels need to visit: the cell sort moves removed
+// particles to the end and leaves the live count in C_NALIVE, and later
+// removals only mark slots in place, so every slot from there on holds a
+// removed particle.  Loading or restoring particles resets the count to 0,
+// which means all n slots.
+__device__ __forceinline__ int64_t live_bound(const unsigned long long *counters, int64_t n) {
+    const unsigned long long a = counters[C_NALIVE];
+    return (a > 0 && (int64_t)a < n) ? (int64_t)a : n;
+}
 
 // Bits of C_FLAGS (sticky).
 constexpr unsigned long long kFlagLongMove = 1ull;    // a move longer than a cell (not deposited)

@@ -202,6 +202,7 @@ __global__ __launch_bounds__(kPushBlock, 4) void k_push(PushParams P, Species cS
     __shared__ double2 snode[kPushLdsNodes * kNodeStride2];
     __shared__ int sred[6][kPushBlock / 64];
     __shared__ double sqm[kMaxSpecies];
+    if ((int64_t)blockIdx.x * kPushBlock >= live_bound(counters, P.n)) return;  // removed particles only
     const int tid = threadIdx.x;
     const int64_t id = (int64_t)blockIdx.x * kPushBlock + tid, idc = id < P.n ? id : P.n - 1;
     int clamps = 0;
@@ -601,6 +602,7 @@ __global__ __launch_bounds__(kDepBlock) void k_deposit(DepCtx D, Species cS, dou
     __shared__ double sQ[kMaxSpecies];
     const int tid = threadIdx.x;
     const int64_t base = (int64_t)blockIdx.x * (kDepBlock * kDepPPT);
+    if (base >= live_bound(counters, n)) return;  // removed particles only
     // Every slot's chord is read at once (slots past n read slot n - 1 and
     // count as dead), so the loads are in flight together.
     uint8_t SP[kDepPPT];

@@ -215,7 +215,7 @@ __device__ __forceinline__ void push32_block(const PushParams &P, const Mixed &M
                                              const float *__restrict__ node, const ParticlePtrs32 &in,
                                              const ParticlePtrs32 &out, unsigned long long *counters, int64_t blk,
                                              float4 *snode, int (*sred)[kPush32Block / 64], double *sqm) {
-    if (P.n <= 0) return;  // uniform over the block
+    if (P.n <= 0 || blk * kPush32Block >= live_bound(counters, P.n)) return;  // uniform: removed particles only
     const int tid = threadIdx.x;
     const int64_t id = blk * kPush32Block + tid, idc = id < P.n ? id : P.n - 1;
     int clamps = 0;
@@ -527,9 +527,9 @@ __device__ __forceinline__ void deposit32_block(const Dep32 &D, const Species &c
                                                 const ParticlePtrs32 &xo, const ParticlePtrs32 &xn, int64_t n,
                                                 const FieldPtrsT<float> &F, unsigned long long *counters, int64_t blk,
                                                 unsigned long long *sm, int (*sred)[kDep32Block / 64], double *sQ) {
-    if (n <= 0) return;  // uniform over the block
-    const int tid = threadIdx.x;
     const int64_t base = blk * (kDep32Block * kDep32PPT);
+    if (n <= 0 || base >= live_bound(counters, n)) return;  // uniform: removed particles only
+    const int tid = threadIdx.x;
     // Every slot's record is read at once (slots past n read slot n - 1 and
     // count as dead), so the loads are in flight together.
     uint8_t SP[kDep32PPT];
