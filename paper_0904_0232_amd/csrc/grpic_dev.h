@@ -58,6 +58,14 @@ __device__ __forceinline__ double sqrt_nr(double x) {
     const double e = fma(-s, y, 1.0);
     return fma(s * e, fma(e, 0.375, 0.5), s);
 }
+// sqrt_nr without the raise to the smallest normal: for x > 0 (normal or
+// subnormal) the same value; 0 gives NaN, which callers must treat as such.
+__device__ __forceinline__ double sqrt_pos(double x) {
+    const double y = __builtin_amdgcn_rsq(x);
+    const double s = x * y;
+    const double e = fma(-s, y, 1.0);
+    return fma(s * e, fma(e, 0.375, 0.5), s);
+}
 __device__ __forceinline__ double rsqrt_nr(double x) {
     const double y = __builtin_amdgcn_rsq(x);
     const double e = fma(-x * y, y, 1.0);
@@ -110,6 +118,18 @@ __device__ __forceinline__ double ks_radius_nr(double a, double x, double y, dou
     double r2;
     return ks_radius_nr(a, x, y, z, r2);
 }
+// The same root with sqrt_pos: NaN where the quartic's discriminant or r^2
+// is exactly 0 (the ring r = 0, z = 0 and, for a = 0, the centre); the
+// area density below treats NaN as inside r_exc.
+__device__ __forceinline__ double ks_radius_pos(double a, double x, double y, double z, double &r2) {
+    const double b = x * x + y * y + z * z - a * a, a2z2 = a * a * (z * z);
+    const double s = sqrt_pos(fma(b, b, 4.0 * a2z2));
+    if (b >= 0.0)
+        r2 = 0.5 * (b + s);
+    else
+        r2 = div_nr(2.0 * a2z2, s - b);
+    return sqrt_pos(r2);
+}
 
 // Area density of a K-face at a hole-relative point (m > 0):
 // sqrt(g_II g_JJ - g_IJ^2) = sqrt(1 + f (1 - k_K^2)) (I, J the other two
@@ -123,8 +143,8 @@ __device__ __forceinline__ double ks_radius_nr(double a, double x, double y, dou
 __device__ __forceinline__ double ks_area_density(double m, double a, double r_exc, int K, double x, double y,
                                                   double z) {
     double r2;
-    const double r = ks_radius_nr(a, x, y, z, r2);
-    if (r < r_exc) return 1.0;
+    const double r = ks_radius_pos(a, x, y, z, r2);
+    if (!(r >= r_exc)) return 1.0;  // also the NaN of r = 0
     const double S4 = fma(r2, r2, a * a * (z * z)), m2r = 2.0 * m * r;
     double num, den;
     if (K == 2) {
