@@ -488,11 +488,12 @@ def jet_study(snapshots=(0, 50, 100, 150, 200, 250, 300, 350, 400, 450, 500)):
     for name, prec, b0, layer in (("B30_fp64", capi.FP64, w["B0"], 0.0), ("B30_fp32", capi.FP32_MIXED, w["B0"], 0.0),
                                   ("B0_fp64", capi.FP64, 0.0, 0.0), ("B30_fp64_absorbing", capi.FP64, w["B0"], 8.0)):
         cfg = R.make_config(w["nx"], ny=w["ny"], nz=w["nz"], m=w["m"], a=w["a"], c=w["c"], dt=w["dt"],
-                            B0=(0.0, 0.0, b0), species=w["species"], r_rm=w["r_rm"], sort_every=5, capacity=ntot,
+                            B0=(0.0, 0.0, b0), species=w["species"], r_rm=w["r_rm"], sort_every=8, capacity=ntot,
                             precision=prec, center=w["center"], outer_layer=layer, outer_damp=0.3 if layer else 0.0)
         r = R.Run(cfg)
         for sp, x, uc in parts:
             r.load(sp, x, uc)
+        r.sort(outputs=False)
         snaps, wall, psteps, done = {}, 0.0, 0, 0
         for t in snapshots:
             if t > done:
