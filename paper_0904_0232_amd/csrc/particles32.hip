@@ -8,6 +8,7 @@
 // (max(r_+ + 4 m, 1.25 r_exc)) of the hole the metric gradients and the
 // Christoffel contraction are evaluated in FP64; the deposition's area
 // densities are FP32 beyond r_fp64 and FP64 within it.
+#include <type_traits>
 #include "grpic_dev.h"
 #include "grpic_impl.h"
 
@@ -183,24 +184,32 @@ __device__ __forceinline__ void stage_box32(const Grid &G, const float *__restri
         const float4 *src = reinterpret_cast<const float4 *>(node);
         const int nb0 = B.n[0], nb01 = B.n[0] * B.n[1];
         const float inv0 = __builtin_amdgcn_rcpf((float)nb0), inv01 = __builtin_amdgcn_rcpf((float)nb01);
-        // kStage32InFlight pieces per thread are read before any is stored,
-        // so the copy takes one or two memory round trips instead of one per piece
+        // N pieces per thread are read before any is stored, so the copy
+        // takes one or two memory round trips instead of one per piece; small
+        // boxes (up to 4 pieces per thread) read 4 at a time
         const int total = count[e] * 4;
-        for (int q0 = tid; q0 < total; q0 += kPush32Block * kStage32InFlight) {
-            float4 v[kStage32InFlight];
+        auto copy = [&](auto in_flight) {
+            constexpr int N = decltype(in_flight)::value;
+            for (int q0 = tid; q0 < total; q0 += kPush32Block * N) {
+                float4 v[N];
 #pragma unroll
-            for (int t = 0; t < kStage32InFlight; t++) {
-                const int q = q0 + t * kPush32Block < total ? q0 + t * kPush32Block : total - 1;
-                const int l = q >> 2, part = q & 3;
-                const int lk = small_div(l, inv01), r = l - lk * nb01, lj = small_div(r, inv0), li = r - lj * nb0;
-                v[t] = src[4 * G.node(B.lo[0] + li, B.lo[1] + lj, B.lo[2] + lk) + part];
-            }
+                for (int t = 0; t < N; t++) {
+                    const int q = q0 + t * kPush32Block < total ? q0 + t * kPush32Block : total - 1;
+                    const int l = q >> 2, part = q & 3;
+                    const int lk = small_div(l, inv01), r = l - lk * nb01, lj = small_div(r, inv0), li = r - lj * nb0;
+                    v[t] = src[4 * G.node(B.lo[0] + li, B.lo[1] + lj, B.lo[2] + lk) + part];
+                }
 #pragma unroll
-            for (int t = 0; t < kStage32InFlight; t++) {  // a clamped slot rewrites piece total - 1 with its own value
-                const int q = q0 + t * kPush32Block < total ? q0 + t * kPush32Block : total - 1;
-                snode[kNode32Stride4 * (q >> 2) + (q & 3)] = v[t];
+                for (int t = 0; t < N; t++) {  // a clamped slot rewrites piece total - 1 with its own value
+                    const int q = q0 + t * kPush32Block < total ? q0 + t * kPush32Block : total - 1;
+                    snode[kNode32Stride4 * (q >> 2) + (q & 3)] = v[t];
+                }
             }
-        }
+        };
+        if (total <= 4 * kPush32Block)
+            copy(std::integral_constant<int, 4>());
+        else
+            copy(std::integral_constant<int, kStage32InFlight>());
     }
     __syncthreads();
 }
