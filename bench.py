@@ -349,6 +349,7 @@ def measure(workload, precision, steps, warmup, sort_every, parts, first_cycle_s
         "graphs": dict(again["graphs"], what=what["graphs"]) if again else None,
         "launches": dict(again["launches"], what=what["launches"]) if again else None,
         "deposit_blocks": {"lds": d["deposit_blocks_lds"], "global": d["deposit_blocks_global"]},
+        "push_blocks": {"lds": d["push_blocks_lds"], "global": d["push_blocks_global"]},
     }
 
 
@@ -852,7 +853,7 @@ def main():
         },
         "kernel_ms_per_launch": m64["kernel_ms_per_launch"],
         "graph_replay": m64["graphs"], "launches_no_events": m64["launches"],
-        "deposit_blocks": m64["deposit_blocks"],
+        "deposit_blocks": m64["deposit_blocks"], "push_blocks": m64["push_blocks"],
         "roofline": roofline,
         "rooflines": rooflines64,
         "cpu_baseline": cpu,
@@ -869,7 +870,7 @@ def main():
             "value": m32["value"], "unit": UNIT, "ms_per_step": m32["ms_per_step"], "dtype": "f32 (FP64 quartic, "
             "near-horizon metric and diagnostics)", "kernel_ms_per_launch": m32["kernel_ms_per_launch"],
             "speedup_vs_fp64": m32["value"] / m64["value"], "live_particles_end": m32["live_end"],
-            "deposit_blocks": m32["deposit_blocks"], "graph_replay": m32["graphs"],
+            "deposit_blocks": m32["deposit_blocks"], "push_blocks": m32["push_blocks"], "graph_replay": m32["graphs"],
             "launches_no_events": m32["launches"],
         }
         line["fp32_mixed"]["roofline"], line["fp32_mixed"]["rooflines"] = rooflines(m32, FP32_PEAK_TFLOPS, True,

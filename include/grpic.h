@@ -121,6 +121,10 @@ typedef struct {
     int64_t deposit_blocks_lds;    /* cumulative deposit blocks whose current was
                                       summed in an LDS box, then flushed       */
     int64_t deposit_blocks_global; /* ... added with global atomics instead     */
+    int64_t push_blocks_lds;       /* cumulative push blocks with live particles
+                                      that gathered from an LDS node box       */
+    int64_t push_blocks_global;    /* ... that found no box within the LDS
+                                      budget and gathered from global memory   */
 } grpic_diag;
 
 typedef struct grpic_s grpic_t;

@@ -59,6 +59,7 @@ class Diag(ctypes.Structure):
         ("gauss_residual_max", ctypes.c_double),
         ("mass_shell_residual_max", ctypes.c_double),
         ("deposit_blocks_lds", ctypes.c_int64), ("deposit_blocks_global", ctypes.c_int64),
+        ("push_blocks_lds", ctypes.c_int64), ("push_blocks_global", ctypes.c_int64),
     ]
 
     def as_dict(self):

@@ -1496,8 +1496,8 @@ int grpic_diagnostics(grpic_t *h, grpic_diag *out) {
                               h->cfg.outer_layer, h->cfg.outer_damp, h->rho_scratch, h->red, h->red_cap, d, s);
     }
     if (rc) return GRPIC_EDEVICE;
-    unsigned long long cnt[C_NCOUNTERS];
-    rc = check(hipMemcpyAsync(cnt, h->counters, sizeof(cnt), hipMemcpyDeviceToHost, s));
+    std::vector<unsigned long long> cnt(kCounterWords);
+    rc = check(hipMemcpyAsync(cnt.data(), h->counters, kCounterWords * 8, hipMemcpyDeviceToHost, s));
     if (!rc) rc = check(hipStreamSynchronize(s));
     if (rc) return rc;
     for (int q = 0; q < GRPIC_MAX_SPECIES; q++) out->n_alive[q] = d.n_alive[q];
@@ -1513,6 +1513,10 @@ int grpic_diagnostics(grpic_t *h, grpic_diag *out) {
     out->mass_shell_residual_max = d.shell_max;
     out->deposit_blocks_lds = (int64_t)cnt[C_DEP_LDS];
     out->deposit_blocks_global = (int64_t)cnt[C_DEP_GLOBAL];
+    for (int q = 0; q < kPushedSlots; q++) {
+        out->push_blocks_lds += (int64_t)cnt[pushed_index((unsigned)q) + kPushedLds];
+        out->push_blocks_global += (int64_t)cnt[pushed_index((unsigned)q) + kPushedGlobal];
+    }
     if ((cnt[C_FLAGS] & kFlagFixedRange) && !h->sticky) h->sticky = GRPIC_EOVERFLOW;
     return h->sticky ? h->sticky : GRPIC_OK;
 }

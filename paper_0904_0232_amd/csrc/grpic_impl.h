@@ -138,9 +138,12 @@ __device__ __forceinline__ void flush_box(const unsigned long long *sm, int V, i
 // The particle-step counter (live particles pushed, summed over steps) gets
 // one increment per wave of every push: it is spread over kPushedSlots cache
 // lines after the first, so same-address atomics do not serialise the push.
-// The counter is the sum of the slots.
+// The counter is the sum of the slots.  The next two words of each slot
+// count push blocks with live particles that staged an LDS node box
+// (kPushedLds) and that did not (kPushedGlobal), once per block.
 constexpr int kPushedSlots = 64;
 constexpr int kCounterWords = 16 * (1 + kPushedSlots);
+constexpr int kPushedLds = 1, kPushedGlobal = 2;
 __host__ __device__ inline int pushed_index(unsigned block) { return 16 * (1 + (int)(block & (kPushedSlots - 1))); }
 
 struct PushParams {

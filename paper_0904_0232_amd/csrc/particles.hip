@@ -31,6 +31,7 @@ struct NodeBox {
     const double2 *lds;
     int lo[3], n[3];
     bool use;
+    bool any;  // the block has a live lane
 };
 
 // L^a += sum over the 8 nodes of W_n (F_n u)^a, nodes addressed from the
@@ -147,6 +148,7 @@ __device__ __forceinline__ void stage_box(const Grid &G, const double *__restric
             a = sred[ax][w] < a ? sred[ax][w] : a;
             b = sred[3 + ax][w] > b ? sred[3 + ax][w] : b;
         }
+        if (ax == 0) B.any = b >= a;
         for (int e = 0; e < 2; e++) {  // e = 1: widened by one cell, within the nodes 0 .. dim
             const int l = a - e < 0 ? 0 : a - e;
             const int h = b + 1 + e > G.dim(ax) ? G.dim(ax) : b + 1 + e;
@@ -233,6 +235,7 @@ __global__ __launch_bounds__(kPushBlock, 4) void k_push(PushParams P, Species cS
         stage_box(P.G, node, live, c0, snode, sred, B);
     }
     const double qm = live ? sqm[sp] : 0.0;  // the table is written before the box's barriers
+    if (tid == 0 && B.any) atomicAdd(&counters[pushed_index(blockIdx.x) + (B.use ? kPushedLds : kPushedGlobal)], 1ull);
 #pragma unroll 1
     for (int st = 0; st < 4; st++) {
         int c[3];

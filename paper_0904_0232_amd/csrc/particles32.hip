@@ -44,6 +44,7 @@ struct NodeBox32 {
     const float4 *lds;
     int lo[3], n[3];
     bool use;
+    bool any;  // the block has a live lane
 };
 
 // L^a += sum over the 8 nodes of W_n (F_n u)^a from the (0,0,0) node p and
@@ -165,6 +166,7 @@ __device__ __forceinline__ void stage_box32(const Grid &G, const float *__restri
             a = sred[ax][w] < a ? sred[ax][w] : a;
             b = sred[3 + ax][w] > b ? sred[3 + ax][w] : b;
         }
+        if (ax == 0) B.any = b >= a;
         for (int e = 0; e < 2; e++) {  // e = 1: widened by one cell, within the nodes 0 .. dim
             const int l = a - e < 0 ? 0 : a - e;
             const int h = b + 1 + e > G.dim(ax) ? G.dim(ax) : b + 1 + e;
@@ -260,6 +262,8 @@ __device__ __forceinline__ void push32_block(const PushParams &P, const Mixed &M
         stage_box32(P.G, node, alive, c0, snode, sred, B);
     }
     const float qm = alive ? (float)sqm[sp] : 0.0f;  // the table is written before the box's barriers
+    if (tid == 0 && B.any)
+        atomicAdd(&counters[pushed_index((unsigned)blk) + (B.use ? kPushedLds : kPushedGlobal)], 1ull);
 #pragma unroll 1
     for (int st = 0; st < 4; st++) {
         int c[3];

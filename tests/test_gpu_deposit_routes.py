@@ -125,6 +125,14 @@ def test_deposit_routes_against_oracle(precision):
     assert runs["cell"]["diag"]["deposit_blocks_global"] == 0 and runs["cell"]["diag"]["deposit_blocks_lds"] > 0
     assert runs["random"]["diag"]["deposit_blocks_lds"] == 0 and runs["random"]["diag"]["deposit_blocks_global"] > 0
     assert runs["mixed"]["diag"]["deposit_blocks_lds"] > 0 and runs["mixed"]["diag"]["deposit_blocks_global"] > 0
+    # the push's node box: staged in LDS for cell-ordered blocks (one row of
+    # 32 cells: 132 nodes, which the first cycle's drift can take past the
+    # 272-node budget), global gathers for blocks spread over the grid
+    for name in ("cell", "random"):
+        say("  push blocks (%s): %d with an LDS node box, %d without" %
+            (name, runs[name]["diag"]["push_blocks_lds"], runs[name]["diag"]["push_blocks_global"]))
+    assert runs["cell"]["diag"]["push_blocks_lds"] > 0
+    assert runs["random"]["diag"]["push_blocks_lds"] == 0 and runs["random"]["diag"]["push_blocks_global"] > 0
     # order independence: the same integers on either route
     ref = runs["cell"]
     n = _inputs()[0][1].shape[1]
